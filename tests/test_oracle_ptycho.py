@@ -1,0 +1,176 @@
+"""Pins of the reconstruction oracle (Eqs. 2-3, mini-batched ePIE/rPIE)
+against the published sequential algorithms, fixed points, projection
+identities and noiseless convergence.  CPU only."""
+import numpy as np
+import pytest
+
+from oracle import fourier, ptycho
+from paper_2608_01746_amd import synth
+
+
+def _tiny_geometry(M=48, Nw=16, r=5.0, n_side=6, step=5, offset=4, seed=1):
+    O = synth.make_object(M, seed)
+    P = synth.make_probe(Nw, r, np.pi)
+    pos = synth.raster_positions(n_side, step, offset)
+    assert pos.max() + Nw <= M
+    return O, P, pos
+
+
+def test_projection_identities():
+    rng = np.random.default_rng(0)
+    Psi = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+    Psi[3, 4] = 0.0
+    A = rng.uniform(0, 2, size=(16, 16))
+    Q = ptycho.modulus_projection(Psi, A)
+    np.testing.assert_allclose(np.abs(Q), A, atol=1e-14)
+    np.testing.assert_allclose(ptycho.modulus_projection(Q, A), Q, atol=1e-14)
+    assert Q[3, 4] == A[3, 4]
+    m = np.abs(Psi) > 0
+    np.testing.assert_allclose(np.angle(Q[m] * np.conj(Psi[m])), 0.0, atol=1e-12)
+
+
+@pytest.mark.parametrize("alg,B,upd", [("epie", 1, False), ("rpie", 4, True), ("epie", 36, True)])
+def test_truth_is_a_fixed_point(alg, B, upd):
+    O, P, pos = _tiny_geometry()
+    I = ptycho.forward_intensity(O, P, pos, 16)
+    prm = ptycho.PtychoParams(alg=alg, alpha=0.3, beta=0.7, batch=B, update_probe=upd)
+    O1, P1, err = ptycho.iterate(O, P, I, pos, 1, prm)
+    assert np.max(np.abs(O1 - O)) < 1e-12
+    assert np.max(np.abs(P1 - P)) < 1e-12
+    assert err[0] < 1e-24
+
+
+def test_rpie_alpha_one_equals_epie_alpha_one():
+    O, P, pos = _tiny_geometry(seed=2)
+    I = ptycho.forward_intensity(synth.make_object(48, 99), P, pos, 16)
+    O0 = np.ones_like(O)
+    a = ptycho.iterate(O0, P, I, pos, 2, ptycho.PtychoParams("epie", 1.0, 1.0, 3, True))
+    b = ptycho.iterate(O0, P, I, pos, 2, ptycho.PtychoParams("rpie", 1.0, 1.0, 3, True))
+    for x, y in zip(a, b):
+        np.testing.assert_allclose(x, y, rtol=1e-14, atol=1e-14)
+
+
+def _textbook_epie(O, P, A, pos, alpha, beta, update_probe):
+    # Maiden & Rodenburg (2009), one position at a time, written directly.
+    Nw = P.shape[0]
+    O = O.copy()
+    P = P.copy()
+    for (y, x), Aj in zip(pos, A):
+        Oj = O[y:y + Nw, x:x + Nw].copy()
+        psi = P * Oj
+        F = np.fft.fft2(psi, norm="ortho")
+        F = Aj * np.exp(1j * np.angle(F))
+        d = np.fft.ifft2(F, norm="ortho") - psi
+        O[y:y + Nw, x:x + Nw] = Oj + alpha * np.conj(P) / np.max(np.abs(P) ** 2) * d
+        if update_probe:
+            P = P + beta * np.conj(Oj) / np.max(np.abs(Oj) ** 2) * d
+    return O, P
+
+
+def test_batch_of_one_is_textbook_epie():
+    O_true, P, pos = _tiny_geometry(seed=3)
+    I = ptycho.forward_intensity(O_true, P, pos, 16)
+    A = ptycho.amplitudes(I)
+    O0 = np.ones_like(O_true)
+    P0 = P * np.exp(0.3j)
+    Oa, Pa, _ = ptycho.iterate(O0, P0, I, pos, 1, ptycho.PtychoParams("epie", 0.8, 0.6, 1, True))
+    Ob, Pb = _textbook_epie(O0, P0, A, pos, 0.8, 0.6, True)
+    np.testing.assert_allclose(Oa, Ob, atol=1e-12)
+    np.testing.assert_allclose(Pa, Pb, atol=1e-12)
+
+
+def test_disjoint_batch_equals_sequential_object_update():
+    O_true = synth.make_object(64, 4)
+    P = synth.make_probe(16, 6.0, np.pi)
+    pos = np.array([[0, 0], [0, 24], [24, 0], [40, 40]], np.int32)
+    I = ptycho.forward_intensity(O_true, P, pos, 16)
+    O0 = np.ones_like(O_true)
+    prm_b = ptycho.PtychoParams("rpie", 0.2, 0.2, 4, False)
+    prm_s = ptycho.PtychoParams("rpie", 0.2, 0.2, 1, False)
+    Ob, _, eb = ptycho.iterate(O0, P, I, pos, 1, prm_b)
+    Os, _, es = ptycho.iterate(O0, P, I, pos, 1, prm_s)
+    np.testing.assert_allclose(Ob, Os, atol=1e-13)
+    np.testing.assert_allclose(eb, es, rtol=1e-13)
+
+
+def test_overlapping_updates_are_averaged():
+    # two identical positions in one batch move O exactly as one would
+    O_true = synth.make_object(32, 5)
+    P = synth.make_probe(16, 6.0, 0.0)
+    pos1 = np.array([[8, 8]], np.int32)
+    pos2 = np.array([[8, 8], [8, 8]], np.int32)
+    I1 = ptycho.forward_intensity(O_true, P, pos1, 16)
+    I2 = np.concatenate([I1, I1])
+    O0 = np.ones_like(O_true)
+    prm = ptycho.PtychoParams("rpie", 0.5, 0.5, 2, False)
+    a, _, _ = ptycho.iterate(O0, P, I1, pos1, 1, prm)
+    b, _, _ = ptycho.iterate(O0, P, I2, pos2, 1, prm)
+    np.testing.assert_allclose(a, b, atol=1e-14)
+
+
+def test_zero_padded_window_placement_is_irrelevant():
+    # |F| is invariant to where the window sits inside the padded frame
+    O = synth.make_object(32, 6)
+    P = synth.make_probe(8, 3.0, 1.0)
+    psi = ptycho.exit_wave(O, P, (4, 4), 32)
+    moved = np.roll(psi, (11, 7), axis=(0, 1))
+    np.testing.assert_allclose(np.abs(fourier.fft2u(psi)), np.abs(fourier.fft2u(moved)), atol=1e-13)
+
+
+def test_nrmse_properties():
+    rng = np.random.default_rng(7)
+    O = rng.standard_normal((20, 20)) + 1j * rng.standard_normal((20, 20))
+    mask = np.ones(O.shape, bool)
+    assert ptycho.nrmse(O * np.exp(0.7j) * 2.0, O, mask) < 1e-14
+    noise = 1e-3 * (rng.standard_normal(O.shape) + 1j * rng.standard_normal(O.shape))
+    v = ptycho.nrmse(O + noise, O, mask)
+    assert 0.5e-3 < v < 2e-3
+
+
+def test_error_metric_zero_at_truth_and_positive_elsewhere():
+    O, P, pos = _tiny_geometry(seed=8)
+    I = ptycho.forward_intensity(O, P, pos, 16)
+    _, _, e0 = ptycho.iterate(O, P, I, pos, 1, ptycho.PtychoParams(batch=6))
+    _, _, e1 = ptycho.iterate(np.ones_like(O), P, I, pos, 1, ptycho.PtychoParams(batch=6))
+    assert e0[0] < 1e-25 and e1[0] > 1e-3
+
+
+def test_noiseless_known_probe_converges():
+    # noiseless data, known probe: rPIE drives the object NRMSE below 1e-6
+    O_true, P, pos = _tiny_geometry(M=48, Nw=16, r=6.0, n_side=7, step=4, offset=4, seed=9)
+    I = ptycho.forward_intensity(O_true, P, pos, 16)
+    mask = ptycho.illumination_mask(P, pos, O_true.shape, 0.5)
+    O = np.ones_like(O_true)
+    prm = ptycho.PtychoParams("rpie", 0.05, 0.1, 1, False)
+    v = 1.0
+    for it in range(40):
+        O, _, _ = ptycho.iterate(O, P, I, pos, 25, prm)
+        v = ptycho.nrmse(O, O_true, mask)
+        if v < 1e-6:
+            break
+    assert v < 1e-6, v
+
+
+def test_batch_of_one_is_textbook_rpie_with_soft_probe():
+    # Maiden, Johnson & Li (2017) regularised update, one position at a time;
+    # a probe with a varying modulus makes alpha and beta matter.
+    rng = np.random.default_rng(12)
+    O_true, P, pos = _tiny_geometry(seed=12)
+    P = P * (0.3 + 0.7 * rng.random(P.shape))
+    I = ptycho.forward_intensity(O_true, P, pos, 16)
+    A = ptycho.amplitudes(I)
+    O = np.ones_like(O_true)
+    Pc = P * np.exp(0.2j)
+    a, b = 0.3, 0.6
+    Oa, Pa, _ = ptycho.iterate(O, Pc, I, pos, 1, ptycho.PtychoParams("rpie", a, b, 1, True))
+    Nw = 16
+    for (y, x), Aj in zip(pos, A):
+        Oj = O[y:y + Nw, x:x + Nw].copy()
+        psi = Pc * Oj
+        F = np.fft.fft2(psi, norm="ortho")
+        d = np.fft.ifft2(Aj * np.exp(1j * np.angle(F)), norm="ortho") - psi
+        P2, O2 = np.abs(Pc) ** 2, np.abs(Oj) ** 2
+        O[y:y + Nw, x:x + Nw] = Oj + np.conj(Pc) * d / ((1 - a) * P2 + a * P2.max())
+        Pc = Pc + np.conj(Oj) * d / ((1 - b) * O2 + b * O2.max())
+    np.testing.assert_allclose(Oa, O, atol=1e-12)
+    np.testing.assert_allclose(Pa, Pc, atol=1e-12)
