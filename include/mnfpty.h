@@ -1,0 +1,169 @@
+/*
+ * mnfpty — HDR-fused far-field ptychography on AMD MI355X (gfx950).
+ *
+ * C ABI of libmnfpty.so.  Every array argument is a plain pointer; the
+ * comment on each argument says whether it lives in device (HBM) or host
+ * memory, its element type and its C-contiguous row-major shape.  The caller
+ * owns every buffer it passes; the library never returns memory.  A context
+ * owns only its internal scratch (grown on demand and reused), FFT twiddle
+ * tables and staging copies of small host arrays.
+ *
+ * All compute calls are asynchronous on the given stream (a hipStream_t
+ * passed as void*, NULL = the device's null stream).  Host arrays are copied
+ * before the call returns, so the caller may reuse them at once.  Calls on
+ * one context must not overlap in time from several host threads.
+ *
+ * Errors: every int-returning call returns 0 or one of the negative codes
+ * below and never prints, throws or exits.  mnf_last_error() returns a
+ * human-readable message for the last failing call on that context.
+ *
+ * Complex numbers are interleaved {float re, im} (the layout of
+ * torch.complex64 / std::complex<float>).
+ */
+#ifndef MNFPTY_H
+#define MNFPTY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MNF_OK            0
+#define MNF_EINVAL       -1   /* bad argument: null pointer, size <= 0, window outside the object, ... */
+#define MNF_EUNSUPPORTED -2   /* detector size without a compiled FFT plan, too many levels/exposures */
+#define MNF_EHIP         -3   /* a HIP runtime call failed; the message holds hipGetErrorString */
+#define MNF_ENOMEM       -4   /* scratch allocation failed */
+
+typedef struct { float re, im; } mnf_c64;
+typedef struct mnf_ctx mnf_ctx;
+
+/* Create a context bound to HIP device `hip_device`.  *out receives the
+ * context (NULL on failure).  Returns MNF_OK, MNF_EINVAL or MNF_EHIP. */
+int mnf_create(mnf_ctx** out, int hip_device);
+
+/* Release a context and its scratch.  Waits for the device first.  NULL is a no-op. */
+void mnf_destroy(mnf_ctx* ctx);
+
+/* Message of the last failing call on ctx ("" if none).  Valid until the next call on ctx. */
+const char* mnf_last_error(const mnf_ctx* ctx);
+
+/* Detector sizes with a compiled FFT plan: writes up to `cap` sizes to
+ * `sizes` (host int32) and returns how many exist. */
+int mnf_supported_sizes(int32_t* sizes, int cap);
+
+/* ------------------------------------------------------------------------
+ * Multi-scale non-linear fusion of exposure brackets
+ * (Methods 3.4: exposure quality Eq. 5, pyramids Eqs. 6-7, modulation and
+ * quantisation Eq. 8, per-exposure reconstruction and accumulation
+ * Eqs. 9-10; the bracket itself is Eq. 1).
+ *
+ * For every scan position j, with I_k = raw[j][k] (detector counts):
+ *   I_bar_k   = clamp((I_k - dark) / (sat - dark), 0, 1)
+ *   W_k       = exp(-(I_bar_k - mu)^2 / (2 sigma^2)) / sum_k' (same)
+ *   I_tilde_k = (I_k - dark) * t[0] / t[k]   (radiometric = 1)
+ *             = I_bar_k                       (radiometric = 0)
+ *   G_l: 5-tap binomial reduce, reflect-101 borders; U: zero-insert + 2 w_G
+ *   out = collapse over l = L..0 of
+ *         sum_k Q_{l,k}(G_l[W_k] (G_l[I_tilde_k] - U(G_{l+1}[I_tilde_k])))
+ *         with base sum_k G_L[W_k] G_L[I_tilde_k],
+ *   Q_{l,k}(x) = step * rint(x / step), step = delta[l] * t[0] / t[k]
+ *   (radiometric) or delta[l] / (sat - dark) (literal); step 0 = identity.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t levels;        /* L band-pass levels (0..12); H and W must be divisible by 2^L, and H, W >= 2^(L+1) */
+    float   mu;            /* weight centre in normalised units (paper's mu) */
+    float   sigma;         /* weight width (paper's sigma), > 0 */
+    float   sat;           /* detector full scale in ADU, > dark */
+    float   dark;          /* dark level in ADU */
+    float   delta[16];     /* quantisation step per level in ADU, l = 0 finest; 0 disables */
+    int32_t radiometric;   /* 1: fuse counts scaled to the shortest exposure; 0: fuse I_bar */
+} mnf_fuse_params;
+
+/* raw        device uint16 [J][K][H][W]   exposure brackets
+ * t          host   float  [K]            exposure times, t[0] the reference (> 0)
+ * fused      device float  [J][H][W]      output I_MNF, same (detector-centred) layout as raw
+ * weights_out device float [J][K][H][W]  normalised weights W_k, or NULL
+ * K <= 16.  Returns MNF_OK, MNF_EINVAL, MNF_EUNSUPPORTED, MNF_ENOMEM or MNF_EHIP. */
+int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
+                   int J, int K, int H, int W, const mnf_fuse_params* params,
+                   float* fused, float* weights_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Far-field forward model (Methods 3.3, Eqs. 2-3):
+ *   I_out[j] = fftshift |F_unitary(pad_Nd(P * O[pos_j window]))|^2
+ * O     device c64 [My][Mx];  P device c64 [Nw][Nw];
+ * pos   host int32 [J][2] (y, x) top-left corner of each window in O;
+ * I_out device float [J][Nd][Nd], detector-centred (zero frequency at Nd/2).
+ * Nw <= Nd, Nd a supported size.  The exit wave sits at the top-left of the
+ * Nd x Nd frame when Nw < Nd. */
+int ptycho_forward(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx,
+                   const mnf_c64* P, int Nw, int Nd, const int32_t* pos, int J,
+                   float* I_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Mini-batched ePIE / rPIE reconstruction from fused intensities.
+ * Exit wave (Eq. 2) -> unitary FFT (Eq. 3) -> Fourier-modulus projection
+ * against A = sqrt(max(I, 0)) -> inverse FFT -> simultaneous object and probe
+ * updates (ePIE: Maiden & Rodenburg 2009; rPIE: Maiden, Johnson & Li 2017),
+ * numerators and denominators summed over each mini-batch of `batch`
+ * consecutive positions of the iteration's order, both updates from the
+ * batch-start state.  Denominators and error sums are float64.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t alg;              /* 0 = ePIE, 1 = rPIE */
+    float   alpha;            /* object step (ePIE: den = max|P|^2/alpha; rPIE: (1-alpha)|P|^2 + alpha max|P|^2) */
+    float   beta;             /* probe step, same forms with |O_j|^2 */
+    int32_t batch;            /* mini-batch size B >= 1 */
+    int32_t update_probe;     /* 0: probe fixed; 1: probe updated */
+    int32_t probe_start_iter; /* first iteration index (it0-based) that updates the probe */
+    int32_t it0;              /* index of the first iteration of this call (for probe_start_iter and resuming) */
+} ptycho_params;
+
+/* O      device c64 [My][Mx]   object, updated in place
+ * P      device c64 [Nw][Nw]   probe, updated in place
+ * I      device float [J][Nd][Nd] fused intensities, detector-centred
+ * pos    host int32 [J][2]     window corners, every window inside O
+ * order  host int32 [n_iter][J] one permutation of 0..J-1 per iteration, or NULL (identity)
+ * err_out device double [n_iter] normalised Fourier error per iteration, or NULL
+ * Returns MNF_OK, MNF_EINVAL, MNF_EUNSUPPORTED, MNF_ENOMEM or MNF_EHIP. */
+int ptycho_iterate(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw,
+                   const float* I, int Nd, const int32_t* pos, int J,
+                   const int32_t* order, int n_iter, const ptycho_params* params,
+                   double* err_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Loss on fused intensities and its gradient (the adjoint of Eqs. 2-3),
+ * exit waves recomputed per chunk of `batch` positions:
+ *   loss = sum_j sum_q l(Psi_j, I_j),  Psi_j = F_unitary(pad(P O_j)),
+ *   Poisson (kind 0): l = |Psi|^2 - I ln(|Psi|^2 + eps), I = max(I, 0)
+ *   amplitude (kind 1): l = (|Psi| - sqrt(I))^2
+ * Gradients use g = dL/dRe + i dL/dIm (PyTorch's complex convention),
+ * scaled by *upstream (host double).
+ * gO device c64 [My][Mx] and gP device c64 [Nw][Nw] are overwritten (either may be NULL).
+ * loss_out device double [1] (may be NULL). */
+int ptycho_grad(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P, int Nw,
+                const float* I, int Nd, const int32_t* pos, int J,
+                int kind, float eps, int batch, double upstream,
+                double* loss_out, mnf_c64* gO, mnf_c64* gP, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Launch timing, for measurement.  With bit c of class_mask set, every
+ * launch of kernel class c is bracketed by HIP events recorded on its
+ * stream.  Classes: 0 rows_fwd (gather + row transforms), 1 cols_modulus
+ * (column transforms + modulus projection + inverse column transforms),
+ * 2 rows_inv (inverse row transforms + exit-wave difference), 3 probe_update,
+ * 4 object_update, 5 small (copies, reductions), 6 fuse, 7 forward,
+ * 8 grad_cols, 9 grad_scatter.  mask 0 disables timing.
+ * mnf_profile_read waits for the recorded events and returns the launch
+ * count and summed duration (ms) of class cls since the last reset. */
+int mnf_profile(mnf_ctx* ctx, uint32_t class_mask);
+int mnf_profile_read(mnf_ctx* ctx, int cls, long long* launches, double* total_ms);
+int mnf_profile_reset(mnf_ctx* ctx);
+const char* mnf_kernel_class_name(int cls);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MNFPTY_H */

@@ -1,0 +1,221 @@
+"""Python binding of libmnfpty: argument marshalling from torch tensors
+(device memory, streams) to the C ABI.  Every computation runs in the
+library's HIP kernels; this module only checks shapes, dtypes and devices,
+passes pointers and raises on error codes."""
+from __future__ import annotations
+
+import ctypes
+import threading
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import lib as _L
+
+
+class MnfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_L.ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+_ctx_lock = threading.Lock()
+_contexts = {}
+
+
+def _ctx(device: torch.device) -> ctypes.c_void_p:
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    with _ctx_lock:
+        c = _contexts.get(idx)
+        if c is None:
+            lib = _L.load()
+            c = ctypes.c_void_p()
+            rc = lib.mnf_create(ctypes.byref(c), idx)
+            if rc != 0:
+                raise MnfError(rc, f"mnf_create({idx}) failed")
+            _contexts[idx] = c
+        return c
+
+
+def _check(rc: int, ctx) -> None:
+    if rc != 0:
+        msg = _L.load().mnf_last_error(ctx)
+        raise MnfError(rc, msg.decode() if msg else "")
+
+
+def _stream(device: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtype, ndim: int) -> None:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise ValueError(f"{name} must have dtype {dtype}, got {t.dtype}")
+    if t.dim() != ndim or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {ndim}-D tensor, got shape {tuple(t.shape)}")
+
+
+def _ptr(t: Optional[torch.Tensor]) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def _host_i32(a, shape_tail, name) -> np.ndarray:
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.int32))
+    if arr.shape[1:] != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [*]{list(shape_tail)}, got {arr.shape}")
+    return arr
+
+
+def _i32p(arr: Optional[np.ndarray]):
+    if arr is None:
+        return None
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+def supported_sizes():
+    lib = _L.load()
+    buf = (ctypes.c_int32 * 32)()
+    n = lib.mnf_supported_sizes(buf, 32)
+    return [buf[i] for i in range(n)]
+
+
+# ------------------------------------------------------------------ fusion
+
+def fuse_exposures(raw: torch.Tensor, t: Sequence[float], levels: int, mu: float = 0.5,
+                   sigma: float = 0.2, sat: float = 65535.0, dark: float = 0.0,
+                   delta: Sequence[float] = (), radiometric: bool = True,
+                   return_weights: bool = False, out: Optional[torch.Tensor] = None):
+    """MNF fusion of raw[J][K][H][W] (uint16 counts) -> fused float32 [J][H][W]."""
+    _dev(raw, "raw", (torch.uint16, torch.int16), 4)
+    J, K, H, W = raw.shape
+    if len(t) != K:
+        raise ValueError("one exposure time per exposure")
+    if len(delta) > 16:
+        raise ValueError("at most 16 quantisation steps")
+    if out is None:
+        out = torch.empty((J, H, W), dtype=torch.float32, device=raw.device)
+    else:
+        _dev(out, "out", torch.float32, 3)
+    wts = torch.empty((J, K, H, W), dtype=torch.float32, device=raw.device) if return_weights else None
+    prm = _L.FuseParamsC()
+    prm.levels, prm.mu, prm.sigma, prm.sat, prm.dark = int(levels), mu, sigma, sat, dark
+    for i, d in enumerate(delta):
+        prm.delta[i] = float(d)
+    prm.radiometric = 1 if radiometric else 0
+    tt = (ctypes.c_float * K)(*[float(x) for x in t])
+    ctx = _ctx(raw.device)
+    rc = _L.load().fuse_exposures(ctx, _ptr(raw), tt, J, K, H, W, ctypes.byref(prm), _ptr(out), _ptr(wts),
+                                  _stream(raw.device))
+    _check(rc, ctx)
+    return (out, wts) if return_weights else out
+
+
+# ----------------------------------------------------------- forward model
+
+def ptycho_forward(O: torch.Tensor, P: torch.Tensor, pos, Nd: int,
+                   out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Detector-centred |F(P O_j)|^2 for every window corner in pos [J][2]."""
+    _dev(O, "O", torch.complex64, 2)
+    _dev(P, "P", torch.complex64, 2)
+    posa = _host_i32(pos, (2,), "pos")
+    J = posa.shape[0]
+    if out is None:
+        out = torch.empty((J, Nd, Nd), dtype=torch.float32, device=O.device)
+    else:
+        _dev(out, "out", torch.float32, 3)
+    ctx = _ctx(O.device)
+    rc = _L.load().ptycho_forward(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], Nd,
+                                  _i32p(posa), J, _ptr(out), _stream(O.device))
+    _check(rc, ctx)
+    return out
+
+
+# ----------------------------------------------------------- reconstruction
+
+ALGS = {"epie": 0, "rpie": 1}
+
+
+def ptycho_iterate(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_iter: int,
+                   alg: str = "rpie", alpha: float = 0.1, beta: float = 0.1, batch: int = 1,
+                   update_probe: bool = False, probe_start_iter: int = 0, order=None, it0: int = 0,
+                   err: bool = True) -> Optional[torch.Tensor]:
+    """Run n_iter mini-batched ePIE/rPIE iterations, updating O and P in place.
+    Returns the float64 error per iteration (device tensor) if err."""
+    _dev(O, "O", torch.complex64, 2)
+    _dev(P, "P", torch.complex64, 2)
+    _dev(I, "I", torch.float32, 3)
+    posa = _host_i32(pos, (2,), "pos")
+    J = posa.shape[0]
+    if I.shape[0] != J or I.shape[1] != I.shape[2]:
+        raise ValueError("I must be [J][Nd][Nd]")
+    orda = None
+    if order is not None:
+        orda = _host_i32(order, (J,), "order")
+        if orda.shape[0] != n_iter:
+            raise ValueError("order must have one row per iteration")
+    prm = _L.PtychoParamsC(ALGS[alg], alpha, beta, batch, 1 if update_probe else 0, probe_start_iter, it0)
+    e = torch.empty(max(n_iter, 1), dtype=torch.float64, device=O.device) if err else None
+    ctx = _ctx(O.device)
+    rc = _L.load().ptycho_iterate(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], _ptr(I),
+                                  I.shape[1], _i32p(posa), J, _i32p(orda), n_iter, ctypes.byref(prm),
+                                  _ptr(e), _stream(O.device))
+    _check(rc, ctx)
+    return e[:n_iter] if err else None
+
+
+# ------------------------------------------------------------------ adjoint
+
+LOSSES = {"poisson": 0, "amplitude": 1}
+
+
+def ptycho_grad(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, kind: str = "poisson",
+                eps: float = 1e-6, batch: int = 32, upstream: float = 1.0, need_gO: bool = True,
+                need_gP: bool = True):
+    """(loss float64 device scalar, gO or None, gP or None)."""
+    _dev(O, "O", torch.complex64, 2)
+    _dev(P, "P", torch.complex64, 2)
+    _dev(I, "I", torch.float32, 3)
+    posa = _host_i32(pos, (2,), "pos")
+    J = posa.shape[0]
+    loss = torch.empty((), dtype=torch.float64, device=O.device)
+    gO = torch.empty_like(O) if need_gO else None
+    gP = torch.empty_like(P) if need_gP else None
+    ctx = _ctx(O.device)
+    rc = _L.load().ptycho_grad(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], _ptr(I),
+                               I.shape[1], _i32p(posa), J, LOSSES[kind], eps, batch, float(upstream),
+                               _ptr(loss), _ptr(gO), _ptr(gP), _stream(O.device))
+    _check(rc, ctx)
+    return loss, gO, gP
+
+
+# ------------------------------------------------------------ launch timing
+
+def profile(classes, device="cuda:0") -> None:
+    """Time every launch of the named kernel classes with HIP events
+    (empty / None disables)."""
+    mask = 0
+    for c in classes or ():
+        mask |= 1 << _L.KERNEL_CLASSES.index(c)
+    dev = torch.device(device)
+    ctx = _ctx(dev)
+    _check(_L.load().mnf_profile(ctx, mask), ctx)
+
+
+def profile_reset(device="cuda:0") -> None:
+    ctx = _ctx(torch.device(device))
+    _check(_L.load().mnf_profile_reset(ctx), ctx)
+
+
+def profile_read(device="cuda:0") -> dict:
+    """{class: (launches, total_ms)} for every class with launches."""
+    ctx = _ctx(torch.device(device))
+    out = {}
+    for i, name in enumerate(_L.KERNEL_CLASSES):
+        n = ctypes.c_longlong()
+        ms = ctypes.c_double()
+        _check(_L.load().mnf_profile_read(ctx, i, ctypes.byref(n), ctypes.byref(ms)), ctx)
+        if n.value:
+            out[name] = (int(n.value), float(ms.value))
+    return out

@@ -1,0 +1,106 @@
+// Shared host/device helpers of libmnfpty: context, error plumbing, scratch.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mnfpty.h"
+
+// Kernel classes for launch timing (see mnf_profile in the public header).
+enum MnfKernelClass {
+    MNF_K_ROWS_FWD = 0,   // gather + row transforms
+    MNF_K_COLS_MODULUS,   // column transforms + modulus projection + inverse column transforms
+    MNF_K_ROWS_INV,       // inverse row transforms + exit-wave difference
+    MNF_K_PROBE_UPDATE,
+    MNF_K_OBJECT_UPDATE,
+    MNF_K_SMALL,          // copies, reductions
+    MNF_K_FUSE,           // fusion kernels
+    MNF_K_FORWARD,        // forward-model column pass
+    MNF_K_GRAD_COLS,      // gradient column pass
+    MNF_K_GRAD_SCATTER,   // gradient object/probe scatter
+    MNF_K_NCLASS
+};
+
+struct MnfProfile {
+    uint32_t mask = 0;
+    std::vector<hipEvent_t> pool;
+    struct Pending { int cls; hipEvent_t a, b; };
+    std::vector<Pending> pending;
+    long long launches[MNF_K_NCLASS] = {};
+    double ms[MNF_K_NCLASS] = {};
+};
+
+struct mnf_ctx {
+    int device = 0;
+    MnfProfile prof;
+    std::string err;
+    // named device scratch buffers, grown on demand and reused across calls
+    std::map<std::string, std::pair<void*, size_t>> scratch;
+    // unitary FFT twiddles exp(-2 pi i n / N), n < N, one table per N (float2 on device)
+    std::map<int, float2*> twiddles;
+    // pinned staging for host -> device copies of small host arrays
+    void* pinned = nullptr;
+    size_t pinned_size = 0;
+    hipEvent_t pinned_done = nullptr;
+};
+
+namespace mnf {
+
+int set_error(mnf_ctx* ctx, int code, const char* fmt, ...);
+
+#define MNF_HIP(ctx, call)                                                          \
+    do {                                                                            \
+        hipError_t e_ = (call);                                                     \
+        if (e_ != hipSuccess)                                                       \
+            return ::mnf::set_error((ctx), MNF_EHIP, "%s failed: %s", #call,        \
+                                    hipGetErrorString(e_));                         \
+    } while (0)
+
+#define MNF_TRY(expr)             \
+    do {                          \
+        int r_ = (expr);          \
+        if (r_ != MNF_OK) return r_; \
+    } while (0)
+
+#define MNF_CHECK_LAUNCH(ctx) MNF_HIP(ctx, hipGetLastError())
+
+// Device scratch buffer `name` of at least `bytes`; *out receives its address.
+int scratch(mnf_ctx* ctx, const char* name, size_t bytes, void** out);
+
+// Copy `bytes` of host memory into device scratch `name` on `stream`.  The
+// host array may be reused as soon as this returns.
+int upload(mnf_ctx* ctx, const char* name, const void* host, size_t bytes,
+           hipStream_t stream, void** dev_out);
+
+// Device twiddle table for length N (computed in float64, rounded to float).
+int twiddles(mnf_ctx* ctx, int N, const float2** out);
+
+// Launch timing: start/stop events around one launch of class `cls`.
+int prof_start(mnf_ctx* ctx, hipStream_t st, hipEvent_t* e0);
+int prof_stop(mnf_ctx* ctx, int cls, hipStream_t st, hipEvent_t e0);
+
+#define MNF_LAUNCH(ctx, cls, st, kernel, grid, block, ...)                             \
+    do {                                                                               \
+        hipEvent_t e0_ = nullptr;                                                      \
+        if ((ctx)->prof.mask & (1u << (cls))) MNF_TRY(::mnf::prof_start((ctx), (st), &e0_)); \
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__);                   \
+        if (e0_) MNF_TRY(::mnf::prof_stop((ctx), (cls), (st), e0_));                  \
+    } while (0)
+
+inline int begin(mnf_ctx* ctx) {
+    if (!ctx) return MNF_EINVAL;
+    ctx->err.clear();
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess)
+        return set_error(ctx, MNF_EHIP, "hipSetDevice(%d) failed: %s", ctx->device,
+                         hipGetErrorString(e));
+    return MNF_OK;
+}
+
+}  // namespace mnf

@@ -1,0 +1,195 @@
+// Context lifetime, error messages, scratch arenas and host staging.
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+
+namespace mnf {
+
+int set_error(mnf_ctx* ctx, int code, const char* fmt, ...) {
+    if (ctx) {
+        char buf[1024];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+int scratch(mnf_ctx* ctx, const char* name, size_t bytes, void** out) {
+    if (bytes == 0) bytes = 256;
+    auto it = ctx->scratch.find(name);
+    if (it != ctx->scratch.end() && it->second.second >= bytes) {
+        *out = it->second.first;
+        return MNF_OK;
+    }
+    if (it != ctx->scratch.end()) {
+        // the old buffer may still be read by queued work
+        MNF_HIP(ctx, hipDeviceSynchronize());
+        MNF_HIP(ctx, hipFree(it->second.first));
+        ctx->scratch.erase(it);
+    }
+    size_t cap = bytes + bytes / 4;  // headroom against small regrowths
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, cap);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(ctx, MNF_ENOMEM, "scratch '%s': hipMalloc(%zu) failed: %s", name, cap,
+                         hipGetErrorString(e));
+    }
+    ctx->scratch[name] = {p, cap};
+    *out = p;
+    return MNF_OK;
+}
+
+int upload(mnf_ctx* ctx, const char* name, const void* host, size_t bytes, hipStream_t stream,
+           void** dev_out) {
+    MNF_TRY(scratch(ctx, name, bytes, dev_out));
+    if (bytes == 0) return MNF_OK;
+    // the previous staged copy must have left the pinned buffer
+    if (ctx->pinned_done) MNF_HIP(ctx, hipEventSynchronize(ctx->pinned_done));
+    if (ctx->pinned_size < bytes) {
+        if (ctx->pinned) MNF_HIP(ctx, hipHostFree(ctx->pinned));
+        ctx->pinned = nullptr;
+        size_t cap = bytes < (1u << 20) ? (1u << 20) : bytes + bytes / 4;
+        MNF_HIP(ctx, hipHostMalloc(&ctx->pinned, cap, hipHostMallocDefault));
+        ctx->pinned_size = cap;
+    }
+    std::memcpy(ctx->pinned, host, bytes);
+    MNF_HIP(ctx, hipMemcpyAsync(*dev_out, ctx->pinned, bytes, hipMemcpyHostToDevice, stream));
+    if (!ctx->pinned_done) MNF_HIP(ctx, hipEventCreateWithFlags(&ctx->pinned_done, hipEventDisableTiming));
+    MNF_HIP(ctx, hipEventRecord(ctx->pinned_done, stream));
+    return MNF_OK;
+}
+
+int twiddles(mnf_ctx* ctx, int N, const float2** out) {
+    auto it = ctx->twiddles.find(N);
+    if (it != ctx->twiddles.end()) {
+        *out = it->second;
+        return MNF_OK;
+    }
+    std::vector<float2> h(N);
+    for (int n = 0; n < N; ++n) {
+        // exact for the multiples of pi/4 through sincos of a reduced angle
+        double a = -2.0 * M_PI * (double)n / (double)N;
+        h[n] = make_float2((float)std::cos(a), (float)std::sin(a));
+    }
+    float2* d = nullptr;
+    MNF_HIP(ctx, hipMalloc(&d, sizeof(float2) * N));
+    MNF_HIP(ctx, hipMemcpy(d, h.data(), sizeof(float2) * N, hipMemcpyHostToDevice));
+    ctx->twiddles[N] = d;
+    *out = d;
+    return MNF_OK;
+}
+
+static int prof_event(mnf_ctx* ctx, hipEvent_t* e) {
+    if (!ctx->prof.pool.empty()) {
+        *e = ctx->prof.pool.back();
+        ctx->prof.pool.pop_back();
+        return MNF_OK;
+    }
+    MNF_HIP(ctx, hipEventCreate(e));
+    return MNF_OK;
+}
+
+int prof_start(mnf_ctx* ctx, hipStream_t st, hipEvent_t* e0) {
+    MNF_TRY(prof_event(ctx, e0));
+    MNF_HIP(ctx, hipEventRecord(*e0, st));
+    return MNF_OK;
+}
+
+int prof_stop(mnf_ctx* ctx, int cls, hipStream_t st, hipEvent_t e0) {
+    hipEvent_t e1;
+    MNF_TRY(prof_event(ctx, &e1));
+    MNF_HIP(ctx, hipEventRecord(e1, st));
+    ctx->prof.pending.push_back({cls, e0, e1});
+    return MNF_OK;
+}
+
+static int prof_drain(mnf_ctx* ctx) {
+    for (auto& p : ctx->prof.pending) {
+        MNF_HIP(ctx, hipEventSynchronize(p.b));
+        float ms = 0.f;
+        MNF_HIP(ctx, hipEventElapsedTime(&ms, p.a, p.b));
+        ctx->prof.launches[p.cls] += 1;
+        ctx->prof.ms[p.cls] += ms;
+        ctx->prof.pool.push_back(p.a);
+        ctx->prof.pool.push_back(p.b);
+    }
+    ctx->prof.pending.clear();
+    return MNF_OK;
+}
+
+}  // namespace mnf
+
+extern "C" {
+
+static const char* kClassNames[MNF_K_NCLASS] = {
+    "rows_fwd", "cols_modulus", "rows_inv", "probe_update", "object_update",
+    "small", "fuse", "forward", "grad_cols", "grad_scatter"};
+
+int mnf_profile(mnf_ctx* ctx, uint32_t class_mask) {
+    MNF_TRY(mnf::begin(ctx));
+    ctx->prof.mask = class_mask;
+    return MNF_OK;
+}
+
+int mnf_profile_read(mnf_ctx* ctx, int cls, long long* launches, double* total_ms) {
+    MNF_TRY(mnf::begin(ctx));
+    if (cls < 0 || cls >= MNF_K_NCLASS) return mnf::set_error(ctx, MNF_EINVAL, "kernel class %d", cls);
+    MNF_TRY(mnf::prof_drain(ctx));
+    if (launches) *launches = ctx->prof.launches[cls];
+    if (total_ms) *total_ms = ctx->prof.ms[cls];
+    return MNF_OK;
+}
+
+int mnf_profile_reset(mnf_ctx* ctx) {
+    MNF_TRY(mnf::begin(ctx));
+    MNF_TRY(mnf::prof_drain(ctx));
+    for (int i = 0; i < MNF_K_NCLASS; ++i) {
+        ctx->prof.launches[i] = 0;
+        ctx->prof.ms[i] = 0.0;
+    }
+    return MNF_OK;
+}
+
+const char* mnf_kernel_class_name(int cls) {
+    return (cls >= 0 && cls < MNF_K_NCLASS) ? kClassNames[cls] : "";
+}
+
+int mnf_create(mnf_ctx** out, int hip_device) {
+    if (!out) return MNF_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+        (void)hipGetLastError();
+        return MNF_EINVAL;
+    }
+    if (hipSetDevice(hip_device) != hipSuccess) return MNF_EHIP;
+    mnf_ctx* c = new mnf_ctx();
+    c->device = hip_device;
+    *out = c;
+    return MNF_OK;
+}
+
+void mnf_destroy(mnf_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& kv : ctx->scratch) (void)hipFree(kv.second.first);
+    for (auto& kv : ctx->twiddles) (void)hipFree(kv.second);
+    for (auto& p : ctx->prof.pending) {
+        (void)hipEventDestroy(p.a);
+        (void)hipEventDestroy(p.b);
+    }
+    for (auto e : ctx->prof.pool) (void)hipEventDestroy(e);
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    if (ctx->pinned_done) (void)hipEventDestroy(ctx->pinned_done);
+    delete ctx;
+}
+
+const char* mnf_last_error(const mnf_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+}  // extern "C"

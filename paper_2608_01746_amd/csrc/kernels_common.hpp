@@ -1,0 +1,63 @@
+// Block-level reductions and launch shapes shared by the pattern kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fft.hpp"
+
+namespace mnf {
+
+constexpr int kMaxBatch = 512;  // positions per mini-batch handled by one launch
+constexpr int kColGroup = 16;   // adjacent columns per column-pass block (16 x 8 B = 128 B rows)
+
+// Row passes: LINES pattern rows per block, T threads per row.
+template <int N>
+struct RowCfg {
+    static constexpr int T = PlanInfo<N>::T;
+    static constexpr int LINES = (256 / T) < N ? (256 / T) : N;
+    static constexpr int THREADS = LINES * T;
+};
+
+// Column passes: C adjacent columns per block, T threads per column.
+template <int N>
+struct ColCfg {
+    static constexpr int T = PlanInfo<N>::T;
+    static constexpr int C = kColGroup < N ? kColGroup : N;
+    static constexpr int THREADS = C * T;
+};
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Block-wide max / sum in a fixed order (waves combined in index order).
+// `red` must hold blockDim.x / 64 elements.  Result valid in every thread.
+__device__ __forceinline__ float block_max(float v, float* red) {
+    v = wave_max(v);
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    float r = red[0];
+    for (int i = 1; i < nw; ++i) r = fmaxf(r, red[i]);
+    return r;
+}
+__device__ __forceinline__ double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int i = 1; i < nw; ++i) r += red[i];
+    return r;
+}
+
+}  // namespace mnf
