@@ -23,7 +23,7 @@ namespace mnf {
 template <int N>
 __global__ void __launch_bounds__(RowCfg<N>::THREADS)
 k_rows_fwd(const float2* __restrict__ O, int Mx, const float2* __restrict__ P, int Nw,
-           const int* __restrict__ pos, const int* __restrict__ bj, float2* __restrict__ S,
+           const int2* __restrict__ bp, float2* __restrict__ S,
            float* __restrict__ maxO2_part, float* __restrict__ maxP2_part,
            const float2* __restrict__ tw_g) {
     constexpr int T = RowCfg<N>::T, LINES = RowCfg<N>::LINES, V = PlanInfo<N>::V;
@@ -31,8 +31,8 @@ k_rows_fwd(const float2* __restrict__ O, int Mx, const float2* __restrict__ P, i
     __shared__ float2 tw[N];
     __shared__ float red[RowCfg<N>::THREADS / 64 + 1];
     const int s = blockIdx.y;
-    const int j = bj[s];
-    const int py = pos[2 * j], px = pos[2 * j + 1];
+    const int2 c = bp[s];
+    const int py = c.x, px = c.y;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int y = blockIdx.x * LINES + line;
     const bool live = y < Nw;
@@ -187,20 +187,15 @@ k_cols_intensity(const float2* __restrict__ S, int Nw, const int* __restrict__ b
 }
 
 // --------------------------------------------------------------- rows_inv
-// grid (ceil(Nw / LINES), nb).  Inverse row transforms of the first Nw rows.
-// DPSI = true : S[s][y][n] = psi'(y, n) - P(y, n) O_j(y, n) for n < Nw
-// DPSI = false: S[s][y][n] = scale * psi'(y, n)              for n < Nw
-template <int N, bool DPSI>
+// grid (ceil(Nw / LINES), nb).  Gradient path: inverse row transforms of the
+// first Nw rows, S[s][y][n] = scale * psi'(y, n) for n < Nw.
+template <int N>
 __global__ void __launch_bounds__(RowCfg<N>::THREADS)
-k_rows_inv(float2* __restrict__ S, const float2* __restrict__ O, int Mx,
-           const float2* __restrict__ P, int Nw, const int* __restrict__ pos,
-           const int* __restrict__ bj, float scale, const float2* __restrict__ tw_g) {
+k_rows_inv(float2* __restrict__ S, int Nw, float scale, const float2* __restrict__ tw_g) {
     constexpr int T = RowCfg<N>::T, LINES = RowCfg<N>::LINES, V = PlanInfo<N>::V;
     __shared__ float2 lds[LINES * RowLds<N>::stride];
     __shared__ float2 tw[N];
     const int s = blockIdx.y;
-    const int j = bj[s];
-    const int py = pos[2 * j], px = pos[2 * j + 1];
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int y = blockIdx.x * LINES + line;
     const bool live = y < Nw;
@@ -214,18 +209,140 @@ k_rows_inv(float2* __restrict__ S, const float2* __restrict__ O, int Mx,
     __syncthreads();
     fft_line<N, true>(x, t, lds, RowLds<N>(line), tw);
     if (!live) return;
-    const float sc = 1.f / (float)N;
-    const float2* Orow = O + (size_t)(py + y) * Mx + px;
-    const float2* Prow = P + (size_t)y * Nw;
+    const float sc = scale / (float)N;
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int n = out_pos<N, true>(t, idx);
-        if (n < Nw) {
-            const float2 v = cscale(x[idx], sc);
-            if constexpr (DPSI) {
-                row[n] = csub(v, cmul(Prow[n], Orow[n]));
-            } else {
-                row[n] = cscale(v, scale);
+        if (n < Nw) row[n] = cscale(x[idx], sc);
+    }
+}
+
+// ------------------------------------------------------- rows_inv_update
+// One block per probe row r (grid Nw), looping over the batch's nb patterns
+// in rounds of ULINES.  For each pattern s the inverse row transform of
+// S[s][r][:] (with the unitary 1/N) gives psi'(r, n), n < Nw, and
+//   MODE 0, 1 (reconstruction):
+//     dpsi = psi' - P(r, n) O_s(r, n);  S[s][r][n] = conj(P(r, n)) dpsi
+//     (the object-update numerator term).  P2old[r][n] = |P(r, n)|^2 of the
+//     batch-start probe, all the object update still needs of it.  MODE 1
+//     also updates the probe row in place from the batch sums (slot order,
+//     float64 denominators):
+//       P(r, n) += sum_s conj(O_s) dpsi / sum_s d_P,s
+//       rPIE: d_P,s = (1 - beta)|O_s|^2 + beta max|O_s|^2;  ePIE: max|O_s|^2 / beta
+//   MODE 2 (gradient): g = upstream * psi';  S[s][r][n] = conj(P(r, n)) g and
+//     gP(r, n) += sum_s conj(O_s(r, n)) g.
+template <int N>
+struct UpdCfg {
+    static constexpr int T = PlanInfo<N>::T;
+    static constexpr int ULINES = N >= 512 ? 8 : RowCfg<N>::LINES;
+    static constexpr int THREADS = ULINES * T;
+};
+
+template <int N, int MODE>
+__global__ void __launch_bounds__(UpdCfg<N>::THREADS)
+k_rows_inv_update(float2* __restrict__ S, const float2* __restrict__ O, int Mx,
+                  float2* __restrict__ P, float* __restrict__ P2old, float2* __restrict__ gP, int Nw,
+                  const int2* __restrict__ bp, int nb,
+                  const float* __restrict__ maxO2_part, int nparts, int rpie, float beta,
+                  float upstream, const float2* __restrict__ tw_g) {
+    constexpr int T = UpdCfg<N>::T, ULINES = UpdCfg<N>::ULINES, V = PlanInfo<N>::V;
+    constexpr int THREADS = UpdCfg<N>::THREADS;
+    constexpr int COLS = (N + THREADS - 1) / THREADS;  // probe columns owned per thread
+    constexpr bool ACC = MODE != 0;                     // probe-row sums over the batch
+    constexpr bool DEN = MODE == 1;
+    __shared__ float2 lds[ULINES * RowLds<N>::stride];
+    __shared__ float2 tw[N];
+    __shared__ float2 c_num[ACC ? ULINES * N : 1];
+    __shared__ float c_den[DEN ? ULINES * N : 1];
+    __shared__ float s_max[DEN ? kMaxBatch : 1];
+    __shared__ int s_py[kMaxBatch], s_px[kMaxBatch];
+    const int r = blockIdx.x;
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+
+    for (int i = threadIdx.x; i < N; i += THREADS) tw[i] = tw_g[i];
+    for (int s = threadIdx.x; s < nb; s += THREADS) {
+        const int2 c = bp[s];
+        s_py[s] = c.x;
+        s_px[s] = c.y;
+        if constexpr (DEN) {
+            float m = 0.f;
+            for (int i = 0; i < nparts; ++i) m = fmaxf(m, maxO2_part[(size_t)s * nparts + i]);
+            s_max[s] = m;
+        }
+    }
+    const float2* Prow = P + (size_t)r * Nw;
+    float2 num[COLS];
+    double den[COLS];
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+        num[c] = make_float2(0.f, 0.f);
+        den[c] = 0.0;
+    }
+    __syncthreads();
+
+    const float sc = (MODE == 2 ? upstream : 1.f) / (float)N;
+    for (int s0 = 0; s0 < nb; s0 += ULINES) {
+        const int s = s0 + line;
+        const bool live = s < nb;
+        float2* row = S + ((size_t)(live ? s : 0) * N + r) * N;
+        float2 x[V];
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx)
+            x[idx] = live ? row[in_pos<N, true>(t, idx)] : make_float2(0.f, 0.f);
+        fft_line<N, true>(x, t, lds, RowLds<N>(line), tw);
+        if (live) {
+            const float2* Orow = O + (size_t)(s_py[s] + r) * Mx + s_px[s];
+            float mO = 0.f;
+            if constexpr (DEN) mO = s_max[s];
+#pragma unroll
+            for (int idx = 0; idx < V; ++idx) {
+                const int n = out_pos<N, true>(t, idx);
+                if (n < Nw) {
+                    const float2 p = Prow[n];
+                    const float2 o = Orow[n];
+                    const float2 d = MODE == 2 ? cscale(x[idx], sc) : csub(cscale(x[idx], sc), cmul(p, o));
+                    row[n] = cconjmul(p, d);
+                    if constexpr (ACC) c_num[line * N + n] = cconjmul(o, d);
+                    if constexpr (DEN) {
+                        const float o2 = cabs2(o);
+                        c_den[line * N + n] = rpie ? (1.f - beta) * o2 + beta * mO : mO / beta;
+                    }
+                }
+            }
+        }
+        if constexpr (ACC) {
+            __syncthreads();
+            const int nl = min(ULINES, nb - s0);
+#pragma unroll
+            for (int c = 0; c < COLS; ++c) {
+                const int n = threadIdx.x + c * THREADS;
+                if (n < Nw) {
+                    for (int l = 0; l < nl; ++l) {
+                        num[c] = cadd(num[c], c_num[l * N + n]);
+                        if constexpr (DEN) den[c] += (double)c_den[l * N + n];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < COLS; ++c) {
+        const int n = threadIdx.x + c * THREADS;
+        if (n >= Nw) continue;
+        if constexpr (MODE == 2) {
+            if (gP) {
+                float2* g = gP + (size_t)r * Nw + n;
+                *g = cadd(*g, num[c]);
+            }
+        } else {
+            float2 p = Prow[n];
+            P2old[(size_t)r * Nw + n] = cabs2(p);
+            if (DEN && den[c] > 0.0) {
+                const double inv = 1.0 / den[c];
+                p.x = (float)((double)p.x + (double)num[c].x * inv);
+                p.y = (float)((double)p.y + (double)num[c].y * inv);
+                P[(size_t)r * Nw + n] = p;
             }
         }
     }

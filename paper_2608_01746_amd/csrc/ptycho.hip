@@ -63,7 +63,8 @@ int forward_n(mnf_ctx* ctx, const Geometry& g, const float2* O, const float2* P,
     const int gr = (g.Nw + RC::LINES - 1) / RC::LINES;
     for (int j0 = 0; j0 < g.J; j0 += chunk) {
         const int nb = std::min(chunk, g.J - j0);
-        MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, nb), dim3(RC::THREADS), O, g.Mx, P, g.Nw, d_pos, d_idx + j0, (float2*)S, (float*)nullptr, (float*)nullptr, tw);
+        MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, nb), dim3(RC::THREADS), O, g.Mx, P, g.Nw,
+                   (const int2*)d_pos + j0, (float2*)S, (float*)nullptr, (float*)nullptr, tw);
         MNF_LAUNCH(ctx, MNF_K_FORWARD, st, k_cols_intensity<N>, dim3(N / CC::C, nb), dim3(CC::THREADS), (const float2*)S, g.Nw, d_idx + j0, I_out, tw);
     }
     MNF_CHECK_LAUNCH(ctx);
@@ -76,7 +77,7 @@ struct IterArgs {
     float2* O;
     float2* P;
     const float* I;
-    const int* d_pos;
+    const int2* d_bpos;   // window corner of every slot of every iteration's order
     const int* d_order;
     size_t order_stride;  // elements between iterations' rows (0: one shared row)
     int n_iter;
@@ -88,17 +89,18 @@ template <int N>
 int iterate_n(mnf_ctx* ctx, const Geometry& g, const IterArgs& a, hipStream_t st) {
     using RC = RowCfg<N>;
     using CC = ColCfg<N>;
+    using UC = UpdCfg<N>;
     const float2* tw;
     MNF_TRY(twiddles(ctx, N, &tw));
     const int B = a.prm.batch;
     const int gr = (g.Nw + RC::LINES - 1) / RC::LINES;
     const int gc = N / CC::C;
-    void *S, *mO, *mP, *errp, *Pn, *sA2p, *sA2;
+    void *S, *mO, *mP, *errp, *P2, *sA2p, *sA2;
     MNF_TRY(scratch(ctx, "S", (size_t)B * N * N * sizeof(float2), &S));
     MNF_TRY(scratch(ctx, "maxO2", (size_t)B * gr * sizeof(float), &mO));
     MNF_TRY(scratch(ctx, "maxP2", (size_t)gr * sizeof(float), &mP));
     MNF_TRY(scratch(ctx, "errpart", (size_t)g.J * gc * sizeof(double), &errp));
-    MNF_TRY(scratch(ctx, "Pn", (size_t)g.Nw * g.Nw * sizeof(float2), &Pn));
+    MNF_TRY(scratch(ctx, "P2old", (size_t)g.Nw * g.Nw * sizeof(float), &P2));
     MNF_TRY(scratch(ctx, "sumA2part", (size_t)g.J * sizeof(double), &sA2p));
     MNF_TRY(scratch(ctx, "sumA2", sizeof(double), &sA2));
     const int rpie = a.prm.alg == 1;
@@ -108,22 +110,29 @@ int iterate_n(mnf_ctx* ctx, const Geometry& g, const IterArgs& a, hipStream_t st
         MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_f64, dim3(1), dim3(256), (const double*)sA2p, (size_t)g.J, (const double*)nullptr, 1.0, (double*)sA2);
     }
     const dim3 obj_grid((g.bw + kObjTileX - 1) / kObjTileX, (g.bh + kObjTileY - 1) / kObjTileY);
-    const int npix = g.Nw * g.Nw;
     for (int i = 0; i < a.n_iter; ++i) {
         const int it = a.prm.it0 + i;
         const bool upd_probe = a.prm.update_probe && it >= a.prm.probe_start_iter;
         const int* ord = a.d_order + (size_t)i * a.order_stride;
+        const int2* bpi = a.d_bpos + (size_t)i * a.order_stride;
         for (int b0 = 0; b0 < g.J; b0 += B) {
             const int nb = std::min(B, g.J - b0);
             const int* bj = ord + b0;
-            MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, nb), dim3(RC::THREADS), a.O, g.Mx, a.P, g.Nw, a.d_pos, bj, (float2*)S, (float*)mO, (float*)mP, tw);
+            const int2* bp = bpi + b0;
+            MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, nb), dim3(RC::THREADS), a.O, g.Mx, a.P, g.Nw,
+                       bp, (float2*)S, (float*)mO, (float*)mP, tw);
             MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, ColOp::Modulus>), dim3(gc, nb), dim3(CC::THREADS), (float2*)S, g.Nw, a.I, bj, (double*)errp, 0.f, tw);
-            MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv<N, true>), dim3(gr, nb), dim3(RC::THREADS), (float2*)S, a.O, g.Mx, a.P, g.Nw, a.d_pos, bj, 1.f, tw);
             if (upd_probe)
-                MNF_LAUNCH(ctx, MNF_K_PROBE_UPDATE, st, k_probe_update, dim3((npix + 255) / 256), dim3(256), (const float2*)S, N, a.O, g.Mx, a.P, (float2*)Pn, g.Nw, a.d_pos, bj, nb, (const float*)mO, gr, rpie, a.prm.beta);
-            MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, obj_grid, dim3(kObjThreads), a.O, g.Mx, g.by0, g.bx0, g.bh, g.bw, (const float2*)S, N, a.P, g.Nw, a.d_pos, bj, nb, (const float*)mP, gr, rpie, a.prm.alpha);
-            if (upd_probe)
-                MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_copy_c64, dim3((npix + 255) / 256), dim3(256), a.P, (const float2*)Pn, npix);
+                MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 1>), dim3(g.Nw), dim3(UC::THREADS),
+                           (float2*)S, (const float2*)a.O, g.Mx, a.P, (float*)P2, (float2*)nullptr, g.Nw,
+                           bp, nb, (const float*)mO, gr, rpie, a.prm.beta, 1.f, tw);
+            else
+                MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 0>), dim3(g.Nw), dim3(UC::THREADS),
+                           (float2*)S, (const float2*)a.O, g.Mx, a.P, (float*)P2, (float2*)nullptr, g.Nw,
+                           bp, nb, (const float*)mO, gr, rpie, a.prm.beta, 1.f, tw);
+            MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, obj_grid, dim3(kObjThreads), a.O, g.Mx,
+                       g.by0, g.bx0, g.bh, g.bw, (const float2*)S, N, (const float*)P2, g.Nw, bp, nb,
+                       (const float*)mP, gr, rpie, a.prm.alpha);
         }
         if (a.err_out)
             MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_f64, dim3(1), dim3(256), (const double*)errp, (size_t)g.J * gc, (const double*)sA2, 1.0, a.err_out + i);
@@ -153,6 +162,7 @@ template <int N>
 int grad_n(mnf_ctx* ctx, const Geometry& g, const GradArgs& a, hipStream_t st) {
     using RC = RowCfg<N>;
     using CC = ColCfg<N>;
+    using UC = UpdCfg<N>;
     const float2* tw;
     MNF_TRY(twiddles(ctx, N, &tw));
     const int B = a.batch;
@@ -170,17 +180,20 @@ int grad_n(mnf_ctx* ctx, const Geometry& g, const GradArgs& a, hipStream_t st) {
     for (int b0 = 0; b0 < g.J; b0 += B) {
         const int nb = std::min(B, g.J - b0);
         const int* bj = a.d_idx + b0;
-        MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, nb), dim3(RC::THREADS), a.O, g.Mx, a.P, g.Nw, a.d_pos, bj, (float2*)S, (float*)nullptr, (float*)nullptr, tw);
+        const int2* bp = (const int2*)a.d_pos + b0;
+        MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, nb), dim3(RC::THREADS), a.O, g.Mx, a.P, g.Nw,
+                   bp, (float2*)S, (float*)nullptr, (float*)nullptr, tw);
         if (a.kind == 0)
             MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, ColOp::PoissonGrad>), dim3(gc, nb), dim3(CC::THREADS), (float2*)S, g.Nw, a.I, bj, (double*)lossp, a.eps, tw);
         else
             MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, ColOp::AmplitudeGrad>), dim3(gc, nb), dim3(CC::THREADS), (float2*)S, g.Nw, a.I, bj, (double*)lossp, a.eps, tw);
         if (!need_grad) continue;
-        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv<N, false>), dim3(gr, nb), dim3(RC::THREADS), (float2*)S, a.O, g.Mx, a.P, g.Nw, a.d_pos, bj, (float)a.upstream, tw);
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 2>), dim3(g.Nw), dim3(UC::THREADS),
+                   (float2*)S, a.O, g.Mx, (float2*)a.P, (float*)nullptr, a.gP, g.Nw, bp, nb,
+                   (const float*)nullptr, 0, 0, 0.f, (float)a.upstream, tw);
         if (a.gO)
-            MNF_LAUNCH(ctx, MNF_K_GRAD_SCATTER, st, k_grad_object, obj_grid, dim3(kObjThreads), a.gO, g.Mx, g.by0, g.bx0, g.bh, g.bw, (const float2*)S, N, a.P, g.Nw, a.d_pos, bj, nb);
-        if (a.gP)
-            MNF_LAUNCH(ctx, MNF_K_GRAD_SCATTER, st, k_grad_probe, dim3((g.Nw * g.Nw + 255) / 256), dim3(256), (const float2*)S, N, a.O, g.Mx, a.gP, g.Nw, a.d_pos, bj, nb);
+            MNF_LAUNCH(ctx, MNF_K_GRAD_SCATTER, st, k_grad_object, obj_grid, dim3(kObjThreads), a.gO, g.Mx,
+                       g.by0, g.bx0, g.bh, g.bw, (const float2*)S, N, g.Nw, bp, nb);
     }
     if (a.loss_out)
         MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_f64, dim3(1), dim3(256), (const double*)lossp, (size_t)g.J * gc, (const double*)nullptr, 1.0, a.loss_out);
@@ -272,12 +285,18 @@ int ptycho_iterate(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw,
             }
         }
         MNF_TRY(upload(ctx, "order", order, sizeof(int32_t) * (size_t)n_iter * J, st, &d_order));
+        std::vector<int32_t> bpos((size_t)n_iter * J * 2);
+        for (size_t k = 0; k < (size_t)n_iter * J; ++k) {
+            bpos[2 * k] = pos[2 * order[k]];
+            bpos[2 * k + 1] = pos[2 * order[k] + 1];
+        }
+        MNF_TRY(upload(ctx, "bpos", bpos.data(), sizeof(int32_t) * bpos.size(), st, &d_pos));
         stride = J;
     } else {
         MNF_TRY(upload_identity(ctx, J, st, &d_order));
+        MNF_TRY(upload(ctx, "pos", pos, sizeof(int32_t) * 2 * J, st, &d_pos));
     }
-    MNF_TRY(upload(ctx, "pos", pos, sizeof(int32_t) * 2 * J, st, &d_pos));
-    IterArgs a{(float2*)O, (float2*)P, I, (const int*)d_pos, (const int*)d_order, stride, n_iter, p, err_out};
+    IterArgs a{(float2*)O, (float2*)P, I, (const int2*)d_pos, (const int*)d_order, stride, n_iter, p, err_out};
     return iterate_any(ctx, g, a, st);
 }
 

@@ -13,8 +13,7 @@ constexpr int kObjTileY = 16, kObjTileX = 64, kObjThreads = 256;
 // Ordered list (in slot order) of the batch slots whose window overlaps the
 // tile [ty0, ty0 + kObjTileY) x [tx0, tx0 + kObjTileX).  Wave 0 builds it with
 // ballots; every thread returns the count.
-__device__ __forceinline__ int tile_window_list(const int* __restrict__ pos, const int* __restrict__ bj,
-                                                int nb, int Nw, int ty0, int tx0,
+__device__ __forceinline__ int tile_window_list(const int2* __restrict__ bp, int nb, int Nw, int ty0, int tx0,
                                                 int* l_slot, int* l_py, int* l_px) {
     __shared__ int count;
     if (threadIdx.x < 64) {
@@ -24,9 +23,9 @@ __device__ __forceinline__ int tile_window_list(const int* __restrict__ pos, con
             bool hit = false;
             int py = 0, px = 0;
             if (s < nb) {
-                const int j = bj[s];
-                py = pos[2 * j];
-                px = pos[2 * j + 1];
+                const int2 c = bp[s];
+                py = c.x;
+                px = c.y;
                 hit = py < ty0 + kObjTileY && py + Nw > ty0 && px < tx0 + kObjTileX && px + Nw > tx0;
             }
             const unsigned long long m = __ballot(hit);
@@ -44,131 +43,136 @@ __device__ __forceinline__ int tile_window_list(const int* __restrict__ pos, con
     return count;
 }
 
-// O[x] += sum_s conj(P(u_s)) D_s(u_s) / sum_s d_O(u_s),  u_s = x - p_s
-//   rPIE: d_O = (1 - alpha)|P|^2 + alpha max|P|^2;  ePIE: d_O = max|P|^2 / alpha
+// O[x] += sum_s W_s(u_s) / sum_s d_O(u_s),  u_s = x - p_s, over the windows of
+// the batch that contain x, where W_s = conj(P) dpsi_s (left in S by
+// rows_inv_update) and, from the batch-start probe intensity P2 = |P|^2,
+//   rPIE: d_O = (1 - alpha) P2 + alpha max P2;  ePIE: d_O = max P2 / alpha.
 // grid (ceil(W / kObjTileX), ceil(H / kObjTileY)) over the box [y0, y0+H) x [x0, x0+W).
+// Each thread owns one column and kObjRows rows of the tile; loads are
+// issued unconditionally from clamped addresses so that several windows'
+// loads are in flight at once.
+constexpr int kObjRows = kObjTileY / (kObjThreads / kObjTileX);
+constexpr int kObjChunk = 8;
+
 __global__ void __launch_bounds__(kObjThreads)
 k_object_update(float2* __restrict__ O, int Mx, int y0, int x0, int H, int W,
-                const float2* __restrict__ S, int N, const float2* __restrict__ P, int Nw,
-                const int* __restrict__ pos, const int* __restrict__ bj, int nb,
+                const float2* __restrict__ S, int N, const float* __restrict__ P2, int Nw,
+                const int2* __restrict__ bp, int nb,
                 const float* __restrict__ maxP2_part, int nparts, int rpie, float alpha) {
     __shared__ int l_slot[kMaxBatch], l_py[kMaxBatch], l_px[kMaxBatch];
     const int ty0 = y0 + blockIdx.y * kObjTileY, tx0 = x0 + blockIdx.x * kObjTileX;
-    const int cnt = tile_window_list(pos, bj, nb, Nw, ty0, tx0, l_slot, l_py, l_px);
+    const int cnt = tile_window_list(bp, nb, Nw, ty0, tx0, l_slot, l_py, l_px);
     if (cnt == 0) return;
     float mp = 0.f;
     for (int i = 0; i < nparts; ++i) mp = fmaxf(mp, maxP2_part[i]);
-    const double maxP2 = mp;
+    const float a = rpie ? 1.f - alpha : 0.f;
+    const double cst = rpie ? (double)alpha * (double)mp : (double)mp / (double)alpha;
     const int xx = tx0 + (threadIdx.x % kObjTileX);
-    for (int r = threadIdx.x / kObjTileX; r < kObjTileY; r += kObjThreads / kObjTileX) {
-        const int yy = ty0 + r;
-        if (yy >= y0 + H || xx >= x0 + W) continue;
-        float2 num = make_float2(0.f, 0.f);
-        double den = 0.0;
-        for (int k = 0; k < cnt; ++k) {
-            const int uy = yy - l_py[k], ux = xx - l_px[k];
-            if (uy < 0 || uy >= Nw || ux < 0 || ux >= Nw) continue;
-            const float2 p = P[uy * Nw + ux];
-            const float2 d = S[((size_t)l_slot[k] * N + uy) * N + ux];
-            num = cadd(num, cconjmul(p, d));
-            const double p2 = (double)cabs2(p);
-            den += rpie ? (1.0 - (double)alpha) * p2 + (double)alpha * maxP2 : maxP2 / (double)alpha;
+    const int yb = ty0 + (threadIdx.x / kObjTileX) * kObjRows;
+    float2 num[kObjRows];
+    double den[kObjRows];
+#pragma unroll
+    for (int q = 0; q < kObjRows; ++q) {
+        num[q] = make_float2(0.f, 0.f);
+        den[q] = 0.0;
+    }
+    // windows in chunks: every load of a chunk is issued before any is used
+    for (int k0 = 0; k0 < cnt; k0 += kObjChunk) {
+        float2 w[kObjChunk][kObjRows];
+        float p2[kObjChunk][kObjRows];
+        bool in[kObjChunk][kObjRows];
+#pragma unroll
+        for (int c = 0; c < kObjChunk; ++c) {
+            const int k = min(k0 + c, cnt - 1);
+            const int ux = xx - l_px[k];
+            const bool inx = k0 + c < cnt && ux >= 0 && ux < Nw;
+            const int uxc = min(max(ux, 0), Nw - 1);
+            const float2* Sk = S + (size_t)l_slot[k] * N * N + uxc;
+#pragma unroll
+            for (int q = 0; q < kObjRows; ++q) {
+                const int uy = yb + q - l_py[k];
+                in[c][q] = inx && uy >= 0 && uy < Nw;
+                const int uyc = min(max(uy, 0), Nw - 1);
+                w[c][q] = Sk[(size_t)uyc * N];
+                p2[c][q] = P2[(size_t)uyc * Nw + uxc];
+            }
         }
-        if (den > 0.0) {
+#pragma unroll
+        for (int c = 0; c < kObjChunk; ++c)
+#pragma unroll
+            for (int q = 0; q < kObjRows; ++q)
+                if (in[c][q]) {
+                    num[q] = cadd(num[q], w[c][q]);
+                    den[q] += (double)(a * p2[c][q]) + cst;
+                }
+    }
+    if (xx >= x0 + W) return;
+#pragma unroll
+    for (int q = 0; q < kObjRows; ++q) {
+        const int yy = yb + q;
+        if (yy < y0 + H && den[q] > 0.0) {
             float2* o = O + (size_t)yy * Mx + xx;
-            const double inv = 1.0 / den;
+            const double inv = 1.0 / den[q];
             float2 v = *o;
-            v.x = (float)((double)v.x + (double)num.x * inv);
-            v.y = (float)((double)v.y + (double)num.y * inv);
+            v.x = (float)((double)v.x + (double)num[q].x * inv);
+            v.y = (float)((double)v.y + (double)num[q].y * inv);
             *o = v;
         }
     }
 }
 
-// Pn(u) = P(u) + sum_s conj(O_s(u)) D_s(u) / sum_s d_P,s(u)   (pre-update O)
-//   rPIE: d_P,s = (1 - beta)|O_s|^2 + beta max|O_s|^2;  ePIE: max|O_s|^2 / beta
-// grid ceil(Nw^2 / 256), block 256.
-__global__ void __launch_bounds__(256)
-k_probe_update(const float2* __restrict__ S, int N, const float2* __restrict__ O, int Mx,
-               const float2* __restrict__ P, float2* __restrict__ Pn, int Nw,
-               const int* __restrict__ pos, const int* __restrict__ bj, int nb,
-               const float* __restrict__ maxO2_part, int nparts, int rpie, float beta) {
-    __shared__ float s_max[kMaxBatch];
-    __shared__ int s_py[kMaxBatch], s_px[kMaxBatch];
-    for (int s = threadIdx.x; s < nb; s += blockDim.x) {
-        float m = 0.f;
-        for (int i = 0; i < nparts; ++i) m = fmaxf(m, maxO2_part[(size_t)s * nparts + i]);
-        s_max[s] = m;
-        const int j = bj[s];
-        s_py[s] = pos[2 * j];
-        s_px[s] = pos[2 * j + 1];
-    }
-    __syncthreads();
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= Nw * Nw) return;
-    const int uy = u / Nw, ux = u % Nw;
-    float2 num = make_float2(0.f, 0.f);
-    double den = 0.0;
-    for (int s = 0; s < nb; ++s) {
-        const float2 o = O[(size_t)(s_py[s] + uy) * Mx + s_px[s] + ux];
-        const float2 d = S[((size_t)s * N + uy) * N + ux];
-        num = cadd(num, cconjmul(o, d));
-        const double o2 = (double)cabs2(o);
-        den += rpie ? (1.0 - (double)beta) * o2 + (double)beta * (double)s_max[s]
-                    : (double)s_max[s] / (double)beta;
-    }
-    float2 p = P[u];
-    if (den > 0.0) {
-        const double inv = 1.0 / den;
-        p.x = (float)((double)p.x + (double)num.x * inv);
-        p.y = (float)((double)p.y + (double)num.y * inv);
-    }
-    Pn[u] = p;
-}
-
-// gO[x] += sum_s conj(P(u_s)) G_s(u_s) over the box (gradient scatter).
+// gO[x] += sum_s W_s(u_s) over the box (gradient scatter), W_s = conj(P) g_s
+// left in S by rows_inv_update.  Same tiling and load scheme as k_object_update.
 __global__ void __launch_bounds__(kObjThreads)
 k_grad_object(float2* __restrict__ gO, int Mx, int y0, int x0, int H, int W,
-              const float2* __restrict__ S, int N, const float2* __restrict__ P, int Nw,
-              const int* __restrict__ pos, const int* __restrict__ bj, int nb) {
+              const float2* __restrict__ S, int N, int Nw, const int2* __restrict__ bp, int nb) {
     __shared__ int l_slot[kMaxBatch], l_py[kMaxBatch], l_px[kMaxBatch];
     const int ty0 = y0 + blockIdx.y * kObjTileY, tx0 = x0 + blockIdx.x * kObjTileX;
-    const int cnt = tile_window_list(pos, bj, nb, Nw, ty0, tx0, l_slot, l_py, l_px);
+    const int cnt = tile_window_list(bp, nb, Nw, ty0, tx0, l_slot, l_py, l_px);
     if (cnt == 0) return;
     const int xx = tx0 + (threadIdx.x % kObjTileX);
-    for (int r = threadIdx.x / kObjTileX; r < kObjTileY; r += kObjThreads / kObjTileX) {
-        const int yy = ty0 + r;
-        if (yy >= y0 + H || xx >= x0 + W) continue;
-        float2 acc = make_float2(0.f, 0.f);
-        bool any = false;
-        for (int k = 0; k < cnt; ++k) {
-            const int uy = yy - l_py[k], ux = xx - l_px[k];
-            if (uy < 0 || uy >= Nw || ux < 0 || ux >= Nw) continue;
-            acc = cadd(acc, cconjmul(P[uy * Nw + ux], S[((size_t)l_slot[k] * N + uy) * N + ux]));
-            any = true;
+    const int yb = ty0 + (threadIdx.x / kObjTileX) * kObjRows;
+    float2 acc[kObjRows];
+    bool any[kObjRows];
+#pragma unroll
+    for (int q = 0; q < kObjRows; ++q) {
+        acc[q] = make_float2(0.f, 0.f);
+        any[q] = false;
+    }
+    for (int k0 = 0; k0 < cnt; k0 += kObjChunk) {
+        float2 w[kObjChunk][kObjRows];
+        bool in[kObjChunk][kObjRows];
+#pragma unroll
+        for (int c = 0; c < kObjChunk; ++c) {
+            const int k = min(k0 + c, cnt - 1);
+            const int ux = xx - l_px[k];
+            const bool inx = k0 + c < cnt && ux >= 0 && ux < Nw;
+            const float2* Sk = S + (size_t)l_slot[k] * N * N + min(max(ux, 0), Nw - 1);
+#pragma unroll
+            for (int q = 0; q < kObjRows; ++q) {
+                const int uy = yb + q - l_py[k];
+                in[c][q] = inx && uy >= 0 && uy < Nw;
+                w[c][q] = Sk[(size_t)min(max(uy, 0), Nw - 1) * N];
+            }
         }
-        if (any) {
+#pragma unroll
+        for (int c = 0; c < kObjChunk; ++c)
+#pragma unroll
+            for (int q = 0; q < kObjRows; ++q)
+                if (in[c][q]) {
+                    acc[q] = cadd(acc[q], w[c][q]);
+                    any[q] = true;
+                }
+    }
+    if (xx >= x0 + W) return;
+#pragma unroll
+    for (int q = 0; q < kObjRows; ++q) {
+        const int yy = yb + q;
+        if (yy < y0 + H && any[q]) {
             float2* g = gO + (size_t)yy * Mx + xx;
-            *g = cadd(*g, acc);
+            *g = cadd(*g, acc[q]);
         }
     }
-}
-
-// gP(u) += sum_s conj(O_s(u)) G_s(u).
-__global__ void __launch_bounds__(256)
-k_grad_probe(const float2* __restrict__ S, int N, const float2* __restrict__ O, int Mx,
-             float2* __restrict__ gP, int Nw, const int* __restrict__ pos,
-             const int* __restrict__ bj, int nb) {
-    const int u = blockIdx.x * blockDim.x + threadIdx.x;
-    if (u >= Nw * Nw) return;
-    const int uy = u / Nw, ux = u % Nw;
-    float2 acc = make_float2(0.f, 0.f);
-    for (int s = 0; s < nb; ++s) {
-        const int j = bj[s];
-        const float2 o = O[(size_t)(pos[2 * j] + uy) * Mx + pos[2 * j + 1] + ux];
-        acc = cadd(acc, cconjmul(o, S[((size_t)s * N + uy) * N + ux]));
-    }
-    gP[u] = cadd(gP[u], acc);
 }
 
 __global__ void k_copy_c64(float2* __restrict__ dst, const float2* __restrict__ src, int n) {
