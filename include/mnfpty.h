@@ -118,6 +118,7 @@ typedef struct {
     int32_t update_probe;     /* 0: probe fixed; 1: probe updated */
     int32_t probe_start_iter; /* first iteration index (it0-based) that updates the probe */
     int32_t it0;              /* index of the first iteration of this call (for probe_start_iter and resuming) */
+    int32_t graph;            /* 1: capture the call's launches in one hipGraph and replay it on the stream */
 } ptycho_params;
 
 /* O      device c64 [My][Mx]   object, updated in place
@@ -131,6 +132,27 @@ int ptycho_iterate(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw,
                    const float* I, int Nd, const int32_t* pos, int J,
                    const int32_t* order, int n_iter, const ptycho_params* params,
                    double* err_out, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Many independent scans of uneven sizes in one call (the same iteration as
+ * ptycho_iterate, applied to every scan).  Scans are grouped by detector
+ * size; each pass of each mini-batch round is one launch covering the
+ * current mini-batch of every scan of that size (grid y spans all of their
+ * positions), so small scans share the GPU with large ones.  With
+ * params->graph = 1 the whole call is captured in one hipGraph and replayed.
+ * Each scan's fields have the meaning of the ptycho_iterate arguments of the
+ * same name; `order` has n_iter rows of that scan's J entries or is NULL. */
+typedef struct {
+    mnf_c64* O; int32_t My, Mx;
+    mnf_c64* P; int32_t Nw;
+    const float* I; int32_t Nd;
+    const int32_t* pos; int32_t J;
+    const int32_t* order;
+    double* err_out;
+} ptycho_scan;
+
+int ptycho_iterate_many(mnf_ctx* ctx, const ptycho_scan* scans, int n_scans, int n_iter,
+                        const ptycho_params* params, void* stream);
 
 /* ------------------------------------------------------------------------
  * Loss on fused intensities and its gradient (the adjoint of Eqs. 2-3),

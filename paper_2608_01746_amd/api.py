@@ -140,7 +140,7 @@ ALGS = {"epie": 0, "rpie": 1}
 def ptycho_iterate(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_iter: int,
                    alg: str = "rpie", alpha: float = 0.1, beta: float = 0.1, batch: int = 1,
                    update_probe: bool = False, probe_start_iter: int = 0, order=None, it0: int = 0,
-                   err: bool = True) -> Optional[torch.Tensor]:
+                   err: bool = True, graph: bool = False) -> Optional[torch.Tensor]:
     """Run n_iter mini-batched ePIE/rPIE iterations, updating O and P in place.
     Returns the float64 error per iteration (device tensor) if err."""
     _dev(O, "O", torch.complex64, 2)
@@ -155,7 +155,8 @@ def ptycho_iterate(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_ite
         orda = _host_i32(order, (J,), "order")
         if orda.shape[0] != n_iter:
             raise ValueError("order must have one row per iteration")
-    prm = _L.PtychoParamsC(ALGS[alg], alpha, beta, batch, 1 if update_probe else 0, probe_start_iter, it0)
+    prm = _L.PtychoParamsC(ALGS[alg], alpha, beta, batch, 1 if update_probe else 0, probe_start_iter, it0,
+                           1 if graph else 0)
     e = torch.empty(max(n_iter, 1), dtype=torch.float64, device=O.device) if err else None
     ctx = _ctx(O.device)
     rc = _L.load().ptycho_iterate(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], _ptr(I),
@@ -163,6 +164,46 @@ def ptycho_iterate(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_ite
                                   _ptr(e), _stream(O.device))
     _check(rc, ctx)
     return e[:n_iter] if err else None
+
+
+def ptycho_iterate_many(scans, n_iter: int, alg: str = "rpie", alpha: float = 0.1, beta: float = 0.1,
+                        batch: int = 32, update_probe: bool = False, probe_start_iter: int = 0, it0: int = 0,
+                        err: bool = True, graph: bool = True):
+    """Iterate many independent scans in one call.  `scans` is a list of dicts
+    with keys O, P, I (tensors), pos (host [J][2]) and optionally order
+    ([n_iter][J]).  O and P are updated in place; returns the per-scan error
+    tensors (float64 [n_iter]) if err."""
+    if not scans:
+        raise ValueError("no scans")
+    arr = (_L.PtychoScanC * len(scans))()
+    keep = []
+    errs = []
+    dev = scans[0]["O"].device
+    for k, sc in enumerate(scans):
+        O, P, I = sc["O"], sc["P"], sc["I"]
+        _dev(O, "O", torch.complex64, 2)
+        _dev(P, "P", torch.complex64, 2)
+        _dev(I, "I", torch.float32, 3)
+        if O.device != dev or P.device != dev or I.device != dev:
+            raise ValueError("all scans must live on one device")
+        posa = _host_i32(sc["pos"], (2,), "pos")
+        J = posa.shape[0]
+        orda = None
+        if sc.get("order") is not None:
+            orda = _host_i32(sc["order"], (J,), "order")
+            if orda.shape[0] != n_iter:
+                raise ValueError("order must have one row per iteration")
+        e = torch.empty(max(n_iter, 1), dtype=torch.float64, device=dev) if err else None
+        errs.append(e[:n_iter] if err else None)
+        keep += [posa, orda]
+        arr[k] = _L.PtychoScanC(O.data_ptr(), O.shape[0], O.shape[1], P.data_ptr(), P.shape[0], I.data_ptr(),
+                                I.shape[1], _i32p(posa), J, _i32p(orda), e.data_ptr() if err else None)
+    prm = _L.PtychoParamsC(ALGS[alg], alpha, beta, batch, 1 if update_probe else 0, probe_start_iter, it0,
+                           1 if graph else 0)
+    ctx = _ctx(dev)
+    rc = _L.load().ptycho_iterate_many(ctx, arr, len(scans), n_iter, ctypes.byref(prm), _stream(dev))
+    _check(rc, ctx)
+    return errs if err else None
 
 
 # ------------------------------------------------------------------ adjoint

@@ -48,6 +48,9 @@ struct mnf_ctx {
     void* pinned = nullptr;
     size_t pinned_size = 0;
     hipEvent_t pinned_done = nullptr;
+    // stream used to capture graphs and the last instantiated graph
+    hipStream_t capture_stream = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace mnf {

@@ -185,6 +185,8 @@ void mnf_destroy(mnf_ctx* ctx) {
         (void)hipEventDestroy(p.b);
     }
     for (auto e : ctx->prof.pool) (void)hipEventDestroy(e);
+    if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->pinned_done) (void)hipEventDestroy(ctx->pinned_done);
     delete ctx;

@@ -8,7 +8,7 @@
 namespace mnf {
 
 constexpr int kMaxBatch = 512;  // positions per mini-batch handled by one launch
-constexpr int kColGroup = 16;   // adjacent columns per column-pass block (16 x 8 B = 128 B rows)
+constexpr int kColGroup = 32;   // adjacent columns per column-pass block (32 x 8 B = 256 B of S, 128 B of I per row)
 
 // Row passes: LINES pattern rows per block, T threads per row.
 template <int N>

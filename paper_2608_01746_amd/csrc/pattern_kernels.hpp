@@ -1,56 +1,55 @@
-// Pattern-pass kernels of the reconstruction and gradient paths.
+// Pattern-pass kernels of the reconstruction, gradient and forward paths.
 //
-// A mini-batch of nb scan positions is processed as three passes over a
-// scratch array S[nb][N][N] (complex float, FFT order):
+// A launch processes a list of slots (scan positions, possibly of several
+// scans of the same detector size N) as three passes over a scratch array
+// S[slot][N][N] (complex float, FFT order):
 //   rows_fwd : exit wave psi = P * O[window] (Eq. 2, zero-padded to N) and
 //              its row transforms
-//   cols_*   : column transforms completing Psi = F psi (Eq. 3), then a
-//              pointwise step (modulus projection, loss gradient or
-//              intensity), then for the first two the inverse column transforms
-//   rows_inv : inverse row transforms and the per-pixel result in the window
-//              (dpsi = psi' - psi for the update, g_psi for the gradient)
-// A pattern is 8 N^2 bytes (512 KiB at N = 256), more than one CU's LDS, so
-// each pass keeps only rows or 16-column slabs on chip.
+//   cols_*   : column transforms completing Psi = F psi (Eq. 3), a pointwise
+//              step (modulus projection, loss gradient or intensity) and, for
+//              the first two, the inverse column transforms
+//   rows_inv_update : inverse row transforms and the per-pixel results
+// A 256^2 pattern is 512 KiB, more than one CU's LDS, so each pass keeps only
+// rows or column slabs on chip; Psi never leaves registers between the
+// forward and inverse column transforms.
 #pragma once
 
 #include "kernels_common.hpp"
+#include "tables.hpp"
 
 namespace mnf {
 
 // -------------------------------------------------------------- rows_fwd
-// grid (ceil(Nw / LINES), nb).  Also writes per-block maxima of |O_j|^2
-// (maxO2_part[s][blockIdx.x]) and, from slot 0, of |P|^2 (maxP2_part[blockIdx.x]).
+// grid (ceil(maxNw / LINES), nslots).  Writes per-block maxima of |O_j|^2,
+// maxO2_part[slot][blockIdx.x] (when not NULL).
 template <int N>
 __global__ void __launch_bounds__(RowCfg<N>::THREADS)
-k_rows_fwd(const float2* __restrict__ O, int Mx, const float2* __restrict__ P, int Nw,
-           const int2* __restrict__ bp, float2* __restrict__ S,
-           float* __restrict__ maxO2_part, float* __restrict__ maxP2_part,
-           const float2* __restrict__ tw_g) {
+k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
+           float2* __restrict__ S, float* __restrict__ maxO2_part, const float2* __restrict__ tw_g) {
     constexpr int T = RowCfg<N>::T, LINES = RowCfg<N>::LINES, V = PlanInfo<N>::V;
     __shared__ float2 lds[LINES * RowLds<N>::stride];
     __shared__ float2 tw[N];
     __shared__ float red[RowCfg<N>::THREADS / 64 + 1];
     const int s = blockIdx.y;
-    const int2 c = bp[s];
-    const int py = c.x, px = c.y;
+    const SlotDev sd = slots[s];
+    const ScanDev& sc = scans[sd.scan];
+    const int Nw = sc.Nw, Mx = sc.Mx;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int y = blockIdx.x * LINES + line;
     const bool live = y < Nw;
 
     float2 x[V];
-    float mO = 0.f, mP = 0.f;
-    const float2* Orow = O + (size_t)(py + y) * Mx + px;
-    const float2* Prow = P + (size_t)y * Nw;
+    float mO = 0.f;
+    const float2* Orow = sc.O + (size_t)(sd.py + (live ? y : 0)) * Mx + sd.px;
+    const float2* Prow = sc.P + (size_t)(live ? y : 0) * Nw;
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int n = in_pos<N, false>(t, idx);
         float2 v = make_float2(0.f, 0.f);
         if (live && n < Nw) {
-            const float2 p = Prow[n];
             const float2 o = Orow[n];
-            v = cmul(p, o);
+            v = cmul(Prow[n], o);
             mO = fmaxf(mO, cabs2(o));
-            mP = fmaxf(mP, cabs2(p));
         }
         x[idx] = v;
     }
@@ -66,16 +65,12 @@ k_rows_fwd(const float2* __restrict__ O, int Mx, const float2* __restrict__ P, i
         mO = block_max(mO, red);
         if (threadIdx.x == 0) maxO2_part[(size_t)s * gridDim.x + blockIdx.x] = mO;
     }
-    if (maxP2_part && s == 0) {
-        mP = block_max(mP, red);
-        if (threadIdx.x == 0) maxP2_part[blockIdx.x] = mP;
-    }
 }
 
 // Pointwise step applied between the forward and inverse column transforms.
-// v is Psi (unitary scaling applied), a_src the fused intensity at that
-// frequency (detector-centred source).  Returns the value to inverse-transform
-// and accumulates the per-pixel error / loss term.
+// v is Psi (unitary scaling applied), Iq the fused intensity at that
+// frequency.  Returns the value to inverse-transform and accumulates the
+// per-pixel error / loss term.
 enum class ColOp { Modulus, PoissonGrad, AmplitudeGrad };
 
 template <ColOp OP>
@@ -105,20 +100,21 @@ __device__ __forceinline__ float2 col_pointwise(float2 v, float Iq, float eps, d
 }
 
 // -------------------------------------------------------- cols_pointwise
-// grid (N / C, nb).  Column transforms, pointwise step, inverse column
-// transforms; writes back the first Nw rows (the rows_inv pass reads no
-// others) and a per-block float64 partial acc_part[j][blockIdx.x].
+// grid (N / C, nslots).  Column transforms, pointwise step, inverse column
+// transforms; writes back the first Nw rows (the inverse row pass reads no
+// others) and a float64 partial err_part[j][blockIdx.x] of the scan.
 template <int N, ColOp OP>
 __global__ void __launch_bounds__(ColCfg<N>::THREADS)
-k_cols_pointwise(float2* __restrict__ S, int Nw, const float* __restrict__ I,
-                 const int* __restrict__ bj, double* __restrict__ acc_part, float eps,
-                 const float2* __restrict__ tw_g) {
+k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
+                 float2* __restrict__ S, float eps, const float2* __restrict__ tw_g) {
     constexpr int C = ColCfg<N>::C, T = ColCfg<N>::T, V = PlanInfo<N>::V;
     __shared__ float2 lds[C * N];
     __shared__ float2 tw[N];
     __shared__ double red[ColCfg<N>::THREADS / 64 + 1];
     const int s = blockIdx.y;
-    const int j = bj[s];
+    const SlotDev sd = slots[s];
+    const ScanDev& sc = scans[sd.scan];
+    const int Nw = sc.Nw;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int kx = blockIdx.x * C + c;
     float2* col = S + (size_t)s * N * N + kx;
@@ -133,37 +129,38 @@ k_cols_pointwise(float2* __restrict__ S, int Nw, const float* __restrict__ I,
     __syncthreads();
     fft_line<N, false>(x, t, lds, ColLds<C>(c), tw);
 
-    const float sc = 1.f / (float)N;
-    const float* Ij = I + (size_t)j * N * N;
+    const float sc1 = 1.f / (float)N;
+    const float* Ij = sc.I + (size_t)sd.j * N * N;
     const int sx = (kx + N / 2) % N;
     double acc = 0.0;
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int ky = out_pos<N, false>(t, idx);
         const int sy = (ky + N / 2) % N;
-        x[idx] = col_pointwise<OP>(cscale(x[idx], sc), Ij[(size_t)sy * N + sx], eps, acc);
+        x[idx] = col_pointwise<OP>(cscale(x[idx], sc1), Ij[(size_t)sy * N + sx], eps, acc);
     }
     fft_line<N, true>(x, t, lds, ColLds<C>(c), tw);
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int y = out_pos<N, true>(t, idx);
-        if (y < Nw) col[(size_t)y * N] = x[idx];  // the 1/N of the unitary inverse is applied by rows_inv
+        if (y < Nw) col[(size_t)y * N] = x[idx];  // the 1/N of the unitary inverse is applied by the row pass
     }
     acc = block_sum(acc, red);
-    if (threadIdx.x == 0) acc_part[(size_t)j * gridDim.x + blockIdx.x] = acc;
+    if (threadIdx.x == 0) sc.err_part[(size_t)sd.j * gridDim.x + blockIdx.x] = acc;
 }
 
 // -------------------------------------------------------- cols_intensity
-// grid (N / C, nb).  Forward model only: I_out[j] = fftshift |Psi|^2.
+// grid (N / C, nslots).  Forward model only: I_out[j] = fftshift |Psi|^2.
 template <int N>
 __global__ void __launch_bounds__(ColCfg<N>::THREADS)
-k_cols_intensity(const float2* __restrict__ S, int Nw, const int* __restrict__ bj,
-                 float* __restrict__ I_out, const float2* __restrict__ tw_g) {
+k_cols_intensity(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
+                 const float2* __restrict__ S, float* __restrict__ I_out, const float2* __restrict__ tw_g) {
     constexpr int C = ColCfg<N>::C, T = ColCfg<N>::T, V = PlanInfo<N>::V;
     __shared__ float2 lds[C * N];
     __shared__ float2 tw[N];
     const int s = blockIdx.y;
-    const int j = bj[s];
+    const SlotDev sd = slots[s];
+    const int Nw = scans[sd.scan].Nw;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int kx = blockIdx.x * C + c;
     const float2* col = S + (size_t)s * N * N + kx;
@@ -177,7 +174,7 @@ k_cols_intensity(const float2* __restrict__ S, int Nw, const int* __restrict__ b
     __syncthreads();
     fft_line<N, false>(x, t, lds, ColLds<C>(c), tw);
     const float sc2 = 1.f / ((float)N * (float)N);
-    float* Ij = I_out + (size_t)j * N * N;
+    float* Ij = I_out + (size_t)sd.j * N * N;
     const int sx = (kx + N / 2) % N;
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
@@ -186,51 +183,21 @@ k_cols_intensity(const float2* __restrict__ S, int Nw, const int* __restrict__ b
     }
 }
 
-// --------------------------------------------------------------- rows_inv
-// grid (ceil(Nw / LINES), nb).  Gradient path: inverse row transforms of the
-// first Nw rows, S[s][y][n] = scale * psi'(y, n) for n < Nw.
-template <int N>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS)
-k_rows_inv(float2* __restrict__ S, int Nw, float scale, const float2* __restrict__ tw_g) {
-    constexpr int T = RowCfg<N>::T, LINES = RowCfg<N>::LINES, V = PlanInfo<N>::V;
-    __shared__ float2 lds[LINES * RowLds<N>::stride];
-    __shared__ float2 tw[N];
-    const int s = blockIdx.y;
-    const int line = threadIdx.x / T, t = threadIdx.x % T;
-    const int y = blockIdx.x * LINES + line;
-    const bool live = y < Nw;
-    float2* row = S + ((size_t)s * N + (live ? y : 0)) * N;
-
-    float2 x[V];
-#pragma unroll
-    for (int idx = 0; idx < V; ++idx)
-        x[idx] = live ? row[in_pos<N, true>(t, idx)] : make_float2(0.f, 0.f);
-    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
-    __syncthreads();
-    fft_line<N, true>(x, t, lds, RowLds<N>(line), tw);
-    if (!live) return;
-    const float sc = scale / (float)N;
-#pragma unroll
-    for (int idx = 0; idx < V; ++idx) {
-        const int n = out_pos<N, true>(t, idx);
-        if (n < Nw) row[n] = cscale(x[idx], sc);
-    }
-}
-
 // ------------------------------------------------------- rows_inv_update
-// One block per probe row r (grid Nw), looping over the batch's nb patterns
-// in rounds of ULINES.  For each pattern s the inverse row transform of
-// S[s][r][:] (with the unitary 1/N) gives psi'(r, n), n < Nw, and
+// grid (maxNw, ngroups): block (r, g) owns probe row r of group g's scan and
+// loops over the group's slots in rounds of ULINES.  For each slot s the
+// inverse row transform of S[s][r][:] (with the unitary 1/N) gives
+// psi'(r, n), n < Nw, and
 //   MODE 0, 1 (reconstruction):
 //     dpsi = psi' - P(r, n) O_s(r, n);  S[s][r][n] = conj(P(r, n)) dpsi
-//     (the object-update numerator term).  P2old[r][n] = |P(r, n)|^2 of the
-//     batch-start probe, all the object update still needs of it.  MODE 1
-//     also updates the probe row in place from the batch sums (slot order,
-//     float64 denominators):
+//     (the object-update numerator term).  P2[r][n] = |P(r, n)|^2 of the
+//     batch-start probe and maxP2_row[r] its row maximum, all the object
+//     update still needs of the probe.  MODE 1 also updates the probe row in
+//     place from the batch sums (slot order, float64 denominators):
 //       P(r, n) += sum_s conj(O_s) dpsi / sum_s d_P,s
 //       rPIE: d_P,s = (1 - beta)|O_s|^2 + beta max|O_s|^2;  ePIE: max|O_s|^2 / beta
 //   MODE 2 (gradient): g = upstream * psi';  S[s][r][n] = conj(P(r, n)) g and
-//     gP(r, n) += sum_s conj(O_s(r, n)) g.
+//     gP(r, n) += sum_s conj(O_s(r, n)) g  (when the scan has a gP).
 template <int N>
 struct UpdCfg {
     static constexpr int T = PlanInfo<N>::T;
@@ -240,9 +207,8 @@ struct UpdCfg {
 
 template <int N, int MODE>
 __global__ void __launch_bounds__(UpdCfg<N>::THREADS)
-k_rows_inv_update(float2* __restrict__ S, const float2* __restrict__ O, int Mx,
-                  float2* __restrict__ P, float* __restrict__ P2old, float2* __restrict__ gP, int Nw,
-                  const int2* __restrict__ bp, int nb,
+k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
+                  const GroupDev* __restrict__ groups, float2* __restrict__ S,
                   const float* __restrict__ maxO2_part, int nparts, int rpie, float beta,
                   float upstream, const float2* __restrict__ tw_g) {
     constexpr int T = UpdCfg<N>::T, ULINES = UpdCfg<N>::ULINES, V = PlanInfo<N>::V;
@@ -256,21 +222,26 @@ k_rows_inv_update(float2* __restrict__ S, const float2* __restrict__ O, int Mx,
     __shared__ float c_den[DEN ? ULINES * N : 1];
     __shared__ float s_max[DEN ? kMaxBatch : 1];
     __shared__ int s_py[kMaxBatch], s_px[kMaxBatch];
+    __shared__ float red[THREADS / 64 + 1];
+    const GroupDev gd = groups[blockIdx.y];
+    const ScanDev& sc = scans[gd.scan];
+    const int Nw = sc.Nw, Mx = sc.Mx, nb = gd.nb;
     const int r = blockIdx.x;
+    if (r >= Nw) return;  // uniform over the block
     const int line = threadIdx.x / T, t = threadIdx.x % T;
 
     for (int i = threadIdx.x; i < N; i += THREADS) tw[i] = tw_g[i];
-    for (int s = threadIdx.x; s < nb; s += THREADS) {
-        const int2 c = bp[s];
-        s_py[s] = c.x;
-        s_px[s] = c.y;
+    for (int k = threadIdx.x; k < nb; k += THREADS) {
+        const SlotDev sd = slots[gd.s0 + k];
+        s_py[k] = sd.py;
+        s_px[k] = sd.px;
         if constexpr (DEN) {
             float m = 0.f;
-            for (int i = 0; i < nparts; ++i) m = fmaxf(m, maxO2_part[(size_t)s * nparts + i]);
-            s_max[s] = m;
+            for (int i = 0; i < nparts; ++i) m = fmaxf(m, maxO2_part[(size_t)(gd.s0 + k) * nparts + i]);
+            s_max[k] = m;
         }
     }
-    const float2* Prow = P + (size_t)r * Nw;
+    const float2* Prow = sc.P + (size_t)r * Nw;
     float2 num[COLS];
     double den[COLS];
 #pragma unroll
@@ -280,27 +251,27 @@ k_rows_inv_update(float2* __restrict__ S, const float2* __restrict__ O, int Mx,
     }
     __syncthreads();
 
-    const float sc = (MODE == 2 ? upstream : 1.f) / (float)N;
-    for (int s0 = 0; s0 < nb; s0 += ULINES) {
-        const int s = s0 + line;
-        const bool live = s < nb;
-        float2* row = S + ((size_t)(live ? s : 0) * N + r) * N;
+    const float scl = (MODE == 2 ? upstream : 1.f) / (float)N;
+    for (int k0 = 0; k0 < nb; k0 += ULINES) {
+        const int k = k0 + line;
+        const bool live = k < nb;
+        float2* row = S + ((size_t)(gd.s0 + (live ? k : 0)) * N + r) * N;
         float2 x[V];
 #pragma unroll
         for (int idx = 0; idx < V; ++idx)
             x[idx] = live ? row[in_pos<N, true>(t, idx)] : make_float2(0.f, 0.f);
         fft_line<N, true>(x, t, lds, RowLds<N>(line), tw);
         if (live) {
-            const float2* Orow = O + (size_t)(s_py[s] + r) * Mx + s_px[s];
+            const float2* Orow = sc.O + (size_t)(s_py[k] + r) * Mx + s_px[k];
             float mO = 0.f;
-            if constexpr (DEN) mO = s_max[s];
+            if constexpr (DEN) mO = s_max[k];
 #pragma unroll
             for (int idx = 0; idx < V; ++idx) {
                 const int n = out_pos<N, true>(t, idx);
                 if (n < Nw) {
                     const float2 p = Prow[n];
                     const float2 o = Orow[n];
-                    const float2 d = MODE == 2 ? cscale(x[idx], sc) : csub(cscale(x[idx], sc), cmul(p, o));
+                    const float2 d = MODE == 2 ? cscale(x[idx], scl) : csub(cscale(x[idx], scl), cmul(p, o));
                     row[n] = cconjmul(p, d);
                     if constexpr (ACC) c_num[line * N + n] = cconjmul(o, d);
                     if constexpr (DEN) {
@@ -312,7 +283,7 @@ k_rows_inv_update(float2* __restrict__ S, const float2* __restrict__ O, int Mx,
         }
         if constexpr (ACC) {
             __syncthreads();
-            const int nl = min(ULINES, nb - s0);
+            const int nl = min(ULINES, nb - k0);
 #pragma unroll
             for (int c = 0; c < COLS; ++c) {
                 const int n = threadIdx.x + c * THREADS;
@@ -326,25 +297,32 @@ k_rows_inv_update(float2* __restrict__ S, const float2* __restrict__ O, int Mx,
             __syncthreads();
         }
     }
+    float pmax = 0.f;
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
         const int n = threadIdx.x + c * THREADS;
         if (n >= Nw) continue;
         if constexpr (MODE == 2) {
-            if (gP) {
-                float2* g = gP + (size_t)r * Nw + n;
+            if (sc.gP) {
+                float2* g = sc.gP + (size_t)r * Nw + n;
                 *g = cadd(*g, num[c]);
             }
         } else {
             float2 p = Prow[n];
-            P2old[(size_t)r * Nw + n] = cabs2(p);
+            const float p2 = cabs2(p);
+            sc.P2[(size_t)r * Nw + n] = p2;
+            pmax = fmaxf(pmax, p2);
             if (DEN && den[c] > 0.0) {
                 const double inv = 1.0 / den[c];
                 p.x = (float)((double)p.x + (double)num[c].x * inv);
                 p.y = (float)((double)p.y + (double)num[c].y * inv);
-                P[(size_t)r * Nw + n] = p;
+                sc.P[(size_t)r * Nw + n] = p;
             }
         }
+    }
+    if constexpr (MODE != 2) {
+        pmax = block_max(pmax, red);
+        if (threadIdx.x == 0) sc.maxP2_row[r] = pmax;
     }
 }
 

@@ -1,6 +1,12 @@
 // Host drivers of the pattern paths: forward model, mini-batched ePIE/rPIE
-// iterations and the loss gradient.
+// iterations (one scan or many) and the loss gradient.
+//
+// Every path is planned on the host into descriptor tables (scans, slots,
+// groups; see tables.hpp) that are uploaded once per call, then issued as a
+// sequence of launches, one per pass.  A reconstruction launch covers the
+// current mini-batch of every scan of one detector size.
 #include <algorithm>
+#include <map>
 #include <vector>
 
 #include "common.hpp"
@@ -19,123 +25,353 @@ bool size_supported(int N) {
     return false;
 }
 
-struct Geometry {
-    int My, Mx, Nw, Nd, J;
-    int by0, bx0, bh, bw;  // union box of all windows
+int row_lines(int N) {
+    switch (N) {
+        case 16: return RowCfg<16>::LINES;
+        case 32: return RowCfg<32>::LINES;
+        case 64: return RowCfg<64>::LINES;
+        case 128: return RowCfg<128>::LINES;
+        case 192: return RowCfg<192>::LINES;
+        case 256: return RowCfg<256>::LINES;
+        case 384: return RowCfg<384>::LINES;
+        default: return RowCfg<512>::LINES;
+    }
+}
+int col_groups(int N) { return N / (kColGroup < N ? kColGroup : N); }
+
+struct ScanIn {
+    float2* O;
+    int My, Mx;
+    float2* P;
+    int Nw;
+    const float* I;
+    int Nd;
+    const int32_t* pos;
+    int J;
+    const int32_t* order;  // [n_iter][J] or NULL
+    double* err_out;
+    float2* gO;
+    float2* gP;
 };
 
-int check_geometry(mnf_ctx* ctx, const void* O, int My, int Mx, const void* P, int Nw, int Nd,
-                   const int32_t* pos, int J, Geometry* g) {
-    if (!O || !P || !pos) return set_error(ctx, MNF_EINVAL, "null pointer argument");
-    if (My <= 0 || Mx <= 0 || Nw <= 0 || Nd <= 0 || J <= 0)
-        return set_error(ctx, MNF_EINVAL, "sizes must be positive (My=%d Mx=%d Nw=%d Nd=%d J=%d)",
-                         My, Mx, Nw, Nd, J);
-    if (!size_supported(Nd))
-        return set_error(ctx, MNF_EUNSUPPORTED, "detector size %d has no FFT plan", Nd);
-    if (Nw > Nd) return set_error(ctx, MNF_EINVAL, "probe window %d larger than detector %d", Nw, Nd);
-    int y0 = My, x0 = Mx, y1 = 0, x1 = 0;
-    for (int j = 0; j < J; ++j) {
-        const int py = pos[2 * j], px = pos[2 * j + 1];
-        if (py < 0 || px < 0 || py + Nw > My || px + Nw > Mx)
-            return set_error(ctx, MNF_EINVAL, "window %d at (%d, %d) lies outside the %dx%d object", j,
-                             py, px, My, Mx);
+struct Box {
+    int y0, x0, h, w;
+};
+
+int check_scan(mnf_ctx* ctx, const ScanIn& s, int idx, Box* box) {
+    if (!s.O || !s.P || !s.pos || !s.I)
+        return set_error(ctx, MNF_EINVAL, "scan %d: null pointer argument", idx);
+    if (s.My <= 0 || s.Mx <= 0 || s.Nw <= 0 || s.Nd <= 0 || s.J <= 0)
+        return set_error(ctx, MNF_EINVAL, "scan %d: sizes must be positive (My=%d Mx=%d Nw=%d Nd=%d J=%d)", idx,
+                         s.My, s.Mx, s.Nw, s.Nd, s.J);
+    if (!size_supported(s.Nd))
+        return set_error(ctx, MNF_EUNSUPPORTED, "scan %d: detector size %d has no FFT plan", idx, s.Nd);
+    if (s.Nw > s.Nd)
+        return set_error(ctx, MNF_EINVAL, "scan %d: probe window %d larger than detector %d", idx, s.Nw, s.Nd);
+    int y0 = s.My, x0 = s.Mx, y1 = 0, x1 = 0;
+    for (int j = 0; j < s.J; ++j) {
+        const int py = s.pos[2 * j], px = s.pos[2 * j + 1];
+        if (py < 0 || px < 0 || py + s.Nw > s.My || px + s.Nw > s.Mx)
+            return set_error(ctx, MNF_EINVAL, "scan %d: window %d at (%d, %d) lies outside the %dx%d object", idx, j,
+                             py, px, s.My, s.Mx);
         y0 = std::min(y0, py);
         x0 = std::min(x0, px);
-        y1 = std::max(y1, py + Nw);
-        x1 = std::max(x1, px + Nw);
+        y1 = std::max(y1, py + s.Nw);
+        x1 = std::max(x1, px + s.Nw);
     }
-    *g = Geometry{My, Mx, Nw, Nd, J, y0, x0, y1 - y0, x1 - x0};
+    *box = Box{y0, x0, y1 - y0, x1 - x0};
+    return MNF_OK;
+}
+
+int check_order(mnf_ctx* ctx, const int32_t* order, int n_iter, int J, int idx) {
+    if (!order) return MNF_OK;
+    std::vector<char> seen(J);
+    for (int i = 0; i < n_iter; ++i) {
+        std::fill(seen.begin(), seen.end(), 0);
+        for (int k = 0; k < J; ++k) {
+            const int v = order[(size_t)i * J + k];
+            if (v < 0 || v >= J || seen[v])
+                return set_error(ctx, MNF_EINVAL, "scan %d: order row %d is not a permutation of 0..%d", idx, i,
+                                 J - 1);
+            seen[v] = 1;
+        }
+    }
+    return MNF_OK;
+}
+
+// One launch of every pass over a list of slots of one detector size.
+struct Launch {
+    int N;
+    size_t slot_off;
+    int nslots;
+    size_t group_off;
+    int ngroups;
+    int tiles;
+    int maxNw;
+};
+
+// Host side of a planned call.
+struct CallPlan {
+    std::vector<ScanDev> scans;
+    std::vector<SlotDev> slots;
+    std::vector<GroupDev> groups;
+    std::vector<Launch> launches;     // in issue order
+    std::vector<int> iter_end;        // launches[iter_end[i-1] .. iter_end[i]) belong to iteration i
+    size_t max_S = 0;                 // bytes of pattern scratch
+    size_t max_maxO2 = 0;             // floats of max partials
+    void* d_scans = nullptr;
+    void* d_slots = nullptr;
+    void* d_groups = nullptr;
+};
+
+void fill_scan_dev(ScanDev& d, const ScanIn& s, const Box& b) {
+    d = ScanDev{};
+    d.O = s.O;
+    d.P = s.P;
+    d.I = s.I;
+    d.gO = s.gO;
+    d.gP = s.gP;
+    d.My = s.My;
+    d.Mx = s.Mx;
+    d.Nw = s.Nw;
+    d.J = s.J;
+    d.by0 = b.y0;
+    d.bx0 = b.x0;
+    d.bh = b.h;
+    d.bw = b.w;
+    d.tiles_x = (b.w + kObjTileX - 1) / kObjTileX;
+}
+
+int tiles_of(const ScanDev& d) { return d.tiles_x * ((d.bh + kObjTileY - 1) / kObjTileY); }
+
+// Slot list of iteration i, round b, for the scans of one size class.
+void plan_round(CallPlan& pl, const std::vector<ScanIn>& in, const std::vector<int>& cls, int i, int b, int B,
+                int N) {
+    Launch L{N, pl.slots.size(), 0, pl.groups.size(), 0, 0, 0};
+    for (int k : cls) {
+        const ScanIn& s = in[k];
+        const int t0 = b * B;
+        if (t0 >= s.J) continue;
+        const int nb = std::min(B, s.J - t0);
+        GroupDev g{k, L.nslots, nb, L.tiles};
+        for (int t = t0; t < t0 + nb; ++t) {
+            const int j = s.order ? s.order[(size_t)i * s.J + t] : t;
+            pl.slots.push_back(SlotDev{k, j, s.pos[2 * j], s.pos[2 * j + 1]});
+        }
+        pl.groups.push_back(g);
+        L.nslots += nb;
+        L.ngroups += 1;
+        L.tiles += tiles_of(pl.scans[k]);
+        L.maxNw = std::max(L.maxNw, s.Nw);
+    }
+    if (L.nslots == 0) return;
+    pl.max_S = std::max(pl.max_S, (size_t)L.nslots * N * N * sizeof(float2));
+    const int gr = (L.maxNw + row_lines(N) - 1) / row_lines(N);
+    pl.max_maxO2 = std::max(pl.max_maxO2, (size_t)L.nslots * gr);
+    pl.launches.push_back(L);
+}
+
+int upload_plan(mnf_ctx* ctx, CallPlan& pl, hipStream_t st) {
+    MNF_TRY(upload(ctx, "plan_scans", pl.scans.data(), sizeof(ScanDev) * pl.scans.size(), st, &pl.d_scans));
+    MNF_TRY(upload(ctx, "plan_slots", pl.slots.data(), sizeof(SlotDev) * pl.slots.size(), st, &pl.d_slots));
+    MNF_TRY(upload(ctx, "plan_groups", pl.groups.data(), sizeof(GroupDev) * std::max<size_t>(1, pl.groups.size()),
+                   st, &pl.d_groups));
+    return MNF_OK;
+}
+
+// ---------------------------------------------------------- launch helpers
+
+template <int N>
+int launch_rows_fwd(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, float2* S, float* mO, const float2* tw,
+                    hipStream_t st) {
+    const int gr = (L.maxNw + RowCfg<N>::LINES - 1) / RowCfg<N>::LINES;
+    MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, L.nslots), dim3(RowCfg<N>::THREADS),
+               (const ScanDev*)pl.d_scans, (const SlotDev*)pl.d_slots + L.slot_off, S, mO, tw);
+    return MNF_OK;
+}
+
+template <int N>
+int issue_iterate_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd,
+                         float2* S, float* mO, hipStream_t st) {
+    const float2* tw;
+    MNF_TRY(twiddles(ctx, N, &tw));
+    const ScanDev* scans = (const ScanDev*)pl.d_scans;
+    const SlotDev* slots = (const SlotDev*)pl.d_slots + L.slot_off;
+    const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
+    const int gr = (L.maxNw + RowCfg<N>::LINES - 1) / RowCfg<N>::LINES;
+    const int rpie = p.alg == 1;
+    MNF_TRY(launch_rows_fwd<N>(ctx, pl, L, S, mO, tw, st));
+    MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, ColOp::Modulus>), dim3(N / ColCfg<N>::C, L.nslots),
+               dim3(ColCfg<N>::THREADS), scans, slots, S, 0.f, tw);
+    if (upd)
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 1>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, tw);
+    else
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 0>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, tw);
+    MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
+               groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
+    return MNF_OK;
+}
+
+int issue_iterate_any(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
+                      float* mO, hipStream_t st) {
+    switch (L.N) {
+        case 16: return issue_iterate_launch<16>(ctx, pl, L, p, upd, S, mO, st);
+        case 32: return issue_iterate_launch<32>(ctx, pl, L, p, upd, S, mO, st);
+        case 64: return issue_iterate_launch<64>(ctx, pl, L, p, upd, S, mO, st);
+        case 128: return issue_iterate_launch<128>(ctx, pl, L, p, upd, S, mO, st);
+        case 192: return issue_iterate_launch<192>(ctx, pl, L, p, upd, S, mO, st);
+        case 256: return issue_iterate_launch<256>(ctx, pl, L, p, upd, S, mO, st);
+        case 384: return issue_iterate_launch<384>(ctx, pl, L, p, upd, S, mO, st);
+        case 512: return issue_iterate_launch<512>(ctx, pl, L, p, upd, S, mO, st);
+        default: return MNF_EUNSUPPORTED;
+    }
+}
+
+// ----------------------------------------------------------------- iterate
+
+int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const ptycho_params& p, hipStream_t st) {
+    const int ns = (int)in.size();
+    if (p.alg != 0 && p.alg != 1) return set_error(ctx, MNF_EINVAL, "alg must be 0 (ePIE) or 1 (rPIE)");
+    if (p.batch < 1 || p.batch > kMaxBatch)
+        return set_error(ctx, MNF_EINVAL, "batch %d outside [1, %d]", p.batch, kMaxBatch);
+    if (!(p.alpha > 0.f) || !(p.beta > 0.f) || p.alpha > 1.f || p.beta > 1.f)
+        return set_error(ctx, MNF_EINVAL, "alpha and beta must lie in (0, 1]");
+    if (n_iter < 0) return set_error(ctx, MNF_EINVAL, "n_iter must be >= 0");
+    CallPlan pl;
+    pl.scans.resize(ns);
+    std::map<int, std::vector<int>> classes;  // detector size -> scans
+    int max_batches = 0;
+    for (int k = 0; k < ns; ++k) {
+        Box b;
+        MNF_TRY(check_scan(ctx, in[k], k, &b));
+        MNF_TRY(check_order(ctx, in[k].order, n_iter, in[k].J, k));
+        fill_scan_dev(pl.scans[k], in[k], b);
+        classes[in[k].Nd].push_back(k);
+        max_batches = std::max(max_batches, (in[k].J + p.batch - 1) / p.batch);
+    }
+    if (n_iter == 0) return MNF_OK;
+
+    // per-scan scratch: P2 [Nw^2], maxP2_row [Nw], error partials [J][N/C], |A|^2 partials [J] and sum
+    size_t f_need = 0, d_need = 0;
+    for (int k = 0; k < ns; ++k) {
+        f_need += (size_t)in[k].Nw * in[k].Nw + in[k].Nw;
+        d_need += (size_t)in[k].J * col_groups(in[k].Nd) + in[k].J + 1;
+    }
+    void *fbuf, *dbuf;
+    MNF_TRY(scratch(ctx, "scan_f32", f_need * sizeof(float), &fbuf));
+    MNF_TRY(scratch(ctx, "scan_f64", d_need * sizeof(double), &dbuf));
+    std::vector<double*> sA2p(ns), sA2(ns);
+    {
+        float* f = (float*)fbuf;
+        double* d = (double*)dbuf;
+        for (int k = 0; k < ns; ++k) {
+            pl.scans[k].P2 = f;
+            f += (size_t)in[k].Nw * in[k].Nw;
+            pl.scans[k].maxP2_row = f;
+            f += in[k].Nw;
+            pl.scans[k].err_part = d;
+            d += (size_t)in[k].J * col_groups(in[k].Nd);
+            sA2p[k] = d;
+            d += in[k].J;
+            sA2[k] = d;
+            d += 1;
+        }
+    }
+    for (int i = 0; i < n_iter; ++i) {
+        for (int b = 0; b < max_batches; ++b)
+            for (auto& kv : classes) plan_round(pl, in, kv.second, i, b, p.batch, kv.first);
+        pl.iter_end.push_back((int)pl.launches.size());
+    }
+    MNF_TRY(upload_plan(ctx, pl, st));
+    // error reduction jobs, one per scan per iteration
+    std::vector<SumJob> jobs;
+    for (int i = 0; i < n_iter; ++i)
+        for (int k = 0; k < ns; ++k)
+            jobs.push_back(SumJob{pl.scans[k].err_part, (size_t)in[k].J * col_groups(in[k].Nd), sA2[k],
+                                  in[k].err_out ? in[k].err_out + i : nullptr});
+    std::vector<SumJob> a2jobs;
+    for (int k = 0; k < ns; ++k) a2jobs.push_back(SumJob{sA2p[k], (size_t)in[k].J, nullptr, sA2[k]});
+    void *d_jobs, *d_a2jobs, *S, *mO;
+    MNF_TRY(upload(ctx, "plan_jobs", jobs.data(), sizeof(SumJob) * jobs.size(), st, &d_jobs));
+    MNF_TRY(upload(ctx, "plan_a2jobs", a2jobs.data(), sizeof(SumJob) * a2jobs.size(), st, &d_a2jobs));
+    MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
+    MNF_TRY(scratch(ctx, "maxO2", pl.max_maxO2 * sizeof(float), &mO));
+    bool any_err = false;
+    for (int k = 0; k < ns; ++k) any_err |= in[k].err_out != nullptr;
+    if (any_err) {
+        for (int k = 0; k < ns; ++k)
+            MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_amplitude2, dim3(in[k].J), dim3(256), in[k].I,
+                       (size_t)in[k].Nd * in[k].Nd, sA2p[k]);
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_jobs, dim3(ns), dim3(256), (const SumJob*)d_a2jobs, 1.0);
+    }
+    MNF_CHECK_LAUNCH(ctx);
+
+    // twiddle tables exist before any capture starts (creating one copies from the host)
+    for (auto& kv : classes) {
+        const float2* tw;
+        MNF_TRY(twiddles(ctx, kv.first, &tw));
+    }
+    // the iterations, optionally captured into one graph
+    hipStream_t run = st;
+    const bool graph = p.graph != 0;
+    const uint32_t saved_mask = ctx->prof.mask;
+    if (graph) {
+        if (!ctx->capture_stream) MNF_HIP(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+        run = ctx->capture_stream;
+        ctx->prof.mask = 0;  // no timing events inside a capture
+        MNF_HIP(ctx, hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal));
+    }
+    int rc = MNF_OK;
+    size_t li = 0;
+    for (int i = 0; i < n_iter && rc == MNF_OK; ++i) {
+        const int it = p.it0 + i;
+        const bool upd = p.update_probe && it >= p.probe_start_iter;
+        for (; li < (size_t)pl.iter_end[i] && rc == MNF_OK; ++li)
+            rc = issue_iterate_any(ctx, pl, pl.launches[li], p, upd, (float2*)S, (float*)mO, run);
+        if (rc == MNF_OK && any_err) {
+            hipLaunchKernelGGL(k_sum_jobs, dim3(ns), dim3(256), 0, run, (const SumJob*)d_jobs + (size_t)i * ns, 1.0);
+        }
+    }
+    if (graph) {
+        ctx->prof.mask = saved_mask;
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(run, &g);
+        if (rc != MNF_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return set_error(ctx, MNF_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        if (ctx->graph_exec) {
+            MNF_HIP(ctx, hipStreamSynchronize(st));
+            MNF_HIP(ctx, hipGraphExecDestroy(ctx->graph_exec));
+            ctx->graph_exec = nullptr;
+        }
+        e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return set_error(ctx, MNF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        MNF_HIP(ctx, hipGraphLaunch(ctx->graph_exec, st));
+        return MNF_OK;
+    }
+    if (rc != MNF_OK) return rc;
+    MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
 }
 
 // ----------------------------------------------------------------- forward
 
 template <int N>
-int forward_n(mnf_ctx* ctx, const Geometry& g, const float2* O, const float2* P, const int* d_pos,
-              const int* d_idx, float* I_out, hipStream_t st) {
-    using RC = RowCfg<N>;
-    using CC = ColCfg<N>;
+int forward_n(mnf_ctx* ctx, const CallPlan& pl, float* I_out, hipStream_t st) {
     const float2* tw;
     MNF_TRY(twiddles(ctx, N, &tw));
-    const int chunk = std::min(g.J, 64);
     void* S;
-    MNF_TRY(scratch(ctx, "S", (size_t)chunk * N * N * sizeof(float2), &S));
-    const int gr = (g.Nw + RC::LINES - 1) / RC::LINES;
-    for (int j0 = 0; j0 < g.J; j0 += chunk) {
-        const int nb = std::min(chunk, g.J - j0);
-        MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, nb), dim3(RC::THREADS), O, g.Mx, P, g.Nw,
-                   (const int2*)d_pos + j0, (float2*)S, (float*)nullptr, (float*)nullptr, tw);
-        MNF_LAUNCH(ctx, MNF_K_FORWARD, st, k_cols_intensity<N>, dim3(N / CC::C, nb), dim3(CC::THREADS), (const float2*)S, g.Nw, d_idx + j0, I_out, tw);
-    }
-    MNF_CHECK_LAUNCH(ctx);
-    return MNF_OK;
-}
-
-// --------------------------------------------------------------- iterate
-
-struct IterArgs {
-    float2* O;
-    float2* P;
-    const float* I;
-    const int2* d_bpos;   // window corner of every slot of every iteration's order
-    const int* d_order;
-    size_t order_stride;  // elements between iterations' rows (0: one shared row)
-    int n_iter;
-    ptycho_params prm;
-    double* err_out;
-};
-
-template <int N>
-int iterate_n(mnf_ctx* ctx, const Geometry& g, const IterArgs& a, hipStream_t st) {
-    using RC = RowCfg<N>;
-    using CC = ColCfg<N>;
-    using UC = UpdCfg<N>;
-    const float2* tw;
-    MNF_TRY(twiddles(ctx, N, &tw));
-    const int B = a.prm.batch;
-    const int gr = (g.Nw + RC::LINES - 1) / RC::LINES;
-    const int gc = N / CC::C;
-    void *S, *mO, *mP, *errp, *P2, *sA2p, *sA2;
-    MNF_TRY(scratch(ctx, "S", (size_t)B * N * N * sizeof(float2), &S));
-    MNF_TRY(scratch(ctx, "maxO2", (size_t)B * gr * sizeof(float), &mO));
-    MNF_TRY(scratch(ctx, "maxP2", (size_t)gr * sizeof(float), &mP));
-    MNF_TRY(scratch(ctx, "errpart", (size_t)g.J * gc * sizeof(double), &errp));
-    MNF_TRY(scratch(ctx, "P2old", (size_t)g.Nw * g.Nw * sizeof(float), &P2));
-    MNF_TRY(scratch(ctx, "sumA2part", (size_t)g.J * sizeof(double), &sA2p));
-    MNF_TRY(scratch(ctx, "sumA2", sizeof(double), &sA2));
-    const int rpie = a.prm.alg == 1;
-
-    if (a.err_out) {
-        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_amplitude2, dim3(g.J), dim3(256), a.I, (size_t)N * N, (double*)sA2p);
-        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_f64, dim3(1), dim3(256), (const double*)sA2p, (size_t)g.J, (const double*)nullptr, 1.0, (double*)sA2);
-    }
-    const dim3 obj_grid((g.bw + kObjTileX - 1) / kObjTileX, (g.bh + kObjTileY - 1) / kObjTileY);
-    for (int i = 0; i < a.n_iter; ++i) {
-        const int it = a.prm.it0 + i;
-        const bool upd_probe = a.prm.update_probe && it >= a.prm.probe_start_iter;
-        const int* ord = a.d_order + (size_t)i * a.order_stride;
-        const int2* bpi = a.d_bpos + (size_t)i * a.order_stride;
-        for (int b0 = 0; b0 < g.J; b0 += B) {
-            const int nb = std::min(B, g.J - b0);
-            const int* bj = ord + b0;
-            const int2* bp = bpi + b0;
-            MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, nb), dim3(RC::THREADS), a.O, g.Mx, a.P, g.Nw,
-                       bp, (float2*)S, (float*)mO, (float*)mP, tw);
-            MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, ColOp::Modulus>), dim3(gc, nb), dim3(CC::THREADS), (float2*)S, g.Nw, a.I, bj, (double*)errp, 0.f, tw);
-            if (upd_probe)
-                MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 1>), dim3(g.Nw), dim3(UC::THREADS),
-                           (float2*)S, (const float2*)a.O, g.Mx, a.P, (float*)P2, (float2*)nullptr, g.Nw,
-                           bp, nb, (const float*)mO, gr, rpie, a.prm.beta, 1.f, tw);
-            else
-                MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 0>), dim3(g.Nw), dim3(UC::THREADS),
-                           (float2*)S, (const float2*)a.O, g.Mx, a.P, (float*)P2, (float2*)nullptr, g.Nw,
-                           bp, nb, (const float*)mO, gr, rpie, a.prm.beta, 1.f, tw);
-            MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, obj_grid, dim3(kObjThreads), a.O, g.Mx,
-                       g.by0, g.bx0, g.bh, g.bw, (const float2*)S, N, (const float*)P2, g.Nw, bp, nb,
-                       (const float*)mP, gr, rpie, a.prm.alpha);
-        }
-        if (a.err_out)
-            MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_f64, dim3(1), dim3(256), (const double*)errp, (size_t)g.J * gc, (const double*)sA2, 1.0, a.err_out + i);
+    MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
+    for (const Launch& L : pl.launches) {
+        MNF_TRY(launch_rows_fwd<N>(ctx, pl, L, (float2*)S, (float*)nullptr, tw, st));
+        MNF_LAUNCH(ctx, MNF_K_FORWARD, st, k_cols_intensity<N>, dim3(N / ColCfg<N>::C, L.nslots),
+                   dim3(ColCfg<N>::THREADS), (const ScanDev*)pl.d_scans, (const SlotDev*)pl.d_slots + L.slot_off,
+                   (const float2*)S, I_out, tw);
     }
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
@@ -143,92 +379,77 @@ int iterate_n(mnf_ctx* ctx, const Geometry& g, const IterArgs& a, hipStream_t st
 
 // ------------------------------------------------------------------ grad
 
-struct GradArgs {
-    const float2* O;
-    const float2* P;
-    const float* I;
-    const int* d_pos;
-    const int* d_idx;
-    int kind;
-    float eps;
-    int batch;
-    double upstream;
-    double* loss_out;
-    float2* gO;
-    float2* gP;
-};
-
 template <int N>
-int grad_n(mnf_ctx* ctx, const Geometry& g, const GradArgs& a, hipStream_t st) {
-    using RC = RowCfg<N>;
-    using CC = ColCfg<N>;
-    using UC = UpdCfg<N>;
+int grad_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, double upstream, double* loss_out,
+           hipStream_t st) {
     const float2* tw;
     MNF_TRY(twiddles(ctx, N, &tw));
-    const int B = a.batch;
-    const int gr = (g.Nw + RC::LINES - 1) / RC::LINES;
-    const int gc = N / CC::C;
-    void *S, *lossp;
-    MNF_TRY(scratch(ctx, "S", (size_t)B * N * N * sizeof(float2), &S));
-    MNF_TRY(scratch(ctx, "losspart", (size_t)g.J * gc * sizeof(double), &lossp));
-    if (a.gO)
-        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_zero_c64, dim3((unsigned)(((size_t)g.My * g.Mx + 255) / 256)), dim3(256), a.gO, (size_t)g.My * g.Mx);
-    if (a.gP)
-        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_zero_c64, dim3((g.Nw * g.Nw + 255) / 256), dim3(256), a.gP, (size_t)g.Nw * g.Nw);
-    const dim3 obj_grid((g.bw + kObjTileX - 1) / kObjTileX, (g.bh + kObjTileY - 1) / kObjTileY);
-    const bool need_grad = a.gO || a.gP;
-    for (int b0 = 0; b0 < g.J; b0 += B) {
-        const int nb = std::min(B, g.J - b0);
-        const int* bj = a.d_idx + b0;
-        const int2* bp = (const int2*)a.d_pos + b0;
-        MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, nb), dim3(RC::THREADS), a.O, g.Mx, a.P, g.Nw,
-                   bp, (float2*)S, (float*)nullptr, (float*)nullptr, tw);
-        if (a.kind == 0)
-            MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, ColOp::PoissonGrad>), dim3(gc, nb), dim3(CC::THREADS), (float2*)S, g.Nw, a.I, bj, (double*)lossp, a.eps, tw);
+    void *S, *lossp, *d_job;
+    MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
+    MNF_TRY(scratch(ctx, "losspart", (size_t)s.J * col_groups(N) * sizeof(double), &lossp));
+    // the scan's partials live in the loss buffer
+    std::vector<ScanDev> sd = pl.scans;
+    sd[0].err_part = (double*)lossp;
+    void* d_scans;
+    MNF_TRY(upload(ctx, "plan_scans", sd.data(), sizeof(ScanDev), st, &d_scans));
+    SumJob job{(const double*)lossp, (size_t)s.J * col_groups(N), nullptr, loss_out};
+    MNF_TRY(upload(ctx, "plan_lossjob", &job, sizeof job, st, &d_job));
+    if (s.gO)
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_zero_c64, dim3((unsigned)(((size_t)s.My * s.Mx + 255) / 256)), dim3(256),
+                   s.gO, (size_t)s.My * s.Mx);
+    if (s.gP)
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_zero_c64, dim3((s.Nw * s.Nw + 255) / 256), dim3(256), s.gP,
+                   (size_t)s.Nw * s.Nw);
+    const ScanDev* scans = (const ScanDev*)d_scans;
+    for (const Launch& L : pl.launches) {
+        const SlotDev* slots = (const SlotDev*)pl.d_slots + L.slot_off;
+        const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
+        const int gr = (L.maxNw + RowCfg<N>::LINES - 1) / RowCfg<N>::LINES;
+        MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, L.nslots), dim3(RowCfg<N>::THREADS), scans,
+                   slots, (float2*)S, (float*)nullptr, tw);
+        if (kind == 0)
+            MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, ColOp::PoissonGrad>),
+                       dim3(N / ColCfg<N>::C, L.nslots), dim3(ColCfg<N>::THREADS), scans, slots, (float2*)S, eps, tw);
         else
-            MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, ColOp::AmplitudeGrad>), dim3(gc, nb), dim3(CC::THREADS), (float2*)S, g.Nw, a.I, bj, (double*)lossp, a.eps, tw);
-        if (!need_grad) continue;
-        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 2>), dim3(g.Nw), dim3(UC::THREADS),
-                   (float2*)S, a.O, g.Mx, (float2*)a.P, (float*)nullptr, a.gP, g.Nw, bp, nb,
-                   (const float*)nullptr, 0, 0, 0.f, (float)a.upstream, tw);
-        if (a.gO)
-            MNF_LAUNCH(ctx, MNF_K_GRAD_SCATTER, st, k_grad_object, obj_grid, dim3(kObjThreads), a.gO, g.Mx,
-                       g.by0, g.bx0, g.bh, g.bw, (const float2*)S, N, g.Nw, bp, nb);
+            MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, ColOp::AmplitudeGrad>),
+                       dim3(N / ColCfg<N>::C, L.nslots), dim3(ColCfg<N>::THREADS), scans, slots, (float2*)S, eps, tw);
+        if (!s.gO && !s.gP) continue;
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 2>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N>::THREADS), scans, slots, groups, (float2*)S, (const float*)nullptr, 0, 0, 0.f,
+                   (float)upstream, tw);
+        if (s.gO)
+            MNF_LAUNCH(ctx, MNF_K_GRAD_SCATTER, st, k_grad_object, dim3(L.tiles), dim3(kObjThreads), scans, slots,
+                       groups, L.ngroups, (const float2*)S, N);
     }
-    if (a.loss_out)
-        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_f64, dim3(1), dim3(256), (const double*)lossp, (size_t)g.J * gc, (const double*)nullptr, 1.0, a.loss_out);
+    if (loss_out) MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_jobs, dim3(1), dim3(256), (const SumJob*)d_job, 1.0);
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
 }
 
-#define MNF_DISPATCH(N, FN, ...)                     \
-    switch (N) {                                     \
-        case 16: return FN<16>(__VA_ARGS__);         \
-        case 32: return FN<32>(__VA_ARGS__);         \
-        case 64: return FN<64>(__VA_ARGS__);         \
-        case 128: return FN<128>(__VA_ARGS__);       \
-        case 192: return FN<192>(__VA_ARGS__);       \
-        case 256: return FN<256>(__VA_ARGS__);       \
-        case 384: return FN<384>(__VA_ARGS__);       \
-        case 512: return FN<512>(__VA_ARGS__);       \
-        default: return MNF_EUNSUPPORTED;            \
+#define MNF_DISPATCH(N, FN, ...)               \
+    switch (N) {                               \
+        case 16: return FN<16>(__VA_ARGS__);   \
+        case 32: return FN<32>(__VA_ARGS__);   \
+        case 64: return FN<64>(__VA_ARGS__);   \
+        case 128: return FN<128>(__VA_ARGS__); \
+        case 192: return FN<192>(__VA_ARGS__); \
+        case 256: return FN<256>(__VA_ARGS__); \
+        case 384: return FN<384>(__VA_ARGS__); \
+        case 512: return FN<512>(__VA_ARGS__); \
+        default: return MNF_EUNSUPPORTED;      \
     }
 
-int forward_any(mnf_ctx* ctx, const Geometry& g, const float2* O, const float2* P, const int* d_pos,
-                const int* d_idx, float* I_out, hipStream_t st) {
-    MNF_DISPATCH(g.Nd, forward_n, ctx, g, O, P, d_pos, d_idx, I_out, st)
-}
-int iterate_any(mnf_ctx* ctx, const Geometry& g, const IterArgs& a, hipStream_t st) {
-    MNF_DISPATCH(g.Nd, iterate_n, ctx, g, a, st)
-}
-int grad_any(mnf_ctx* ctx, const Geometry& g, const GradArgs& a, hipStream_t st) {
-    MNF_DISPATCH(g.Nd, grad_n, ctx, g, a, st)
-}
-
-int upload_identity(mnf_ctx* ctx, int J, hipStream_t st, void** d) {
-    std::vector<int32_t> idx(J);
-    for (int j = 0; j < J; ++j) idx[j] = j;
-    return upload(ctx, "identity", idx.data(), sizeof(int32_t) * J, st, d);
+// Single-scan plan with the identity order in chunks of `chunk` positions.
+int plan_identity(mnf_ctx* ctx, const ScanIn& s, int chunk, CallPlan& pl, hipStream_t st) {
+    Box b;
+    MNF_TRY(check_scan(ctx, s, 0, &b));
+    pl.scans.resize(1);
+    fill_scan_dev(pl.scans[0], s, b);
+    std::vector<int> cls{0};
+    std::vector<ScanIn> in{s};
+    const int nr = (s.J + chunk - 1) / chunk;
+    for (int r = 0; r < nr; ++r) plan_round(pl, in, cls, 0, r, chunk, s.Nd);
+    return upload_plan(ctx, pl, st);
 }
 
 }  // namespace
@@ -245,79 +466,50 @@ int ptycho_forward(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64
                    const int32_t* pos, int J, float* I_out, void* stream) {
     MNF_TRY(begin(ctx));
     if (!I_out) return set_error(ctx, MNF_EINVAL, "null output");
-    Geometry g;
-    MNF_TRY(check_geometry(ctx, O, My, Mx, P, Nw, Nd, pos, J, &g));
     hipStream_t st = (hipStream_t)stream;
-    void *d_pos, *d_idx;
-    MNF_TRY(upload(ctx, "pos", pos, sizeof(int32_t) * 2 * J, st, &d_pos));
-    MNF_TRY(upload_identity(ctx, J, st, &d_idx));
-    return forward_any(ctx, g, (const float2*)O, (const float2*)P, (const int*)d_pos, (const int*)d_idx,
-                       I_out, st);
+    // I_out stands in for the scan's intensity pointer (validated, not read)
+    ScanIn s{(float2*)O, My, Mx, (float2*)P, Nw, I_out, Nd, pos, J, nullptr, nullptr, nullptr, nullptr};
+    CallPlan pl;
+    MNF_TRY(plan_identity(ctx, s, 64, pl, st));
+    MNF_DISPATCH(Nd, forward_n, ctx, pl, I_out, st)
 }
 
 int ptycho_iterate(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw, const float* I, int Nd,
-                   const int32_t* pos, int J, const int32_t* order, int n_iter,
-                   const ptycho_params* params, double* err_out, void* stream) {
+                   const int32_t* pos, int J, const int32_t* order, int n_iter, const ptycho_params* params,
+                   double* err_out, void* stream) {
     MNF_TRY(begin(ctx));
-    if (!I || !params) return set_error(ctx, MNF_EINVAL, "null pointer argument");
-    if (n_iter < 0) return set_error(ctx, MNF_EINVAL, "n_iter must be >= 0");
-    Geometry g;
-    MNF_TRY(check_geometry(ctx, O, My, Mx, P, Nw, Nd, pos, J, &g));
-    const ptycho_params& p = *params;
-    if (p.alg != 0 && p.alg != 1) return set_error(ctx, MNF_EINVAL, "alg must be 0 (ePIE) or 1 (rPIE)");
-    if (p.batch < 1 || p.batch > kMaxBatch)
-        return set_error(ctx, MNF_EINVAL, "batch %d outside [1, %d]", p.batch, kMaxBatch);
-    if (!(p.alpha > 0.f) || !(p.beta > 0.f) || p.alpha > 1.f || p.beta > 1.f)
-        return set_error(ctx, MNF_EINVAL, "alpha and beta must lie in (0, 1]");
-    if (n_iter == 0) return MNF_OK;
-    hipStream_t st = (hipStream_t)stream;
-    void *d_pos, *d_order;
-    size_t stride = 0;
-    if (order) {
-        std::vector<char> seen(J);
-        for (int i = 0; i < n_iter; ++i) {
-            std::fill(seen.begin(), seen.end(), 0);
-            for (int k = 0; k < J; ++k) {
-                const int v = order[(size_t)i * J + k];
-                if (v < 0 || v >= J || seen[v])
-                    return set_error(ctx, MNF_EINVAL, "order row %d is not a permutation of 0..%d", i, J - 1);
-                seen[v] = 1;
-            }
-        }
-        MNF_TRY(upload(ctx, "order", order, sizeof(int32_t) * (size_t)n_iter * J, st, &d_order));
-        std::vector<int32_t> bpos((size_t)n_iter * J * 2);
-        for (size_t k = 0; k < (size_t)n_iter * J; ++k) {
-            bpos[2 * k] = pos[2 * order[k]];
-            bpos[2 * k + 1] = pos[2 * order[k] + 1];
-        }
-        MNF_TRY(upload(ctx, "bpos", bpos.data(), sizeof(int32_t) * bpos.size(), st, &d_pos));
-        stride = J;
-    } else {
-        MNF_TRY(upload_identity(ctx, J, st, &d_order));
-        MNF_TRY(upload(ctx, "pos", pos, sizeof(int32_t) * 2 * J, st, &d_pos));
-    }
-    IterArgs a{(float2*)O, (float2*)P, I, (const int2*)d_pos, (const int*)d_order, stride, n_iter, p, err_out};
-    return iterate_any(ctx, g, a, st);
+    if (!params) return set_error(ctx, MNF_EINVAL, "null params");
+    std::vector<ScanIn> in{ScanIn{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, pos, J, order, err_out, nullptr,
+                                  nullptr}};
+    return run_iterate(ctx, in, n_iter, *params, (hipStream_t)stream);
 }
 
-int ptycho_grad(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P, int Nw, const float* I,
-                int Nd, const int32_t* pos, int J, int kind, float eps, int batch, double upstream,
-                double* loss_out, mnf_c64* gO, mnf_c64* gP, void* stream) {
+int ptycho_iterate_many(mnf_ctx* ctx, const ptycho_scan* scans, int n_scans, int n_iter,
+                        const ptycho_params* params, void* stream) {
     MNF_TRY(begin(ctx));
-    if (!I) return set_error(ctx, MNF_EINVAL, "null intensity");
+    if (!params || !scans) return set_error(ctx, MNF_EINVAL, "null pointer argument");
+    if (n_scans <= 0) return set_error(ctx, MNF_EINVAL, "n_scans must be positive");
+    std::vector<ScanIn> in;
+    for (int k = 0; k < n_scans; ++k) {
+        const ptycho_scan& s = scans[k];
+        in.push_back(ScanIn{(float2*)s.O, s.My, s.Mx, (float2*)s.P, s.Nw, s.I, s.Nd, s.pos, s.J, s.order,
+                            s.err_out, nullptr, nullptr});
+    }
+    return run_iterate(ctx, in, n_iter, *params, (hipStream_t)stream);
+}
+
+int ptycho_grad(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P, int Nw, const float* I, int Nd,
+                const int32_t* pos, int J, int kind, float eps, int batch, double upstream, double* loss_out,
+                mnf_c64* gO, mnf_c64* gP, void* stream) {
+    MNF_TRY(begin(ctx));
     if (kind != 0 && kind != 1) return set_error(ctx, MNF_EINVAL, "kind must be 0 (Poisson) or 1 (amplitude)");
-    if (batch < 1 || batch > kMaxBatch)
-        return set_error(ctx, MNF_EINVAL, "batch %d outside [1, %d]", batch, kMaxBatch);
+    if (batch < 1 || batch > kMaxBatch) return set_error(ctx, MNF_EINVAL, "batch %d outside [1, %d]", batch, kMaxBatch);
     if (!(eps >= 0.f)) return set_error(ctx, MNF_EINVAL, "eps must be >= 0");
-    Geometry g;
-    MNF_TRY(check_geometry(ctx, O, My, Mx, P, Nw, Nd, pos, J, &g));
     hipStream_t st = (hipStream_t)stream;
-    void *d_pos, *d_idx;
-    MNF_TRY(upload(ctx, "pos", pos, sizeof(int32_t) * 2 * J, st, &d_pos));
-    MNF_TRY(upload_identity(ctx, J, st, &d_idx));
-    GradArgs a{(const float2*)O, (const float2*)P, I, (const int*)d_pos, (const int*)d_idx, kind, eps,
-               batch, upstream, loss_out, (float2*)gO, (float2*)gP};
-    return grad_any(ctx, g, a, st);
+    ScanIn s{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, pos, J, nullptr, nullptr, (float2*)gO, (float2*)gP};
+    CallPlan pl;
+    MNF_TRY(plan_identity(ctx, s, batch, pl, st));
+    MNF_DISPATCH(Nd, grad_n, ctx, pl, s, kind, eps, upstream, loss_out, st)
 }
 
 }  // extern "C"

@@ -1,39 +1,57 @@
-// Object / probe accumulation kernels (mini-batched ePIE / rPIE updates and
-// the gradient scatter).  Output-stationary: every output pixel is owned by
-// one thread, which sums the contributions of the batch's windows in slot
-// order, so results are deterministic and no atomics are used.
+// Object accumulation kernels (mini-batched ePIE / rPIE object update and
+// the gradient scatter), reductions and small helpers.
+//
+// Output-stationary: every object pixel is owned by one thread, which sums
+// the contributions of its group's windows in slot order, so results are
+// deterministic and no atomics are used.  One launch covers every group
+// (scan) of the launch: block b belongs to the group whose tile range
+// [tile0, tile0 + tiles) contains b.
 #pragma once
 
 #include "kernels_common.hpp"
+#include "tables.hpp"
 
 namespace mnf {
 
 constexpr int kObjTileY = 16, kObjTileX = 64, kObjThreads = 256;
+constexpr int kObjRows = kObjTileY / (kObjThreads / kObjTileX);
+constexpr int kObjChunk = 8;
 
-// Ordered list (in slot order) of the batch slots whose window overlaps the
-// tile [ty0, ty0 + kObjTileY) x [tx0, tx0 + kObjTileX).  Wave 0 builds it with
+// Group of object-update block `b` (groups ordered by tile0).
+__device__ __forceinline__ int find_group(const GroupDev* __restrict__ groups, int ngroups, int b) {
+    int lo = 0, hi = ngroups - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (groups[mid].tile0 <= b) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Ordered list (in slot order) of the group's windows overlapping the tile
+// [ty0, ty0 + kObjTileY) x [tx0, tx0 + kObjTileX).  Wave 0 builds it with
 // ballots; every thread returns the count.
-__device__ __forceinline__ int tile_window_list(const int2* __restrict__ bp, int nb, int Nw, int ty0, int tx0,
-                                                int* l_slot, int* l_py, int* l_px) {
+__device__ __forceinline__ int tile_window_list(const SlotDev* __restrict__ slots, const GroupDev& gd,
+                                                int Nw, int ty0, int tx0, int* l_slot, int* l_py,
+                                                int* l_px) {
     __shared__ int count;
     if (threadIdx.x < 64) {
         int cnt = 0;
-        for (int base = 0; base < nb; base += 64) {
-            const int s = base + (int)threadIdx.x;
+        for (int base = 0; base < gd.nb; base += 64) {
+            const int k = base + (int)threadIdx.x;
             bool hit = false;
             int py = 0, px = 0;
-            if (s < nb) {
-                const int2 c = bp[s];
-                py = c.x;
-                px = c.y;
+            if (k < gd.nb) {
+                const SlotDev sd = slots[gd.s0 + k];
+                py = sd.py;
+                px = sd.px;
                 hit = py < ty0 + kObjTileY && py + Nw > ty0 && px < tx0 + kObjTileX && px + Nw > tx0;
             }
             const unsigned long long m = __ballot(hit);
             if (hit) {
-                const int k = cnt + __popcll(m & ((1ull << threadIdx.x) - 1ull));
-                l_slot[k] = s;
-                l_py[k] = py;
-                l_px[k] = px;
+                const int q = cnt + __popcll(m & ((1ull << threadIdx.x) - 1ull));
+                l_slot[q] = gd.s0 + k;
+                l_py[q] = py;
+                l_px[q] = px;
             }
             cnt += __popcll(m);
         }
@@ -43,32 +61,34 @@ __device__ __forceinline__ int tile_window_list(const int2* __restrict__ bp, int
     return count;
 }
 
-// O[x] += sum_s W_s(u_s) / sum_s d_O(u_s),  u_s = x - p_s, over the windows of
-// the batch that contain x, where W_s = conj(P) dpsi_s (left in S by
-// rows_inv_update) and, from the batch-start probe intensity P2 = |P|^2,
+// O[x] += sum_s W_s(u_s) / sum_s d_O(u_s),  u_s = x - p_s, over the windows
+// of the group that contain x, where W_s = conj(P) dpsi_s (left in S by the
+// inverse row pass) and, from the batch-start probe intensity P2 = |P|^2,
 //   rPIE: d_O = (1 - alpha) P2 + alpha max P2;  ePIE: d_O = max P2 / alpha.
-// grid (ceil(W / kObjTileX), ceil(H / kObjTileY)) over the box [y0, y0+H) x [x0, x0+W).
-// Each thread owns one column and kObjRows rows of the tile; loads are
-// issued unconditionally from clamped addresses so that several windows'
-// loads are in flight at once.
-constexpr int kObjRows = kObjTileY / (kObjThreads / kObjTileX);
-constexpr int kObjChunk = 8;
-
+// Each thread owns one column and kObjRows rows of a 16 x 64 tile; the loads
+// of a chunk of windows are all issued before any is used.
 __global__ void __launch_bounds__(kObjThreads)
-k_object_update(float2* __restrict__ O, int Mx, int y0, int x0, int H, int W,
-                const float2* __restrict__ S, int N, const float* __restrict__ P2, int Nw,
-                const int2* __restrict__ bp, int nb,
-                const float* __restrict__ maxP2_part, int nparts, int rpie, float alpha) {
+k_object_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
+                const GroupDev* __restrict__ groups, int ngroups, const float2* __restrict__ S, int N,
+                int rpie, float alpha) {
     __shared__ int l_slot[kMaxBatch], l_py[kMaxBatch], l_px[kMaxBatch];
-    const int ty0 = y0 + blockIdx.y * kObjTileY, tx0 = x0 + blockIdx.x * kObjTileX;
-    const int cnt = tile_window_list(bp, nb, Nw, ty0, tx0, l_slot, l_py, l_px);
+    __shared__ float red[kObjThreads / 64];
+    const GroupDev gd = groups[find_group(groups, ngroups, blockIdx.x)];
+    const ScanDev& sc = scans[gd.scan];
+    const int Nw = sc.Nw;
+    const int tile = blockIdx.x - gd.tile0;
+    const int ty0 = sc.by0 + (tile / sc.tiles_x) * kObjTileY;
+    const int tx0 = sc.bx0 + (tile % sc.tiles_x) * kObjTileX;
+    const int cnt = tile_window_list(slots, gd, Nw, ty0, tx0, l_slot, l_py, l_px);
     if (cnt == 0) return;
     float mp = 0.f;
-    for (int i = 0; i < nparts; ++i) mp = fmaxf(mp, maxP2_part[i]);
+    for (int i = threadIdx.x; i < Nw; i += kObjThreads) mp = fmaxf(mp, sc.maxP2_row[i]);
+    mp = block_max(mp, red);
     const float a = rpie ? 1.f - alpha : 0.f;
     const double cst = rpie ? (double)alpha * (double)mp : (double)mp / (double)alpha;
     const int xx = tx0 + (threadIdx.x % kObjTileX);
     const int yb = ty0 + (threadIdx.x / kObjTileX) * kObjRows;
+    const float* P2 = sc.P2;
     float2 num[kObjRows];
     double den[kObjRows];
 #pragma unroll
@@ -76,7 +96,6 @@ k_object_update(float2* __restrict__ O, int Mx, int y0, int x0, int H, int W,
         num[q] = make_float2(0.f, 0.f);
         den[q] = 0.0;
     }
-    // windows in chunks: every load of a chunk is issued before any is used
     for (int k0 = 0; k0 < cnt; k0 += kObjChunk) {
         float2 w[kObjChunk][kObjRows];
         float p2[kObjChunk][kObjRows];
@@ -106,12 +125,12 @@ k_object_update(float2* __restrict__ O, int Mx, int y0, int x0, int H, int W,
                     den[q] += (double)(a * p2[c][q]) + cst;
                 }
     }
-    if (xx >= x0 + W) return;
+    if (xx >= sc.bx0 + sc.bw) return;
 #pragma unroll
     for (int q = 0; q < kObjRows; ++q) {
         const int yy = yb + q;
-        if (yy < y0 + H && den[q] > 0.0) {
-            float2* o = O + (size_t)yy * Mx + xx;
+        if (yy < sc.by0 + sc.bh && den[q] > 0.0) {
+            float2* o = sc.O + (size_t)yy * sc.Mx + xx;
             const double inv = 1.0 / den[q];
             float2 v = *o;
             v.x = (float)((double)v.x + (double)num[q].x * inv);
@@ -121,15 +140,20 @@ k_object_update(float2* __restrict__ O, int Mx, int y0, int x0, int H, int W,
     }
 }
 
-// gO[x] += sum_s W_s(u_s) over the box (gradient scatter), W_s = conj(P) g_s
-// left in S by rows_inv_update.  Same tiling and load scheme as k_object_update.
+// gO[x] += sum_s W_s(u_s) (gradient scatter), W_s = conj(P) g_s left in S by
+// the inverse row pass.  Same tiling and load scheme as k_object_update.
 __global__ void __launch_bounds__(kObjThreads)
-k_grad_object(float2* __restrict__ gO, int Mx, int y0, int x0, int H, int W,
-              const float2* __restrict__ S, int N, int Nw, const int2* __restrict__ bp, int nb) {
+k_grad_object(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
+              const GroupDev* __restrict__ groups, int ngroups, const float2* __restrict__ S, int N) {
     __shared__ int l_slot[kMaxBatch], l_py[kMaxBatch], l_px[kMaxBatch];
-    const int ty0 = y0 + blockIdx.y * kObjTileY, tx0 = x0 + blockIdx.x * kObjTileX;
-    const int cnt = tile_window_list(bp, nb, Nw, ty0, tx0, l_slot, l_py, l_px);
-    if (cnt == 0) return;
+    const GroupDev gd = groups[find_group(groups, ngroups, blockIdx.x)];
+    const ScanDev& sc = scans[gd.scan];
+    const int Nw = sc.Nw;
+    const int tile = blockIdx.x - gd.tile0;
+    const int ty0 = sc.by0 + (tile / sc.tiles_x) * kObjTileY;
+    const int tx0 = sc.bx0 + (tile % sc.tiles_x) * kObjTileX;
+    const int cnt = tile_window_list(slots, gd, Nw, ty0, tx0, l_slot, l_py, l_px);
+    if (cnt == 0 || !sc.gO) return;
     const int xx = tx0 + (threadIdx.x % kObjTileX);
     const int yb = ty0 + (threadIdx.x / kObjTileX) * kObjRows;
     float2 acc[kObjRows];
@@ -164,20 +188,15 @@ k_grad_object(float2* __restrict__ gO, int Mx, int y0, int x0, int H, int W,
                     any[q] = true;
                 }
     }
-    if (xx >= x0 + W) return;
+    if (xx >= sc.bx0 + sc.bw) return;
 #pragma unroll
     for (int q = 0; q < kObjRows; ++q) {
         const int yy = yb + q;
-        if (yy < y0 + H && any[q]) {
-            float2* g = gO + (size_t)yy * Mx + xx;
+        if (yy < sc.by0 + sc.bh && any[q]) {
+            float2* g = sc.gO + (size_t)yy * sc.Mx + xx;
             *g = cadd(*g, acc[q]);
         }
     }
-}
-
-__global__ void k_copy_c64(float2* __restrict__ dst, const float2* __restrict__ src, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
 }
 
 __global__ void k_zero_c64(float2* __restrict__ dst, size_t n) {
@@ -185,19 +204,26 @@ __global__ void k_zero_c64(float2* __restrict__ dst, size_t n) {
     if (i < n) dst[i] = make_float2(0.f, 0.f);
 }
 
-// out[0] = scale * sum(in[0..n)) in a fixed order (one block of 256 threads);
-// if div != NULL the result is divided by *div (0 when *div == 0).
+// One block per job: out = scale * sum(in[0..n)) in a fixed order, divided by
+// *div when div is given (0 when *div == 0).
+struct SumJob {
+    const double* in;
+    size_t n;
+    const double* div;
+    double* out;
+};
+
 __global__ void __launch_bounds__(256)
-k_sum_f64(const double* __restrict__ in, size_t n, const double* __restrict__ div, double scale,
-          double* __restrict__ out) {
+k_sum_jobs(const SumJob* __restrict__ jobs, double scale) {
     __shared__ double red[4];
+    const SumJob jb = jobs[blockIdx.x];
     double a = 0.0;
-    for (size_t i = threadIdx.x; i < n; i += 256) a += in[i];
+    for (size_t i = threadIdx.x; i < jb.n; i += 256) a += jb.in[i];
     a = block_sum(a, red);
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && jb.out) {
         double r = a * scale;
-        if (div) r = *div > 0.0 ? r / *div : 0.0;
-        *out = r;
+        if (jb.div) r = *jb.div > 0.0 ? r / *jb.div : 0.0;
+        *jb.out = r;
     }
 }
 

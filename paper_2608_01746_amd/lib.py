@@ -25,7 +25,14 @@ class FuseParamsC(ctypes.Structure):
 
 class PtychoParamsC(ctypes.Structure):
     _fields_ = [("alg", c_int32), ("alpha", c_float), ("beta", c_float), ("batch", c_int32),
-                ("update_probe", c_int32), ("probe_start_iter", c_int32), ("it0", c_int32)]
+                ("update_probe", c_int32), ("probe_start_iter", c_int32), ("it0", c_int32),
+                ("graph", c_int32)]
+
+
+class PtychoScanC(ctypes.Structure):
+    _fields_ = [("O", c_void_p), ("My", c_int32), ("Mx", c_int32), ("P", c_void_p), ("Nw", c_int32),
+                ("I", c_void_p), ("Nd", c_int32), ("pos", POINTER(c_int32)), ("J", c_int32),
+                ("order", POINTER(c_int32)), ("err_out", c_void_p)]
 
 
 # name -> (restype, argtypes)
@@ -41,6 +48,8 @@ SIGNATURES = {
     "ptycho_iterate": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
                                POINTER(c_int32), c_int, POINTER(c_int32), c_int,
                                POINTER(PtychoParamsC), c_void_p, c_void_p]),
+    "ptycho_iterate_many": (c_int, [c_void_p, POINTER(PtychoScanC), c_int, c_int, POINTER(PtychoParamsC),
+                                    c_void_p]),
     "ptycho_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
                             POINTER(c_int32), c_int, c_int, c_float, c_int, c_double,
                             c_void_p, c_void_p, c_void_p, c_void_p]),

@@ -41,10 +41,32 @@ def test_binding_signatures_cover_the_header(lib):
     assert sorted(lib.SIGNATURES) == _declared()
 
 
-def test_struct_layouts_match_header(lib):
+def test_struct_layouts_match_header(lib, tmp_path):
+    # compile the header with the host C compiler and compare every field offset
     import ctypes
-    assert ctypes.sizeof(lib.FuseParamsC) == 4 * 5 + 4 * 16 + 4
-    assert ctypes.sizeof(lib.PtychoParamsC) == 7 * 4
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    structs = {"mnf_fuse_params": lib.FuseParamsC, "ptycho_params": lib.PtychoParamsC,
+               "ptycho_scan": lib.PtychoScanC}
+    src = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, py in structs.items():
+        src.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            src.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    src += ["return 0;", "}"]
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
 
 
 def test_supported_sizes_without_gpu(lib):
