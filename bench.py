@@ -12,11 +12,25 @@ value = 400 * 200 / (seconds per step).
 The synthetic exposure stack is simulated once before timing (the library's
 forward model on the GPU, Poisson + Gaussian detector noise on the host).
 
+--workload multiscan times the uneven-size workload instead: 64 independent
+scans (N in {128,192,256,384,512}, 50-1000 Fermat-spiral positions each,
+30,537 positions in all), rPIE mini-batch 32, 20 iterations, every scan
+advanced by one ptycho_iterate_many call captured in a hipGraph.  Its
+intensities come straight from the forward model (no noise or fusion), which
+does not change the reconstruction's work.
+
+Roofline: achieved = (algorithmic bytes per position update, 20 N^2 + 16 N^2 / B)
+x (positions one launch of the dominant kernel processes) / (its mean launch
+duration, HIP events on the launch stream over the timed region).  traffic =
+counter-measured bytes per launch of that kernel from profiles/, or null when
+the kernel sources changed since the counters were taken.
+
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -33,18 +47,35 @@ def algo_bytes_per_update(N: int, B: int) -> float:
     return 20.0 * N * N + 16.0 * N * N / B
 
 
-# per-pass minimum traffic of one pattern (bytes) used for the per-kernel roofline
-def pass_bytes(name: str, N: int, Nw: int) -> float:
-    if name == "rows_fwd":      # read P row-block and O patch, write transformed rows
-        return 8.0 * Nw * Nw + 8.0 * Nw * N
-    if name == "cols_modulus":  # read the transformed rows and the fused intensity, write back
-        return 8.0 * Nw * N + 4.0 * N * N + 8.0 * Nw * N
-    if name == "rows_inv":      # read rows, O patch; write dpsi
-        return 8.0 * Nw * N + 8.0 * Nw * Nw + 8.0 * Nw * Nw
-    return float("nan")
-
-
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["fft.hpp", "kernels_common.hpp", "pattern_kernels.hpp", "update_kernels.hpp", "tables.hpp"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2608_01746_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """Counter-measured bytes per launch (fetch x 2.0 + write x 1.0) of `kernel`
+    from profiles/lab256_counters.txt, if taken with the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "lab256_counters.txt")
+    if not os.path.exists(path):
+        return None
+    src_hash, rows = None, {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) >= 2 and parts[0] == "source_hash":
+            src_hash = parts[1]
+        elif len(parts) == 3 and parts[0] in ("rows_fwd", "cols_modulus", "rows_inv", "object_update"):
+            rows[parts[0]] = (float(parts[1]), float(parts[2]))
+    if src_hash != kernel_source_hash() or kernel not in rows:
+        return None
+    f, w = rows[kernel]
+    return (2.0 * f + w) * 1024.0
 
 
 def cpu_baseline(w, O_true, P, clean, scale, seconds: float):
@@ -71,33 +102,40 @@ def cpu_baseline(w, O_true, P, clean, scale, seconds: float):
     return n / dt, n, dt
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--iters", type=int, default=200, help="rPIE iterations per step")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="first run one plain 256 MiB device copy (a known-size reference for HBM counters)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
-        return 2
+def profile_dominant(api, run_step, classes):
+    """Time one step with events around every launch of `classes`; return the
+    dominant class and the per-class (launches, ms)."""
+    import torch
+    api.profile(classes)
+    api.profile_reset()
+    run_step()
+    torch.cuda.synchronize()
+    ranks = api.profile_read()
+    api.profile([])
+    dominant = max((k for k in ranks if k in ("rows_fwd", "cols_modulus", "rows_inv", "object_update")),
+                   key=lambda k: ranks[k][1])
+    return dominant, ranks
 
+
+def roofline(dominant, nlaunch, kms, positions_per_launch, N, B):
+    avg_us = kms / nlaunch * 1e3
+    bytes_launch = algo_bytes_per_update(N, B) * positions_per_launch
+    achieved = bytes_launch / (avg_us * 1e-6) / 1e9
+    traffic = measured_traffic(dominant)
+    return {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic),
+            "avg_launch_us": round(avg_us, 2), "launches": nlaunch,
+            "algorithmic_bytes_per_launch": round(bytes_launch)}
+
+
+PASSES = ["rows_fwd", "cols_modulus", "rows_inv", "object_update", "fuse"]
+
+
+def run_lab(args, api, synth, dev):
     import numpy as np
     import torch
 
-    from paper_2608_01746_amd import api, synth
-
-    dev = torch.device("cuda:0")
-    if args.copy_calibration:
-        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     w = synth.lab_workload()
     n_iter = args.iters
     O_true = w.object()
@@ -107,6 +145,7 @@ def main() -> int:
     clean_t = api.ptycho_forward(Ot, Pt, w.pos, w.Nd)
     torch.cuda.synchronize()
     clean = clean_t.cpu().numpy().astype(np.float64)
+    del Ot, Pt, clean_t
     scale = synth.flux_scale(clean.max(), w.sat)
     print(f"# simulating {w.J} x {len(w.t)} exposures of {w.Nd}^2", file=sys.stderr, flush=True)
     raw = torch.from_numpy(synth.expose(clean, w.t, w.sat, w.sigma_read, 2002, scale)).to(dev)
@@ -118,50 +157,34 @@ def main() -> int:
     O = torch.empty_like(O0)
     Pw = torch.empty_like(P0)
     fused = torch.empty((w.J, w.Nd, w.Nd), dtype=torch.float32, device=dev)
+    state = {}
 
     def step():
         O.copy_(O0)
         Pw.copy_(P0)
         api.fuse_exposures(raw, w.t, w.levels, sat=float(w.sat), delta=delta, out=fused)
-        return api.ptycho_iterate(O, Pw, fused, w.pos, n_iter, alg="rpie", alpha=0.1, beta=0.1,
-                                  batch=w.batch, update_probe=True, probe_start_iter=5, order=order)
+        state["err"] = api.ptycho_iterate(O, Pw, fused, w.pos, n_iter, alg="rpie", alpha=0.1, beta=0.1,
+                                          batch=w.batch, update_probe=True, probe_start_iter=5, order=order)
 
-    # warm-up; the first warm-up step times every kernel class to find the dominant one
-    api.profile(["rows_fwd", "cols_modulus", "rows_inv", "probe_update", "object_update", "fuse"])
-    api.profile_reset()
-    for i in range(max(args.warmup, 1)):
-        err = step()
-        if i == 0:
-            torch.cuda.synchronize()
-            ranks = api.profile_read()
-            api.profile([])
-    torch.cuda.synchronize()
-    dominant = max((k for k in ranks if k != "fuse"), key=lambda k: ranks[k][1])
+    dominant, ranks = profile_dominant(api, step, PASSES)
     print("# per-class ms (warm-up step): " +
           ", ".join(f"{k} {v[1]:.2f} ({v[0]})" for k, v in ranks.items()), file=sys.stderr, flush=True)
-
+    for _ in range(args.warmup - 1):
+        step()
     # timed region: events bracket only the dominant kernel's launches
     api.profile([dominant])
     api.profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        err = step()
+        step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     nlaunch, kms = api.profile_read()[dominant]
     api.profile([])
-    final_err = float(err[-1].item())
-
     dt = (t1 - t0) / args.steps
-    updates = w.J * n_iter
-    value = updates / dt
-    # per launch the dominant pass processes one mini-batch (32 positions, 16 in the last)
-    per_launch_patterns = w.J / math.ceil(w.J / w.batch)
-    avg_us = kms / nlaunch * 1e3
-    bytes_launch = pass_bytes(dominant, w.Nd, w.Nw) * per_launch_patterns
-    achieved = bytes_launch / (avg_us * 1e-6) / 1e9
-
+    value = w.J * n_iter / dt
+    per_launch = w.J / math.ceil(w.J / w.batch)
     out = {
         "metric": "scan-position updates/s at 256^2 FP32 (lab-scale rPIE, mini-batch 32, fusion included)",
         "value": round(value, 1),
@@ -179,14 +202,9 @@ def main() -> int:
                                "6-level fusion, rPIE B=32, %d iterations" % n_iter,
                    "positions": w.J, "pattern": w.Nd, "batch": w.batch, "iterations": n_iter,
                    "exposures": len(w.t), "levels": w.levels},
-        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "avg_launch_us": round(avg_us, 2), "launches": nlaunch,
-                     "algorithmic_bytes_per_launch": bytes_launch},
-        "whole_path_hbm": {"algorithmic_bytes_per_update": algo_bytes_per_update(w.Nd, w.batch),
-                           "achieved_GBs": round(algo_bytes_per_update(w.Nd, w.batch) * value / 1e9, 1),
-                           "frac": round(algo_bytes_per_update(w.Nd, w.batch) * value / 1e9 / HBM_PEAK_GBS, 4)},
-        "final_fourier_error": final_err,
+        "roofline": roofline(dominant, nlaunch, kms, per_launch, w.Nd, w.batch),
+        "per_class_ms_one_step": {k: round(v[1], 3) for k, v in ranks.items()},
+        "final_fourier_error": float(state["err"][-1].item()),
     }
     if not args.no_cpu:
         v, n, sec = cpu_baseline(w, O_true, P, clean, scale, args.cpu_seconds)
@@ -194,6 +212,108 @@ def main() -> int:
                                "kind": "oracle",
                                "sample": f"{n} rPIE position updates (mini-batches of {w.batch}) of the "
                                          f"same workload in float64 NumPy, {sec:.1f} s"}
+    return out
+
+
+def run_multiscan(args, api, synth, dev):
+    import numpy as np
+    import torch
+
+    ws = synth.multiscan_workloads(64)
+    n_iter = args.iters
+    scans = []
+    for w in ws:
+        O_true = torch.from_numpy(w.object().astype(np.complex64)).to(dev)
+        P = w.probe()
+        Pt = torch.from_numpy(P.astype(np.complex64)).to(dev)
+        I = api.ptycho_forward(O_true, Pt, w.pos, w.Nd)
+        energy = float(np.sum(np.abs(P) ** 2)) * 0.75 ** 2
+        P0 = torch.from_numpy(synth.flat_probe_guess(w.Nw, w.radius, energy).astype(np.complex64)).to(dev)
+        O0 = torch.ones((w.M, w.M), dtype=torch.complex64, device=dev)
+        scans.append(dict(O0=O0, P0=P0, O=torch.empty_like(O0), P=torch.empty_like(P0), I=I, pos=w.pos,
+                          order=synth.random_orders(w.J, n_iter, w.seed)))
+        del O_true, Pt
+    torch.cuda.synchronize()
+    total_J = sum(w.J for w in ws)
+    print(f"# {len(ws)} scans, {total_J} positions", file=sys.stderr, flush=True)
+    state = {}
+
+    def step(graph=True):
+        for sc in scans:
+            sc["O"].copy_(sc["O0"])
+            sc["P"].copy_(sc["P0"])
+        state["err"] = api.ptycho_iterate_many(scans, n_iter, alg="rpie", alpha=0.1, beta=0.1, batch=32,
+                                               update_probe=True, probe_start_iter=5, graph=graph)
+
+    dominant, ranks = profile_dominant(api, lambda: step(False), PASSES)
+    print("# per-class ms (direct-launch step): " +
+          ", ".join(f"{k} {v[1]:.2f} ({v[0]})" for k, v in ranks.items()), file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dt = (t1 - t0) / args.steps
+    value = total_J * n_iter / dt
+    nlaunch, kms = ranks[dominant]
+    # positions per launch of the dominant pass, averaged over the step
+    per_launch = total_J * n_iter / nlaunch
+    Nbar = math.sqrt(sum(w.J * w.Nd ** 2 for w in ws) / total_J)
+    return {
+        "metric": "scan-position updates/s, 64 uneven scans in one graph-captured call",
+        "value": round(value, 1),
+        "unit": "position-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded objects/probes, noiseless forward-model intensities)",
+        "config": {"workload": "multiscan: 64 scans, N in {128,192,256,384,512}, 50-1000 Fermat-spiral "
+                               "positions, rPIE B=32, %d iterations" % n_iter,
+                   "scans": len(ws), "positions": total_J, "iterations": n_iter},
+        "roofline": dict(roofline(dominant, nlaunch, kms, per_launch, Nbar, 32),
+                         note="per-launch events from one step with direct launches; N = rms pattern size"),
+        "per_class_ms_direct_step": {k: round(v[1], 3) for k, v in ranks.items()},
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--iters", type=int, default=None, help="iterations per step (200 lab, 20 multiscan)")
+    ap.add_argument("--workload", choices=["lab", "multiscan"], default="lab")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 256 MiB device copy (a known-size reference for HBM counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        return 2
+    if args.iters is None:
+        args.iters = 200 if args.workload == "lab" else 20
+
+    import torch
+
+    from paper_2608_01746_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    out = run_lab(args, api, synth, dev) if args.workload == "lab" else run_multiscan(args, api, synth, dev)
     print(json.dumps(out))
     return 0
 

@@ -170,6 +170,25 @@ int ptycho_grad(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P
                 double* loss_out, mnf_c64* gO, mnf_c64* gP, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Launch-shape tuning.  Every pattern pass is compiled in two shapes (rows:
+ * the default lines per block or half as many; columns: 32 columns per block
+ * or 16), giving four variants per detector size: bit 0 selects the row
+ * shape, bit 1 the column shape.  Variants change only launch geometry, never
+ * the algorithm or the mini-batch, and give identical results up to the
+ * order of float64 partial sums of the error.
+ *
+ * mnf_autotune times the four variants on a synthetic scan of `nslots`
+ * positions (one mini-batch of that size per iteration, `reps` iterations),
+ * keeps the fastest for size Nd on this context and returns its index
+ * (0..3), or a negative error.  times_us (host double[4] or NULL) receives
+ * the mean time of one iteration per variant.  It synchronises the stream.
+ * mnf_set_variant / mnf_get_variant store or read a variant (e.g. from a
+ * tuning cache kept by the caller). */
+int mnf_autotune(mnf_ctx* ctx, int Nd, int nslots, int reps, double* times_us, void* stream);
+int mnf_set_variant(mnf_ctx* ctx, int Nd, int variant);
+int mnf_get_variant(mnf_ctx* ctx, int Nd);
+
+/* ------------------------------------------------------------------------
  * Launch timing, for measurement.  With bit c of class_mask set, every
  * launch of kernel class c is bracketed by HIP events recorded on its
  * stream.  Classes: 0 rows_fwd (gather + row transforms), 1 cols_modulus

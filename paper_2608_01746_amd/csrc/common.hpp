@@ -48,6 +48,8 @@ struct mnf_ctx {
     void* pinned = nullptr;
     size_t pinned_size = 0;
     hipEvent_t pinned_done = nullptr;
+    // launch-shape variant per detector size: bit 0 rows, bit 1 columns (0 = defaults)
+    std::map<int, int> variant;
     // stream used to capture graphs and the last instantiated graph
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;

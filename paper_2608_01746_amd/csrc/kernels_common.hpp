@@ -10,19 +10,24 @@ namespace mnf {
 constexpr int kMaxBatch = 512;  // positions per mini-batch handled by one launch
 constexpr int kColGroup = 32;   // adjacent columns per column-pass block (32 x 8 B = 256 B of S, 128 B of I per row)
 
+// Launch shapes.  Each pass has two compiled variants (0: the default, 1:
+// half as many lines or columns per block); the tuner picks one per size.
+//
 // Row passes: LINES pattern rows per block, T threads per row.
-template <int N>
+template <int N, int RV = 0>
 struct RowCfg {
     static constexpr int T = PlanInfo<N>::T;
-    static constexpr int LINES = (256 / T) < N ? (256 / T) : N;
+    static constexpr int LINES0 = (256 / T) < N ? (256 / T) : N;
+    static constexpr int LINES = RV == 0 ? LINES0 : (LINES0 > 1 ? LINES0 / 2 : 1);
     static constexpr int THREADS = LINES * T;
 };
 
 // Column passes: C adjacent columns per block, T threads per column.
-template <int N>
+template <int N, int CV = 0>
 struct ColCfg {
     static constexpr int T = PlanInfo<N>::T;
-    static constexpr int C = kColGroup < N ? kColGroup : N;
+    static constexpr int C0 = kColGroup < N ? kColGroup : N;
+    static constexpr int C = CV == 0 ? C0 : C0 / 2;
     static constexpr int THREADS = C * T;
 };
 

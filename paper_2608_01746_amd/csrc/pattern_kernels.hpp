@@ -22,14 +22,14 @@ namespace mnf {
 // -------------------------------------------------------------- rows_fwd
 // grid (ceil(maxNw / LINES), nslots).  Writes per-block maxima of |O_j|^2,
 // maxO2_part[slot][blockIdx.x] (when not NULL).
-template <int N>
-__global__ void __launch_bounds__(RowCfg<N>::THREADS)
+template <int N, int RV>
+__global__ void __launch_bounds__((RowCfg<N, RV>::THREADS))
 k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
            float2* __restrict__ S, float* __restrict__ maxO2_part, const float2* __restrict__ tw_g) {
-    constexpr int T = RowCfg<N>::T, LINES = RowCfg<N>::LINES, V = PlanInfo<N>::V;
+    constexpr int T = RowCfg<N, RV>::T, LINES = RowCfg<N, RV>::LINES, V = PlanInfo<N>::V;
     __shared__ float2 lds[LINES * RowLds<N>::stride];
     __shared__ float2 tw[N];
-    __shared__ float red[RowCfg<N>::THREADS / 64 + 1];
+    __shared__ float red[RowCfg<N, RV>::THREADS / 64 + 1];
     const int s = blockIdx.y;
     const SlotDev sd = slots[s];
     const ScanDev& sc = scans[sd.scan];
@@ -103,14 +103,14 @@ __device__ __forceinline__ float2 col_pointwise(float2 v, float Iq, float eps, d
 // grid (N / C, nslots).  Column transforms, pointwise step, inverse column
 // transforms; writes back the first Nw rows (the inverse row pass reads no
 // others) and a float64 partial err_part[j][blockIdx.x] of the scan.
-template <int N, ColOp OP>
-__global__ void __launch_bounds__(ColCfg<N>::THREADS)
+template <int N, int CV, ColOp OP>
+__global__ void __launch_bounds__((ColCfg<N, CV>::THREADS))
 k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
                  float2* __restrict__ S, float eps, const float2* __restrict__ tw_g) {
-    constexpr int C = ColCfg<N>::C, T = ColCfg<N>::T, V = PlanInfo<N>::V;
+    constexpr int C = ColCfg<N, CV>::C, T = ColCfg<N, CV>::T, V = PlanInfo<N>::V;
     __shared__ float2 lds[C * N];
     __shared__ float2 tw[N];
-    __shared__ double red[ColCfg<N>::THREADS / 64 + 1];
+    __shared__ double red[ColCfg<N, CV>::THREADS / 64 + 1];
     const int s = blockIdx.y;
     const SlotDev sd = slots[s];
     const ScanDev& sc = scans[sd.scan];
@@ -151,11 +151,11 @@ k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
 
 // -------------------------------------------------------- cols_intensity
 // grid (N / C, nslots).  Forward model only: I_out[j] = fftshift |Psi|^2.
-template <int N>
-__global__ void __launch_bounds__(ColCfg<N>::THREADS)
+template <int N, int CV>
+__global__ void __launch_bounds__((ColCfg<N, CV>::THREADS))
 k_cols_intensity(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
                  const float2* __restrict__ S, float* __restrict__ I_out, const float2* __restrict__ tw_g) {
-    constexpr int C = ColCfg<N>::C, T = ColCfg<N>::T, V = PlanInfo<N>::V;
+    constexpr int C = ColCfg<N, CV>::C, T = ColCfg<N, CV>::T, V = PlanInfo<N>::V;
     __shared__ float2 lds[C * N];
     __shared__ float2 tw[N];
     const int s = blockIdx.y;
@@ -198,21 +198,22 @@ k_cols_intensity(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
 //       rPIE: d_P,s = (1 - beta)|O_s|^2 + beta max|O_s|^2;  ePIE: max|O_s|^2 / beta
 //   MODE 2 (gradient): g = upstream * psi';  S[s][r][n] = conj(P(r, n)) g and
 //     gP(r, n) += sum_s conj(O_s(r, n)) g  (when the scan has a gP).
-template <int N>
+template <int N, int RV = 0>
 struct UpdCfg {
     static constexpr int T = PlanInfo<N>::T;
-    static constexpr int ULINES = N >= 512 ? 8 : RowCfg<N>::LINES;
+    static constexpr int ULINES0 = N >= 512 ? 8 : RowCfg<N, 0>::LINES;
+    static constexpr int ULINES = RV == 0 ? ULINES0 : (ULINES0 > 1 ? ULINES0 / 2 : 1);
     static constexpr int THREADS = ULINES * T;
 };
 
-template <int N, int MODE>
-__global__ void __launch_bounds__(UpdCfg<N>::THREADS)
+template <int N, int RV, int MODE>
+__global__ void __launch_bounds__((UpdCfg<N, RV>::THREADS))
 k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
                   const GroupDev* __restrict__ groups, float2* __restrict__ S,
                   const float* __restrict__ maxO2_part, int nparts, int rpie, float beta,
                   float upstream, const float2* __restrict__ tw_g) {
-    constexpr int T = UpdCfg<N>::T, ULINES = UpdCfg<N>::ULINES, V = PlanInfo<N>::V;
-    constexpr int THREADS = UpdCfg<N>::THREADS;
+    constexpr int T = UpdCfg<N, RV>::T, ULINES = UpdCfg<N, RV>::ULINES, V = PlanInfo<N>::V;
+    constexpr int THREADS = UpdCfg<N, RV>::THREADS;
     constexpr int COLS = (N + THREADS - 1) / THREADS;  // probe columns owned per thread
     constexpr bool ACC = MODE != 0;                     // probe-row sums over the batch
     constexpr bool DEN = MODE == 1;

@@ -25,19 +25,28 @@ bool size_supported(int N) {
     return false;
 }
 
-int row_lines(int N) {
+template <int RV>
+int row_lines_v(int N) {
     switch (N) {
-        case 16: return RowCfg<16>::LINES;
-        case 32: return RowCfg<32>::LINES;
-        case 64: return RowCfg<64>::LINES;
-        case 128: return RowCfg<128>::LINES;
-        case 192: return RowCfg<192>::LINES;
-        case 256: return RowCfg<256>::LINES;
-        case 384: return RowCfg<384>::LINES;
-        default: return RowCfg<512>::LINES;
+        case 16: return RowCfg<16, RV>::LINES;
+        case 32: return RowCfg<32, RV>::LINES;
+        case 64: return RowCfg<64, RV>::LINES;
+        case 128: return RowCfg<128, RV>::LINES;
+        case 192: return RowCfg<192, RV>::LINES;
+        case 256: return RowCfg<256, RV>::LINES;
+        case 384: return RowCfg<384, RV>::LINES;
+        default: return RowCfg<512, RV>::LINES;
     }
 }
-int col_groups(int N) { return N / (kColGroup < N ? kColGroup : N); }
+int variant_of(mnf_ctx* ctx, int N) {
+    auto it = ctx->variant.find(N);
+    return it == ctx->variant.end() ? 0 : it->second;
+}
+int row_lines(mnf_ctx* ctx, int N) { return (variant_of(ctx, N) & 1) ? row_lines_v<1>(N) : row_lines_v<0>(N); }
+int col_groups(mnf_ctx* ctx, int N) {
+    const int c0 = kColGroup < N ? kColGroup : N;
+    return N / ((variant_of(ctx, N) & 2) ? c0 / 2 : c0);
+}
 
 struct ScanIn {
     float2* O;
@@ -145,8 +154,8 @@ void fill_scan_dev(ScanDev& d, const ScanIn& s, const Box& b) {
 int tiles_of(const ScanDev& d) { return d.tiles_x * ((d.bh + kObjTileY - 1) / kObjTileY); }
 
 // Slot list of iteration i, round b, for the scans of one size class.
-void plan_round(CallPlan& pl, const std::vector<ScanIn>& in, const std::vector<int>& cls, int i, int b, int B,
-                int N) {
+void plan_round(mnf_ctx* ctx, CallPlan& pl, const std::vector<ScanIn>& in, const std::vector<int>& cls, int i,
+                int b, int B, int N) {
     Launch L{N, pl.slots.size(), 0, pl.groups.size(), 0, 0, 0};
     for (int k : cls) {
         const ScanIn& s = in[k];
@@ -166,7 +175,7 @@ void plan_round(CallPlan& pl, const std::vector<ScanIn>& in, const std::vector<i
     }
     if (L.nslots == 0) return;
     pl.max_S = std::max(pl.max_S, (size_t)L.nslots * N * N * sizeof(float2));
-    const int gr = (L.maxNw + row_lines(N) - 1) / row_lines(N);
+    const int gr = (L.maxNw + row_lines(ctx, N) - 1) / row_lines(ctx, N);
     pl.max_maxO2 = std::max(pl.max_maxO2, (size_t)L.nslots * gr);
     pl.launches.push_back(L);
 }
@@ -181,16 +190,16 @@ int upload_plan(mnf_ctx* ctx, CallPlan& pl, hipStream_t st) {
 
 // ---------------------------------------------------------- launch helpers
 
-template <int N>
-int launch_rows_fwd(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, float2* S, float* mO, const float2* tw,
-                    hipStream_t st) {
-    const int gr = (L.maxNw + RowCfg<N>::LINES - 1) / RowCfg<N>::LINES;
-    MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, L.nslots), dim3(RowCfg<N>::THREADS),
-               (const ScanDev*)pl.d_scans, (const SlotDev*)pl.d_slots + L.slot_off, S, mO, tw);
+template <int N, int RV>
+int launch_rows_fwd(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ScanDev* scans, float2* S, float* mO,
+                    const float2* tw, hipStream_t st) {
+    const int gr = (L.maxNw + RowCfg<N, RV>::LINES - 1) / RowCfg<N, RV>::LINES;
+    MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, (k_rows_fwd<N, RV>), dim3(gr, L.nslots), dim3(RowCfg<N, RV>::THREADS),
+               scans, (const SlotDev*)pl.d_slots + L.slot_off, S, mO, tw);
     return MNF_OK;
 }
 
-template <int N>
+template <int N, int RV, int CV>
 int issue_iterate_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd,
                          float2* S, float* mO, hipStream_t st) {
     const float2* tw;
@@ -198,33 +207,44 @@ int issue_iterate_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, cons
     const ScanDev* scans = (const ScanDev*)pl.d_scans;
     const SlotDev* slots = (const SlotDev*)pl.d_slots + L.slot_off;
     const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
-    const int gr = (L.maxNw + RowCfg<N>::LINES - 1) / RowCfg<N>::LINES;
+    const int gr = (L.maxNw + RowCfg<N, RV>::LINES - 1) / RowCfg<N, RV>::LINES;
     const int rpie = p.alg == 1;
-    MNF_TRY(launch_rows_fwd<N>(ctx, pl, L, S, mO, tw, st));
-    MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, ColOp::Modulus>), dim3(N / ColCfg<N>::C, L.nslots),
-               dim3(ColCfg<N>::THREADS), scans, slots, S, 0.f, tw);
+    MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, tw, st)));
+    MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, CV, ColOp::Modulus>),
+               dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, S, 0.f, tw);
     if (upd)
-        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 1>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, tw);
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 1>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, tw);
     else
-        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 0>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, tw);
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 0>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, tw);
     MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
     return MNF_OK;
 }
 
+template <int N>
+int issue_iterate_n(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
+                    float* mO, hipStream_t st) {
+    switch (variant_of(ctx, N)) {
+        case 1: return issue_iterate_launch<N, 1, 0>(ctx, pl, L, p, upd, S, mO, st);
+        case 2: return issue_iterate_launch<N, 0, 1>(ctx, pl, L, p, upd, S, mO, st);
+        case 3: return issue_iterate_launch<N, 1, 1>(ctx, pl, L, p, upd, S, mO, st);
+        default: return issue_iterate_launch<N, 0, 0>(ctx, pl, L, p, upd, S, mO, st);
+    }
+}
+
 int issue_iterate_any(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
                       float* mO, hipStream_t st) {
     switch (L.N) {
-        case 16: return issue_iterate_launch<16>(ctx, pl, L, p, upd, S, mO, st);
-        case 32: return issue_iterate_launch<32>(ctx, pl, L, p, upd, S, mO, st);
-        case 64: return issue_iterate_launch<64>(ctx, pl, L, p, upd, S, mO, st);
-        case 128: return issue_iterate_launch<128>(ctx, pl, L, p, upd, S, mO, st);
-        case 192: return issue_iterate_launch<192>(ctx, pl, L, p, upd, S, mO, st);
-        case 256: return issue_iterate_launch<256>(ctx, pl, L, p, upd, S, mO, st);
-        case 384: return issue_iterate_launch<384>(ctx, pl, L, p, upd, S, mO, st);
-        case 512: return issue_iterate_launch<512>(ctx, pl, L, p, upd, S, mO, st);
+        case 16: return issue_iterate_n<16>(ctx, pl, L, p, upd, S, mO, st);
+        case 32: return issue_iterate_n<32>(ctx, pl, L, p, upd, S, mO, st);
+        case 64: return issue_iterate_n<64>(ctx, pl, L, p, upd, S, mO, st);
+        case 128: return issue_iterate_n<128>(ctx, pl, L, p, upd, S, mO, st);
+        case 192: return issue_iterate_n<192>(ctx, pl, L, p, upd, S, mO, st);
+        case 256: return issue_iterate_n<256>(ctx, pl, L, p, upd, S, mO, st);
+        case 384: return issue_iterate_n<384>(ctx, pl, L, p, upd, S, mO, st);
+        case 512: return issue_iterate_n<512>(ctx, pl, L, p, upd, S, mO, st);
         default: return MNF_EUNSUPPORTED;
     }
 }
@@ -257,7 +277,7 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     size_t f_need = 0, d_need = 0;
     for (int k = 0; k < ns; ++k) {
         f_need += (size_t)in[k].Nw * in[k].Nw + in[k].Nw;
-        d_need += (size_t)in[k].J * col_groups(in[k].Nd) + in[k].J + 1;
+        d_need += (size_t)in[k].J * col_groups(ctx, in[k].Nd) + in[k].J + 1;
     }
     void *fbuf, *dbuf;
     MNF_TRY(scratch(ctx, "scan_f32", f_need * sizeof(float), &fbuf));
@@ -272,7 +292,7 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
             pl.scans[k].maxP2_row = f;
             f += in[k].Nw;
             pl.scans[k].err_part = d;
-            d += (size_t)in[k].J * col_groups(in[k].Nd);
+            d += (size_t)in[k].J * col_groups(ctx, in[k].Nd);
             sA2p[k] = d;
             d += in[k].J;
             sA2[k] = d;
@@ -281,7 +301,7 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     }
     for (int i = 0; i < n_iter; ++i) {
         for (int b = 0; b < max_batches; ++b)
-            for (auto& kv : classes) plan_round(pl, in, kv.second, i, b, p.batch, kv.first);
+            for (auto& kv : classes) plan_round(ctx, pl, in, kv.second, i, b, p.batch, kv.first);
         pl.iter_end.push_back((int)pl.launches.size());
     }
     MNF_TRY(upload_plan(ctx, pl, st));
@@ -289,7 +309,7 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     std::vector<SumJob> jobs;
     for (int i = 0; i < n_iter; ++i)
         for (int k = 0; k < ns; ++k)
-            jobs.push_back(SumJob{pl.scans[k].err_part, (size_t)in[k].J * col_groups(in[k].Nd), sA2[k],
+            jobs.push_back(SumJob{pl.scans[k].err_part, (size_t)in[k].J * col_groups(ctx, in[k].Nd), sA2[k],
                                   in[k].err_out ? in[k].err_out + i : nullptr});
     std::vector<SumJob> a2jobs;
     for (int k = 0; k < ns; ++k) a2jobs.push_back(SumJob{sA2p[k], (size_t)in[k].J, nullptr, sA2[k]});
@@ -361,38 +381,48 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
 
 // ----------------------------------------------------------------- forward
 
-template <int N>
-int forward_n(mnf_ctx* ctx, const CallPlan& pl, float* I_out, hipStream_t st) {
+template <int N, int RV, int CV>
+int forward_v(mnf_ctx* ctx, const CallPlan& pl, float* I_out, hipStream_t st) {
     const float2* tw;
     MNF_TRY(twiddles(ctx, N, &tw));
     void* S;
     MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
     for (const Launch& L : pl.launches) {
-        MNF_TRY(launch_rows_fwd<N>(ctx, pl, L, (float2*)S, (float*)nullptr, tw, st));
-        MNF_LAUNCH(ctx, MNF_K_FORWARD, st, k_cols_intensity<N>, dim3(N / ColCfg<N>::C, L.nslots),
-                   dim3(ColCfg<N>::THREADS), (const ScanDev*)pl.d_scans, (const SlotDev*)pl.d_slots + L.slot_off,
+        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, (const ScanDev*)pl.d_scans, (float2*)S, (float*)nullptr, tw, st)));
+        MNF_LAUNCH(ctx, MNF_K_FORWARD, st, (k_cols_intensity<N, CV>), dim3(N / ColCfg<N, CV>::C, L.nslots),
+                   dim3(ColCfg<N, CV>::THREADS), (const ScanDev*)pl.d_scans, (const SlotDev*)pl.d_slots + L.slot_off,
                    (const float2*)S, I_out, tw);
     }
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
 }
 
+template <int N>
+int forward_n(mnf_ctx* ctx, const CallPlan& pl, float* I_out, hipStream_t st) {
+    switch (variant_of(ctx, N)) {
+        case 1: return forward_v<N, 1, 0>(ctx, pl, I_out, st);
+        case 2: return forward_v<N, 0, 1>(ctx, pl, I_out, st);
+        case 3: return forward_v<N, 1, 1>(ctx, pl, I_out, st);
+        default: return forward_v<N, 0, 0>(ctx, pl, I_out, st);
+    }
+}
+
 // ------------------------------------------------------------------ grad
 
-template <int N>
-int grad_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, double upstream, double* loss_out,
+template <int N, int RV, int CV>
+int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, double upstream, double* loss_out,
            hipStream_t st) {
     const float2* tw;
     MNF_TRY(twiddles(ctx, N, &tw));
     void *S, *lossp, *d_job;
     MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
-    MNF_TRY(scratch(ctx, "losspart", (size_t)s.J * col_groups(N) * sizeof(double), &lossp));
+    MNF_TRY(scratch(ctx, "losspart", (size_t)s.J * col_groups(ctx, N) * sizeof(double), &lossp));
     // the scan's partials live in the loss buffer
     std::vector<ScanDev> sd = pl.scans;
     sd[0].err_part = (double*)lossp;
     void* d_scans;
     MNF_TRY(upload(ctx, "plan_scans", sd.data(), sizeof(ScanDev), st, &d_scans));
-    SumJob job{(const double*)lossp, (size_t)s.J * col_groups(N), nullptr, loss_out};
+    SumJob job{(const double*)lossp, (size_t)s.J * col_groups(ctx, N), nullptr, loss_out};
     MNF_TRY(upload(ctx, "plan_lossjob", &job, sizeof job, st, &d_job));
     if (s.gO)
         MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_zero_c64, dim3((unsigned)(((size_t)s.My * s.Mx + 255) / 256)), dim3(256),
@@ -404,18 +434,18 @@ int grad_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
     for (const Launch& L : pl.launches) {
         const SlotDev* slots = (const SlotDev*)pl.d_slots + L.slot_off;
         const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
-        const int gr = (L.maxNw + RowCfg<N>::LINES - 1) / RowCfg<N>::LINES;
-        MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, k_rows_fwd<N>, dim3(gr, L.nslots), dim3(RowCfg<N>::THREADS), scans,
-                   slots, (float2*)S, (float*)nullptr, tw);
+        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, (float2*)S, (float*)nullptr, tw, st)));
         if (kind == 0)
-            MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, ColOp::PoissonGrad>),
-                       dim3(N / ColCfg<N>::C, L.nslots), dim3(ColCfg<N>::THREADS), scans, slots, (float2*)S, eps, tw);
+            MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, CV, ColOp::PoissonGrad>),
+                       dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, (float2*)S,
+                       eps, tw);
         else
-            MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, ColOp::AmplitudeGrad>),
-                       dim3(N / ColCfg<N>::C, L.nslots), dim3(ColCfg<N>::THREADS), scans, slots, (float2*)S, eps, tw);
+            MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, CV, ColOp::AmplitudeGrad>),
+                       dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, (float2*)S,
+                       eps, tw);
         if (!s.gO && !s.gP) continue;
-        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 2>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N>::THREADS), scans, slots, groups, (float2*)S, (const float*)nullptr, 0, 0, 0.f,
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 2>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, (float2*)S, (const float*)nullptr, 0, 0, 0.f,
                    (float)upstream, tw);
         if (s.gO)
             MNF_LAUNCH(ctx, MNF_K_GRAD_SCATTER, st, k_grad_object, dim3(L.tiles), dim3(kObjThreads), scans, slots,
@@ -424,6 +454,17 @@ int grad_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
     if (loss_out) MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_jobs, dim3(1), dim3(256), (const SumJob*)d_job, 1.0);
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
+}
+
+template <int N>
+int grad_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, double upstream, double* loss_out,
+           hipStream_t st) {
+    switch (variant_of(ctx, N)) {
+        case 1: return grad_v<N, 1, 0>(ctx, pl, s, kind, eps, upstream, loss_out, st);
+        case 2: return grad_v<N, 0, 1>(ctx, pl, s, kind, eps, upstream, loss_out, st);
+        case 3: return grad_v<N, 1, 1>(ctx, pl, s, kind, eps, upstream, loss_out, st);
+        default: return grad_v<N, 0, 0>(ctx, pl, s, kind, eps, upstream, loss_out, st);
+    }
 }
 
 #define MNF_DISPATCH(N, FN, ...)               \
@@ -448,13 +489,93 @@ int plan_identity(mnf_ctx* ctx, const ScanIn& s, int chunk, CallPlan& pl, hipStr
     std::vector<int> cls{0};
     std::vector<ScanIn> in{s};
     const int nr = (s.J + chunk - 1) / chunk;
-    for (int r = 0; r < nr; ++r) plan_round(pl, in, cls, 0, r, chunk, s.Nd);
+    for (int r = 0; r < nr; ++r) plan_round(ctx, pl, in, cls, 0, r, chunk, s.Nd);
     return upload_plan(ctx, pl, st);
+}
+
+// Time every launch-shape variant for detector size N on a synthetic scan of
+// `nslots` positions iterated `reps` times in mini-batches of `nslots`.
+int autotune_impl(mnf_ctx* ctx, int N, int nslots, int reps, double* times_us, hipStream_t st) {
+    if (!size_supported(N)) return set_error(ctx, MNF_EUNSUPPORTED, "detector size %d has no FFT plan", N);
+    if (nslots < 1 || nslots > kMaxBatch) return set_error(ctx, MNF_EINVAL, "nslots outside [1, %d]", kMaxBatch);
+    if (reps < 1) return set_error(ctx, MNF_EINVAL, "reps must be positive");
+    int side = 1;
+    while (side * side < nslots) ++side;
+    const int step = N / 4 > 0 ? N / 4 : 1;
+    const int M = N + (side - 1) * step;
+    void *O, *P, *I;
+    MNF_TRY(scratch(ctx, "tune_O", (size_t)M * M * sizeof(float2), &O));
+    MNF_TRY(scratch(ctx, "tune_P", (size_t)N * N * sizeof(float2), &P));
+    MNF_TRY(scratch(ctx, "tune_I", (size_t)nslots * N * N * sizeof(float), &I));
+    hipLaunchKernelGGL(k_fill_c64, dim3((unsigned)(((size_t)M * M + 255) / 256)), dim3(256), 0, st, (float2*)O,
+                       (size_t)M * M, make_float2(1.f, 0.f));
+    hipLaunchKernelGGL(k_fill_c64, dim3((unsigned)(((size_t)N * N + 255) / 256)), dim3(256), 0, st, (float2*)P,
+                       (size_t)N * N, make_float2(0.5f, 0.5f));
+    hipLaunchKernelGGL(k_fill_f32, dim3((unsigned)(((size_t)nslots * N * N + 255) / 256)), dim3(256), 0, st,
+                       (float*)I, (size_t)nslots * N * N, 1.f);
+    std::vector<int32_t> pos(2 * nslots);
+    for (int k = 0; k < nslots; ++k) {
+        pos[2 * k] = (k / side) * step;
+        pos[2 * k + 1] = (k % side) * step;
+    }
+    std::vector<ScanIn> in{ScanIn{(float2*)O, M, M, (float2*)P, N, (const float*)I, N, pos.data(), nslots, nullptr,
+                                  nullptr, nullptr, nullptr}};
+    ptycho_params p{1, 0.1f, 0.1f, nslots, 1, 0, 0, 0};
+    hipEvent_t e0, e1;
+    MNF_HIP(ctx, hipEventCreate(&e0));
+    MNF_HIP(ctx, hipEventCreate(&e1));
+    const int saved = variant_of(ctx, N);
+    int best = 0;
+    double best_t = 1e300;
+    int rc = MNF_OK;
+    for (int v = 0; v < 4 && rc == MNF_OK; ++v) {
+        ctx->variant[N] = v;
+        rc = run_iterate(ctx, in, 1, p, st);  // warm-up (also sizes the scratch)
+        if (rc != MNF_OK) break;
+        if (hipEventRecord(e0, st) != hipSuccess) { rc = MNF_EHIP; break; }
+        rc = run_iterate(ctx, in, reps, p, st);
+        if (rc != MNF_OK) break;
+        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = MNF_EHIP; break; }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1e3 * ms / reps;
+        if (times_us) times_us[v] = us;
+        if (us < best_t) {
+            best_t = us;
+            best = v;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != MNF_OK) {
+        ctx->variant[N] = saved;
+        return rc == MNF_EHIP ? set_error(ctx, MNF_EHIP, "event timing failed during tuning") : rc;
+    }
+    ctx->variant[N] = best;
+    return best;
 }
 
 }  // namespace
 
 extern "C" {
+
+int mnf_autotune(mnf_ctx* ctx, int Nd, int nslots, int reps, double* times_us, void* stream) {
+    MNF_TRY(begin(ctx));
+    return autotune_impl(ctx, Nd, nslots, reps, times_us, (hipStream_t)stream);
+}
+
+int mnf_set_variant(mnf_ctx* ctx, int Nd, int variant) {
+    MNF_TRY(begin(ctx));
+    if (!size_supported(Nd)) return set_error(ctx, MNF_EUNSUPPORTED, "detector size %d has no FFT plan", Nd);
+    if (variant < 0 || variant > 3) return set_error(ctx, MNF_EINVAL, "variant must be 0..3");
+    ctx->variant[Nd] = variant;
+    return MNF_OK;
+}
+
+int mnf_get_variant(mnf_ctx* ctx, int Nd) {
+    MNF_TRY(begin(ctx));
+    return variant_of(ctx, Nd);
+}
 
 int mnf_supported_sizes(int32_t* sizes, int cap) {
     const int n = (int)(sizeof(kSizes) / sizeof(kSizes[0]));

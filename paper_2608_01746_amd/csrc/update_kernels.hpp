@@ -199,6 +199,16 @@ k_grad_object(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slo
     }
 }
 
+__global__ void k_fill_c64(float2* __restrict__ dst, size_t n, float2 v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+
+__global__ void k_fill_f32(float* __restrict__ dst, size_t n, float v) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = v;
+}
+
 __global__ void k_zero_c64(float2* __restrict__ dst, size_t n) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) dst[i] = make_float2(0.f, 0.f);

@@ -53,6 +53,9 @@ SIGNATURES = {
     "ptycho_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
                             POINTER(c_int32), c_int, c_int, c_float, c_int, c_double,
                             c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mnf_autotune": (c_int, [c_void_p, c_int, c_int, c_int, POINTER(c_double), c_void_p]),
+    "mnf_set_variant": (c_int, [c_void_p, c_int, c_int]),
+    "mnf_get_variant": (c_int, [c_void_p, c_int]),
     "mnf_profile": (c_int, [c_void_p, ctypes.c_uint32]),
     "mnf_profile_read": (c_int, [c_void_p, c_int, POINTER(ctypes.c_longlong), POINTER(c_double)]),
     "mnf_profile_reset": (c_int, [c_void_p]),
