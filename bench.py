@@ -132,12 +132,20 @@ def roofline(dominant, nlaunch, kms, positions_per_launch, N, B):
 PASSES = ["rows_fwd", "cols_modulus", "rows_inv", "object_update", "fuse"]
 
 
+def tune_sizes(sizes, batch):
+    """Pick the launch-shape variant per detector size (timed once, cached)."""
+    from paper_2608_01746_amd import tune
+    out = tune.autotune(sizes, batch=batch, reps=5)
+    return {str(N): e["variant"] for N, e in out.items()}
+
+
 def run_lab(args, api, synth, dev):
     import numpy as np
     import torch
 
     w = synth.lab_workload()
     n_iter = args.iters
+    tuned = tune_sizes([w.Nd], w.batch) if args.tune else None
     O_true = w.object()
     P = w.probe()
     Ot = torch.from_numpy(O_true.astype(np.complex64)).to(dev)
@@ -204,6 +212,7 @@ def run_lab(args, api, synth, dev):
                    "exposures": len(w.t), "levels": w.levels},
         "roofline": roofline(dominant, nlaunch, kms, per_launch, w.Nd, w.batch),
         "per_class_ms_one_step": {k: round(v[1], 3) for k, v in ranks.items()},
+        "launch_variants": tuned,
         "final_fourier_error": float(state["err"][-1].item()),
     }
     if not args.no_cpu:
@@ -221,6 +230,7 @@ def run_multiscan(args, api, synth, dev):
 
     ws = synth.multiscan_workloads(64)
     n_iter = args.iters
+    tuned = tune_sizes(sorted({w.Nd for w in ws}), 32) if args.tune else None
     scans = []
     for w in ws:
         O_true = torch.from_numpy(w.object().astype(np.complex64)).to(dev)
@@ -281,6 +291,7 @@ def run_multiscan(args, api, synth, dev):
         "roofline": dict(roofline(dominant, nlaunch, kms, per_launch, Nbar, 32),
                          note="per-launch events from one step with direct launches; N = rms pattern size"),
         "per_class_ms_direct_step": {k: round(v[1], 3) for k, v in ranks.items()},
+        "launch_variants": tuned,
     }
 
 
@@ -293,6 +304,8 @@ def main() -> int:
     ap.add_argument("--workload", choices=["lab", "multiscan"], default="lab")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tune", dest="tune", action="store_false",
+                    help="keep the default launch shapes instead of the tuned ones")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 256 MiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()

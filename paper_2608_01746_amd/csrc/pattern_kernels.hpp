@@ -119,26 +119,27 @@ k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
     const int kx = blockIdx.x * C + c;
     float2* col = S + (size_t)s * N * N + kx;
 
+    // the fused intensity at this thread's output frequencies is loaded with
+    // the column, before the transform
+    const float* Ij = sc.I + (size_t)sd.j * N * N;
+    const int sx = (kx + N / 2) % N;
     float2 x[V];
+    float Iq[V];
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int y = in_pos<N, false>(t, idx);
         x[idx] = y < Nw ? col[(size_t)y * N] : make_float2(0.f, 0.f);
+        const int ky = out_pos<N, false>(t, idx);
+        Iq[idx] = Ij[(size_t)((ky + N / 2) % N) * N + sx];
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
     __syncthreads();
     fft_line<N, false>(x, t, lds, ColLds<C>(c), tw);
 
     const float sc1 = 1.f / (float)N;
-    const float* Ij = sc.I + (size_t)sd.j * N * N;
-    const int sx = (kx + N / 2) % N;
     double acc = 0.0;
 #pragma unroll
-    for (int idx = 0; idx < V; ++idx) {
-        const int ky = out_pos<N, false>(t, idx);
-        const int sy = (ky + N / 2) % N;
-        x[idx] = col_pointwise<OP>(cscale(x[idx], sc1), Ij[(size_t)sy * N + sx], eps, acc);
-    }
+    for (int idx = 0; idx < V; ++idx) x[idx] = col_pointwise<OP>(cscale(x[idx], sc1), Iq[idx], eps, acc);
     fft_line<N, true>(x, t, lds, ColLds<C>(c), tw);
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
@@ -201,7 +202,8 @@ k_cols_intensity(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
 template <int N, int RV = 0>
 struct UpdCfg {
     static constexpr int T = PlanInfo<N>::T;
-    static constexpr int ULINES0 = N >= 512 ? 8 : RowCfg<N, 0>::LINES;
+    // lines per block: a whole 32-slot mini-batch in one round where LDS allows
+    static constexpr int ULINES0 = N <= 256 ? (512 / T < 32 ? 512 / T : 32) : (N == 384 ? 16 : 8);
     static constexpr int ULINES = RV == 0 ? ULINES0 : (ULINES0 > 1 ? ULINES0 / 2 : 1);
     static constexpr int THREADS = ULINES * T;
 };
@@ -217,13 +219,16 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
     constexpr int COLS = (N + THREADS - 1) / THREADS;  // probe columns owned per thread
     constexpr bool ACC = MODE != 0;                     // probe-row sums over the batch
     constexpr bool DEN = MODE == 1;
+    // the transform's exchange buffer doubles as the per-line numerator buffer
+    // once a round's transforms are done (both hold ULINES x N complex values)
     __shared__ float2 lds[ULINES * RowLds<N>::stride];
     __shared__ float2 tw[N];
-    __shared__ float2 c_num[ACC ? ULINES * N : 1];
+    __shared__ float2 s_prow[N];
     __shared__ float c_den[DEN ? ULINES * N : 1];
     __shared__ float s_max[DEN ? kMaxBatch : 1];
     __shared__ int s_py[kMaxBatch], s_px[kMaxBatch];
     __shared__ float red[THREADS / 64 + 1];
+    float2* c_num = lds;
     const GroupDev gd = groups[blockIdx.y];
     const ScanDev& sc = scans[gd.scan];
     const int Nw = sc.Nw, Mx = sc.Mx, nb = gd.nb;
@@ -231,7 +236,11 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
     if (r >= Nw) return;  // uniform over the block
     const int line = threadIdx.x / T, t = threadIdx.x % T;
 
-    for (int i = threadIdx.x; i < N; i += THREADS) tw[i] = tw_g[i];
+    const float2* Prow = sc.P + (size_t)r * Nw;
+    for (int i = threadIdx.x; i < N; i += THREADS) {
+        tw[i] = tw_g[i];
+        s_prow[i] = i < Nw ? Prow[i] : make_float2(0.f, 0.f);
+    }
     for (int k = threadIdx.x; k < nb; k += THREADS) {
         const SlotDev sd = slots[gd.s0 + k];
         s_py[k] = sd.py;
@@ -242,7 +251,6 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             s_max[k] = m;
         }
     }
-    const float2* Prow = sc.P + (size_t)r * Nw;
     float2 num[COLS];
     double den[COLS];
 #pragma unroll
@@ -256,27 +264,31 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
     for (int k0 = 0; k0 < nb; k0 += ULINES) {
         const int k = k0 + line;
         const bool live = k < nb;
-        float2* row = S + ((size_t)(gd.s0 + (live ? k : 0)) * N + r) * N;
-        float2 x[V];
+        const int kk = live ? k : 0;
+        float2* row = S + ((size_t)(gd.s0 + kk) * N + r) * N;
+        const float2* Orow = sc.O + (size_t)(s_py[kk] + r) * Mx + s_px[kk];
+        // every global load of the round is issued before the transform
+        float2 x[V], o[V];
 #pragma unroll
-        for (int idx = 0; idx < V; ++idx)
+        for (int idx = 0; idx < V; ++idx) {
             x[idx] = live ? row[in_pos<N, true>(t, idx)] : make_float2(0.f, 0.f);
+            const int n = out_pos<N, true>(t, idx);
+            o[idx] = live && n < Nw ? Orow[n] : make_float2(0.f, 0.f);
+        }
         fft_line<N, true>(x, t, lds, RowLds<N>(line), tw);
         if (live) {
-            const float2* Orow = sc.O + (size_t)(s_py[k] + r) * Mx + s_px[k];
             float mO = 0.f;
             if constexpr (DEN) mO = s_max[k];
 #pragma unroll
             for (int idx = 0; idx < V; ++idx) {
                 const int n = out_pos<N, true>(t, idx);
                 if (n < Nw) {
-                    const float2 p = Prow[n];
-                    const float2 o = Orow[n];
-                    const float2 d = MODE == 2 ? cscale(x[idx], scl) : csub(cscale(x[idx], scl), cmul(p, o));
+                    const float2 p = s_prow[n];
+                    const float2 d = MODE == 2 ? cscale(x[idx], scl) : csub(cscale(x[idx], scl), cmul(p, o[idx]));
                     row[n] = cconjmul(p, d);
-                    if constexpr (ACC) c_num[line * N + n] = cconjmul(o, d);
+                    if constexpr (ACC) c_num[line * N + n] = cconjmul(o[idx], d);
                     if constexpr (DEN) {
-                        const float o2 = cabs2(o);
+                        const float o2 = cabs2(o[idx]);
                         c_den[line * N + n] = rpie ? (1.f - beta) * o2 + beta * mO : mO / beta;
                     }
                 }
@@ -309,7 +321,7 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                 *g = cadd(*g, num[c]);
             }
         } else {
-            float2 p = Prow[n];
+            float2 p = s_prow[n];
             const float p2 = cabs2(p);
             sc.P2[(size_t)r * Nw + n] = p2;
             pmax = fmaxf(pmax, p2);
