@@ -170,6 +170,53 @@ int ptycho_grad(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P
                 double* loss_out, mnf_c64* gO, mnf_c64* gP, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Warm-start network: a four-level U-Net mapping a log-scaled fused pattern
+ * [n][H][H] to the amplitude and phase of the illuminated object patch
+ * [n][H/4][H/4][2] (channels last).  Level l (size H/2^l, width widths[l])
+ * has two 3x3 convolutions + ReLU; 2x2 stride-2 convolutions + ReLU join the
+ * levels; a 2x2 transposed convolution + ReLU returns from level 3 to level
+ * 2, its output concatenated (first) with the level-2 encoder output; two
+ * 3x3 convolutions (width widths[2]) + ReLU and a 1x1 head give 2 outputs.
+ * Input x = ln(1 + max(I, 0)) * log_scale.  BF16 MFMA convolutions with
+ * float32 accumulation; bf16 activations; float32 parameters, per layer
+ * W[taps][c_in][c_out] then b[c_out], in the order above (taps 9, 4 or 1).
+ * The network extends the method (the paper reconstructs without one); it
+ * supplies a starting object for the iterations. */
+typedef struct {
+    int32_t H;          /* input size, a multiple of 8, >= 16 */
+    int32_t widths[4];  /* channel widths of the four levels, multiples of 8, <= 256 */
+} mnf_unet_shape;
+
+/* Number of float32 parameters of the network (host call; -1 for NULL). */
+long long unet_param_count(const mnf_unet_shape* shape);
+
+/* params device float[count]; I device float [n][H][H]; out device float [n][H/4][H/4][2]. */
+int unet_forward(mnf_ctx* ctx, const mnf_unet_shape* shape, const float* params, const float* I,
+                 float log_scale, int n, float* out, void* stream);
+
+/* One training step on a batch: forward, mean-squared-error loss against
+ * target (device float [n][H/4][H/4][2]), backward, and (when adam_m and
+ * adam_v are given) an Adam update of params (beta1 0.9, beta2 0.999,
+ * eps 1e-8, bias-corrected with `step` >= 1).  loss_out (device double[1]),
+ * grad_out (device float[count]) and out (device float [n][H/4][H/4][2])
+ * are optional. */
+int unet_train_step(mnf_ctx* ctx, const mnf_unet_shape* shape, float* params, float* adam_m, float* adam_v,
+                    int step, float lr, const float* I, float log_scale, const float* target, int n,
+                    double* loss_out, float* grad_out, float* out, void* stream);
+
+/* Single convolution layers (the network's building blocks).
+ * mode 0: 3x3 stride 1 pad 1; 1: 2x2 stride 2; 2: 2x2 transposed stride 2; 3: 1x1.
+ * x device bf16 (uint16 bits) [n][H][H][Ci]; W device float [taps][Ci][Co]; b device float [Co] or NULL;
+ * y device float [n][Ho][Ho][Co] (Ho = H, H/2, 2H, H). */
+int mnf_conv2d(mnf_ctx* ctx, int mode, const uint16_t* x, int n, int H, int Ci, const float* W, const float* b,
+               int Co, int relu, float* y, void* stream);
+/* Gradients of a layer given dy (bf16 [n][Ho][Ho][Co]) and, if not NULL, the layer's ReLU output act
+ * (bf16, same layout; dy is masked by act > 0): dx (bf16 [n][H][H][Ci], may be NULL), dW (float
+ * [taps][Ci][Co]) and db (float [Co]) (both or neither). */
+int mnf_conv2d_grad(mnf_ctx* ctx, int mode, const uint16_t* x, int n, int H, int Ci, const float* W, int Co,
+                    const uint16_t* dy, const uint16_t* act, uint16_t* dx, float* dW, float* db, void* stream);
+
+/* ------------------------------------------------------------------------
  * Launch-shape tuning.  Every pattern pass is compiled in two shapes (rows:
  * the default lines per block or half as many; columns: 32 columns per block
  * or 16), giving four variants per detector size: bit 0 selects the row

@@ -260,3 +260,86 @@ def profile_read(device="cuda:0") -> dict:
         if n.value:
             out[name] = (int(n.value), float(ms.value))
     return out
+
+
+# ------------------------------------------------------------ warm start
+
+def unet_shape(H: int, widths):
+    s = _L.UnetShapeC()
+    s.H = int(H)
+    for i, w in enumerate(widths):
+        s.widths[i] = int(w)
+    return s
+
+
+def unet_param_count(H: int, widths) -> int:
+    return int(_L.load().unet_param_count(ctypes.byref(unet_shape(H, widths))))
+
+
+def unet_forward(params: torch.Tensor, I: torch.Tensor, log_scale: float, H: int, widths,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Network output [n][H/4][H/4][2] (amplitude, phase) for fused patterns I [n][H][H]."""
+    _dev(params, "params", torch.float32, 1)
+    _dev(I, "I", torch.float32, 3)
+    n = I.shape[0]
+    if out is None:
+        out = torch.empty((n, H // 4, H // 4, 2), dtype=torch.float32, device=I.device)
+    shp = unet_shape(H, widths)
+    ctx = _ctx(I.device)
+    rc = _L.load().unet_forward(ctx, ctypes.byref(shp), _ptr(params), _ptr(I), float(log_scale), n, _ptr(out),
+                                _stream(I.device))
+    _check(rc, ctx)
+    return out
+
+
+def unet_train_step(params: torch.Tensor, adam_m: Optional[torch.Tensor], adam_v: Optional[torch.Tensor],
+                    step: int, lr: float, I: torch.Tensor, log_scale: float, target: torch.Tensor, H: int, widths,
+                    grads: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One Adam step (or only gradients when adam_m/adam_v are None); returns the float64 loss."""
+    _dev(params, "params", torch.float32, 1)
+    _dev(I, "I", torch.float32, 3)
+    _dev(target, "target", torch.float32, 4)
+    n = I.shape[0]
+    loss = torch.empty((), dtype=torch.float64, device=I.device)
+    shp = unet_shape(H, widths)
+    ctx = _ctx(I.device)
+    rc = _L.load().unet_train_step(ctx, ctypes.byref(shp), _ptr(params), _ptr(adam_m), _ptr(adam_v), int(step),
+                                   float(lr), _ptr(I), float(log_scale), _ptr(target), n, _ptr(loss), _ptr(grads),
+                                   _ptr(out), _stream(I.device))
+    _check(rc, ctx)
+    return loss
+
+
+CONV_MODES = {"conv3": 0, "down": 1, "up": 2, "conv1": 3}
+
+
+def conv2d(mode: str, x: torch.Tensor, W: torch.Tensor, b: Optional[torch.Tensor], relu: bool = False):
+    """One convolution layer: x bf16 [n][H][H][Ci], W float [taps][Ci][Co] -> float [n][Ho][Ho][Co]."""
+    _dev(x, "x", torch.bfloat16, 4)
+    _dev(W, "W", torch.float32, 3)
+    n, H, _, Ci = x.shape
+    Co = W.shape[2]
+    Ho = {"conv3": H, "down": H // 2, "up": 2 * H, "conv1": H}[mode]
+    y = torch.empty((n, Ho, Ho, Co), dtype=torch.float32, device=x.device)
+    ctx = _ctx(x.device)
+    rc = _L.load().mnf_conv2d(ctx, CONV_MODES[mode], _ptr(x), n, H, Ci, _ptr(W), _ptr(b), Co, 1 if relu else 0,
+                              _ptr(y), _stream(x.device))
+    _check(rc, ctx)
+    return y
+
+
+def conv2d_grad(mode: str, x: torch.Tensor, W: torch.Tensor, dy: torch.Tensor, act: Optional[torch.Tensor] = None):
+    """(dx bf16, dW float, db float) of one layer; dy is masked by act > 0 when act is given."""
+    _dev(x, "x", torch.bfloat16, 4)
+    _dev(W, "W", torch.float32, 3)
+    _dev(dy, "dy", torch.bfloat16, 4)
+    n, H, _, Ci = x.shape
+    Co = W.shape[2]
+    dx = torch.empty_like(x)
+    dW = torch.empty_like(W)
+    db = torch.empty(Co, dtype=torch.float32, device=x.device)
+    ctx = _ctx(x.device)
+    rc = _L.load().mnf_conv2d_grad(ctx, CONV_MODES[mode], _ptr(x), n, H, Ci, _ptr(W), Co, _ptr(dy), _ptr(act),
+                                   _ptr(dx), _ptr(dW), _ptr(db), _stream(x.device))
+    _check(rc, ctx)
+    return dx, dW, db

@@ -1,0 +1,391 @@
+// BF16 MFMA convolution kernels of the warm-start network (implicit GEMM,
+// float32 accumulation, channels-last activations).
+//
+// Forward and input-gradient convolutions are one GEMM kernel,
+//   out[m][n] = sum_k A[m][k] Bt[n][k]  (+ bias, + residual, ReLU),
+// where the rows of A are gathered from the input tensor according to the
+// layer kind (MODE) and Bt holds bf16 weights in GEMM order [n][k], prepared
+// from the float32 parameters by k_prep_weights.  The four kinds are closed
+// under taking the input gradient:
+//   CONV3 (3x3, stride 1, pad 1) -> CONV3 with flipped taps, transposed;
+//   DOWN  (2x2, stride 2)        -> UP  with transposed taps;
+//   UP    (2x2 transposed)       -> DOWN with transposed taps;
+//   CONV1                        -> CONV1 transposed.
+// A ReLU backward is fused into the A gather (A = dAct * (act > 0)).
+// The weight gradient is a second GEMM over pixels (split over pixel ranges
+// into float32 partials, reduced in a fixed order).
+//
+// MFMA: v_mfma_f32_32x32x16_bf16.  Lane l supplies A[i = l % 32][k = 8 (l / 32) + 0..7]
+// and B[k = 8 (l / 32) + 0..7][j = l % 32]; accumulator register v holds
+// C[8 (v / 4) + 4 (l / 32) + (v % 4)][l % 32].
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels_common.hpp"
+
+namespace mnf {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+enum ConvMode { CONV3 = 0, DOWN = 1, UP = 2, CONV1 = 3 };
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));  // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+
+struct ConvArgs {
+    const uint16_t* in;     // [n][Hin][Win][in_cs] bf16, channels [in_co, in_co + Cin)
+    int in_cs, in_co;
+    const uint16_t* mask;   // ReLU mask source laid out like `in` (MASK), or null
+    int mask_cs, mask_co;
+    const uint16_t* Bt;     // [taps_b][Nout][Kpad] bf16 (taps_b = 4 for UP, else 1)
+    int Kpad;
+    const float* bias;      // [Nout] or null
+    const uint16_t* resid;  // addend at the output pixels [..][res_cs], channels from res_co, or null
+    int res_cs, res_co;
+    void* out;              // [n][Hout][Wout][out_cs], channels [out_co, out_co + Nout)
+    int out_cs, out_co;
+    int n, Hin, Win, Cin, Hout, Wout, Nout;
+    int relu;
+    int M;                  // rows of the GEMM (output pixels; for UP 4 parity groups of per_pad rows)
+    int per_pad;            // UP: input pixels per parity group rounded up to the row tile
+};
+
+constexpr int kGemmBM = 128, kGemmBN = 64, kGemmBK = 32, kGemmThreads = 256;
+constexpr int kLdsK = kGemmBK + 8;  // padded row (bf16) of the LDS tiles
+
+// Input pixel feeding GEMM row m and column k (tap = k / Cin) for the forward
+// gather; returns false for zero padding.  For UP the tap is the output
+// pixel's parity and every k of a row reads the same input pixel.
+template <int MODE>
+__device__ __forceinline__ bool gather_pixel(const ConvArgs& a, int m, int tap, size_t* pix) {
+    if constexpr (MODE == UP) {
+        const int r = m % a.per_pad;
+        *pix = (size_t)r;
+        return r < a.n * a.Hin * a.Win;
+    } else {
+        const int x = m % a.Wout;
+        const int t1 = m / a.Wout;
+        const int y = t1 % a.Hout;
+        const int img = t1 / a.Hout;
+        int yy, xx;
+        if constexpr (MODE == CONV3) {
+            yy = y + tap / 3 - 1;
+            xx = x + tap % 3 - 1;
+        } else if constexpr (MODE == DOWN) {
+            yy = 2 * y + tap / 2;
+            xx = 2 * x + tap % 2;
+        } else {
+            yy = y;
+            xx = x;
+        }
+        if (yy < 0 || yy >= a.Hin || xx < 0 || xx >= a.Win) return false;
+        *pix = ((size_t)img * a.Hin + yy) * a.Win + xx;
+        return true;
+    }
+}
+
+// Output pixel of GEMM row m (UP rows are grouped by output parity).
+template <int MODE>
+__device__ __forceinline__ size_t out_pixel(const ConvArgs& a, int m) {
+    if constexpr (MODE == UP) {
+        const int q = m / a.per_pad, r = m % a.per_pad;
+        const int x = r % a.Win, t1 = r / a.Win;
+        const int y = t1 % a.Hin, img = t1 / a.Hin;
+        return ((size_t)img * a.Hout + 2 * y + q / 2) * a.Wout + 2 * x + q % 2;
+    } else {
+        return (size_t)m;
+    }
+}
+
+// Eight consecutive GEMM columns k .. k+7 of row m (bf16 bits), masked.
+template <int MODE, bool MASK, bool VEC>
+__device__ __forceinline__ uint4 load_a8(const ConvArgs& a, int m, int k) {
+    uint4 r = make_uint4(0, 0, 0, 0);
+    if (m >= a.M) return r;
+    const int K = (MODE == CONV3 ? 9 : (MODE == DOWN ? 4 : 1)) * a.Cin;
+    if constexpr (VEC) {
+        if (k >= K) return r;
+        const int tap = k / a.Cin, ci = k % a.Cin;
+        size_t pix;
+        if (!gather_pixel<MODE>(a, m, tap, &pix)) return r;
+        r = *(const uint4*)(a.in + pix * a.in_cs + a.in_co + ci);
+        if constexpr (MASK) {
+            const uint4 g = *(const uint4*)(a.mask + pix * a.mask_cs + a.mask_co + ci);
+            uint32_t* rv = (uint32_t*)&r;
+            const uint32_t* gv = (const uint32_t*)&g;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t lo = (gv[q] & 0xffffu), hi = gv[q] >> 16;
+                const bool plo = lo != 0 && !(lo & 0x8000u), phi = hi != 0 && !(hi & 0x8000u);
+                rv[q] = (plo ? (rv[q] & 0xffffu) : 0u) | (phi ? (rv[q] & 0xffff0000u) : 0u);
+            }
+        }
+        return r;
+    } else {
+        uint16_t v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            v[q] = 0;
+            const int kk = k + q;
+            if (kk < K) {
+                const int tap = kk / a.Cin, ci = kk % a.Cin;
+                size_t pix;
+                if (gather_pixel<MODE>(a, m, tap, &pix)) {
+                    uint16_t x = a.in[pix * a.in_cs + a.in_co + ci];
+                    if constexpr (MASK) {
+                        const uint16_t g = a.mask[pix * a.mask_cs + a.mask_co + ci];
+                        if (g == 0 || (g & 0x8000u)) x = 0;
+                    }
+                    v[q] = x;
+                }
+            }
+        }
+        r.x = v[0] | ((uint32_t)v[1] << 16);
+        r.y = v[2] | ((uint32_t)v[3] << 16);
+        r.z = v[4] | ((uint32_t)v[5] << 16);
+        r.w = v[6] | ((uint32_t)v[7] << 16);
+        return r;
+    }
+}
+
+template <int MODE, bool MASK, bool VEC, bool OUT_F32>
+__global__ void __launch_bounds__(kGemmThreads) k_conv_gemm(ConvArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t sA[kGemmBM * kLdsK];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[kGemmBN * kLdsK];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int m0 = blockIdx.x * kGemmBM, n0 = blockIdx.y * kGemmBN;
+    const uint16_t* Bt = a.Bt;
+    if constexpr (MODE == UP) Bt += (size_t)(m0 / a.per_pad) * a.Nout * a.Kpad;  // the tile's parity selects the tap
+    f32x16_t acc0 = {}, acc1 = {};
+    // per-thread load slots: two A chunks (rows tid/4 and 64 + tid/4), one B chunk
+    const int ar = tid >> 2, ac = (tid & 3) * 8;
+    const int bn = tid >> 2, bc = (tid & 3) * 8;
+    uint4 ra0, ra1, rb;
+    auto fetch = [&](int k0) {
+        ra0 = load_a8<MODE, MASK, VEC>(a, m0 + ar, k0 + ac);
+        ra1 = load_a8<MODE, MASK, VEC>(a, m0 + 64 + ar, k0 + ac);
+        rb = make_uint4(0, 0, 0, 0);
+        if (n0 + bn < a.Nout) rb = *(const uint4*)(Bt + (size_t)(n0 + bn) * a.Kpad + k0 + bc);
+    };
+    fetch(0);
+    for (int k0 = 0; k0 < a.Kpad; k0 += kGemmBK) {
+        __syncthreads();
+        *(uint4*)(sA + ar * kLdsK + ac) = ra0;
+        *(uint4*)(sA + (64 + ar) * kLdsK + ac) = ra1;
+        *(uint4*)(sB + bn * kLdsK + bc) = rb;
+        __syncthreads();
+        if (k0 + kGemmBK < a.Kpad) fetch(k0 + kGemmBK);  // next chunk in flight during the MFMAs
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int kk = s * 16 + 8 * (lane >> 5);
+            const bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sA + (32 * w + (lane & 31)) * kLdsK + kk));
+            const bf16x8_t b0 = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (lane & 31) * kLdsK + kk));
+            const bf16x8_t b1 = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (32 + (lane & 31)) * kLdsK + kk));
+            acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
+            acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
+        }
+    }
+    // epilogue
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+        const int j = n0 + 32 * nb + (lane & 31);
+        if (j >= a.Nout) continue;
+        const float bj = a.bias ? a.bias[j] : 0.f;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = 32 * w + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+            const int m = m0 + i;
+            if (m >= a.M) continue;
+            if (MODE == UP && m % a.per_pad >= a.n * a.Hin * a.Win) continue;
+            float y = (nb == 0 ? acc0[v] : acc1[v]) + bj;
+            const size_t op = out_pixel<MODE>(a, m);
+            if (a.resid) y += bf2f(a.resid[op * a.res_cs + a.res_co + j]);
+            if (a.relu) y = fmaxf(y, 0.f);
+            if constexpr (OUT_F32)
+                ((float*)a.out)[op * a.out_cs + a.out_co + j] = y;
+            else
+                ((uint16_t*)a.out)[op * a.out_cs + a.out_co + j] = f2bf(y);
+        }
+    }
+}
+
+// ------------------------------------------------------------ weight grad
+// dW[tap][ci][co] partials over pixel ranges: grid (ceil(Co/64), ceil(Ci/64), taps * splits).
+// Rows of the GEMM are input channels, columns output channels, the reduction
+// runs over pixels: output pixels for CONV3/DOWN/CONV1 (input gathered at the
+// tap's shift), input pixels for UP (gradient gathered at the tap's parity).
+struct WgradArgs {
+    const uint16_t* in;    // layer input (bf16), channels [in_co, in_co + Cin) of stride in_cs
+    int in_cs, in_co;
+    const uint16_t* dout;  // gradient w.r.t. the layer output (bf16), stride dout_cs
+    int dout_cs;
+    const uint16_t* act;   // layer output for the ReLU mask, or null
+    int act_cs, act_co;
+    float* part;           // [splits][taps][Ci][Co]
+    int n, Hin, Win, Cin, Hout, Wout, Cout;
+    int taps, splits;
+    int P;                 // pixels in the reduction
+};
+
+constexpr int kWgK = 32;
+
+template <int MODE>
+__global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t sA[64 * kLdsK];  // [ci][pixel]
+    __shared__ __attribute__((aligned(16))) uint16_t sB[64 * kLdsK];  // [co][pixel]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int co0 = blockIdx.x * 64, ci0 = blockIdx.y * 64;
+    const int tap = blockIdx.z % a.taps, split = blockIdx.z / a.taps;
+    const int per = (a.P + a.splits - 1) / a.splits;
+    const int p_begin = split * per, p_end = min(a.P, p_begin + per);
+    f32x16_t acc = {};
+    const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
+    // loader: thread -> (pixel tid / 8, 8 consecutive channels (tid % 8) * 8)
+    const int lp = tid >> 3, lc = (tid & 7) * 8;
+    for (int p0 = p_begin; p0 < p_end; p0 += kWgK) {
+        const int p = p0 + lp;
+        uint16_t va[8], vb[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) va[q] = vb[q] = 0;
+        if (p < p_end) {
+            // input pixel and gradient pixel of this reduction index
+            size_t ipix, gpix;
+            bool ok = true;
+            if constexpr (MODE == UP) {
+                const int x = p % a.Win, t1 = p / a.Win, y = t1 % a.Hin, img = t1 / a.Hin;
+                ipix = (size_t)p;
+                gpix = ((size_t)img * a.Hout + 2 * y + tap / 2) * a.Wout + 2 * x + tap % 2;
+            } else {
+                const int x = p % a.Wout, t1 = p / a.Wout, y = t1 % a.Hout, img = t1 / a.Hout;
+                int yy = y, xx = x;
+                if constexpr (MODE == CONV3) {
+                    yy = y + tap / 3 - 1;
+                    xx = x + tap % 3 - 1;
+                } else if constexpr (MODE == DOWN) {
+                    yy = 2 * y + tap / 2;
+                    xx = 2 * x + tap % 2;
+                }
+                ok = yy >= 0 && yy < a.Hin && xx >= 0 && xx < a.Win;
+                ipix = ((size_t)img * a.Hin + yy) * a.Win + xx;
+                gpix = (size_t)p;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int ci = ci0 + lc + q, co = co0 + lc + q;
+                if (ok && ci < a.Cin) va[q] = a.in[ipix * a.in_cs + a.in_co + ci];
+                if (co < a.Cout) {
+                    uint16_t g = a.dout[gpix * a.dout_cs + co];
+                    if (a.act) {
+                        const uint16_t h = a.act[gpix * a.act_cs + a.act_co + co];
+                        if (h == 0 || (h & 0x8000u)) g = 0;
+                    }
+                    vb[q] = g;
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            sA[(lc + q) * kLdsK + lp] = va[q];
+            sB[(lc + q) * kLdsK + lp] = vb[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int kk = s * 16 + 8 * (lane >> 5);
+            const bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sA + (wr + (lane & 31)) * kLdsK + kk));
+            const bf16x8_t bv = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (wc + (lane & 31)) * kLdsK + kk));
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
+        }
+    }
+    const int j = co0 + wc + (lane & 31);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int i = ci0 + wr + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+        if (i < a.Cin && j < a.Cout)
+            a.part[(((size_t)split * a.taps + tap) * a.Cin + i) * a.Cout + j] = acc[v];
+    }
+}
+
+// dW = sum over splits (fixed order); grid ceil(taps*Ci*Co / 256).
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, size_t count, float* __restrict__ dW) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part[(size_t)k * count + i];
+    dW[i] = s;
+}
+
+// Bias gradient partials: part[b][co] = sum over a pixel range of dZ[pix][co]
+// (ReLU mask from act when given); grid (nb), block 256, Cout <= 256.
+__global__ void __launch_bounds__(256)
+k_bias_partial(const uint16_t* __restrict__ dout, int cs, const uint16_t* __restrict__ act, int act_cs, int act_co,
+               int Cout, int P, int per, float* __restrict__ part) {
+    const int co = threadIdx.x;
+    const int p0 = blockIdx.x * per, p1 = min(P, p0 + per);
+    if (co >= Cout) return;
+    float s = 0.f;
+    for (int p = p0; p < p1; ++p) {
+        const uint16_t g = dout[(size_t)p * cs + co];
+        if (act) {
+            const uint16_t h = act[(size_t)p * act_cs + act_co + co];
+            if (h == 0 || (h & 0x8000u)) continue;
+        }
+        s += bf2f(g);
+    }
+    part[(size_t)blockIdx.x * Cout + co] = s;
+}
+
+__global__ void k_bias_reduce(const float* __restrict__ part, int nb, int Cout, float* __restrict__ db) {
+    const int co = blockIdx.x * blockDim.x + threadIdx.x;
+    if (co >= Cout) return;
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += part[(size_t)b * Cout + co];
+    db[co] = s;
+}
+
+// GEMM-order bf16 weights from float32 W[taps][Ci][Co]:
+//   kind 0: Bt[co][tap * Ci + ci] = W[tap][ci][co]            (forward CONV3 / DOWN / CONV1)
+//   kind 1: Bt[ci][tap * Co + co] = W[taps - 1 - tap][ci][co] (input gradient of CONV3, flipped)
+//   kind 2: Bt[tap][co][ci]       = W[tap][ci][co]            (forward UP)
+//   kind 3: Bt[tap][ci][co]       = W[tap][ci][co]            (input gradient of DOWN, as UP)
+//   kind 4: Bt[ci][tap * Co + co] = W[tap][ci][co]            (input gradient of UP / CONV1, as DOWN / CONV1)
+// Rows are padded with zeros to Kpad.
+__global__ void k_prep_weights(const float* __restrict__ W, int taps, int Ci, int Co, int kind, int Kpad,
+                               uint16_t* __restrict__ Bt) {
+    const size_t total = (kind == 2 || kind == 3) ? (size_t)taps * (kind == 2 ? Co : Ci) * Kpad
+                                                  : (size_t)(kind == 0 ? Co : Ci) * Kpad;
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const int k = (int)(i % Kpad);
+    const size_t row = i / Kpad;
+    float v = 0.f;
+    if (kind == 0) {
+        const int co = (int)row;
+        if (k < taps * Ci) v = W[((size_t)(k / Ci) * Ci + k % Ci) * Co + co];
+    } else if (kind == 1 || kind == 4) {
+        const int ci = (int)row;
+        if (k < taps * Co) {
+            const int tap = kind == 1 ? taps - 1 - k / Co : k / Co;
+            v = W[((size_t)tap * Ci + ci) * Co + k % Co];
+        }
+    } else if (kind == 2) {
+        const int tap = (int)(row / Co), co = (int)(row % Co);
+        if (k < Ci) v = W[((size_t)tap * Ci + k) * Co + co];
+    } else {
+        const int tap = (int)(row / Ci), ci = (int)(row % Ci);
+        if (k < Co) v = W[((size_t)tap * Ci + ci) * Co + k];
+    }
+    Bt[i] = f2bf(v);
+}
+
+}  // namespace mnf

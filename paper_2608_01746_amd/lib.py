@@ -29,6 +29,10 @@ class PtychoParamsC(ctypes.Structure):
                 ("graph", c_int32)]
 
 
+class UnetShapeC(ctypes.Structure):
+    _fields_ = [("H", c_int32), ("widths", c_int32 * 4)]
+
+
 class PtychoScanC(ctypes.Structure):
     _fields_ = [("O", c_void_p), ("My", c_int32), ("Mx", c_int32), ("P", c_void_p), ("Nw", c_int32),
                 ("I", c_void_p), ("Nd", c_int32), ("pos", POINTER(c_int32)), ("J", c_int32),
@@ -53,6 +57,15 @@ SIGNATURES = {
     "ptycho_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
                             POINTER(c_int32), c_int, c_int, c_float, c_int, c_double,
                             c_void_p, c_void_p, c_void_p, c_void_p]),
+    "unet_param_count": (ctypes.c_longlong, [POINTER(UnetShapeC)]),
+    "unet_forward": (c_int, [c_void_p, POINTER(UnetShapeC), c_void_p, c_void_p, c_float, c_int, c_void_p,
+                             c_void_p]),
+    "unet_train_step": (c_int, [c_void_p, POINTER(UnetShapeC), c_void_p, c_void_p, c_void_p, c_int, c_float,
+                                c_void_p, c_float, c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "mnf_conv2d": (c_int, [c_void_p, c_int, c_void_p, c_int, c_int, c_int, c_void_p, c_void_p, c_int, c_int,
+                           c_void_p, c_void_p]),
+    "mnf_conv2d_grad": (c_int, [c_void_p, c_int, c_void_p, c_int, c_int, c_int, c_void_p, c_int, c_void_p,
+                                c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "mnf_autotune": (c_int, [c_void_p, c_int, c_int, c_int, POINTER(c_double), c_void_p]),
     "mnf_set_variant": (c_int, [c_void_p, c_int, c_int]),
     "mnf_get_variant": (c_int, [c_void_p, c_int]),

@@ -12,7 +12,7 @@ HEADER = os.path.join(ROOT, "include", "mnfpty.h")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\**\s+\**(\w+)\s*\(", text, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?(?:\w+\s+)*\w+\**\s+\**(\w+)\s*\(", text, flags=re.M)))
 
 
 @pytest.fixture(scope="module")
