@@ -217,6 +217,41 @@ int mnf_conv2d_grad(mnf_ctx* ctx, int mode, const uint16_t* x, int n, int H, int
                     const uint16_t* dy, const uint16_t* act, uint16_t* dx, float* dW, float* db, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Warm-start support.
+ *
+ * detector_expose: synthetic detector exposures of clean intensities, for
+ * generating training and test data at scale (the forward model of the
+ * measurement, Methods: a bracket of exposures t_k of one pattern).
+ *   raw[j][k] = clip(rint(Poisson(scale * t_k * max(clean[j], 0)) + N(0, sigma_read^2)), 0, sat)
+ * clean device float [J][H][W]; t host float [K] (K <= 16); raw device uint16 [J][K][H][W].
+ * Random numbers come from the counter-based Philox4x32-10 generator keyed by
+ * `seed`, one counter per output element, so the result depends only on the
+ * seed and the element index.  Poisson draws use inversion below a mean of
+ * 12 and a rounded normal approximation above; normals use Box-Muller.
+ * Errors: MNF_EINVAL for null pointers, non-positive sizes, K > 16,
+ * negative scale or sigma_read, or sat outside (0, 65535]. */
+int detector_expose(mnf_ctx* ctx, const float* clean, int J, int H, int W, const float* t, int K, float scale,
+                    float sat, float sigma_read, unsigned long long seed, uint16_t* raw, void* stream);
+
+/* ptycho_stitch: starting object from predicted patches (amplitude, phase)
+ * of each scan window, averaged with the probe intensity as weight:
+ *   O[x] = sum_j |P(x - p_j)|^2 a_j(x - p_j) exp(i phi_j(x - p_j)) / sum_j |P(x - p_j)|^2
+ * over the windows covering x, and O[x] = 1 where the weight is zero.
+ * patches device float [J][Nw][Nw][2] (amplitude, phase; the network's output
+ * layout); P device c64 [Nw][Nw]; pos host int32 [J][2] (y, x) window corners;
+ * O device c64 [My][Mx], overwritten.  MNF_EINVAL for a window outside O. */
+int ptycho_stitch(mnf_ctx* ctx, const float* patches, const mnf_c64* P, int Nw, const int32_t* pos, int J,
+                  mnf_c64* O, int My, int Mx, void* stream);
+
+/* mnf_nrmse: normalised object error after the best complex scale,
+ *   min_gamma ||gamma O - O_true|| / ||O_true|| = sqrt(1 - |<O, O_true>|^2 / (||O||^2 ||O_true||^2)),
+ * over the n elements whose mask byte is non-zero (mask NULL = all), summed
+ * in float64.  O, O_true device c64 [n]; mask device uint8 [n] or NULL;
+ * out device double [1].  0 when O_true is zero on the mask; 1 when O is. */
+int mnf_nrmse(mnf_ctx* ctx, const mnf_c64* O, const mnf_c64* O_true, const uint8_t* mask, long long n,
+              double* out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Launch-shape tuning.  Every pattern pass is compiled in two shapes (rows:
  * the default lines per block or half as many; columns: 32 columns per block
  * or 16), giving four variants per detector size: bit 0 selects the row

@@ -177,3 +177,22 @@ def nrmse(O: np.ndarray, O_true: np.ndarray, mask: np.ndarray) -> float:
     b = O_true[mask]
     gamma = np.vdot(a, b) / np.vdot(a, a)
     return float(np.linalg.norm(gamma * a - b) / np.linalg.norm(b))
+
+
+def stitch(patches: np.ndarray, P: np.ndarray, pos: np.ndarray, shape) -> np.ndarray:
+    """Starting object from per-window (amplitude, phase) predictions
+    patches [J][Nw][Nw][2]: the |P|^2-weighted mean of a e^{i phi} over the
+    windows covering each pixel, 1 where the summed weight is zero.  This is
+    the warm-start reading of an extension the paper does not specify."""
+    Nw = P.shape[0]
+    num = np.zeros(shape, complex)
+    den = np.zeros(shape)
+    w = np.abs(P) ** 2
+    for j, (y, x) in enumerate(pos):
+        v = patches[j, ..., 0] * np.exp(1j * patches[j, ..., 1])
+        num[y:y + Nw, x:x + Nw] += w * v
+        den[y:y + Nw, x:x + Nw] += w
+    out = np.ones(shape, complex)
+    cov = den > 0
+    out[cov] = num[cov] / den[cov]
+    return out

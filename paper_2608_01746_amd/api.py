@@ -343,3 +343,61 @@ def conv2d_grad(mode: str, x: torch.Tensor, W: torch.Tensor, dy: torch.Tensor, a
                                    _ptr(dx), _ptr(dW), _ptr(db), _stream(x.device))
     _check(rc, ctx)
     return dx, dW, db
+
+
+def detector_expose(clean: torch.Tensor, t: Sequence[float], scale: float, sat: float, sigma_read: float,
+                    seed: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """uint16 exposure stack [J][K][H][W] of clean intensities [J][H][W] (Philox-keyed by seed)."""
+    _dev(clean, "clean", torch.float32, 3)
+    J, H, W = clean.shape
+    K = len(t)
+    if out is None:
+        out = torch.empty((J, K, H, W), dtype=torch.uint16, device=clean.device)
+    else:
+        _dev(out, "out", torch.uint16, 4)
+        if tuple(out.shape) != (J, K, H, W):
+            raise ValueError("out must have shape [J][K][H][W]")
+    tt = (ctypes.c_float * max(K, 1))(*[float(x) for x in t])
+    ctx = _ctx(clean.device)
+    rc = _L.load().detector_expose(ctx, _ptr(clean), J, H, W, tt, K, float(scale), float(sat), float(sigma_read),
+                                   int(seed) & 0xFFFFFFFFFFFFFFFF, _ptr(out), _stream(clean.device))
+    _check(rc, ctx)
+    return out
+
+
+def ptycho_stitch(patches: torch.Tensor, P: torch.Tensor, pos, shape, out: Optional[torch.Tensor] = None):
+    """Probe-intensity-weighted starting object [My][Mx] from patches [J][Nw][Nw][2] (amplitude, phase)."""
+    _dev(patches, "patches", torch.float32, 4)
+    _dev(P, "P", torch.complex64, 2)
+    posa = _host_i32(pos, (2,), "pos")
+    J, Nw = patches.shape[0], patches.shape[1]
+    if patches.shape[1:] != (Nw, Nw, 2) or tuple(P.shape) != (Nw, Nw) or posa.shape[0] != J:
+        raise ValueError("patches must be [J][Nw][Nw][2] with P [Nw][Nw] and J positions")
+    My, Mx = shape
+    if out is None:
+        out = torch.empty((My, Mx), dtype=torch.complex64, device=patches.device)
+    else:
+        _dev(out, "out", torch.complex64, 2)
+    ctx = _ctx(patches.device)
+    rc = _L.load().ptycho_stitch(ctx, _ptr(patches), _ptr(P), Nw, _i32p(posa), J, _ptr(out), My, Mx,
+                                 _stream(patches.device))
+    _check(rc, ctx)
+    return out
+
+
+def nrmse(O: torch.Tensor, O_true: torch.Tensor, mask: Optional[torch.Tensor] = None,
+          out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """float64 device scalar min_gamma ||gamma O - O_true|| / ||O_true|| over the mask."""
+    if not (O.is_cuda and O_true.is_cuda and O.dtype == torch.complex64 and O_true.dtype == torch.complex64):
+        raise ValueError("O and O_true must be complex64 CUDA tensors")
+    if O.shape != O_true.shape or not O.is_contiguous() or not O_true.is_contiguous():
+        raise ValueError("O and O_true must be contiguous and of one shape")
+    if mask is not None and (mask.dtype not in (torch.uint8, torch.bool) or mask.shape != O.shape
+                             or not mask.is_contiguous() or not mask.is_cuda):
+        raise ValueError("mask must be a contiguous uint8/bool CUDA tensor of O's shape")
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=O.device)
+    ctx = _ctx(O.device)
+    rc = _L.load().mnf_nrmse(ctx, _ptr(O), _ptr(O_true), _ptr(mask), O.numel(), _ptr(out), _stream(O.device))
+    _check(rc, ctx)
+    return out

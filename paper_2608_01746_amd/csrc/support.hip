@@ -1,0 +1,184 @@
+// Supporting kernels of the reconstruction workflow: detector exposures of a
+// clean intensity (synthetic data at scale), stitching of predicted object
+// patches into a starting object, and the object NRMSE.
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+#include "kernels_common.hpp"
+
+using namespace mnf;
+
+namespace {
+
+// Philox4x32-10 counter-based generator (Salmon, Moraes, Dror & Shaw, SC 2011):
+// ten rounds of two 32x32->64 multiplications on a 128-bit counter with a
+// 64-bit key bumped by the Weyl constants.
+__device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c = make_uint4(hi1 ^ c.y ^ k.x, lo1, hi0 ^ c.w ^ k.y, lo0);
+        k.x += 0x9E3779B9u;
+        k.y += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// uniform in (0, 1]
+__device__ __forceinline__ float u01(uint32_t v) { return ((float)(v >> 8) + 1.f) * (1.f / 16777216.f); }
+
+// counts = clip(rint(Poisson(scale t_k clean) + N(0, sigma^2)), 0, sat).
+// Poisson by inversion below lambda = 12, by a rounded normal above.
+__global__ void k_expose(const float* __restrict__ clean, int J, int K, size_t npix, const float* __restrict__ t,
+                         float scale, float sat, float sigma, uint2 key, uint16_t* __restrict__ raw) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)J * K * npix;
+    if (i >= total) return;
+    const size_t q = i % npix;
+    const size_t jk = i / npix;
+    const int k = (int)(jk % K);
+    const size_t j = jk / K;
+    const float lam = fmaxf(clean[j * npix + q], 0.f) * scale * t[k];
+    const uint4 r = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), 0u, 0u), key);
+    // r.x drives the Poisson inversion; r.z, r.w give two normals (Box-Muller).
+    const float u1 = u01(r.x), u3 = u01(r.z), u4 = u01(r.w);
+    const float rad = sqrtf(-2.f * logf(u3));
+    const float z1 = rad * cospif(2.f * u4), z2 = rad * sinpif(2.f * u4);
+    float c;
+    if (lam < 12.f) {
+        float p = expf(-lam), F = p;
+        int x = 0;
+        while (u1 > F && x < 64) {
+            ++x;
+            p *= lam / (float)x;
+            F += p;
+        }
+        c = (float)x;
+    } else {
+        c = rintf(lam + sqrtf(lam) * z1);
+    }
+    c = rintf(c + sigma * z2);
+    raw[i] = (uint16_t)fminf(fmaxf(c, 0.f), sat);
+}
+
+// O[x] = sum_j |P(u_j)|^2 amp_j(u_j) e^{i phase_j(u_j)} / sum_j |P(u_j)|^2 over the windows
+// containing x (u_j = x - p_j); 1 where no window (or only zero probe) covers x.
+__global__ void __launch_bounds__(256)
+k_stitch(const float* __restrict__ patches, const float2* __restrict__ P, const int2* __restrict__ pos, int J,
+         int Nw, float2* __restrict__ O, int My, int Mx) {
+    __shared__ int2 sp[256];
+    const int x = blockIdx.x * 16 + (threadIdx.x % 16);
+    const int y = blockIdx.y * 16 + (threadIdx.x / 16);
+    float2 num = make_float2(0.f, 0.f);
+    float den = 0.f;
+    for (int j0 = 0; j0 < J; j0 += 256) {
+        __syncthreads();
+        if (j0 + (int)threadIdx.x < J) sp[threadIdx.x] = pos[j0 + threadIdx.x];
+        __syncthreads();
+        const int nj = min(256, J - j0);
+        for (int jj = 0; jj < nj; ++jj) {
+            const int uy = y - sp[jj].x, ux = x - sp[jj].y;
+            if (uy < 0 || uy >= Nw || ux < 0 || ux >= Nw) continue;
+            const float w = cabs2(P[uy * Nw + ux]);
+            const float* pa = patches + (((size_t)(j0 + jj) * Nw + uy) * Nw + ux) * 2;
+            float s, c;
+            sincosf(pa[1], &s, &c);
+            num.x += w * pa[0] * c;
+            num.y += w * pa[0] * s;
+            den += w;
+        }
+    }
+    if (y < My && x < Mx) O[(size_t)y * Mx + x] = den > 0.f ? make_float2(num.x / den, num.y / den) : make_float2(1.f, 0.f);
+}
+
+// Per-block float64 sums over masked pixels: <O, T> (re, im), |O|^2, |T|^2.
+__global__ void __launch_bounds__(256)
+k_nrmse_part(const float2* __restrict__ O, const float2* __restrict__ T, const uint8_t* __restrict__ mask, size_t n,
+             double* __restrict__ part) {
+    __shared__ double red[4];
+    double s[4] = {0, 0, 0, 0};
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        if (mask && !mask[i]) continue;
+        const float2 o = O[i], t = T[i];
+        s[0] += (double)o.x * t.x + (double)o.y * t.y;
+        s[1] += (double)o.x * t.y - (double)o.y * t.x;
+        s[2] += (double)o.x * o.x + (double)o.y * o.y;
+        s[3] += (double)t.x * t.x + (double)t.y * t.y;
+    }
+    for (int c = 0; c < 4; ++c) {
+        const double v = block_sum(s[c], red);
+        if (threadIdx.x == 0) part[blockIdx.x * 4 + c] = v;
+        __syncthreads();
+    }
+}
+
+// min_gamma ||gamma O - T|| / ||T|| = sqrt(1 - |<O,T>|^2 / (|O|^2 |T|^2)).
+__global__ void k_nrmse_final(const double* __restrict__ part, int nb, double* __restrict__ out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s[4] = {0, 0, 0, 0};
+    for (int b = 0; b < nb; ++b)
+        for (int c = 0; c < 4; ++c) s[c] += part[b * 4 + c];
+    const double ip2 = s[0] * s[0] + s[1] * s[1];
+    double r = s[3] > 0.0 ? 1.0 - (s[2] > 0.0 ? ip2 / (s[2] * s[3]) : 0.0) : 0.0;
+    *out = sqrt(r > 0.0 ? r : 0.0);
+}
+
+}  // namespace
+
+extern "C" {
+
+int detector_expose(mnf_ctx* ctx, const float* clean, int J, int H, int W, const float* t, int K, float scale,
+                    float sat, float sigma_read, unsigned long long seed, uint16_t* raw, void* stream) {
+    MNF_TRY(begin(ctx));
+    if (!clean || !t || !raw || J <= 0 || H <= 0 || W <= 0 || K <= 0 || K > 16)
+        return set_error(ctx, MNF_EINVAL, "bad exposure arguments");
+    if (!(scale >= 0.f) || !(sat > 0.f) || !(sigma_read >= 0.f) || sat > 65535.f)
+        return set_error(ctx, MNF_EINVAL, "scale, sat and sigma_read must be non-negative (sat <= 65535)");
+    hipStream_t st = (hipStream_t)stream;
+    void* dt;
+    MNF_TRY(upload(ctx, "expose_t", t, sizeof(float) * K, st, &dt));
+    const size_t npix = (size_t)H * W, total = (size_t)J * K * npix;
+    const uint2 key = make_uint2((uint32_t)seed, (uint32_t)(seed >> 32));
+    MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_expose, dim3((unsigned)((total + 255) / 256)), dim3(256), clean, J, K, npix,
+               (const float*)dt, scale, sat, sigma_read, key, raw);
+    MNF_CHECK_LAUNCH(ctx);
+    return MNF_OK;
+}
+
+int ptycho_stitch(mnf_ctx* ctx, const float* patches, const mnf_c64* P, int Nw, const int32_t* pos, int J,
+                  mnf_c64* O, int My, int Mx, void* stream) {
+    MNF_TRY(begin(ctx));
+    if (!patches || !P || !pos || !O || J <= 0 || Nw <= 0 || My <= 0 || Mx <= 0)
+        return set_error(ctx, MNF_EINVAL, "bad stitching arguments");
+    for (int j = 0; j < J; ++j)
+        if (pos[2 * j] < 0 || pos[2 * j + 1] < 0 || pos[2 * j] + Nw > My || pos[2 * j + 1] + Nw > Mx)
+            return set_error(ctx, MNF_EINVAL, "window %d lies outside the object", j);
+    hipStream_t st = (hipStream_t)stream;
+    void* dpos;
+    MNF_TRY(upload(ctx, "stitch_pos", pos, sizeof(int32_t) * 2 * J, st, &dpos));
+    MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_stitch, dim3((Mx + 15) / 16, (My + 15) / 16), dim3(256), patches,
+               (const float2*)P, (const int2*)dpos, J, Nw, (float2*)O, My, Mx);
+    MNF_CHECK_LAUNCH(ctx);
+    return MNF_OK;
+}
+
+int mnf_nrmse(mnf_ctx* ctx, const mnf_c64* O, const mnf_c64* O_true, const uint8_t* mask, long long n, double* out,
+              void* stream) {
+    MNF_TRY(begin(ctx));
+    if (!O || !O_true || !out || n <= 0) return set_error(ctx, MNF_EINVAL, "bad NRMSE arguments");
+    hipStream_t st = (hipStream_t)stream;
+    const int nb = 256;
+    void* part;
+    MNF_TRY(scratch(ctx, "nrmse_part", (size_t)nb * 4 * sizeof(double), &part));
+    MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_nrmse_part, dim3(nb), dim3(256), (const float2*)O, (const float2*)O_true, mask,
+               (size_t)n, (double*)part);
+    MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_nrmse_final, dim3(1), dim3(64), (const double*)part, nb, out);
+    MNF_CHECK_LAUNCH(ctx);
+    return MNF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+"""Supporting kernels of the warm-start workflow on the GPU: synthetic
+detector exposures (statistics of the Philox-driven Poisson + Gaussian
+model), probe-weighted stitching of predicted patches and the float64
+NRMSE, the last two against the float64 oracle."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import ptycho
+from paper_2608_01746_amd import synth
+
+from _cases import c64
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_01746_amd import api as _api
+    return _api
+
+
+def _expose(api, lam, t, sat, sigma, seed, n=1 << 18):
+    clean = torch.full((1, 512, n // 512), float(lam), dtype=torch.float32, device=DEV)
+    raw = api.detector_expose(clean, t, 1.0, sat, sigma, seed)
+    torch.cuda.synchronize()
+    return raw.cpu().numpy().astype(np.float64).reshape(len(t), -1)
+
+
+@pytest.mark.parametrize("lam,sigma", [(0.5, 0.0), (3.0, 0.0), (11.5, 0.0), (12.5, 0.0), (12.5, 2.0),
+                                       (80.0, 2.0), (2000.0, 3.0)])
+def test_exposure_mean_and_variance(api, lam, sigma):
+    # sigma > 0 only where clipping at zero is negligible (mean >= 3 standard deviations)
+    c = _expose(api, lam, [1.0, 2.0], 65535, sigma, seed=11)
+    for k, tk in enumerate([1.0, 2.0]):
+        x = c[k]
+        m = lam * tk
+        v = m + sigma ** 2 + (1.0 / 12.0 if sigma > 0 else 0.0)
+        n = x.size
+        assert abs(x.mean() - m) < 5 * np.sqrt(v / n) + 0.01, (lam, tk, x.mean())
+        assert abs(x.var() / v - 1.0) < 0.03, (lam, tk, x.var(), v)
+    # the two exposures draw independent numbers
+    assert abs(np.corrcoef(c[0], c[1])[0, 1]) < 0.01
+
+
+def test_small_mean_is_exact_poisson(api):
+    lam = 0.5
+    x = _expose(api, lam, [1.0], 65535, 0.0, seed=3)[0]
+    n = x.size
+    for kval in range(4):
+        p = np.exp(-lam) * lam ** kval / np.prod(np.arange(1, kval + 1))
+        assert abs(np.mean(x == kval) - p) < 5 * np.sqrt(p * (1 - p) / n), kval
+
+
+def test_exposure_clips_and_is_seeded(api):
+    a = _expose(api, 3000.0, [1.0, 10.0], 4095, 2.0, seed=7, n=1 << 14)
+    assert a.max() == 4095 and a[0].max() < 4095 and a.min() >= 0
+    assert np.all(a[1] == 4095)
+    b = _expose(api, 3000.0, [1.0, 10.0], 4095, 2.0, seed=7, n=1 << 14)
+    assert np.array_equal(a, b)
+    c = _expose(api, 3000.0, [1.0, 10.0], 4095, 2.0, seed=8, n=1 << 14)
+    assert not np.array_equal(a[0], c[0])
+    z = _expose(api, 0.0, [1.0], 4095, 0.0, seed=7, n=1 << 14)
+    assert np.all(z == 0)
+
+
+def test_exposure_rejects_bad_arguments(api):
+    clean = torch.ones((1, 8, 8), device=DEV)
+    with pytest.raises(api.MnfError, match="MNF_EINVAL"):
+        api.detector_expose(clean, [1.0], 1.0, 70000.0, 1.0, 1)
+    with pytest.raises(api.MnfError, match="MNF_EINVAL"):
+        api.detector_expose(clean, [1.0], -1.0, 4095.0, 1.0, 1)
+
+
+@pytest.mark.parametrize("J,Nw,M", [(1, 16, 40), (37, 16, 64), (100, 64, 192)])
+def test_stitch_matches_oracle(api, J, Nw, M):
+    rng = np.random.default_rng(J)
+    pos = rng.integers(0, M - Nw + 1, size=(J, 2)).astype(np.int32)
+    P = c64(synth.make_probe(Nw, Nw / 4.0, np.pi))
+    patches = np.stack([rng.uniform(0.5, 1.0, (J, Nw, Nw)), rng.uniform(-1.5, 1.5, (J, Nw, Nw))], -1)
+    patches = patches.astype(np.float32).astype(np.float64)
+    want = ptycho.stitch(patches, P, pos, (M, M))
+    got = api.ptycho_stitch(torch.from_numpy(patches.astype(np.float32)).to(DEV),
+                            torch.from_numpy(P.astype(np.complex64)).to(DEV), pos, (M, M))
+    got = got.cpu().numpy()
+    # float32 sums of at most J weighted terms of size ~1
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-5
+    assert np.abs(got - want).max() < 5e-5
+
+
+def test_stitch_rejects_window_outside(api):
+    P = torch.ones((16, 16), dtype=torch.complex64, device=DEV)
+    patches = torch.zeros((1, 16, 16, 2), device=DEV)
+    with pytest.raises(api.MnfError, match="outside"):
+        api.ptycho_stitch(patches, P, [[30, 0]], (40, 40))
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_nrmse_matches_oracle(api, masked):
+    rng = np.random.default_rng(5)
+    T = c64(synth.make_object(300, 4))
+    O = c64(T * 1.7 * np.exp(0.4j) + 0.05 * (rng.standard_normal(T.shape) + 1j * rng.standard_normal(T.shape)))
+    mask = rng.random(T.shape) < 0.6 if masked else np.ones(T.shape, bool)
+    want = ptycho.nrmse(O, T, mask)
+    got = api.nrmse(torch.from_numpy(O.astype(np.complex64)).to(DEV),
+                    torch.from_numpy(T.astype(np.complex64)).to(DEV),
+                    torch.from_numpy(mask.astype(np.uint8)).to(DEV) if masked else None).item()
+    assert abs(got - want) <= 1e-9 * want
+    # degenerate cases: identical inputs give 0, orthogonal inputs give 1
+    Tt = torch.from_numpy(T.astype(np.complex64)).to(DEV)
+    assert api.nrmse(Tt, Tt).item() < 1e-6
+    a = torch.zeros(8, dtype=torch.complex64, device=DEV)
+    b = torch.zeros(8, dtype=torch.complex64, device=DEV)
+    a[:4] = 1
+    b[4:] = 1
+    assert abs(api.nrmse(b, a).item() - 1.0) < 1e-15

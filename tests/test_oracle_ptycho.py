@@ -174,3 +174,45 @@ def test_batch_of_one_is_textbook_rpie_with_soft_probe():
         Pc = Pc + np.conj(Oj) * d / ((1 - b) * O2 + b * O2.max())
     np.testing.assert_allclose(Oa, O, atol=1e-12)
     np.testing.assert_allclose(Pa, Pc, atol=1e-12)
+
+
+def test_nrmse_closed_forms():
+    # orthogonal estimate: nothing to align, error 1; half-and-half mixture: sqrt(1/2)
+    T = np.zeros(8, complex)
+    T[:4] = 1.0
+    O = np.zeros(8, complex)
+    O[4:] = 1.0
+    m = np.ones(8, bool)
+    assert abs(ptycho.nrmse(O, T, m) - 1.0) < 1e-15
+    assert abs(ptycho.nrmse(T + O, T, m) - np.sqrt(0.5)) < 1e-15
+    # the mask removes pixels entirely
+    m2 = np.arange(8) < 4
+    assert ptycho.nrmse(T + O, T, m2) < 1e-15
+
+
+def test_stitch_reproduces_truth_and_fills_uncovered():
+    O, P, pos = _tiny_geometry()
+    Nw = P.shape[0]
+    patches = np.stack([np.stack([np.abs(O[y:y + Nw, x:x + Nw]), np.angle(O[y:y + Nw, x:x + Nw])], -1)
+                        for y, x in pos])
+    S = ptycho.stitch(patches, P, pos, O.shape)
+    cov = np.zeros(O.shape)
+    for y, x in pos:
+        cov[y:y + Nw, x:x + Nw] += np.abs(P) ** 2
+    assert np.abs(S - O)[cov > 0].max() < 1e-12
+    assert np.all(S[cov == 0] == 1.0)
+
+
+def test_stitch_weighted_mean_by_hand():
+    # two 2x2 windows overlapping in one column; probe intensities 1 and 4
+    P = np.array([[1.0, 2.0], [1.0, 2.0]], complex)
+    pos = np.array([[0, 0], [0, 1]])
+    patches = np.zeros((2, 2, 2, 2))
+    patches[0, ..., 0] = 2.0
+    patches[1, ..., 0] = 1.0
+    patches[1, ..., 1] = np.pi / 2
+    S = ptycho.stitch(patches, P, pos, (2, 4))
+    # column 0: window 0 only (u=0, w=1) -> 2; column 1: window 0 at u=1 (w=4, value 2)
+    # and window 1 at u=0 (w=1, value i) -> (8 + i) / 5; column 2: window 1 only -> i; column 3: 1
+    want = np.array([2.0, (8 + 1j) / 5, 1j, 1.0])
+    assert np.abs(S - want[None, :]).max() < 1e-15
