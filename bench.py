@@ -19,6 +19,12 @@ advanced by one ptycho_iterate_many call captured in a hipGraph.  Its
 intensities come straight from the forward model (no noise or fusion), which
 does not change the reconstruction's work.
 
+--workload warmstart measures the second half of the headline metric:
+time to object NRMSE 1e-2 from the U-Net's stitched start versus a flat
+start (t_plain / t_warm), after training the network on 50,000 simulated
+fused patterns (training time reported separately, excluded).  Its roofline
+entry is the network's forward pass in TFLOP/s against the bf16 MFMA peak.
+
 Roofline: achieved = (algorithmic bytes per position update, 20 N^2 + 16 N^2 / B)
 x (positions one launch of the dominant kernel processes) / (its mean launch
 duration, HIP events on the launch stream over the timed region).  traffic =
@@ -166,15 +172,18 @@ def run_lab(args, api, synth, dev):
     Pw = torch.empty_like(P0)
     fused = torch.empty((w.J, w.Nd, w.Nd), dtype=torch.float32, device=dev)
     state = {}
+    graph = False
 
     def step():
         O.copy_(O0)
         Pw.copy_(P0)
         api.fuse_exposures(raw, w.t, w.levels, sat=float(w.sat), delta=delta, out=fused)
         state["err"] = api.ptycho_iterate(O, Pw, fused, w.pos, n_iter, alg="rpie", alpha=0.1, beta=0.1,
-                                          batch=w.batch, update_probe=True, probe_start_iter=5, order=order)
+                                          batch=w.batch, update_probe=True, probe_start_iter=5, order=order,
+                                          graph=graph)
 
     dominant, ranks = profile_dominant(api, step, PASSES)
+    graph = args.graph
     print("# per-class ms (warm-up step): " +
           ", ".join(f"{k} {v[1]:.2f} ({v[0]})" for k, v in ranks.items()), file=sys.stderr, flush=True)
     for _ in range(args.warmup - 1):
@@ -188,8 +197,11 @@ def run_lab(args, api, synth, dev):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    nlaunch, kms = api.profile_read()[dominant]
+    prof = api.profile_read()
     api.profile([])
+    # inside a captured graph no per-launch events are recorded: take them
+    # from the direct-launch warm-up step instead
+    nlaunch, kms = ranks[dominant] if graph else prof[dominant]
     dt = (t1 - t0) / args.steps
     value = w.J * n_iter / dt
     per_launch = w.J / math.ceil(w.J / w.batch)
@@ -213,6 +225,7 @@ def run_lab(args, api, synth, dev):
         "roofline": roofline(dominant, nlaunch, kms, per_launch, w.Nd, w.batch),
         "per_class_ms_one_step": {k: round(v[1], 3) for k, v in ranks.items()},
         "launch_variants": tuned,
+        "graph": graph,
         "final_fourier_error": float(state["err"][-1].item()),
     }
     if not args.no_cpu:
@@ -295,17 +308,151 @@ def run_multiscan(args, api, synth, dev):
     }
 
 
+def run_warmstart(args, api, synth, dev):
+    """Learned warm start on the small geometry with a 256^2 detector: train
+    the U-Net (excluded from the timed comparison), then for ten test objects
+    time reaching object NRMSE 1e-2 from the network's stitched start and from
+    a flat start.  The threshold is taken on noise-free patterns (see the
+    note in the output); on MNF-fused noisy patterns the NRMSE reached after
+    the same iteration budgets is reported beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2608_01746_amd import warmstart as ws
+
+    S = ws.setup()
+    params = ws.init_params(ws.WIDTHS, 0, dev)
+    train_info = None
+    if args.params_in:
+        params.copy_(torch.from_numpy(np.load(args.params_in)).to(dev))
+    else:
+        tr = ws.simulate(S, range(5000, 5000 + args.train_objects), "fused", dev, relative=True)
+        print(f"# training on {tr['I'].shape[0]} fused patterns for up to {args.train_seconds:.0f} s",
+              file=sys.stderr, flush=True)
+        train_info = ws.train(S, tr, params, epochs=args.epochs, time_budget=args.train_seconds,
+                              log=lambda m: print("# " + m, file=sys.stderr, flush=True)
+                              if m.split()[1].endswith("000") else None)
+        del tr
+        torch.cuda.empty_cache()
+    if args.params_out:
+        np.save(args.params_out, params.cpu().numpy())
+    # inference throughput of the dominant kernels (one launch sequence per 100 patterns)
+    te_clean = ws.simulate(S, range(9000, 9010), "clean", dev)
+    I100 = te_clean["I"][:100]
+    out = torch.empty((100, S.w.Nw, S.w.Nw, 2), dtype=torch.float32, device=dev)
+    for _ in range(2):
+        api.unet_forward(params, I100, S.log_scale, ws.H, ws.WIDTHS, out=out)
+    t_inf = min(ws._elapsed(lambda: api.unet_forward(params, I100, S.log_scale, ws.H, ws.WIDTHS, out=out), dev)
+                for _ in range(5))
+    fwd_flops = sum(ws.layer_flops(ws.H, ws.WIDTHS))
+    infer_tfs = 100 * fwd_flops / t_inf / 1e12
+    res_c = ws.time_to_threshold(S, te_clean, params, tau=1e-2, max_plain=200, max_warm=50, sync=True)
+    te_f = ws.simulate(S, range(9000, 9010), "fused", dev)
+    res_f = ws.time_to_threshold(S, te_f, params, tau=1e-2, max_plain=200, max_warm=50, sync=True)
+    both = [r for r in res_c if r.get("t_warm") is not None and r.get("t_plain") is not None]
+    ratio = (sum(r["t_plain"] for r in both) / sum(r["t_warm"] for r in both)) if both else None
+    med = lambda xs: float(np.median(xs)) if xs else None
+    per_obj = [{"n_plain": r["n_plain"], "n_warm": r.get("n_warm"), "nrmse_start": round(r["nrmse_init"], 4),
+                "t_plain_ms": None if r.get("t_plain") is None else round(r["t_plain"] * 1e3, 3),
+                "t_warm_ms": None if r.get("t_warm") is None else round(r["t_warm"] * 1e3, 3)} for r in res_c]
+    fused = {"nrmse_flat_start": round(med([r["plain_curve"][0] for r in res_f]), 4),
+             "nrmse_warm_start": round(med([r["warm_curve"][0] for r in res_f]), 4),
+             "nrmse_plain_200": round(med([r["plain_curve"][-1] for r in res_f]), 4),
+             "nrmse_plain_best": round(med([min(r["plain_curve"]) for r in res_f]), 4),
+             "nrmse_warm_50": round(med([r["warm_curve"][-1] for r in res_f]), 4)}
+    t_iter = med([r["t_iter"] for r in res_c])
+    out_json = {
+        "metric": "time-to-NRMSE 1e-2, warm vs plain (t_plain / t_warm)",
+        "value": None if ratio is None else round(ratio, 3),
+        "unit": "x",
+        "n_gpus": 1,
+        "steps": len(res_c),
+        "warmup": 1,
+        "ms_per_step": None if not both else round(1e3 * sum(r["t_warm"] for r in both) / len(both), 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16 network (f32 accumulate), f32 iterations",
+        "data": "synthetic (seeded objects 5000.. for training, 9000..9009 for test)",
+        "config": {"workload": "warm-start: 192^2 object, 64^2 probe r=16 known, 100 raster positions, "
+                               "256^2 detector, rPIE B=10; U-Net 32/64/128/256 on 256^2 log patterns, "
+                               "window-relative phase labels, phase-aligned stitching",
+                   "threshold": 1e-2, "max_plain": 200, "max_warm": 50,
+                   "objects_reaching_in_both": len(both)},
+        "roofline": {"bound": "mfma", "kernel": "U-Net forward (100 patterns)", "achieved": round(infer_tfs, 1),
+                     "peak": 2500.0, "unit": "TFLOP/s", "frac": round(infer_tfs / 2500.0, 4), "traffic": None,
+                     "flops_per_launch_sequence": 100 * fwd_flops, "seconds": round(t_inf, 6)},
+        "t_iter_ms": round(t_iter * 1e3, 4),
+        "t_start_ms": round(med([r["t_start"] for r in res_c]) * 1e3, 3),
+        "n_plain_median": med([r["n_plain"] for r in res_c if r["n_plain"] is not None]),
+        "n_warm_median": med([r["n_warm"] for r in res_c if r.get("n_warm") is not None]),
+        "per_object": per_obj,
+        "fused_noisy_patterns": fused,
+        "note": "MNF-fused patterns of this detector model hold every reconstruction at NRMSE ~0.2 (fusion "
+                "deviation), so the 1e-2 threshold is timed on the noise-free patterns the fusion returns in "
+                "the unsaturated, noise-free limit; the network is trained on fused noisy patterns only. "
+                "t_warm = network inference + aligned stitching + n_warm iterations, one event-timed run; "
+                "t_plain = n_plain iterations from a flat start, one event-timed run",
+    }
+    if train_info is not None:
+        tf = train_info["samples_per_s"] * ws.train_flops_per_sample(ws.H, ws.WIDTHS) / 1e12
+        out_json["training"] = {"samples": train_info["steps"] * 64, "seconds": round(train_info["seconds"], 1),
+                                "samples_per_s": round(train_info["samples_per_s"], 1),
+                                "tflops": round(tf, 1), "final_loss": train_info["history"][-1][1]
+                                if train_info["history"] else None}
+    if not args.no_cpu:
+        out_json["cpu_baseline"] = warm_cpu_baseline(S, te_clean, args.cpu_seconds)
+    return out_json
+
+
+def warm_cpu_baseline(S, data, seconds):
+    """The float64 oracle's plain rPIE on the first test object: seconds per
+    iteration over a bounded number of iterations, scaled to that object's
+    iteration count to NRMSE 1e-2."""
+    import numpy as np
+
+    from oracle import ptycho as optycho
+    w = S.w
+    J = len(S.pos)
+    I = data["I"][:J].cpu().numpy().astype(np.float64)
+    s = data["scales"][0]
+    O_true = data["objects"][0]
+    mask = optycho.illumination_mask(S.P, S.pos, O_true.shape)
+    prm = optycho.PtychoParams(alg="rpie", alpha=0.1, batch=w.batch, update_probe=False)
+    O = np.ones_like(O_true)
+    P = np.sqrt(s) * S.P
+    t0 = time.perf_counter()
+    it = 0
+    reached = None
+    while time.perf_counter() - t0 < seconds and it < 200:
+        O, _, _ = optycho.iterate(O, P, I, S.pos, 1, prm, it0=it)
+        it += 1
+        if optycho.nrmse(O, O_true, mask) <= 1e-2:
+            reached = it
+            break
+    dt = (time.perf_counter() - t0) / it
+    return {"value": round(dt * (reached if reached else it), 3), "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": f"plain rPIE to NRMSE 1e-2 on test object 9000 in float64 NumPy: {it} iterations "
+                      f"({'reached' if reached else 'not reached'}), {dt * 1e3:.0f} ms each"}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=None, help="iterations per step (200 lab, 20 multiscan)")
-    ap.add_argument("--workload", choices=["lab", "multiscan"], default="lab")
+    ap.add_argument("--workload", choices=["lab", "multiscan", "warmstart"], default="lab")
+    ap.add_argument("--train-seconds", type=float, default=240.0, help="warm start: training time budget")
+    ap.add_argument("--train-objects", type=int, default=500, help="warm start: training objects x 100 patterns")
+    ap.add_argument("--epochs", type=float, default=100.0, help="warm start: epoch cap")
+    ap.add_argument("--params-in", default=None, help="warm start: load trained parameters (.npy) instead")
+    ap.add_argument("--params-out", default=None, help="warm start: save the trained parameters (.npy)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="keep the default launch shapes instead of the tuned ones")
+    ap.add_argument("--graph", action="store_true", help="lab: capture each step's iterations in a hipGraph")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 256 MiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()
@@ -326,7 +473,8 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    out = run_lab(args, api, synth, dev) if args.workload == "lab" else run_multiscan(args, api, synth, dev)
+    run = {"lab": run_lab, "multiscan": run_multiscan, "warmstart": run_warmstart}[args.workload]
+    out = run(args, api, synth, dev)
     print(json.dumps(out))
     return 0
 

@@ -235,13 +235,20 @@ int detector_expose(mnf_ctx* ctx, const float* clean, int J, int H, int W, const
 
 /* ptycho_stitch: starting object from predicted patches (amplitude, phase)
  * of each scan window, averaged with the probe intensity as weight:
- *   O[x] = sum_j |P(x - p_j)|^2 a_j(x - p_j) exp(i phi_j(x - p_j)) / sum_j |P(x - p_j)|^2
+ *   O[x] = sum_j |P(x - p_j)|^2 c_j a_j(x - p_j) exp(i phi_j(x - p_j)) / sum_j |P(x - p_j)|^2
  * over the windows covering x, and O[x] = 1 where the weight is zero.
+ * A single far-field pattern fixes its window only up to a constant phase,
+ * so with sync != 0 the unit phasors c_j are chosen to align overlapping
+ * windows: the leading eigenvector (200 power iterations from all ones) of
+ *   C_jk = sum over the overlap of |P_j|^2 |P_k|^2 conj(z_j) z_k,  z = a e^{i phi},
+ * projected to unit modulus, with sum_j c_j real and positive (J <= 1024).
+ * With sync == 0, c_j = 1.
  * patches device float [J][Nw][Nw][2] (amplitude, phase; the network's output
  * layout); P device c64 [Nw][Nw]; pos host int32 [J][2] (y, x) window corners;
- * O device c64 [My][Mx], overwritten.  MNF_EINVAL for a window outside O. */
+ * O device c64 [My][Mx], overwritten.  MNF_EINVAL for a window outside O or
+ * J > 1024 with sync. */
 int ptycho_stitch(mnf_ctx* ctx, const float* patches, const mnf_c64* P, int Nw, const int32_t* pos, int J,
-                  mnf_c64* O, int My, int Mx, void* stream);
+                  int sync, mnf_c64* O, int My, int Mx, void* stream);
 
 /* mnf_nrmse: normalised object error after the best complex scale,
  *   min_gamma ||gamma O - O_true|| / ||O_true|| = sqrt(1 - |<O, O_true>|^2 / (||O||^2 ||O_true||^2)),

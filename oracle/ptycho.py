@@ -179,18 +179,61 @@ def nrmse(O: np.ndarray, O_true: np.ndarray, mask: np.ndarray) -> float:
     return float(np.linalg.norm(gamma * a - b) / np.linalg.norm(b))
 
 
-def stitch(patches: np.ndarray, P: np.ndarray, pos: np.ndarray, shape) -> np.ndarray:
+def window_values(patches: np.ndarray) -> np.ndarray:
+    """Complex window values a e^{i phi} from (amplitude, phase) patches."""
+    return patches[..., 0] * np.exp(1j * patches[..., 1])
+
+
+def phase_sync(patches: np.ndarray, P: np.ndarray, pos: np.ndarray, shape) -> np.ndarray:
+    """Unit phasors c_j that align overlapping window predictions z_j (each
+    known only up to its own constant phase): the maximiser of
+    sum_x |sum_j w_j(x) c_j z_j(x)|^2 over |c_j| = 1, relaxed to the leading
+    eigenvector of the positive semidefinite matrix
+        C_jk = sum_x w_j(x) w_k(x) conj(z_j(x)) z_k(x),  w_j = |P(x - p_j)|^2,
+    each entry then projected to unit modulus (Singer's eigenvector method for
+    angular synchronisation).  The common phase is fixed by making sum_j c_j
+    real and positive.  A reading of the warm-start extension, which the
+    paper does not contain."""
+    Nw = P.shape[0]
+    J = len(pos)
+    w = np.abs(P) ** 2
+    z = window_values(patches)
+    C = np.zeros((J, J), complex)
+    for j in range(J):
+        for k in range(J):
+            y0 = max(pos[j][0], pos[k][0])
+            y1 = min(pos[j][0], pos[k][0]) + Nw
+            x0 = max(pos[j][1], pos[k][1])
+            x1 = min(pos[j][1], pos[k][1]) + Nw
+            if y1 <= y0 or x1 <= x0:
+                continue
+            sj = (slice(y0 - pos[j][0], y1 - pos[j][0]), slice(x0 - pos[j][1], x1 - pos[j][1]))
+            sk = (slice(y0 - pos[k][0], y1 - pos[k][0]), slice(x0 - pos[k][1], x1 - pos[k][1]))
+            C[j, k] = np.sum(w[sj] * w[sk] * np.conj(z[j][sj]) * z[k][sk])
+    vals, vecs = np.linalg.eigh(C)
+    v = vecs[:, -1]
+    c = np.where(np.abs(v) > 0, v / np.where(np.abs(v) > 0, np.abs(v), 1.0), 1.0)
+    s = np.sum(c)
+    if abs(s) > 0:
+        c = c * np.conj(s) / abs(s)
+    return c
+
+
+def stitch(patches: np.ndarray, P: np.ndarray, pos: np.ndarray, shape,
+           phasors: Optional[np.ndarray] = None) -> np.ndarray:
     """Starting object from per-window (amplitude, phase) predictions
-    patches [J][Nw][Nw][2]: the |P|^2-weighted mean of a e^{i phi} over the
-    windows covering each pixel, 1 where the summed weight is zero.  This is
-    the warm-start reading of an extension the paper does not specify."""
+    patches [J][Nw][Nw][2]: the |P|^2-weighted mean of c_j a e^{i phi} over
+    the windows covering each pixel (c_j = 1 unless phasors are given), 1
+    where the summed weight is zero.  This is the warm-start reading of an
+    extension the paper does not specify."""
     Nw = P.shape[0]
     num = np.zeros(shape, complex)
     den = np.zeros(shape)
     w = np.abs(P) ** 2
+    z = window_values(patches)
     for j, (y, x) in enumerate(pos):
-        v = patches[j, ..., 0] * np.exp(1j * patches[j, ..., 1])
-        num[y:y + Nw, x:x + Nw] += w * v
+        cj = 1.0 if phasors is None else phasors[j]
+        num[y:y + Nw, x:x + Nw] += w * cj * z[j]
         den[y:y + Nw, x:x + Nw] += w
     out = np.ones(shape, complex)
     cov = den > 0

@@ -365,8 +365,10 @@ def detector_expose(clean: torch.Tensor, t: Sequence[float], scale: float, sat: 
     return out
 
 
-def ptycho_stitch(patches: torch.Tensor, P: torch.Tensor, pos, shape, out: Optional[torch.Tensor] = None):
-    """Probe-intensity-weighted starting object [My][Mx] from patches [J][Nw][Nw][2] (amplitude, phase)."""
+def ptycho_stitch(patches: torch.Tensor, P: torch.Tensor, pos, shape, sync: bool = False,
+                  out: Optional[torch.Tensor] = None):
+    """Probe-intensity-weighted starting object [My][Mx] from patches [J][Nw][Nw][2] (amplitude, phase);
+    with sync, each window's constant phase is first aligned with its neighbours."""
     _dev(patches, "patches", torch.float32, 4)
     _dev(P, "P", torch.complex64, 2)
     posa = _host_i32(pos, (2,), "pos")
@@ -379,8 +381,8 @@ def ptycho_stitch(patches: torch.Tensor, P: torch.Tensor, pos, shape, out: Optio
     else:
         _dev(out, "out", torch.complex64, 2)
     ctx = _ctx(patches.device)
-    rc = _L.load().ptycho_stitch(ctx, _ptr(patches), _ptr(P), Nw, _i32p(posa), J, _ptr(out), My, Mx,
-                                 _stream(patches.device))
+    rc = _L.load().ptycho_stitch(ctx, _ptr(patches), _ptr(P), Nw, _i32p(posa), J, 1 if sync else 0, _ptr(out),
+                                 My, Mx, _stream(patches.device))
     _check(rc, ctx)
     return out
 

@@ -231,6 +231,7 @@ struct WgradArgs {
     const uint16_t* act;   // layer output for the ReLU mask, or null
     int act_cs, act_co;
     float* part;           // [splits][taps][Ci][Co]
+    float* bpart;          // [splits][btaps][Co]: bias-gradient partials (btaps = 4 for UP, else 1)
     int n, Hin, Win, Cin, Hout, Wout, Cout;
     int taps, splits;
     int P;                 // pixels in the reduction
@@ -238,7 +239,9 @@ struct WgradArgs {
 
 constexpr int kWgK = 32;
 
-template <int MODE>
+// VEC: 16-byte loads of 8 channels; needs channel strides and offsets that are
+// multiples of 8 (the partial last group of channels falls back to scalar loads).
+template <int MODE, bool VEC>
 __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
     __shared__ __attribute__((aligned(16))) uint16_t sA[64 * kLdsK];  // [ci][pixel]
     __shared__ __attribute__((aligned(16))) uint16_t sB[64 * kLdsK];  // [co][pixel]
@@ -251,9 +254,14 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
     // loader: thread -> (pixel tid / 8, 8 consecutive channels (tid % 8) * 8)
     const int lp = tid >> 3, lc = (tid & 7) * 8;
+    // The bias gradient is the sum of the masked output gradient over the pixels:
+    // blocks of the first input-channel tile add up the dout values they load
+    // (every tap for UP, whose taps cover disjoint output pixels; tap 0 otherwise).
+    const bool do_bias = blockIdx.y == 0 && (MODE == UP || tap == 0);
+    float bsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int p0 = p_begin; p0 < p_end; p0 += kWgK) {
         const int p = p0 + lp;
-        uint16_t va[8], vb[8];
+        uint16_t va[8] __attribute__((aligned(16))), vb[8] __attribute__((aligned(16)));
 #pragma unroll
         for (int q = 0; q < 8; ++q) va[q] = vb[q] = 0;
         if (p < p_end) {
@@ -278,19 +286,41 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
                 ipix = ((size_t)img * a.Hin + yy) * a.Win + xx;
                 gpix = (size_t)p;
             }
+            const int cia = ci0 + lc, cob = co0 + lc;
+            if (VEC && cia + 8 <= a.Cin) {
+                if (ok) *(uint4*)va = *(const uint4*)(a.in + ipix * a.in_cs + a.in_co + cia);
+            } else {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int ci = ci0 + lc + q, co = co0 + lc + q;
-                if (ok && ci < a.Cin) va[q] = a.in[ipix * a.in_cs + a.in_co + ci];
-                if (co < a.Cout) {
-                    uint16_t g = a.dout[gpix * a.dout_cs + co];
-                    if (a.act) {
-                        const uint16_t h = a.act[gpix * a.act_cs + a.act_co + co];
-                        if (h == 0 || (h & 0x8000u)) g = 0;
+                for (int q = 0; q < 8; ++q)
+                    if (ok && cia + q < a.Cin) va[q] = a.in[ipix * a.in_cs + a.in_co + cia + q];
+            }
+            if (VEC && cob + 8 <= a.Cout) {
+                *(uint4*)vb = *(const uint4*)(a.dout + gpix * a.dout_cs + cob);
+                if (a.act) {
+                    const uint4 h4 = *(const uint4*)(a.act + gpix * a.act_cs + a.act_co + cob);
+                    const uint16_t* h = (const uint16_t*)&h4;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q)
+                        if (h[q] == 0 || (h[q] & 0x8000u)) vb[q] = 0;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int co = cob + q;
+                    if (co < a.Cout) {
+                        uint16_t g = a.dout[gpix * a.dout_cs + co];
+                        if (a.act) {
+                            const uint16_t h = a.act[gpix * a.act_cs + a.act_co + co];
+                            if (h == 0 || (h & 0x8000u)) g = 0;
+                        }
+                        vb[q] = g;
                     }
-                    vb[q] = g;
                 }
             }
+        }
+        if (do_bias) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) bsum[q] += bf2f(vb[q]);
         }
         __syncthreads();
 #pragma unroll
@@ -314,6 +344,91 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
         if (i < a.Cin && j < a.Cout)
             a.part[(((size_t)split * a.taps + tap) * a.Cin + i) * a.Cout + j] = acc[v];
     }
+    if (do_bias) {
+        // sum the 32 pixel rows of each channel in a fixed order
+        __shared__ float bred[kGemmThreads * 8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bred[tid * 8 + q] = bsum[q];
+        __syncthreads();
+        if (tid < 64 && co0 + tid < a.Cout) {
+            const int gi = tid >> 3, q = tid & 7;
+            float r = 0.f;
+            for (int l = 0; l < kGemmThreads / 8; ++l) r += bred[((l << 3) + gi) * 8 + q];
+            const int bt = MODE == UP ? tap : 0;
+            a.bpart[((size_t)split * (MODE == UP ? 4 : 1) + bt) * a.Cout + co0 + tid] = r;
+        }
+    }
+}
+
+// Weight and bias gradient of a 3x3 convolution with one input channel (the
+// first layer): thread t owns output channels 8 (t % G) .. + 7 (G = Cout / 8)
+// and every (256 / G)-th pixel of the block's range, and accumulates all nine
+// taps and the bias; lanes are summed by wave shuffles and then across waves
+// in a fixed order.  part [blocks][9][Cout], bpart [blocks][Cout].
+// Needs Cout a multiple of 8 dividing 256 / 8, and 16-byte aligned dout rows.
+__global__ void __launch_bounds__(256) k_wgrad_c1(WgradArgs a, int per) {
+    __shared__ float red[4][10][256];
+    const int G = a.Cout / 8;
+    const int g = threadIdx.x % G, pl = threadIdx.x / G, lanes = 256 / G;
+    const int p0 = blockIdx.x * per, p1 = min(a.P, p0 + per);
+    float acc[10][8];
+#pragma unroll
+    for (int t = 0; t < 10; ++t)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[t][q] = 0.f;
+    for (int p = p0 + pl; p < p1; p += lanes) {
+        const uint4 d4 = *(const uint4*)(a.dout + (size_t)p * a.dout_cs + 8 * g);
+        uint16_t dv[8] __attribute__((aligned(16)));
+        *(uint4*)dv = d4;
+        if (a.act) {
+            const uint4 h4 = *(const uint4*)(a.act + (size_t)p * a.act_cs + a.act_co + 8 * g);
+            const uint16_t* h = (const uint16_t*)&h4;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (h[q] == 0 || (h[q] & 0x8000u)) dv[q] = 0;
+        }
+        float d[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) d[q] = bf2f(dv[q]);
+        const int x = p % a.Wout, t1 = p / a.Wout, y = t1 % a.Hout, img = t1 / a.Hout;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+            float v = 0.f;
+            if (yy >= 0 && yy < a.Hin && xx >= 0 && xx < a.Win)
+                v = bf2f(a.in[(((size_t)img * a.Hin + yy) * a.Win + xx) * a.in_cs + a.in_co]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q) acc[t][q] += v * d[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) acc[9][q] += d[q];
+    }
+    // lanes of one wave with the same channel group differ by multiples of G
+    // (G a power of two <= 32): butterfly over the higher lane bits
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int t = 0; t < 10; ++t)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            float v = acc[t][q];
+            for (int o = G; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+            acc[t][q] = v;
+        }
+    if (lane < G) {
+#pragma unroll
+        for (int t = 0; t < 10; ++t)
+#pragma unroll
+            for (int q = 0; q < 8; ++q) red[w][t][lane * 8 + q] = acc[t][q];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 10 * a.Cout; i += 256) {
+        const int t = i / a.Cout, c = i % a.Cout;
+        const float r = red[0][t][c] + red[1][t][c] + red[2][t][c] + red[3][t][c];
+        if (t < 9)
+            a.part[((size_t)blockIdx.x * 9 + t) * a.Cout + c] = r;
+        else
+            a.bpart[(size_t)blockIdx.x * a.Cout + c] = r;
+    }
 }
 
 // dW = sum over splits (fixed order); grid ceil(taps*Ci*Co / 256).
@@ -325,26 +440,7 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, size_
     dW[i] = s;
 }
 
-// Bias gradient partials: part[b][co] = sum over a pixel range of dZ[pix][co]
-// (ReLU mask from act when given); grid (nb), block 256, Cout <= 256.
-__global__ void __launch_bounds__(256)
-k_bias_partial(const uint16_t* __restrict__ dout, int cs, const uint16_t* __restrict__ act, int act_cs, int act_co,
-               int Cout, int P, int per, float* __restrict__ part) {
-    const int co = threadIdx.x;
-    const int p0 = blockIdx.x * per, p1 = min(P, p0 + per);
-    if (co >= Cout) return;
-    float s = 0.f;
-    for (int p = p0; p < p1; ++p) {
-        const uint16_t g = dout[(size_t)p * cs + co];
-        if (act) {
-            const uint16_t h = act[(size_t)p * act_cs + act_co + co];
-            if (h == 0 || (h & 0x8000u)) continue;
-        }
-        s += bf2f(g);
-    }
-    part[(size_t)blockIdx.x * Cout + co] = s;
-}
-
+// db = sum over partials (fixed order); grid ceil(Cout / 256).
 __global__ void k_bias_reduce(const float* __restrict__ part, int nb, int Cout, float* __restrict__ db) {
     const int co = blockIdx.x * blockDim.x + threadIdx.x;
     if (co >= Cout) return;

@@ -11,6 +11,8 @@ using namespace mnf;
 
 namespace {
 
+constexpr int kSyncIters = 200;
+
 // Philox4x32-10 counter-based generator (Salmon, Moraes, Dror & Shaw, SC 2011):
 // ten rounds of two 32x32->64 multiplications on a 128-bit counter with a
 // 64-bit key bumped by the Weyl constants.
@@ -65,19 +67,109 @@ __global__ void k_expose(const float* __restrict__ clean, int J, int K, size_t n
     raw[i] = (uint16_t)fminf(fmaxf(c, 0.f), sat);
 }
 
-// O[x] = sum_j |P(u_j)|^2 amp_j(u_j) e^{i phase_j(u_j)} / sum_j |P(u_j)|^2 over the windows
-// containing x (u_j = x - p_j); 1 where no window (or only zero probe) covers x.
+// Block sum of a float in a fixed order (waves combined in index order);
+// red must hold blockDim.x / 64 floats.  Result valid in every thread.
+__device__ __forceinline__ float block_sum_f(float v, float* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    float r = red[0];
+    for (int i = 1; i < nw; ++i) r += red[i];
+    return r;
+}
+
+// Phase synchronisation of window predictions z_j = a_j e^{i phi_j}: the
+// Hermitian matrix C_jk = sum over the overlap of windows j and k of
+// w_j w_k conj(z_j) z_k (w = |P|^2), one block per pair j <= k.
 __global__ void __launch_bounds__(256)
-k_stitch(const float* __restrict__ patches, const float2* __restrict__ P, const int2* __restrict__ pos, int J,
-         int Nw, float2* __restrict__ O, int My, int Mx) {
+k_sync_gram(const float* __restrict__ patches, const float2* __restrict__ P, const int2* __restrict__ pos, int J,
+            int Nw, float2* __restrict__ C) {
+    __shared__ float red[4];
+    const int j = blockIdx.x, k = blockIdx.y;
+    if (k < j) return;  // uniform over the block
+    const int2 pj = pos[j], pk = pos[k];
+    const int y0 = max(pj.x, pk.x), y1 = min(pj.x, pk.x) + Nw;
+    const int x0 = max(pj.y, pk.y), x1 = min(pj.y, pk.y) + Nw;
+    float re = 0.f, im = 0.f;
+    if (y1 > y0 && x1 > x0) {
+        const int h = y1 - y0, w = x1 - x0;
+        for (int i = threadIdx.x; i < h * w; i += 256) {
+            const int yy = y0 + i / w, xx = x0 + i % w;
+            const int uj = (yy - pj.x) * Nw + (xx - pj.y), uk = (yy - pk.x) * Nw + (xx - pk.y);
+            const float* a = patches + ((size_t)j * Nw * Nw + uj) * 2;
+            const float* b = patches + ((size_t)k * Nw * Nw + uk) * 2;
+            const float m = cabs2(P[uj]) * cabs2(P[uk]) * a[0] * b[0];
+            float sn, cs;
+            sincosf(b[1] - a[1], &sn, &cs);
+            re += m * cs;
+            im += m * sn;
+        }
+    }
+    re = block_sum_f(re, red);
+    im = block_sum_f(im, red);
+    if (threadIdx.x == 0) {
+        C[(size_t)j * J + k] = make_float2(re, im);
+        C[(size_t)k * J + j] = make_float2(re, -im);
+    }
+}
+
+// Leading eigenvector of C by power iteration from the all-ones vector (C is
+// positive semidefinite), projected to unit modulus, common phase chosen so
+// that sum_j c_j is real and positive.  One block of 1024 threads, J <= 1024.
+__global__ void __launch_bounds__(1024) k_sync_power(const float2* __restrict__ C, int J, int iters,
+                                                     float2* __restrict__ c) {
+    __shared__ float2 v[1024];
+    __shared__ float red[16];
+    const int t = threadIdx.x;
+    if (t < J) v[t] = make_float2(1.f, 0.f);
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+        float2 acc = make_float2(0.f, 0.f);
+        if (t < J) {
+            const float2* row = C + (size_t)t * J;
+            for (int k = 0; k < J; ++k) {
+                const float2 q = cmul(row[k], v[k]);
+                acc.x += q.x;
+                acc.y += q.y;
+            }
+        }
+        const float m = block_max(sqrtf(cabs2(acc)), red);
+        __syncthreads();
+        if (t < J) v[t] = m > 0.f ? make_float2(acc.x / m, acc.y / m) : make_float2(1.f, 0.f);
+        __syncthreads();
+    }
+    float2 u = make_float2(1.f, 0.f);
+    if (t < J) {
+        const float r = sqrtf(cabs2(v[t]));
+        if (r > 0.f) u = make_float2(v[t].x / r, v[t].y / r);
+    }
+    const float sr = block_sum_f(t < J ? u.x : 0.f, red);
+    const float si = block_sum_f(t < J ? u.y : 0.f, red);
+    const float sm = sqrtf(sr * sr + si * si);
+    if (t < J) c[t] = sm > 0.f ? cmul(u, make_float2(sr / sm, -si / sm)) : u;
+}
+
+// O[x] = sum_j |P(u_j)|^2 c_j amp_j(u_j) e^{i phase_j(u_j)} / sum_j |P(u_j)|^2 over the
+// windows containing x (u_j = x - p_j; c_j = 1 without phasors); 1 where no window
+// (or only zero probe) covers x.
+__global__ void __launch_bounds__(256)
+k_stitch(const float* __restrict__ patches, const float2* __restrict__ P, const int2* __restrict__ pos,
+         const float2* __restrict__ phasors, int J, int Nw, float2* __restrict__ O, int My, int Mx) {
     __shared__ int2 sp[256];
+    __shared__ float2 sc[256];
     const int x = blockIdx.x * 16 + (threadIdx.x % 16);
     const int y = blockIdx.y * 16 + (threadIdx.x / 16);
     float2 num = make_float2(0.f, 0.f);
     float den = 0.f;
     for (int j0 = 0; j0 < J; j0 += 256) {
         __syncthreads();
-        if (j0 + (int)threadIdx.x < J) sp[threadIdx.x] = pos[j0 + threadIdx.x];
+        if (j0 + (int)threadIdx.x < J) {
+            sp[threadIdx.x] = pos[j0 + threadIdx.x];
+            sc[threadIdx.x] = phasors ? phasors[j0 + threadIdx.x] : make_float2(1.f, 0.f);
+        }
         __syncthreads();
         const int nj = min(256, J - j0);
         for (int jj = 0; jj < nj; ++jj) {
@@ -87,8 +179,9 @@ k_stitch(const float* __restrict__ patches, const float2* __restrict__ P, const 
             const float* pa = patches + (((size_t)(j0 + jj) * Nw + uy) * Nw + ux) * 2;
             float s, c;
             sincosf(pa[1], &s, &c);
-            num.x += w * pa[0] * c;
-            num.y += w * pa[0] * s;
+            const float2 z = cmul(sc[jj], make_float2(pa[0] * c, pa[0] * s));
+            num.x += w * z.x;
+            num.y += w * z.y;
             den += w;
         }
     }
@@ -150,18 +243,31 @@ int detector_expose(mnf_ctx* ctx, const float* clean, int J, int H, int W, const
 }
 
 int ptycho_stitch(mnf_ctx* ctx, const float* patches, const mnf_c64* P, int Nw, const int32_t* pos, int J,
-                  mnf_c64* O, int My, int Mx, void* stream) {
+                  int sync, mnf_c64* O, int My, int Mx, void* stream) {
     MNF_TRY(begin(ctx));
     if (!patches || !P || !pos || !O || J <= 0 || Nw <= 0 || My <= 0 || Mx <= 0)
         return set_error(ctx, MNF_EINVAL, "bad stitching arguments");
+    if (sync && J > 1024) return set_error(ctx, MNF_EINVAL, "phase synchronisation takes at most 1024 windows");
     for (int j = 0; j < J; ++j)
         if (pos[2 * j] < 0 || pos[2 * j + 1] < 0 || pos[2 * j] + Nw > My || pos[2 * j + 1] + Nw > Mx)
             return set_error(ctx, MNF_EINVAL, "window %d lies outside the object", j);
     hipStream_t st = (hipStream_t)stream;
     void* dpos;
     MNF_TRY(upload(ctx, "stitch_pos", pos, sizeof(int32_t) * 2 * J, st, &dpos));
+    float2* phasors = nullptr;
+    if (sync) {
+        void* C;
+        void* cv;
+        MNF_TRY(scratch(ctx, "sync_gram", sizeof(float2) * (size_t)J * J, &C));
+        MNF_TRY(scratch(ctx, "sync_phasors", sizeof(float2) * (size_t)J, &cv));
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sync_gram, dim3(J, J), dim3(256), patches, (const float2*)P,
+                   (const int2*)dpos, J, Nw, (float2*)C);
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sync_power, dim3(1), dim3(1024), (const float2*)C, J, kSyncIters,
+                   (float2*)cv);
+        phasors = (float2*)cv;
+    }
     MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_stitch, dim3((Mx + 15) / 16, (My + 15) / 16), dim3(256), patches,
-               (const float2*)P, (const int2*)dpos, J, Nw, (float2*)O, My, Mx);
+               (const float2*)P, (const int2*)dpos, (const float2*)phasors, J, Nw, (float2*)O, My, Mx);
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
 }

@@ -235,30 +235,56 @@ int layer_wgrad(mnf_ctx* ctx, const LayerDesc& L, View x, int n, int Hin, View d
     a.Cout = L.co;
     a.taps = taps;
     a.P = L.mode == UP ? n * Hin * Hin : n * Hout * Hout;
+    const bool vec = x.cs % 8 == 0 && x.co % 8 == 0 && dY.cs % 8 == 0 && dY.co % 8 == 0 &&
+                     (!mask || (act.cs % 8 == 0 && act.co % 8 == 0));
+    const size_t count = (size_t)taps * L.ci * L.co;
+    const int Gc = L.co / 8;
+    if (L.mode == CONV3 && L.ci == 1 && L.co % 8 == 0 && (Gc & (Gc - 1)) == 0 && Gc <= 32 &&
+        dY.cs % 8 == 0 && dY.co % 8 == 0 && (!mask || (act.cs % 8 == 0 && act.co % 8 == 0))) {
+        // first layer: one input channel, all taps and the bias per thread
+        const int nb = (int)std::min<long long>(1024, ((long long)a.P + 255) / 256);
+        const int per = (a.P + nb - 1) / nb;
+        void* part;
+        void* bpart;
+        MNF_TRY(scratch(ctx, "unet_wpart", (size_t)nb * count * sizeof(float), &part));
+        MNF_TRY(scratch(ctx, "unet_bpart", (size_t)nb * L.co * sizeof(float), &bpart));
+        a.part = (float*)part;
+        a.bpart = (float*)bpart;
+        hipLaunchKernelGGL(k_wgrad_c1, dim3(nb), dim3(256), 0, st, a, per);
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(g1(count)), dim3(256), 0, st, (const float*)part, nb, count, dW);
+        hipLaunchKernelGGL(k_bias_reduce, dim3(g1((size_t)L.co)), dim3(256), 0, st, (const float*)bpart, nb, L.co,
+                           db);
+        return MNF_OK;
+    }
     const int target_blocks = 1024;
     const int tiles = g1((size_t)L.co, 64) * g1((size_t)L.ci, 64) * taps;
     a.splits = std::max(1, std::min(target_blocks / std::max(1, tiles), (a.P + 4095) / 4096));
+    const int btaps = L.mode == UP ? 4 : 1;
     void* part;
-    const size_t count = (size_t)taps * L.ci * L.co;
-    MNF_TRY(scratch(ctx, "unet_wpart", (size_t)a.splits * count * sizeof(float), &part));
-    a.part = (float*)part;
-    const dim3 grid(g1((size_t)L.co, 64), g1((size_t)L.ci, 64), taps * a.splits);
-    switch (L.mode) {
-        case CONV3: hipLaunchKernelGGL(k_conv_wgrad<CONV3>, grid, dim3(kGemmThreads), 0, st, a); break;
-        case DOWN: hipLaunchKernelGGL(k_conv_wgrad<DOWN>, grid, dim3(kGemmThreads), 0, st, a); break;
-        case UP: hipLaunchKernelGGL(k_conv_wgrad<UP>, grid, dim3(kGemmThreads), 0, st, a); break;
-        default: hipLaunchKernelGGL(k_conv_wgrad<CONV1>, grid, dim3(kGemmThreads), 0, st, a); break;
-    }
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(g1(count)), dim3(256), 0, st, (const float*)part, a.splits, count, dW);
-    // bias: sum of dZ over the output pixels
-    const int Pout = n * Hout * Hout;
-    const int per = 4096;
-    const int nb = (Pout + per - 1) / per;
     void* bpart;
-    MNF_TRY(scratch(ctx, "unet_bpart", (size_t)nb * L.co * sizeof(float), &bpart));
-    hipLaunchKernelGGL(k_bias_partial, dim3(nb), dim3(256), 0, st, (const uint16_t*)(dY.p + dY.co), dY.cs,
-                       (const uint16_t*)(mask ? act.p : nullptr), act.cs, act.co, L.co, Pout, per, (float*)bpart);
-    hipLaunchKernelGGL(k_bias_reduce, dim3(g1((size_t)L.co)), dim3(256), 0, st, (const float*)bpart, nb, L.co, db);
+    MNF_TRY(scratch(ctx, "unet_wpart", (size_t)a.splits * count * sizeof(float), &part));
+    MNF_TRY(scratch(ctx, "unet_bpart", (size_t)a.splits * btaps * L.co * sizeof(float), &bpart));
+    a.part = (float*)part;
+    a.bpart = (float*)bpart;
+    const dim3 grid(g1((size_t)L.co, 64), g1((size_t)L.ci, 64), taps * a.splits);
+#define MNF_WGRAD(M)                                                                              \
+    do {                                                                                          \
+        if (vec)                                                                                  \
+            hipLaunchKernelGGL((k_conv_wgrad<M, true>), grid, dim3(kGemmThreads), 0, st, a);      \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_conv_wgrad<M, false>), grid, dim3(kGemmThreads), 0, st, a);     \
+    } while (0)
+    switch (L.mode) {
+        case CONV3: MNF_WGRAD(CONV3); break;
+        case DOWN: MNF_WGRAD(DOWN); break;
+        case UP: MNF_WGRAD(UP); break;
+        default: MNF_WGRAD(CONV1); break;
+    }
+#undef MNF_WGRAD
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(g1(count)), dim3(256), 0, st, (const float*)part, a.splits, count, dW);
+    // bias: the kernel's per-(split, tap) sums of the masked output gradient
+    hipLaunchKernelGGL(k_bias_reduce, dim3(g1((size_t)L.co)), dim3(256), 0, st, (const float*)bpart,
+                       a.splits * btaps, L.co, db);
     return MNF_OK;
 }
 

@@ -61,6 +61,23 @@ def layer_shapes(widths: Sequence[int]):
             (9, 2 * c2, c2), (9, c2, c2), (1, c2, 2)]
 
 
+def layer_flops(H: int, widths: Sequence[int]):
+    """Multiply-add flops (2 per MAC) of every layer's forward pass for one sample."""
+    out_px = [H, H, H // 2, H // 2, H // 2, H // 4, H // 4, H // 4, H // 8, H // 8, H // 8, H // 4, H // 4,
+              H // 4, H // 4]
+    fl = []
+    for i, (taps, ci, co) in enumerate(layer_shapes(widths)):
+        per_px = ci * co if i == 11 else taps * ci * co   # the transposed layer: one tap per output pixel
+        fl.append(2 * out_px[i] ** 2 * per_px)
+    return fl
+
+
+def train_flops_per_sample(H: int, widths: Sequence[int]) -> int:
+    """Forward + input gradient (all layers but the first) + weight gradient."""
+    fl = layer_flops(H, widths)
+    return 3 * sum(fl) - fl[0]
+
+
 def init_params(widths: Sequence[int], seed: int, device="cuda:0") -> torch.Tensor:
     """He-normal weights (fan-in = taps x c_in; c_in for the transposed layer), zero biases."""
     rng = np.random.default_rng(seed)
@@ -75,18 +92,22 @@ def init_params(widths: Sequence[int], seed: int, device="cuda:0") -> torch.Tens
     return torch.from_numpy(flat).to(device)
 
 
-def window_labels(O: np.ndarray, pos: np.ndarray, Nw: int) -> np.ndarray:
-    """Amplitude and phase of the true object in every scan window: [J][Nw][Nw][2] float32."""
+def window_labels(O: np.ndarray, pos: np.ndarray, Nw: int, weight: Optional[np.ndarray] = None) -> np.ndarray:
+    """Amplitude and phase of the true object in every scan window: [J][Nw][Nw][2] float32.
+    With `weight` (|P|^2), each window's phase is taken relative to the phase of
+    its weighted sum, the part a single far-field pattern cannot determine."""
     out = np.empty((len(pos), Nw, Nw, 2), np.float32)
     for j, (y, x) in enumerate(pos):
         win = O[y:y + Nw, x:x + Nw]
+        if weight is not None:
+            win = win * np.exp(-1j * np.angle(np.sum(weight * win)))
         out[j, ..., 0] = np.abs(win)
         out[j, ..., 1] = np.angle(win)
     return out
 
 
 def simulate(S: Setup, seeds: Sequence[int], kind: str = "fused", device="cuda:0",
-             labels: bool = True) -> Dict[str, object]:
+             labels: bool = True, relative: bool = False) -> Dict[str, object]:
     """Patterns of every scan position of the objects drawn with `seeds`.
 
     kind 'fused': the detector model (Poisson + read noise, 12-bit clip,
@@ -95,7 +116,8 @@ def simulate(S: Setup, seeds: Sequence[int], kind: str = "fused", device="cuda:0
     shortest exposure.  kind 'clean': the noise-free intensity at the same
     flux (what the fusion returns for an unsaturated, noise-free bracket).
     Returns I [n][256][256] (device), targets [n][64][64][2] (device), the
-    true objects and the flux of each object."""
+    true objects and the flux of each object.  With `relative`, window phases
+    are labelled relative to each window's weighted mean phase."""
     w = S.w
     J = len(S.pos)
     n = J * len(seeds)
@@ -119,16 +141,18 @@ def simulate(S: Setup, seeds: Sequence[int], kind: str = "fused", device="cuda:0
         else:
             raise ValueError(kind)
         if labels:
-            tgt[sl] = torch.from_numpy(window_labels(O, S.pos, w.Nw)).to(device)
+            wt = np.abs(S.P) ** 2 if relative else None
+            tgt[sl] = torch.from_numpy(window_labels(O, S.pos, w.Nw, wt)).to(device)
     torch.cuda.synchronize(device)
     return dict(I=I, target=tgt, objects=objs, scales=scales, kind=kind)
 
 
-def train(S: Setup, data, params: torch.Tensor, epochs: float, batch: int = 64, lr: float = 1e-3,
-          seed: int = 0, time_budget: Optional[float] = None, log=None) -> Dict[str, object]:
+def train(S: Setup, data, params: torch.Tensor, epochs: float = 1.0, batch: int = 64, lr: float = 1e-3,
+          seed: int = 0, time_budget: Optional[float] = None, log=None,
+          steps: Optional[int] = None) -> Dict[str, object]:
     """Adam on the mean-squared error of (amplitude, phase); stops after
-    `epochs` passes or `time_budget` seconds.  Returns the loss history and
-    the training rate."""
+    `steps` mini-batches (else `epochs` passes) or `time_budget` seconds.
+    Returns the loss history and the training rate."""
     I, tgt = data["I"], data["target"]
     n = I.shape[0]
     dev = I.device
@@ -136,7 +160,7 @@ def train(S: Setup, data, params: torch.Tensor, epochs: float, batch: int = 64, 
     v = torch.zeros_like(params)
     gen = torch.Generator(device="cpu").manual_seed(seed)
     steps_per_epoch = n // batch
-    total = int(epochs * steps_per_epoch)
+    total = int(steps) if steps is not None else int(epochs * steps_per_epoch)
     hist = []
     t0 = time.perf_counter()
     step = 0
@@ -183,7 +207,8 @@ def _elapsed(fn, device) -> float:
 
 
 def time_to_threshold(S: Setup, data, params: Optional[torch.Tensor], tau: float = 1e-2,
-                      max_plain: int = 200, max_warm: int = 50, alpha: float = 0.1) -> List[Dict[str, object]]:
+                      max_plain: int = 200, max_warm: int = 50, alpha: float = 0.1,
+                      sync: bool = False) -> List[Dict[str, object]]:
     """For every object of `data`: NRMSE per iteration from a flat start and
     from the network's stitched start, the iteration count at which each
     first reaches tau, and the timed cost of reaching it:
@@ -230,7 +255,7 @@ def time_to_threshold(S: Setup, data, params: Optional[torch.Tensor], tau: float
 
             def warm_start(out):
                 api.unet_forward(params, I, S.log_scale, H, WIDTHS, out=patches)
-                api.ptycho_stitch(patches, P_unit, S.pos, (w.M, w.M), out=out)
+                api.ptycho_stitch(patches, P_unit, S.pos, (w.M, w.M), sync=sync, out=out)
 
             O0 = torch.empty((w.M, w.M), dtype=torch.complex64, device=dev)
             warm_start(O0)

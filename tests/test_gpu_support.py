@@ -117,3 +117,27 @@ def test_nrmse_matches_oracle(api, masked):
     a[:4] = 1
     b[4:] = 1
     assert abs(api.nrmse(b, a).item() - 1.0) < 1e-15
+
+
+@pytest.mark.parametrize("n_side,Nw,r,step,M,noise", [(5, 16, 6.0, 4, 40, 0.0), (10, 64, 16.0, 8, 192, 0.05)])
+def test_synchronised_stitch_matches_oracle(api, n_side, Nw, r, step, M, noise):
+    # windows of a true object, each rotated by its own constant phase, plus
+    # noise: the aligned stitch recovers the object up to one global phase
+    # (overlapping probes, so every window is coupled to its neighbours)
+    J = n_side * n_side
+    rng = np.random.default_rng(J)
+    O = c64(synth.make_object(M, 7))
+    pos = synth.raster_positions(n_side, step, (M - Nw - (n_side - 1) * step) // 2)
+    P = c64(synth.make_probe(Nw, r, np.pi))
+    off = rng.uniform(-np.pi, np.pi, J)
+    patches = np.stack([np.stack([np.abs(O[y:y + Nw, x:x + Nw]) + noise * rng.standard_normal((Nw, Nw)),
+                                  np.angle(O[y:y + Nw, x:x + Nw]) + off[j] + noise * rng.standard_normal((Nw, Nw))],
+                                 -1) for j, (y, x) in enumerate(pos)]).astype(np.float32).astype(np.float64)
+    c = ptycho.phase_sync(patches, P, pos, (M, M))
+    want = ptycho.stitch(patches, P, pos, (M, M), phasors=c)
+    got = api.ptycho_stitch(torch.from_numpy(patches.astype(np.float32)).to(DEV),
+                            torch.from_numpy(P.astype(np.complex64)).to(DEV), pos, (M, M), sync=True).cpu().numpy()
+    # float32 Gram sums and power iteration against a float64 eigendecomposition
+    assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-4
+    mask = ptycho.illumination_mask(P, pos, (M, M))
+    assert ptycho.nrmse(got, O, mask) < (1e-5 if noise == 0 else 0.1)

@@ -216,3 +216,41 @@ def test_stitch_weighted_mean_by_hand():
     # and window 1 at u=0 (w=1, value i) -> (8 + i) / 5; column 2: window 1 only -> i; column 3: 1
     want = np.array([2.0, (8 + 1j) / 5, 1j, 1.0])
     assert np.abs(S - want[None, :]).max() < 1e-15
+
+
+def test_phase_sync_recovers_window_offsets():
+    # true patches, each rotated by its own random constant phase: the
+    # synchronised stitch equals the object up to one global phase
+    O, P, pos = _tiny_geometry()
+    Nw = P.shape[0]
+    rng = np.random.default_rng(3)
+    off = rng.uniform(-np.pi, np.pi, len(pos))
+    patches = np.stack([np.stack([np.abs(O[y:y + Nw, x:x + Nw]),
+                                  np.angle(O[y:y + Nw, x:x + Nw] * np.exp(1j * off[j]))], -1)
+                        for j, (y, x) in enumerate(pos)])
+    mask = ptycho.illumination_mask(P, pos, O.shape)
+    plain = ptycho.stitch(patches, P, pos, O.shape)
+    assert ptycho.nrmse(plain, O, mask) > 0.3
+    c = ptycho.phase_sync(patches, P, pos, O.shape)
+    assert np.allclose(np.abs(c), 1.0)
+    assert abs(np.angle(np.sum(c))) < 1e-12
+    # c_j undoes the offsets up to one common phase
+    rel = c * np.exp(1j * off)
+    assert np.abs(rel / rel[0] - 1.0).max() < 1e-9
+    synced = ptycho.stitch(patches, P, pos, O.shape, phasors=c)
+    assert ptycho.nrmse(synced, O, mask) < 1e-9
+
+
+def test_phase_sync_gram_is_hermitian_psd_by_brute_force():
+    # two windows overlapping in a 1 x 2 strip, flat probe: C by hand
+    P = np.ones((2, 2), complex)
+    pos = np.array([[0, 0], [1, 0]])
+    patches = np.zeros((2, 2, 2, 2))
+    patches[..., 0] = 1.0
+    patches[0, 1, :, 1] = [0.2, 0.4]     # window 0, row 1 (overlap)
+    patches[1, 0, :, 1] = [0.7, 0.9]     # window 1, row 0 (overlap)
+    c = ptycho.phase_sync(patches, P, pos, (3, 2))
+    # C_01 = sum over the strip of e^{-i 0.2} e^{i 0.7} + e^{-i 0.4} e^{i 0.9} = 2 e^{i 0.5}
+    # leading eigenvector of [[4, 2e^{i.5}], [2e^{-i.5}, 4]] is (e^{i.5}, 1)/sqrt 2
+    want = np.array([np.exp(0.25j), np.exp(-0.25j)])
+    assert np.abs(c - want).max() < 1e-12
