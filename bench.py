@@ -308,6 +308,48 @@ def run_multiscan(args, api, synth, dev):
     }
 
 
+def run_batch_sweep(args, api, synth, dev):
+    """Launch latency versus work: the lab-scale scan reconstructed with
+    mini-batches of 8..256 (same kernels), per-launch duration of every pass
+    from HIP events and the iteration rate.  One JSON object per batch size
+    under "sweep"; the headline value is the configured batch's rate."""
+    import numpy as np
+    import torch
+
+    w = synth.lab_workload()
+    O_true = torch.from_numpy(w.object().astype(np.complex64)).to(dev)
+    P = torch.from_numpy(w.probe().astype(np.complex64)).to(dev)
+    I = api.ptycho_forward(O_true, P, w.pos, w.Nd)
+    rows = []
+    for B in (8, 16, 32, 64, 128, 256):
+        O = torch.ones_like(O_true)
+        Pw = P.clone()
+        api.ptycho_iterate(O, Pw, I, w.pos, 2, batch=B, update_probe=True)
+        api.profile(PASSES[:4])
+        api.profile_reset()
+        api.ptycho_iterate(O, Pw, I, w.pos, 5, batch=B, update_probe=True)
+        torch.cuda.synchronize()
+        prof = api.profile_read()
+        api.profile([])
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        api.ptycho_iterate(O, Pw, I, w.pos, args.iters, batch=B, update_probe=True)
+        e1.record()
+        e1.synchronize()
+        it_ms = e0.elapsed_time(e1) / args.iters
+        rows.append({"batch": B, "ms_per_iteration": round(it_ms, 4), "updates_per_s": round(w.J / it_ms * 1e3),
+                     "us_per_launch": {k: round(v[1] / v[0] * 1e3, 2) for k, v in prof.items()}})
+        print(f"# B={B}: {rows[-1]}", file=sys.stderr, flush=True)
+    ref = next(r for r in rows if r["batch"] == w.batch)
+    return {"metric": "scan-position updates/s at 256^2 FP32 versus mini-batch size (reconstruction only)",
+            "value": ref["updates_per_s"], "unit": "position-updates/s", "n_gpus": 1, "steps": args.iters,
+            "warmup": 2, "ms_per_step": ref["ms_per_iteration"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic (noiseless forward-model intensities)",
+            "config": {"workload": "lab-256 geometry, rPIE with probe update, mini-batch 8..256"},
+            "sweep": rows}
+
+
 def run_warmstart(args, api, synth, dev):
     """Learned warm start on the small geometry with a 256^2 detector: train
     the U-Net (excluded from the timed comparison), then for ten test objects
@@ -442,7 +484,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=None, help="iterations per step (200 lab, 20 multiscan)")
-    ap.add_argument("--workload", choices=["lab", "multiscan", "warmstart"], default="lab")
+    ap.add_argument("--workload", choices=["lab", "multiscan", "warmstart", "batch-sweep"], default="lab")
     ap.add_argument("--train-seconds", type=float, default=240.0, help="warm start: training time budget")
     ap.add_argument("--train-objects", type=int, default=500, help="warm start: training objects x 100 patterns")
     ap.add_argument("--epochs", type=float, default=100.0, help="warm start: epoch cap")
@@ -473,7 +515,8 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    run = {"lab": run_lab, "multiscan": run_multiscan, "warmstart": run_warmstart}[args.workload]
+    run = {"lab": run_lab, "multiscan": run_multiscan, "warmstart": run_warmstart,
+           "batch-sweep": run_batch_sweep}[args.workload]
     out = run(args, api, synth, dev)
     print(json.dumps(out))
     return 0

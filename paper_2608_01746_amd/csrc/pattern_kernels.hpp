@@ -31,8 +31,9 @@ k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
     __shared__ float2 tw[N];
     __shared__ float red[RowCfg<N, RV>::THREADS / 64 + 1];
     const int s = blockIdx.y;
+    const ScanDev sc0 = scans[0];
     const SlotDev sd = slots[s];
-    const ScanDev& sc = scans[sd.scan];
+    const ScanDev sc = scan_desc(scans, sc0, sd.scan);
     const int Nw = sc.Nw, Mx = sc.Mx;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int y = blockIdx.x * LINES + line;
@@ -112,8 +113,9 @@ k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
     __shared__ float2 tw[N];
     __shared__ double red[ColCfg<N, CV>::THREADS / 64 + 1];
     const int s = blockIdx.y;
+    const ScanDev sc0 = scans[0];
     const SlotDev sd = slots[s];
-    const ScanDev& sc = scans[sd.scan];
+    const ScanDev sc = scan_desc(scans, sc0, sd.scan);
     const int Nw = sc.Nw;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int kx = blockIdx.x * C + c;
@@ -160,8 +162,9 @@ k_cols_intensity(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
     __shared__ float2 lds[C * N];
     __shared__ float2 tw[N];
     const int s = blockIdx.y;
+    const ScanDev sc0 = scans[0];
     const SlotDev sd = slots[s];
-    const int Nw = scans[sd.scan].Nw;
+    const int Nw = scan_desc(scans, sc0, sd.scan).Nw;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int kx = blockIdx.x * C + c;
     const float2* col = S + (size_t)s * N * N + kx;
@@ -229,8 +232,9 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
     __shared__ int s_py[kMaxBatch], s_px[kMaxBatch];
     __shared__ float red[THREADS / 64 + 1];
     float2* c_num = lds;
+    const ScanDev sc0 = scans[0];
     const GroupDev gd = groups[blockIdx.y];
-    const ScanDev& sc = scans[gd.scan];
+    const ScanDev sc = scan_desc(scans, sc0, gd.scan);
     const int Nw = sc.Nw, Mx = sc.Mx, nb = gd.nb;
     const int r = blockIdx.x;
     if (r >= Nw) return;  // uniform over the block

@@ -25,6 +25,15 @@ struct ScanDev {
     int pad_[3];
 };
 
+// Scan descriptor `idx` given entry 0 loaded up front, in parallel with the
+// slot or group entry that names the scan: a launch over a single scan (the
+// common case) then waits for one table load before its data loads instead
+// of two dependent ones.
+__device__ __forceinline__ ScanDev scan_desc(const ScanDev* __restrict__ scans, const ScanDev& first, int idx) {
+    if (idx == 0) return first;
+    return scans[idx];
+}
+
 struct SlotDev {
     int scan;   // index into the scan table
     int j;      // position index within the scan

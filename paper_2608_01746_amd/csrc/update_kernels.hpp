@@ -73,8 +73,9 @@ k_object_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ s
                 int rpie, float alpha) {
     __shared__ int l_slot[kMaxBatch], l_py[kMaxBatch], l_px[kMaxBatch];
     __shared__ float red[kObjThreads / 64];
+    const ScanDev sc0 = scans[0];
     const GroupDev gd = groups[find_group(groups, ngroups, blockIdx.x)];
-    const ScanDev& sc = scans[gd.scan];
+    const ScanDev sc = scan_desc(scans, sc0, gd.scan);
     const int Nw = sc.Nw;
     const int tile = blockIdx.x - gd.tile0;
     const int ty0 = sc.by0 + (tile / sc.tiles_x) * kObjTileY;
@@ -146,8 +147,9 @@ __global__ void __launch_bounds__(kObjThreads)
 k_grad_object(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
               const GroupDev* __restrict__ groups, int ngroups, const float2* __restrict__ S, int N) {
     __shared__ int l_slot[kMaxBatch], l_py[kMaxBatch], l_px[kMaxBatch];
+    const ScanDev sc0 = scans[0];
     const GroupDev gd = groups[find_group(groups, ngroups, blockIdx.x)];
-    const ScanDev& sc = scans[gd.scan];
+    const ScanDev sc = scan_desc(scans, sc0, gd.scan);
     const int Nw = sc.Nw;
     const int tile = blockIdx.x - gd.tile0;
     const int ty0 = sc.by0 + (tile / sc.tiles_x) * kObjTileY;

@@ -152,7 +152,9 @@ def train(S: Setup, data, params: torch.Tensor, epochs: float = 1.0, batch: int 
           steps: Optional[int] = None) -> Dict[str, object]:
     """Adam on the mean-squared error of (amplitude, phase); stops after
     `steps` mini-batches (else `epochs` passes) or `time_budget` seconds.
-    Returns the loss history and the training rate."""
+    The learning rate drops tenfold for the last fifth of the steps (of the
+    steps the time budget allows, estimated after 100 steps).  Returns the
+    loss history and the training rate."""
     I, tgt = data["I"], data["target"]
     n = I.shape[0]
     dev = I.device
@@ -165,6 +167,7 @@ def train(S: Setup, data, params: torch.Tensor, epochs: float = 1.0, batch: int 
     t0 = time.perf_counter()
     step = 0
     loss_sum = torch.zeros((), dtype=torch.float64, device=dev)
+    decay_at = int(0.8 * total)
     while step < total:
         perm = torch.randperm(n, generator=gen).to(dev)
         for b in range(steps_per_epoch):
@@ -172,7 +175,12 @@ def train(S: Setup, data, params: torch.Tensor, epochs: float = 1.0, batch: int 
                 break
             idx = perm[b * batch:(b + 1) * batch]
             step += 1
-            loss = api.unet_train_step(params, m, v, step, lr, I.index_select(0, idx), S.log_scale,
+            if time_budget is not None and step == 101:
+                torch.cuda.synchronize(dev)
+                per = (time.perf_counter() - t0) / 100
+                decay_at = int(0.8 * min(total, int(time_budget / per)))
+            cur_lr = lr if step <= decay_at else 0.1 * lr
+            loss = api.unet_train_step(params, m, v, step, cur_lr, I.index_select(0, idx), S.log_scale,
                                        tgt.index_select(0, idx), H, WIDTHS)
             loss_sum += loss
             if step % 100 == 0:

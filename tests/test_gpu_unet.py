@@ -74,6 +74,20 @@ def test_conv_gradients(api, mode, n, H, Ci, Co, masked):
     assert np.all(np.abs(d - rdx) <= 2.0 ** -8 * np.abs(rdx) + 1e-6 * np.abs(rdx).max())
 
 
+# large layers (the full network's sizes at batch 4)
+LARGE = [("down", 4, 256, 32, 256), ("conv1", 4, 128, 64, 256), ("conv3", 4, 128, 32, 256)]
+
+
+@pytest.mark.parametrize("mode,n,H,Ci,Co", LARGE)
+def test_large_layer_forward(api, mode, n, H, Ci, Co):
+    test_conv_forward(api, mode, n, H, Ci, Co)
+
+
+@pytest.mark.parametrize("mode,n,H,Ci,Co", [("conv1", 4, 128, 256, 64), ("conv3", 4, 128, 256, 8)])
+def test_large_layer_gradients(api, mode, n, H, Ci, Co):
+    test_conv_gradients(api, mode, n, H, Ci, Co, True)
+
+
 WID = (8, 16, 16, 24)
 
 
