@@ -1,12 +1,22 @@
 // Multi-scale non-linear fusion (Methods 3.4, Eqs. 5-10) of exposure brackets.
 //
-// Positions are processed in chunks sized to a scratch budget.  For each
-// exposure k the chunk's Gaussian pyramids of I_tilde_k and W_k are built
-// level by level in HBM scratch, and the modulated, quantised band-pass
-// coefficients are accumulated over k into one fused pyramid F_l.  The
-// per-exposure reconstructions of Eq. 9 are linear in their coefficients,
-// so collapsing the summed pyramid once equals summing the K per-exposure
-// collapses (Eq. 10); quantisation is applied per exposure before the sum.
+// Level 0 is never stored.  Its values (I_tilde_k and the weight W_k, Eq. 5
+// normalised over the K frames) are pointwise functions of the K raw counts
+// of a pixel, cheaper to recompute from the 2-byte counts than to write and
+// re-read as 4-byte pyramids:
+//   1. k_fuse_level1: level 1 of every exposure's image and weight pyramid
+//      straight from the raw counts (reduce of the recomputed level 0);
+//   2. per exposure, levels 2..L by reduce, and the modulated, quantised
+//      band-pass coefficients of levels 1..L-1 plus the weighted base of
+//      level L accumulated over exposures into one fused pyramid F_l;
+//   3. collapse of F down to level 1;
+//   4. k_fuse_final: per level-0 pixel, the level-0 coefficients of all
+//      exposures (recomputed level 0 minus the expanded level 1), quantised
+//      per exposure, summed, plus the expanded level-1 collapse.
+// The per-exposure reconstructions of Eq. 9 are linear in their
+// coefficients, so collapsing the summed pyramid once equals summing the K
+// per-exposure collapses (Eq. 10); quantisation is applied per exposure
+// before the sum.
 //
 // Filters (per axis, reflect-101 borders on the grid the filter runs on):
 //   reduce : out[i] = sum_{m=-2..2} w[m] x[2i + m],  w = [1 4 6 4 1] / 16
@@ -35,33 +45,83 @@ struct FuseConsts {
 
 __device__ __forceinline__ int reflect101(int i, int n) { return i < 0 ? -i : (i >= n ? 2 * (n - 1) - i : i); }
 
-// Level 0 of exposure k for every pixel of the chunk: I_tilde_k and the
-// normalised weight W_k (computed from all K frames of the pixel).
-__global__ void __launch_bounds__(256)
-k_fuse_level0(const uint16_t* __restrict__ raw, int K, int k, size_t npix, size_t total,
-              FuseConsts c, float* __restrict__ GI, float* __restrict__ GW,
-              float* __restrict__ weights_out) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const size_t jj = i / npix, q = i % npix;
-    const uint16_t* px = raw + jj * (size_t)K * npix + q;
-    float wsum = 0.f, wk = 0.f, Ik = 0.f, Ibar_k = 0.f;
-    for (int kk = 0; kk < K; ++kk) {
-        const float I = (float)px[(size_t)kk * npix];
-        const float Ib = fminf(fmaxf((I - c.dark) * c.inv_range, 0.f), 1.f);
-        const float d = Ib - c.mu;
-        const float w = expf(-d * d * c.inv_2s2);
-        wsum += w;
-        if (kk == k) {
-            wk = w;
-            Ik = I;
-            Ibar_k = Ib;
+// Tap m of the binomial kernel [1 4 6 4 1] / 16.
+__device__ __forceinline__ float binom5(int m) {
+    return m == 2 ? 0.375f : ((m & 1) ? 0.25f : 0.0625f);
+}
+
+// Level 0 of every exposure at one pixel: I_tilde_k and the weight W_k
+// normalised over the K frames of the pixel.  KM >= K is a compile-time bound
+// so that the per-exposure values stay in registers.
+template <int KM>
+__device__ __forceinline__ void level0_at(const uint16_t* __restrict__ px, size_t npix, int K, const FuseConsts& c,
+                                          float* gi, float* gw) {
+    float wsum = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) {
+        gi[kk] = gw[kk] = 0.f;
+        if (kk < K) {
+            const float I = (float)px[(size_t)kk * npix];
+            const float Ib = fminf(fmaxf((I - c.dark) * c.inv_range, 0.f), 1.f);
+            const float d = Ib - c.mu;
+            const float w = expf(-d * d * c.inv_2s2);
+            wsum += w;
+            gw[kk] = w;
+            gi[kk] = c.radiometric ? (I - c.dark) * c.scale[kk] : Ib;
         }
     }
-    const float W = wk / fmaxf(wsum, 1e-30f);
-    GI[i] = c.radiometric ? (Ik - c.dark) * c.scale[k] : Ibar_k;
-    GW[i] = W;
-    if (weights_out) weights_out[(jj * K + k) * npix + q] = W;
+    const float inv = 1.f / fmaxf(wsum, 1e-30f);
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) gw[kk] = gw[kk] * inv;
+}
+
+// Level 1 of the image and weight pyramids of all K exposures, reduced from
+// the recomputed level 0: thread per level-1 pixel of the chunk (total =
+// nj * (H/2) * (W/2)); GI1 and GW1 are [K][total].
+template <int KM>
+__global__ void __launch_bounds__(256)
+k_fuse_level1(const uint16_t* __restrict__ raw, int K, int H, int W, size_t total, FuseConsts c,
+              float* __restrict__ GI1, float* __restrict__ GW1) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // the chunk keeps totals below 2^31
+    if (i >= (int)total) return;
+    const int h1 = H >> 1, w1 = W >> 1;
+    const size_t npix = (size_t)H * W;
+    const int jj = i / (h1 * w1);
+    const int r = i - jj * (h1 * w1);
+    const int oy = r / w1, ox = r - oy * w1;
+    const uint16_t* base = raw + (size_t)jj * K * npix;
+    float si[KM], sw[KM];
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) si[kk] = sw[kk] = 0.f;
+#pragma unroll 1
+    for (int a = 0; a < 5; ++a) {
+        const int yy = reflect101(2 * oy + a - 2, H);
+        float ri[KM], rw[KM];
+#pragma unroll
+        for (int kk = 0; kk < KM; ++kk) ri[kk] = rw[kk] = 0.f;
+#pragma unroll 1
+        for (int b = 0; b < 5; ++b) {
+            const int xx = reflect101(2 * ox + b - 2, W);
+            float gi[KM], gw[KM];
+            level0_at<KM>(base + (size_t)yy * W + xx, npix, K, c, gi, gw);
+#pragma unroll
+            for (int kk = 0; kk < KM; ++kk) {
+                ri[kk] += binom5(b) * gi[kk];
+                rw[kk] += binom5(b) * gw[kk];
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KM; ++kk) {
+            si[kk] += binom5(a) * ri[kk];
+            sw[kk] += binom5(a) * rw[kk];
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk)
+        if (kk < K) {
+            GI1[(size_t)kk * total + i] = si[kk];
+            GW1[(size_t)kk * total + i] = sw[kk];
+        }
 }
 
 // G_{l+1} = D(G_l * w_G) for the image and the weight pyramids together.
@@ -169,9 +229,55 @@ k_fuse_collapse(const float* __restrict__ Rc, const float* F, int h, int w, size
     out[i] = F[i] + expand_at(Rc + jj * (size_t)hc * wc, hc, wc, y, x);
 }
 
-__global__ void k_copy_f32(float* __restrict__ dst, const float* __restrict__ src, size_t n) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = src[i];
+struct Level0Steps {
+    float step[kMaxK];  // level-0 quantisation step of each exposure (0 = none)
+};
+
+// Level 0 and the output: per pixel of the chunk (total = nj * H * W), the
+// level-0 coefficient of every exposure, G_0[W_k] (G_0[I_k] - U(G_1[I_k])),
+// quantised with its own step and summed over k, plus U(R_1) (the fused
+// pyramid collapsed to level 1).  With L = 0 the output is the weighted sum
+// of the level-0 images.  Optionally writes the normalised weights.
+template <int KM>
+__global__ void __launch_bounds__(256)
+k_fuse_final(const uint16_t* __restrict__ raw, int K, int H, int W, size_t total, FuseConsts c, Level0Steps q,
+             const float* __restrict__ GI1, const float* __restrict__ R1, int L, float* __restrict__ out,
+             float* __restrict__ weights_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // the chunk keeps totals below 2^31
+    if (i >= (int)total) return;
+    const size_t npix = (size_t)H * W;
+    const int jj = i / (H * W), pq = i - jj * (H * W);
+    const int y = pq / W, x = pq - y * W;
+    float gi[KM], gw[KM];
+    level0_at<KM>(raw + (size_t)jj * K * npix + pq, npix, K, c, gi, gw);
+    if (weights_out) {
+#pragma unroll
+        for (int kk = 0; kk < KM; ++kk)
+            if (kk < K) weights_out[((size_t)jj * K + kk) * npix + pq] = gw[kk];
+    }
+    float F = 0.f;
+    if (L == 0) {
+#pragma unroll
+        for (int kk = 0; kk < KM; ++kk)
+            if (kk < K) {
+                const float v = gw[kk] * gi[kk];
+                F = kk == 0 ? v : F + v;
+            }
+        out[i] = F;
+        return;
+    }
+    const int h1 = H >> 1, w1 = W >> 1;
+    const size_t n1 = (total / npix) * (size_t)h1 * w1;  // level-1 pixels of the chunk
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk)
+        if (kk < K) {
+            const float lap = gi[kk] - expand_at(GI1 + (size_t)kk * n1 + (size_t)jj * h1 * w1, h1, w1, y, x);
+            float v = gw[kk] * lap;
+            const float st = q.step[kk];
+            if (st > 0.f) v = st * rintf(v / st);
+            F = kk == 0 ? v : F + v;
+        }
+    out[i] = F + expand_at(R1 + (size_t)jj * h1 * w1, h1, w1, y, x);
 }
 
 inline dim3 grid1d(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -217,51 +323,85 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
                                                   : d / ((double)p->sat - (double)p->dark));
         }
 
-    // pyramid offsets per position (floats)
-    std::vector<size_t> off(L + 2, 0);
-    for (int l = 0; l <= L; ++l) off[l + 1] = off[l] + (size_t)(H >> l) * (W >> l);
-    const size_t per_pos = off[L + 1];
-    const size_t budget = (size_t)1 << 30;  // bytes of scratch for three pyramids
-    const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)J, budget / (3 * per_pos * sizeof(float))));
-    void *gi_v, *gw_v, *f_v;
-    MNF_TRY(scratch(ctx, "fuseGI", (size_t)chunk * per_pos * sizeof(float), &gi_v));
-    MNF_TRY(scratch(ctx, "fuseGW", (size_t)chunk * per_pos * sizeof(float), &gw_v));
-    MNF_TRY(scratch(ctx, "fuseF", (size_t)chunk * per_pos * sizeof(float), &f_v));
-    float* GI = (float*)gi_v;
-    float* GWp = (float*)gw_v;
-    float* F = (float*)f_v;
+    const size_t npix_all = (size_t)H * W;
+    if (npix_all > (size_t)(INT32_MAX / 2)) return set_error(ctx, MNF_EUNSUPPORTED, "pattern of %d x %d too large", H, W);
+    // per-position scratch (floats): level 1 of all K image and weight
+    // pyramids, levels 2..L of one exposure's pyramids, fused levels 1..L
+    std::vector<size_t> offF(L + 2, 0), offS(L + 2, 0);
+    for (int l = 1; l <= L; ++l) offF[l + 1] = offF[l] + (size_t)(H >> l) * (W >> l);
+    for (int l = 2; l <= L; ++l) offS[l + 1] = offS[l] + (size_t)(H >> l) * (W >> l);
+    const size_t n1pos = L >= 1 ? (size_t)(H >> 1) * (W >> 1) : 0;
+    const size_t per_pos = 2 * (size_t)K * n1pos + 2 * offS[L + 1] + offF[L + 1];
+    const size_t budget = (size_t)1 << 30;
+    size_t chunk_cap = per_pos == 0 ? (size_t)J : budget / (per_pos * sizeof(float));
+    chunk_cap = std::min(chunk_cap, (size_t)(INT32_MAX / 2) / npix_all);  // 32-bit pixel indices in a chunk
+    const int chunk = (int)std::max<size_t>(1, std::min<size_t>((size_t)J, chunk_cap));
+    float *GI1 = nullptr, *GW1 = nullptr, *SI = nullptr, *SW = nullptr, *F = nullptr;
+    if (L >= 1) {
+        void *a1, *a2, *a3, *a4, *a5;
+        MNF_TRY(scratch(ctx, "fuseGI1", (size_t)chunk * K * n1pos * sizeof(float), &a1));
+        MNF_TRY(scratch(ctx, "fuseGW1", (size_t)chunk * K * n1pos * sizeof(float), &a2));
+        MNF_TRY(scratch(ctx, "fuseSI", std::max<size_t>(1, (size_t)chunk * offS[L + 1]) * sizeof(float), &a3));
+        MNF_TRY(scratch(ctx, "fuseSW", std::max<size_t>(1, (size_t)chunk * offS[L + 1]) * sizeof(float), &a4));
+        MNF_TRY(scratch(ctx, "fuseF", (size_t)chunk * offF[L + 1] * sizeof(float), &a5));
+        GI1 = (float*)a1;
+        GW1 = (float*)a2;
+        SI = (float*)a3;
+        SW = (float*)a4;
+        F = (float*)a5;
+    }
+    Level0Steps q0{};
+    for (int k = 0; k < K; ++k) q0.step[k] = L >= 1 ? step[k] : 0.f;
     const size_t npix = (size_t)H * W;
+    const bool small_k = K <= 8;
 
     for (int j0 = 0; j0 < J; j0 += chunk) {
         const int nj = std::min(chunk, J - j0);
-        // level-l arrays of the chunk are [nj][h_l][w_l] at offset nj * off[l]
-        auto lvl = [&](float* base, int l) { return base + (size_t)nj * off[l]; };
         const uint16_t* rawc = raw + (size_t)j0 * K * npix;
-        for (int k = 0; k < K; ++k) {
-            const size_t n0 = (size_t)nj * npix;
-            MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level0, grid1d(n0), dim3(256), rawc, K, k, npix, n0, c, GI, GWp, weights_out ? weights_out + (size_t)j0 * K * npix : (float*)nullptr);
-            for (int l = 0; l < L; ++l) {
-                const int h = H >> l, w = W >> l;
-                const size_t n1 = (size_t)nj * (h >> 1) * (w >> 1);
-                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_reduce, grid1d(n1), dim3(256), lvl(GI, l), lvl(GWp, l), h, w, n1, lvl(GI, l + 1), lvl(GWp, l + 1));
+        const size_t n1 = (size_t)nj * n1pos;
+        if (L >= 1) {
+            if (small_k)
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level1<8>, grid1d(n1), dim3(256), rawc, K, H, W, n1, c, GI1, GW1);
+            else
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level1<kMaxK>, grid1d(n1), dim3(256), rawc, K, H, W, n1, c, GI1,
+                           GW1);
+            // level-l arrays (l >= 1) of exposure k and of the fused pyramid
+            auto lvlI = [&](int k, int l) { return l == 1 ? GI1 + (size_t)k * n1 : SI + (size_t)nj * offS[l]; };
+            auto lvlW = [&](int k, int l) { return l == 1 ? GW1 + (size_t)k * n1 : SW + (size_t)nj * offS[l]; };
+            auto lvlF = [&](int l) { return F + (size_t)nj * offF[l]; };
+            for (int k = 0; k < K; ++k) {
+                for (int l = 1; l < L; ++l) {
+                    const int h = H >> l, w = W >> l;
+                    const size_t nn = (size_t)nj * (h >> 1) * (w >> 1);
+                    MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_reduce, grid1d(nn), dim3(256), lvlI(k, l), lvlW(k, l), h, w,
+                               nn, lvlI(k, l + 1), lvlW(k, l + 1));
+                }
+                for (int l = 1; l <= L; ++l) {
+                    const int h = H >> l, w = W >> l;
+                    const size_t nn = (size_t)nj * h * w;
+                    const float sl = l < L ? step[(size_t)l * K + k] : 0.f;
+                    MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_band, grid1d(nn), dim3(256), lvlI(k, l), lvlW(k, l),
+                               l < L ? lvlI(k, l + 1) : (const float*)nullptr, h, w, nn, sl, l == L ? 1 : 0,
+                               k == 0 ? 1 : 0, lvlF(l));
+                }
             }
-            for (int l = 0; l <= L; ++l) {
+            for (int l = L - 1; l >= 1; --l) {
                 const int h = H >> l, w = W >> l;
-                const size_t n = (size_t)nj * h * w;
-                const float s = l < L ? step[(size_t)l * K + k] : 0.f;
-                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_band, grid1d(n), dim3(256), lvl(GI, l), lvl(GWp, l), l < L ? lvl(GI, l + 1) : (const float*)nullptr, h, w, n, s, l == L ? 1 : 0,
-                                   k == 0 ? 1 : 0, lvl(F, l));
+                const size_t nn = (size_t)nj * h * w;
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_collapse, grid1d(nn), dim3(256), lvlF(l + 1), lvlF(l), h, w, nn,
+                           lvlF(l));
             }
         }
+        const size_t n0 = (size_t)nj * npix;
         float* outc = fused + (size_t)j0 * npix;
-        if (L == 0) {
-            MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_copy_f32, grid1d((size_t)nj * npix), dim3(256), outc, lvl(F, 0), (size_t)nj * npix);
-        }
-        for (int l = L - 1; l >= 0; --l) {
-            const int h = H >> l, w = W >> l;
-            const size_t n = (size_t)nj * h * w;
-            MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_collapse, grid1d(n), dim3(256), lvl(F, l + 1), lvl(F, l), h, w, n, l == 0 ? outc : lvl(F, l));
-        }
+        float* wout = weights_out ? weights_out + (size_t)j0 * K * npix : (float*)nullptr;
+        const float* R1 = L >= 1 ? F : (const float*)nullptr;  // fused level 1 sits first in F
+        if (small_k)
+            MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_final<8>, grid1d(n0), dim3(256), rawc, K, H, W, n0, c, q0,
+                       (const float*)GI1, R1, L, outc, wout);
+        else
+            MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_final<kMaxK>, grid1d(n0), dim3(256), rawc, K, H, W, n0, c, q0,
+                       (const float*)GI1, R1, L, outc, wout);
     }
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
