@@ -64,7 +64,7 @@ __device__ __forceinline__ void level0_at(const uint16_t* __restrict__ px, size_
             const float I = (float)px[(size_t)kk * npix];
             const float Ib = fminf(fmaxf((I - c.dark) * c.inv_range, 0.f), 1.f);
             const float d = Ib - c.mu;
-            const float w = expf(-d * d * c.inv_2s2);
+            const float w = __expf(-d * d * c.inv_2s2);  // hardware exp2 path: a few ulp, far inside the 1e-6 weight bound
             wsum += w;
             gw[kk] = w;
             gi[kk] = c.radiometric ? (I - c.dark) * c.scale[kk] : Ib;
@@ -155,42 +155,39 @@ k_fuse_reduce(const float* __restrict__ GI, const float* __restrict__ GW, int h,
     GW1[i] = sw;
 }
 
-// Expand of a coarse image g (hc x wc) evaluated at fine pixel (y, x).
+// Expand of a coarse image g (hc x wc) evaluated at fine pixel (y, x),
+// without branches: always three coarse rows and columns, the third with
+// weight 0 at odd positions (adding 0 * g leaves the sum unchanged), so that
+// neighbouring lanes of alternating parity run the same instructions.
+//   even: taps (c-1, c, c+1) weights (1/8, 3/4, 1/8), c-1 -> 1 at the border
+//   odd : taps (c, c+1, -)   weights (1/2, 1/2, 0),   c+1 -> hc-1 at the border
 __device__ __forceinline__ float expand_at(const float* __restrict__ g, int hc, int wc, int y, int x) {
-    int iy[3], ix[3];
-    float wy[3], wx[3];
-    int ny, nx;
     const int cy = y >> 1, cx = x >> 1;
-    if ((y & 1) == 0) {
-        iy[0] = cy - 1 < 0 ? 1 : cy - 1;
-        iy[1] = cy;
-        iy[2] = cy + 1 >= hc ? hc - 1 : cy + 1;
-        wy[0] = 0.125f; wy[1] = 0.75f; wy[2] = 0.125f;
-        ny = 3;
-    } else {
-        iy[0] = cy;
-        iy[1] = cy + 1 >= hc ? hc - 1 : cy + 1;
-        wy[0] = 0.5f; wy[1] = 0.5f;
-        ny = 2;
-    }
-    if ((x & 1) == 0) {
-        ix[0] = cx - 1 < 0 ? 1 : cx - 1;
-        ix[1] = cx;
-        ix[2] = cx + 1 >= wc ? wc - 1 : cx + 1;
-        wx[0] = 0.125f; wx[1] = 0.75f; wx[2] = 0.125f;
-        nx = 3;
-    } else {
-        ix[0] = cx;
-        ix[1] = cx + 1 >= wc ? wc - 1 : cx + 1;
-        wx[0] = 0.5f; wx[1] = 0.5f;
-        nx = 2;
-    }
-    float s = 0.f;
-    for (int a = 0; a < ny; ++a) {
-        float r = 0.f;
-        for (int b = 0; b < nx; ++b) r += wx[b] * g[(size_t)iy[a] * wc + ix[b]];
-        s += wy[a] * r;
-    }
+    const bool ey = (y & 1) == 0, ex = (x & 1) == 0;
+    const int up = cy + 1 >= hc ? hc - 1 : cy + 1, rt = cx + 1 >= wc ? wc - 1 : cx + 1;
+    const int iy0 = ey ? (cy - 1 < 0 ? 1 : cy - 1) : cy, iy1 = ey ? cy : up, iy2 = up;
+    const int ix0 = ex ? (cx - 1 < 0 ? 1 : cx - 1) : cx, ix1 = ex ? cx : rt, ix2 = rt;
+    const float wy0 = ey ? 0.125f : 0.5f, wy1 = ey ? 0.75f : 0.5f, wy2 = ey ? 0.125f : 0.f;
+    const float wx0 = ex ? 0.125f : 0.5f, wx1 = ex ? 0.75f : 0.5f, wx2 = ex ? 0.125f : 0.f;
+    const float* r0 = g + (size_t)iy0 * wc;
+    const float* r1 = g + (size_t)iy1 * wc;
+    const float* r2 = g + (size_t)iy2 * wc;
+    float s = 0.f, r;
+    r = 0.f;
+    r += wx0 * r0[ix0];
+    r += wx1 * r0[ix1];
+    r += wx2 * r0[ix2];
+    s += wy0 * r;
+    r = 0.f;
+    r += wx0 * r1[ix0];
+    r += wx1 * r1[ix1];
+    r += wx2 * r1[ix2];
+    s += wy1 * r;
+    r = 0.f;
+    r += wx0 * r2[ix0];
+    r += wx1 * r2[ix1];
+    r += wx2 * r2[ix2];
+    s += wy2 * r;
     return s;
 }
 
