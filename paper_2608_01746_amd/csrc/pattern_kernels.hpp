@@ -75,14 +75,15 @@ k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
 enum class ColOp { Modulus, PoissonGrad, AmplitudeGrad };
 
 template <ColOp OP>
-__device__ __forceinline__ float2 col_pointwise(float2 v, float Iq, float eps, double& acc) {
+__device__ __forceinline__ float2 col_pointwise(float2 v, float Iq, float eps, float& accf, double& acc) {
     const float m2 = cabs2(v);
     if constexpr (OP == ColOp::Modulus) {
-        // Fourier-modulus projection against A = sqrt(max(I, 0)); error (|Psi| - A)^2
+        // Fourier-modulus projection against A = sqrt(max(I, 0)); error (|Psi| - A)^2.
+        // Correctly rounded square root and quotient: sequential updates amplify rounding.
         const float a = sqrtf(fmaxf(Iq, 0.f));
         const float mag = sqrtf(m2);
         const float d = mag - a;
-        acc += (double)d * (double)d;
+        accf += d * d;  // a thread's V terms in float32, then float64 across threads
         return m2 > 1e-30f ? cscale(v, a / mag) : make_float2(a, 0.f);
     } else if constexpr (OP == ColOp::PoissonGrad) {
         // l = |Psi|^2 - I ln(|Psi|^2 + eps); g = 2 (1 - I / (|Psi|^2 + eps)) Psi
@@ -94,7 +95,7 @@ __device__ __forceinline__ float2 col_pointwise(float2 v, float Iq, float eps, d
         const float a = sqrtf(fmaxf(Iq, 0.f));
         const float mag = sqrtf(m2);
         const float d = mag - a;
-        acc += (double)d * (double)d;
+        accf += d * d;
         const float f = m2 > 1e-30f ? 2.f * (1.f - a / mag) : 2.f;
         return cscale(v, f);
     }
@@ -140,8 +141,10 @@ k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
 
     const float sc1 = 1.f / (float)N;
     double acc = 0.0;
+    float accf = 0.f;
 #pragma unroll
-    for (int idx = 0; idx < V; ++idx) x[idx] = col_pointwise<OP>(cscale(x[idx], sc1), Iq[idx], eps, acc);
+    for (int idx = 0; idx < V; ++idx) x[idx] = col_pointwise<OP>(cscale(x[idx], sc1), Iq[idx], eps, accf, acc);
+    acc += (double)accf;
     fft_line<N, true>(x, t, lds, ColLds<C>(c), tw);
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
