@@ -89,6 +89,20 @@ int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
                    int J, int K, int H, int W, const mnf_fuse_params* params,
                    float* fused, float* weights_out, void* stream);
 
+/* Linear baselines the fusion is compared against (the Introduction and
+ * Results 2.2-2.3 name linear integration and single exposures without a
+ * formula).
+ * mode 0: per pixel, sum_k m_k (I_k - dark) / sum_k m_k t_k times t[0] over the
+ *         frames below saturation (m_k = [I_k < sat]); the shortest frame's
+ *         I_0 - dark where every frame is saturated.  For Poisson frames this
+ *         is the maximum-likelihood rate, in counts of the shortest exposure.
+ * mode 1: the shortest frame alone, I_0 - dark.
+ * raw device uint16 [J][K][H][W]; t host float [K] (exposure 0 the shortest);
+ * fused device float [J][H][W].  MNF_EINVAL for null pointers, sizes <= 0,
+ * non-positive times, sat <= dark or another mode. */
+int fuse_linear(mnf_ctx* ctx, const uint16_t* raw, const float* t, int J, int K, int H, int W, float sat,
+                float dark, int mode, float* fused, void* stream);
+
 /* ------------------------------------------------------------------------
  * Far-field forward model (Methods 3.3, Eqs. 2-3):
  *   I_out[j] = fftshift |F_unitary(pad_Nd(P * O[pos_j window]))|^2

@@ -15,6 +15,7 @@ ptycho   exit wave (Eq. 2), Fourier-modulus projection, mini-batched
 adjoint  Poisson / amplitude loss on the far-field intensity and its
          gradient with respect to object and probe
 unet     float64 reference of the warm-start network (forward, backward)
+baselines linear-integration and single-exposure fusion, image metrics
 
 Every function states the passage it follows; readings the paper leaves
 open are named where they are used.

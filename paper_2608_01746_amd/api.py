@@ -112,6 +112,26 @@ def fuse_exposures(raw: torch.Tensor, t: Sequence[float], levels: int, mu: float
     return (out, wts) if return_weights else out
 
 
+def fuse_linear(raw: torch.Tensor, t: Sequence[float], sat: float, dark: float = 0.0, mode: str = "linear",
+                out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Linear baselines of raw[J][K][H][W]: 'linear' (rate over unsaturated frames, in counts of
+    the shortest exposure) or 'shortest' (the shortest frame alone) -> float32 [J][H][W]."""
+    _dev(raw, "raw", (torch.uint16, torch.int16), 4)
+    J, K, H, W = raw.shape
+    if len(t) != K:
+        raise ValueError("one exposure time per exposure")
+    if out is None:
+        out = torch.empty((J, H, W), dtype=torch.float32, device=raw.device)
+    else:
+        _dev(out, "out", torch.float32, 3)
+    tt = (ctypes.c_float * K)(*[float(x) for x in t])
+    ctx = _ctx(raw.device)
+    rc = _L.load().fuse_linear(ctx, _ptr(raw), tt, J, K, H, W, float(sat), float(dark),
+                               {"linear": 0, "shortest": 1}[mode], _ptr(out), _stream(raw.device))
+    _check(rc, ctx)
+    return out
+
+
 # ----------------------------------------------------------- forward model
 
 def ptycho_forward(O: torch.Tensor, P: torch.Tensor, pos, Nd: int,

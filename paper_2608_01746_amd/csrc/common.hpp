@@ -1,6 +1,7 @@
 // Shared host/device helpers of libmnfpty: context, error plumbing, scratch.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
@@ -86,16 +87,23 @@ int upload(mnf_ctx* ctx, const char* name, const void* host, size_t bytes,
 // Device twiddle table for length N (computed in float64, rounded to float).
 int twiddles(mnf_ctx* ctx, int N, const float2** out);
 
-// Launch timing: start/stop events around one launch of class `cls`.
-int prof_start(mnf_ctx* ctx, hipStream_t st, hipEvent_t* e0);
-int prof_stop(mnf_ctx* ctx, int cls, hipStream_t st, hipEvent_t e0);
+// Launch timing: a pair of timing events for one launch of class `cls`,
+// passed to the launch itself (hipExtLaunchKernel records them at the start
+// and the end of that kernel's execution, so the interval excludes the
+// queue's dispatch gaps), then queued until read.
+int prof_pair(mnf_ctx* ctx, hipEvent_t* e0, hipEvent_t* e1);
+void prof_push(mnf_ctx* ctx, int cls, hipEvent_t e0, hipEvent_t e1);
 
-#define MNF_LAUNCH(ctx, cls, st, kernel, grid, block, ...)                             \
-    do {                                                                               \
-        hipEvent_t e0_ = nullptr;                                                      \
-        if ((ctx)->prof.mask & (1u << (cls))) MNF_TRY(::mnf::prof_start((ctx), (st), &e0_)); \
-        hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__);                   \
-        if (e0_) MNF_TRY(::mnf::prof_stop((ctx), (cls), (st), e0_));                  \
+#define MNF_LAUNCH(ctx, cls, st, kernel, grid, block, ...)                                   \
+    do {                                                                                     \
+        if ((ctx)->prof.mask & (1u << (cls))) {                                              \
+            hipEvent_t e0_ = nullptr, e1_ = nullptr;                                         \
+            MNF_TRY(::mnf::prof_pair((ctx), &e0_, &e1_));                                    \
+            hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0_, e1_, 0, __VA_ARGS__);     \
+            ::mnf::prof_push((ctx), (cls), e0_, e1_);                                        \
+        } else {                                                                             \
+            hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__);                     \
+        }                                                                                    \
     } while (0)
 
 inline int begin(mnf_ctx* ctx) {

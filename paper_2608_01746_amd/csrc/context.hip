@@ -94,19 +94,13 @@ static int prof_event(mnf_ctx* ctx, hipEvent_t* e) {
     return MNF_OK;
 }
 
-int prof_start(mnf_ctx* ctx, hipStream_t st, hipEvent_t* e0) {
+int prof_pair(mnf_ctx* ctx, hipEvent_t* e0, hipEvent_t* e1) {
     MNF_TRY(prof_event(ctx, e0));
-    MNF_HIP(ctx, hipEventRecord(*e0, st));
+    MNF_TRY(prof_event(ctx, e1));
     return MNF_OK;
 }
 
-int prof_stop(mnf_ctx* ctx, int cls, hipStream_t st, hipEvent_t e0) {
-    hipEvent_t e1;
-    MNF_TRY(prof_event(ctx, &e1));
-    MNF_HIP(ctx, hipEventRecord(e1, st));
-    ctx->prof.pending.push_back({cls, e0, e1});
-    return MNF_OK;
-}
+void prof_push(mnf_ctx* ctx, int cls, hipEvent_t e0, hipEvent_t e1) { ctx->prof.pending.push_back({cls, e0, e1}); }
 
 static int prof_drain(mnf_ctx* ctx) {
     for (auto& p : ctx->prof.pending) {

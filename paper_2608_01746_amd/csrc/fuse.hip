@@ -281,6 +281,33 @@ inline dim3 grid1d(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
 }  // namespace
 
+// Linear baselines: per pixel, the rate sum_k m_k (I_k - dark) / sum_k m_k t_k
+// over the frames below saturation (m_k = [I_k < sat]) times t_1 (mode 0),
+// the shortest frame's value where every frame is saturated; or the shortest
+// frame alone (mode 1).
+__global__ void __launch_bounds__(256)
+k_fuse_linear(const uint16_t* __restrict__ raw, int K, size_t npix, size_t total, const float* __restrict__ t,
+              float sat, float dark, int mode, float* __restrict__ out) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const size_t jj = i / npix, q = i % npix;
+    const uint16_t* px = raw + jj * (size_t)K * npix + q;
+    const float first = (float)px[0] - dark;
+    if (mode == 1) {
+        out[i] = first;
+        return;
+    }
+    float num = 0.f, den = 0.f;
+    for (int k = 0; k < K; ++k) {
+        const float I = (float)px[(size_t)k * npix];
+        if (I < sat) {
+            num += I - dark;
+            den += t[k];
+        }
+    }
+    out[i] = den > 0.f ? num / den * t[0] : first;
+}
+
 extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t, int J, int K, int H, int W,
                               const mnf_fuse_params* p, float* fused, float* weights_out, void* stream) {
     MNF_TRY(begin(ctx));
@@ -400,6 +427,26 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
             MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_final<kMaxK>, grid1d(n0), dim3(256), rawc, K, H, W, n0, c, q0,
                        (const float*)GI1, R1, L, outc, wout);
     }
+    MNF_CHECK_LAUNCH(ctx);
+    return MNF_OK;
+}
+
+extern "C" int fuse_linear(mnf_ctx* ctx, const uint16_t* raw, const float* t, int J, int K, int H, int W, float sat,
+                           float dark, int mode, float* fused, void* stream) {
+    MNF_TRY(begin(ctx));
+    if (!raw || !t || !fused) return set_error(ctx, MNF_EINVAL, "null pointer argument");
+    if (J <= 0 || K <= 0 || H <= 0 || W <= 0)
+        return set_error(ctx, MNF_EINVAL, "sizes must be positive (J=%d K=%d H=%d W=%d)", J, K, H, W);
+    if (mode != 0 && mode != 1) return set_error(ctx, MNF_EINVAL, "mode must be 0 (linear) or 1 (shortest frame)");
+    if (!(sat > dark)) return set_error(ctx, MNF_EINVAL, "sat must exceed dark");
+    for (int k = 0; k < K; ++k)
+        if (!(t[k] > 0.f)) return set_error(ctx, MNF_EINVAL, "exposure time %d must be positive", k);
+    hipStream_t st = (hipStream_t)stream;
+    void* dt;
+    MNF_TRY(upload(ctx, "linear_t", t, sizeof(float) * K, st, &dt));
+    const size_t npix = (size_t)H * W, total = (size_t)J * npix;
+    MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_linear, grid1d(total), dim3(256), raw, K, npix, total, (const float*)dt,
+               sat, dark, mode, fused);
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
 }

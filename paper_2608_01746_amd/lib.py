@@ -47,6 +47,8 @@ SIGNATURES = {
     "mnf_supported_sizes": (c_int, [POINTER(c_int32), c_int]),
     "fuse_exposures": (c_int, [c_void_p, c_void_p, POINTER(c_float), c_int, c_int, c_int, c_int,
                                POINTER(FuseParamsC), c_void_p, c_void_p, c_void_p]),
+    "fuse_linear": (c_int, [c_void_p, c_void_p, POINTER(c_float), c_int, c_int, c_int, c_int, c_float, c_float,
+                            c_int, c_void_p, c_void_p]),
     "ptycho_forward": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_int,
                                POINTER(c_int32), c_int, c_void_p, c_void_p]),
     "ptycho_iterate": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
