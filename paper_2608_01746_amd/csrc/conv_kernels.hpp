@@ -59,8 +59,20 @@ struct ConvArgs {
     int per_pad;            // UP: input pixels per parity group rounded up to the row tile
 };
 
-constexpr int kGemmBM = 128, kGemmBN = 64, kGemmBK = 32, kGemmThreads = 256;
-constexpr int kLdsK = kGemmBK + 8;  // padded row (bf16) of the LDS tiles
+constexpr int kGemmBM = 128, kGemmBN = 64, kGemmThreads = 256;
+
+// K chunk per global round trip: 64 (four MFMA steps per wave) for long
+// reductions, 32 for short ones (the first layer has K = 9); Kpad is K rounded
+// up to the chunk, so the chunk follows from Kpad alone (Kpad > 64 <=> 64).
+__host__ __device__ constexpr int gemm_bk(int K) { return K <= 64 ? 32 : 64; }
+
+template <int BK>
+struct GemmTile {
+    static constexpr int LDS = BK + 8;                  // padded LDS row (bf16)
+    static constexpr int TPR = BK / 8;                  // threads per row, 8 columns each
+    static constexpr int RSTEP = kGemmThreads / TPR;    // rows one pass of the block loads
+    static constexpr int ACH = kGemmBM / RSTEP, BCH = kGemmBN / RSTEP;
+};
 
 // Input pixel feeding GEMM row m and column k (tap = k / Cin) for the forward
 // gather; returns false for zero padding.  For UP the tap is the output
@@ -157,39 +169,43 @@ __device__ __forceinline__ uint4 load_a8(const ConvArgs& a, int m, int k) {
     }
 }
 
-template <int MODE, bool MASK, bool VEC, bool OUT_F32>
+template <int MODE, bool MASK, bool VEC, bool OUT_F32, int BK>
 __global__ void __launch_bounds__(kGemmThreads) k_conv_gemm(ConvArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t sA[kGemmBM * kLdsK];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[kGemmBN * kLdsK];
+    using G = GemmTile<BK>;
+    __shared__ __attribute__((aligned(16))) uint16_t sA[kGemmBM * G::LDS];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[kGemmBN * G::LDS];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int m0 = blockIdx.x * kGemmBM, n0 = blockIdx.y * kGemmBN;
     const uint16_t* Bt = a.Bt;
     if constexpr (MODE == UP) Bt += (size_t)(m0 / a.per_pad) * a.Nout * a.Kpad;  // the tile's parity selects the tap
     f32x16_t acc0 = {}, acc1 = {};
-    // per-thread load slots: two A chunks (rows tid/4 and 64 + tid/4), one B chunk
-    const int ar = tid >> 2, ac = (tid & 3) * 8;
-    const int bn = tid >> 2, bc = (tid & 3) * 8;
-    uint4 ra0, ra1, rb;
+    // per-thread load slots: A rows tid/TPR + RSTEP q, B rows likewise, eight columns each
+    const int ar = tid / G::TPR, ac = (tid % G::TPR) * 8;
+    uint4 ra[G::ACH], rb[G::BCH];
     auto fetch = [&](int k0) {
-        ra0 = load_a8<MODE, MASK, VEC>(a, m0 + ar, k0 + ac);
-        ra1 = load_a8<MODE, MASK, VEC>(a, m0 + 64 + ar, k0 + ac);
-        rb = make_uint4(0, 0, 0, 0);
-        if (n0 + bn < a.Nout) rb = *(const uint4*)(Bt + (size_t)(n0 + bn) * a.Kpad + k0 + bc);
+#pragma unroll
+        for (int q = 0; q < G::ACH; ++q) ra[q] = load_a8<MODE, MASK, VEC>(a, m0 + G::RSTEP * q + ar, k0 + ac);
+#pragma unroll
+        for (int q = 0; q < G::BCH; ++q) {
+            const int n = n0 + G::RSTEP * q + ar;
+            rb[q] = n < a.Nout ? *(const uint4*)(Bt + (size_t)n * a.Kpad + k0 + ac) : make_uint4(0, 0, 0, 0);
+        }
     };
     fetch(0);
-    for (int k0 = 0; k0 < a.Kpad; k0 += kGemmBK) {
+    for (int k0 = 0; k0 < a.Kpad; k0 += BK) {
         __syncthreads();
-        *(uint4*)(sA + ar * kLdsK + ac) = ra0;
-        *(uint4*)(sA + (64 + ar) * kLdsK + ac) = ra1;
-        *(uint4*)(sB + bn * kLdsK + bc) = rb;
-        __syncthreads();
-        if (k0 + kGemmBK < a.Kpad) fetch(k0 + kGemmBK);  // next chunk in flight during the MFMAs
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
+        for (int q = 0; q < G::ACH; ++q) *(uint4*)(sA + (G::RSTEP * q + ar) * G::LDS + ac) = ra[q];
+#pragma unroll
+        for (int q = 0; q < G::BCH; ++q) *(uint4*)(sB + (G::RSTEP * q + ar) * G::LDS + ac) = rb[q];
+        __syncthreads();
+        if (k0 + BK < a.Kpad) fetch(k0 + BK);  // next chunk in flight during the MFMAs
+#pragma unroll
+        for (int s = 0; s < BK / 16; ++s) {
             const int kk = s * 16 + 8 * (lane >> 5);
-            const bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sA + (32 * w + (lane & 31)) * kLdsK + kk));
-            const bf16x8_t b0 = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (lane & 31) * kLdsK + kk));
-            const bf16x8_t b1 = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (32 + (lane & 31)) * kLdsK + kk));
+            const bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sA + (32 * w + (lane & 31)) * G::LDS + kk));
+            const bf16x8_t b0 = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (lane & 31) * G::LDS + kk));
+            const bf16x8_t b1 = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (32 + (lane & 31)) * G::LDS + kk));
             acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
         }
@@ -237,14 +253,84 @@ struct WgradArgs {
     int P;                 // pixels in the reduction
 };
 
-constexpr int kWgK = 32;
+constexpr int kWgK = 64;           // pixels per global round trip
+constexpr int kWgLds = kWgK + 8;  // padded row (bf16) of the weight-gradient LDS tiles
+
+// Input pixel and output-gradient pixel of reduction index p at this tap;
+// false where the input pixel is zero padding.
+template <int MODE>
+__device__ __forceinline__ bool wgrad_pixels(const WgradArgs& a, int p, int tap, size_t* ipix, size_t* gpix) {
+    if constexpr (MODE == UP) {
+        const int x = p % a.Win, t1 = p / a.Win, y = t1 % a.Hin, img = t1 / a.Hin;
+        *ipix = (size_t)p;
+        *gpix = ((size_t)img * a.Hout + 2 * y + tap / 2) * a.Wout + 2 * x + tap % 2;
+        return true;
+    } else {
+        const int x = p % a.Wout, t1 = p / a.Wout, y = t1 % a.Hout, img = t1 / a.Hout;
+        int yy = y, xx = x;
+        if constexpr (MODE == CONV3) {
+            yy = y + tap / 3 - 1;
+            xx = x + tap % 3 - 1;
+        } else if constexpr (MODE == DOWN) {
+            yy = 2 * y + tap / 2;
+            xx = 2 * x + tap % 2;
+        }
+        *ipix = ((size_t)img * a.Hin + yy) * a.Win + xx;
+        *gpix = (size_t)p;
+        return yy >= 0 && yy < a.Hin && xx >= 0 && xx < a.Win;
+    }
+}
+
+// Eight input channels (va) and eight masked output-gradient channels (vb) of
+// reduction index p (zeros outside the range, the padding and the channels).
+template <int MODE, bool VEC>
+__device__ __forceinline__ void wgrad_load(const WgradArgs& a, int p, int p_end, int tap, int cia, int cob,
+                                           uint16_t* va, uint16_t* vb) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) va[q] = vb[q] = 0;
+    if (p >= p_end) return;
+    size_t ipix, gpix;
+    const bool ok = wgrad_pixels<MODE>(a, p, tap, &ipix, &gpix);
+    if (VEC && cia + 8 <= a.Cin) {
+        if (ok) *(uint4*)va = *(const uint4*)(a.in + ipix * a.in_cs + a.in_co + cia);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (ok && cia + q < a.Cin) va[q] = a.in[ipix * a.in_cs + a.in_co + cia + q];
+    }
+    if (VEC && cob + 8 <= a.Cout) {
+        *(uint4*)vb = *(const uint4*)(a.dout + gpix * a.dout_cs + cob);
+        if (a.act) {
+            const uint4 h4 = *(const uint4*)(a.act + gpix * a.act_cs + a.act_co + cob);
+            const uint16_t* h = (const uint16_t*)&h4;
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (h[q] == 0 || (h[q] & 0x8000u)) vb[q] = 0;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int co = cob + q;
+            if (co < a.Cout) {
+                uint16_t g = a.dout[gpix * a.dout_cs + co];
+                if (a.act) {
+                    const uint16_t h = a.act[gpix * a.act_cs + a.act_co + co];
+                    if (h == 0 || (h & 0x8000u)) g = 0;
+                }
+                vb[q] = g;
+            }
+        }
+    }
+}
 
 // VEC: 16-byte loads of 8 channels; needs channel strides and offsets that are
 // multiples of 8 (the partial last group of channels falls back to scalar loads).
+// Each thread loads two adjacent pixels per round trip, so the transposition
+// into the [channel][pixel] LDS tiles writes 32-bit pixel pairs.
 template <int MODE, bool VEC>
 __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t sA[64 * kLdsK];  // [ci][pixel]
-    __shared__ __attribute__((aligned(16))) uint16_t sB[64 * kLdsK];  // [co][pixel]
+    __shared__ __attribute__((aligned(16))) uint16_t sA[64 * kWgLds];  // [ci][pixel]
+    __shared__ __attribute__((aligned(16))) uint16_t sB[64 * kWgLds];  // [co][pixel]
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int co0 = blockIdx.x * 64, ci0 = blockIdx.y * 64;
     const int tap = blockIdx.z % a.taps, split = blockIdx.z / a.taps;
@@ -252,7 +338,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
     const int p_begin = split * per, p_end = min(a.P, p_begin + per);
     f32x16_t acc = {};
     const int wr = (w & 1) * 32, wc = (w >> 1) * 32;
-    // loader: thread -> (pixel tid / 8, 8 consecutive channels (tid % 8) * 8)
+    // loader: thread -> (pixels 2 (tid / 8) and 2 (tid / 8) + 1, 8 consecutive channels (tid % 8) * 8)
     const int lp = tid >> 3, lc = (tid & 7) * 8;
     // The bias gradient is the sum of the masked output gradient over the pixels:
     // blocks of the first input-channel tile add up the dout values they load
@@ -260,80 +346,26 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
     const bool do_bias = blockIdx.y == 0 && (MODE == UP || tap == 0);
     float bsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     for (int p0 = p_begin; p0 < p_end; p0 += kWgK) {
-        const int p = p0 + lp;
-        uint16_t va[8] __attribute__((aligned(16))), vb[8] __attribute__((aligned(16)));
-#pragma unroll
-        for (int q = 0; q < 8; ++q) va[q] = vb[q] = 0;
-        if (p < p_end) {
-            // input pixel and gradient pixel of this reduction index
-            size_t ipix, gpix;
-            bool ok = true;
-            if constexpr (MODE == UP) {
-                const int x = p % a.Win, t1 = p / a.Win, y = t1 % a.Hin, img = t1 / a.Hin;
-                ipix = (size_t)p;
-                gpix = ((size_t)img * a.Hout + 2 * y + tap / 2) * a.Wout + 2 * x + tap % 2;
-            } else {
-                const int x = p % a.Wout, t1 = p / a.Wout, y = t1 % a.Hout, img = t1 / a.Hout;
-                int yy = y, xx = x;
-                if constexpr (MODE == CONV3) {
-                    yy = y + tap / 3 - 1;
-                    xx = x + tap % 3 - 1;
-                } else if constexpr (MODE == DOWN) {
-                    yy = 2 * y + tap / 2;
-                    xx = 2 * x + tap % 2;
-                }
-                ok = yy >= 0 && yy < a.Hin && xx >= 0 && xx < a.Win;
-                ipix = ((size_t)img * a.Hin + yy) * a.Win + xx;
-                gpix = (size_t)p;
-            }
-            const int cia = ci0 + lc, cob = co0 + lc;
-            if (VEC && cia + 8 <= a.Cin) {
-                if (ok) *(uint4*)va = *(const uint4*)(a.in + ipix * a.in_cs + a.in_co + cia);
-            } else {
-#pragma unroll
-                for (int q = 0; q < 8; ++q)
-                    if (ok && cia + q < a.Cin) va[q] = a.in[ipix * a.in_cs + a.in_co + cia + q];
-            }
-            if (VEC && cob + 8 <= a.Cout) {
-                *(uint4*)vb = *(const uint4*)(a.dout + gpix * a.dout_cs + cob);
-                if (a.act) {
-                    const uint4 h4 = *(const uint4*)(a.act + gpix * a.act_cs + a.act_co + cob);
-                    const uint16_t* h = (const uint16_t*)&h4;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q)
-                        if (h[q] == 0 || (h[q] & 0x8000u)) vb[q] = 0;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    const int co = cob + q;
-                    if (co < a.Cout) {
-                        uint16_t g = a.dout[gpix * a.dout_cs + co];
-                        if (a.act) {
-                            const uint16_t h = a.act[gpix * a.act_cs + a.act_co + co];
-                            if (h == 0 || (h & 0x8000u)) g = 0;
-                        }
-                        vb[q] = g;
-                    }
-                }
-            }
-        }
+        uint16_t va0[8] __attribute__((aligned(16))), vb0[8] __attribute__((aligned(16)));
+        uint16_t va1[8] __attribute__((aligned(16))), vb1[8] __attribute__((aligned(16)));
+        wgrad_load<MODE, VEC>(a, p0 + 2 * lp, p_end, tap, ci0 + lc, co0 + lc, va0, vb0);
+        wgrad_load<MODE, VEC>(a, p0 + 2 * lp + 1, p_end, tap, ci0 + lc, co0 + lc, va1, vb1);
         if (do_bias) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) bsum[q] += bf2f(vb[q]);
+            for (int q = 0; q < 8; ++q) bsum[q] += bf2f(vb0[q]) + bf2f(vb1[q]);
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-            sA[(lc + q) * kLdsK + lp] = va[q];
-            sB[(lc + q) * kLdsK + lp] = vb[q];
+            *(uint32_t*)(sA + (lc + q) * kWgLds + 2 * lp) = (uint32_t)va0[q] | ((uint32_t)va1[q] << 16);
+            *(uint32_t*)(sB + (lc + q) * kWgLds + 2 * lp) = (uint32_t)vb0[q] | ((uint32_t)vb1[q] << 16);
         }
         __syncthreads();
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
+        for (int s = 0; s < kWgK / 16; ++s) {
             const int kk = s * 16 + 8 * (lane >> 5);
-            const bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sA + (wr + (lane & 31)) * kLdsK + kk));
-            const bf16x8_t bv = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (wc + (lane & 31)) * kLdsK + kk));
+            const bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sA + (wr + (lane & 31)) * kWgLds + kk));
+            const bf16x8_t bv = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (wc + (lane & 31)) * kWgLds + kk));
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc, 0, 0, 0);
         }
     }
@@ -345,7 +377,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
             a.part[(((size_t)split * a.taps + tap) * a.Cin + i) * a.Cout + j] = acc[v];
     }
     if (do_bias) {
-        // sum the 32 pixel rows of each channel in a fixed order
+        // sum the 32 pixel-pair rows of each channel in a fixed order
         __shared__ float bred[kGemmThreads * 8];
 #pragma unroll
         for (int q = 0; q < 8; ++q) bred[tid * 8 + q] = bsum[q];
@@ -358,6 +390,30 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
             a.bpart[((size_t)split * (MODE == UP ? 4 : 1) + bt) * a.Cout + co0 + tid] = r;
         }
     }
+}
+
+// dW = sum over splits (fixed order); grid ceil(taps*Ci*Co / 256).
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, size_t count, float* __restrict__ dW) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    float s = 0.f;
+    for (int k = 0; k < splits; ++k) s += part[(size_t)k * count + i];
+    dW[i] = s;
+}
+
+// The same sum for many partials and few outputs: one wave per output, lane l
+// adding partials l, l + 64, ..., then a butterfly across the wave (a fixed
+// order); grid ceil(count / 4), block 256.
+__global__ void __launch_bounds__(256) k_wgrad_reduce_wide(const float* __restrict__ part, int splits, size_t count,
+                                                           float* __restrict__ dW) {
+    const size_t i = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    float s = 0.f;
+    if (i < count)
+        for (int k = lane; k < splits; k += 64) s += part[(size_t)k * count + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (i < count && lane == 0) dW[i] = s;
 }
 
 // Weight and bias gradient of a 3x3 convolution with one input channel (the
@@ -431,23 +487,7 @@ __global__ void __launch_bounds__(256) k_wgrad_c1(WgradArgs a, int per) {
     }
 }
 
-// dW = sum over splits (fixed order); grid ceil(taps*Ci*Co / 256).
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, size_t count, float* __restrict__ dW) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= count) return;
-    float s = 0.f;
-    for (int k = 0; k < splits; ++k) s += part[(size_t)k * count + i];
-    dW[i] = s;
-}
 
-// db = sum over partials (fixed order); grid ceil(Cout / 256).
-__global__ void k_bias_reduce(const float* __restrict__ part, int nb, int Cout, float* __restrict__ db) {
-    const int co = blockIdx.x * blockDim.x + threadIdx.x;
-    if (co >= Cout) return;
-    float s = 0.f;
-    for (int b = 0; b < nb; ++b) s += part[(size_t)b * Cout + co];
-    db[co] = s;
-}
 
 // GEMM-order bf16 weights from float32 W[taps][Ci][Co]:
 //   kind 0: Bt[co][tap * Ci + ci] = W[tap][ci][co]            (forward CONV3 / DOWN / CONV1)

@@ -62,6 +62,8 @@ int check_shape(mnf_ctx* ctx, const mnf_unet_shape* s) {
 
 inline unsigned g1(size_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
 int round_up(int x, int m) { return (x + m - 1) / m * m; }
+// GEMM reduction length padded to the kernel's K chunk.
+int kpad_of(int K) { return round_up(K, gemm_bk(K)); }
 
 // A bf16 channels-last tensor view.
 struct View {
@@ -75,24 +77,25 @@ int launch_conv(mnf_ctx* ctx, int mode, bool mask, bool out_f32, const ConvArgs&
     const bool vec = a.Cin % 8 == 0 && a.in_cs % 8 == 0 && a.in_co % 8 == 0 &&
                      (!mask || (a.mask_cs % 8 == 0 && a.mask_co % 8 == 0));
     const dim3 grid(g1((size_t)a.M, kGemmBM), g1((size_t)a.Nout, kGemmBN));
-#define MNF_CONV_CASE(MD)                                                                                      \
-    if (mode == MD) {                                                                                          \
-        if (mask) {                                                                                            \
-            if (vec) hipLaunchKernelGGL((k_conv_gemm<MD, true, true, false>), grid, dim3(kGemmThreads), 0, st, a); \
-            else hipLaunchKernelGGL((k_conv_gemm<MD, true, false, false>), grid, dim3(kGemmThreads), 0, st, a);    \
-        } else if (out_f32) {                                                                                  \
-            if (vec) hipLaunchKernelGGL((k_conv_gemm<MD, false, true, true>), grid, dim3(kGemmThreads), 0, st, a); \
-            else hipLaunchKernelGGL((k_conv_gemm<MD, false, false, true>), grid, dim3(kGemmThreads), 0, st, a);    \
-        } else {                                                                                               \
-            if (vec) hipLaunchKernelGGL((k_conv_gemm<MD, false, true, false>), grid, dim3(kGemmThreads), 0, st, a); \
-            else hipLaunchKernelGGL((k_conv_gemm<MD, false, false, false>), grid, dim3(kGemmThreads), 0, st, a);   \
-        }                                                                                                      \
+#define MNF_CONV_BK(MD, MK, VC, OF)                                                                    \
+    if (a.Kpad > 64) hipLaunchKernelGGL((k_conv_gemm<MD, MK, VC, OF, 64>), grid, dim3(kGemmThreads), 0, st, a); \
+    else hipLaunchKernelGGL((k_conv_gemm<MD, MK, VC, OF, 32>), grid, dim3(kGemmThreads), 0, st, a);
+#define MNF_CONV_CASE(MD)                                                                              \
+    if (mode == MD) {                                                                                  \
+        if (mask) {                                                                                    \
+            if (vec) { MNF_CONV_BK(MD, true, true, false) } else { MNF_CONV_BK(MD, true, false, false) } \
+        } else if (out_f32) {                                                                          \
+            if (vec) { MNF_CONV_BK(MD, false, true, true) } else { MNF_CONV_BK(MD, false, false, true) } \
+        } else {                                                                                       \
+            if (vec) { MNF_CONV_BK(MD, false, true, false) } else { MNF_CONV_BK(MD, false, false, false) } \
+        }                                                                                              \
     }
     MNF_CONV_CASE(CONV3)
     MNF_CONV_CASE(DOWN)
     MNF_CONV_CASE(UP)
     MNF_CONV_CASE(CONV1)
 #undef MNF_CONV_CASE
+#undef MNF_CONV_BK
     return MNF_OK;
 }
 
@@ -127,8 +130,8 @@ ConvArgs fwd_args(int mode, View in, int n, int Hin, int Ci, const uint16_t* Bt,
     a.Nout = Co;
     a.relu = relu ? 1 : 0;
     set_rows(a, mode);
-    a.Kpad = round_up(taps_of(mode) * Ci, kGemmBK);
-    if (mode == UP) a.Kpad = round_up(Ci, kGemmBK);
+    a.Kpad = kpad_of(taps_of(mode) * Ci);
+    if (mode == UP) a.Kpad = kpad_of(Ci);
     return a;
 }
 
@@ -161,7 +164,7 @@ ConvArgs dgrad_args(int mode, View dY, View act, bool mask, int n, int Hout, int
     a.Hout = a.Wout = dm == DOWN ? Hout / 2 : (dm == UP ? Hout * 2 : Hout);
     a.Nout = Ci;
     set_rows(a, dm);
-    a.Kpad = dm == UP ? round_up(Co, kGemmBK) : round_up(taps_of(dm) * Co, kGemmBK);
+    a.Kpad = dm == UP ? kpad_of(Co) : kpad_of(taps_of(dm) * Co);
     return a;
 }
 
@@ -173,22 +176,22 @@ int prep_layer_weights(mnf_ctx* ctx, const LayerDesc& L, const float* W, uint16_
     switch (L.mode) {
         case CONV3:
             kf = 0; kd = 1;
-            Kf = round_up(9 * L.ci, kGemmBK); Kd = round_up(9 * L.co, kGemmBK);
+            Kf = kpad_of(9 * L.ci); Kd = kpad_of(9 * L.co);
             nf = (size_t)L.co * Kf; nd = (size_t)L.ci * Kd;
             break;
         case DOWN:
             kf = 0; kd = 3;
-            Kf = round_up(4 * L.ci, kGemmBK); Kd = round_up(L.co, kGemmBK);
+            Kf = kpad_of(4 * L.ci); Kd = kpad_of(L.co);
             nf = (size_t)L.co * Kf; nd = (size_t)4 * L.ci * Kd;
             break;
         case UP:
             kf = 2; kd = 4;
-            Kf = round_up(L.ci, kGemmBK); Kd = round_up(4 * L.co, kGemmBK);
+            Kf = kpad_of(L.ci); Kd = kpad_of(4 * L.co);
             nf = (size_t)4 * L.co * Kf; nd = (size_t)L.ci * Kd;
             break;
         default:
             kf = 0; kd = 4;
-            Kf = round_up(L.ci, kGemmBK); Kd = round_up(L.co, kGemmBK);
+            Kf = kpad_of(L.ci); Kd = kpad_of(L.co);
             nf = (size_t)L.co * Kf; nd = (size_t)L.ci * Kd;
             break;
     }
@@ -199,19 +202,28 @@ int prep_layer_weights(mnf_ctx* ctx, const LayerDesc& L, const float* W, uint16_
 
 size_t bf_size(const LayerDesc& L) {
     switch (L.mode) {
-        case CONV3: return (size_t)L.co * round_up(9 * L.ci, kGemmBK);
-        case DOWN: return (size_t)L.co * round_up(4 * L.ci, kGemmBK);
-        case UP: return (size_t)4 * L.co * round_up(L.ci, kGemmBK);
-        default: return (size_t)L.co * round_up(L.ci, kGemmBK);
+        case CONV3: return (size_t)L.co * kpad_of(9 * L.ci);
+        case DOWN: return (size_t)L.co * kpad_of(4 * L.ci);
+        case UP: return (size_t)4 * L.co * kpad_of(L.ci);
+        default: return (size_t)L.co * kpad_of(L.ci);
     }
 }
 size_t bd_size(const LayerDesc& L) {
     switch (L.mode) {
-        case CONV3: return (size_t)L.ci * round_up(9 * L.co, kGemmBK);
-        case DOWN: return (size_t)4 * L.ci * round_up(L.co, kGemmBK);
-        case UP: return (size_t)L.ci * round_up(4 * L.co, kGemmBK);
-        default: return (size_t)L.ci * round_up(L.co, kGemmBK);
+        case CONV3: return (size_t)L.ci * kpad_of(9 * L.co);
+        case DOWN: return (size_t)4 * L.ci * kpad_of(L.co);
+        case UP: return (size_t)L.ci * kpad_of(4 * L.co);
+        default: return (size_t)L.ci * kpad_of(L.co);
     }
+}
+
+// Fixed-order sum of `splits` float32 partial arrays of `count` values: one
+// thread per value for few partials, one wave per value for many.
+void reduce_partials(const float* part, int splits, size_t count, float* out, hipStream_t st) {
+    if (splits >= 64)
+        hipLaunchKernelGGL(k_wgrad_reduce_wide, dim3(g1(count, 4)), dim3(256), 0, st, part, splits, count, out);
+    else
+        hipLaunchKernelGGL(k_wgrad_reduce, dim3(g1(count)), dim3(256), 0, st, part, splits, count, out);
 }
 
 // Weight and bias gradient of a layer into dW (float32, [taps][ci][co]) and db.
@@ -251,9 +263,8 @@ int layer_wgrad(mnf_ctx* ctx, const LayerDesc& L, View x, int n, int Hin, View d
         a.part = (float*)part;
         a.bpart = (float*)bpart;
         hipLaunchKernelGGL(k_wgrad_c1, dim3(nb), dim3(256), 0, st, a, per);
-        hipLaunchKernelGGL(k_wgrad_reduce, dim3(g1(count)), dim3(256), 0, st, (const float*)part, nb, count, dW);
-        hipLaunchKernelGGL(k_bias_reduce, dim3(g1((size_t)L.co)), dim3(256), 0, st, (const float*)bpart, nb, L.co,
-                           db);
+        reduce_partials((const float*)part, nb, count, dW, st);
+        reduce_partials((const float*)bpart, nb, (size_t)L.co, db, st);
         return MNF_OK;
     }
     const int target_blocks = 1024;
@@ -281,10 +292,9 @@ int layer_wgrad(mnf_ctx* ctx, const LayerDesc& L, View x, int n, int Hin, View d
         default: MNF_WGRAD(CONV1); break;
     }
 #undef MNF_WGRAD
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(g1(count)), dim3(256), 0, st, (const float*)part, a.splits, count, dW);
+    reduce_partials((const float*)part, a.splits, count, dW, st);
     // bias: the kernel's per-(split, tap) sums of the masked output gradient
-    hipLaunchKernelGGL(k_bias_reduce, dim3(g1((size_t)L.co)), dim3(256), 0, st, (const float*)bpart,
-                       a.splits * btaps, L.co, db);
+    reduce_partials((const float*)bpart, a.splits * btaps, (size_t)L.co, db, st);
     return MNF_OK;
 }
 
