@@ -25,6 +25,7 @@ start (t_plain / t_warm), after training the network on 50,000 simulated
 fused patterns (training time reported separately, excluded).  Its roofline
 entry is the network's forward pass in TFLOP/s against the bf16 MFMA peak.
 
+--workload unet times the network's training step and inference alone.
 --workload batch-sweep times the lab-scale reconstruction at mini-batches
 8..256 (per-launch durations of every pass), and --workload fusion-compare
 compares MNF with linear integration and the shortest frame on the small
@@ -441,6 +442,49 @@ def _illum_mask(P, pos, shape, frac=0.1):
     return ill >= frac * ill.max()
 
 
+def run_unet(args, api, synth, dev):
+    """The warm-start network's kernels alone: Adam training steps at batch 64
+    and inference over 100 patterns, 256^2 inputs, widths 32/64/128/256, timed
+    with events; value = training samples/s, roofline = training TFLOP/s
+    (forward + input gradient + weight gradient flops of the layer shapes)
+    against the dense bf16 MFMA peak."""
+    import torch
+
+    from paper_2608_01746_amd import warmstart as ws
+
+    S = ws.setup()
+    data = ws.simulate(S, range(5000, 5004), "fused", dev, relative=True)
+    params = ws.init_params(ws.WIDTHS, 0, dev)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    I, T = data["I"][:64].contiguous(), data["target"][:64].contiguous()
+    for step in range(1, 4):
+        api.unet_train_step(params, m, v, step, 1e-3, I, S.log_scale, T, ws.H, ws.WIDTHS)
+    n_steps = max(args.steps, 10)
+
+    def train():
+        for k in range(n_steps):
+            api.unet_train_step(params, m, v, 4 + k, 1e-3, I, S.log_scale, T, ws.H, ws.WIDTHS)
+
+    t_train = ws._elapsed(train, dev) / n_steps
+    I100 = data["I"][:100].contiguous()
+    out = torch.empty((100, S.w.Nw, S.w.Nw, 2), dtype=torch.float32, device=dev)
+    api.unet_forward(params, I100, S.log_scale, ws.H, ws.WIDTHS, out=out)
+    t_inf = ws._elapsed(lambda: [api.unet_forward(params, I100, S.log_scale, ws.H, ws.WIDTHS, out=out)
+                                 for _ in range(n_steps)], dev) / n_steps
+    tf_train = 64 * ws.train_flops_per_sample(ws.H, ws.WIDTHS) / t_train / 1e12
+    tf_inf = 100 * sum(ws.layer_flops(ws.H, ws.WIDTHS)) / t_inf / 1e12
+    return {"metric": "U-Net training samples/s (256^2 inputs, batch 64, Adam)", "value": round(64 / t_train, 1),
+            "unit": "samples/s", "n_gpus": 1, "steps": n_steps, "warmup": 3, "ms_per_step": round(t_train * 1e3, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "bf16 (f32 accumulate, f32 master weights)", "data": "synthetic (simulated fused patterns)",
+            "config": {"workload": "U-Net 32/64/128/256, 256^2 log-fused input -> 64^2 x 2 output, batch 64"},
+            "roofline": {"bound": "mfma", "kernel": "whole training step", "achieved": round(tf_train, 1),
+                         "peak": 2500.0, "unit": "TFLOP/s", "frac": round(tf_train / 2500.0, 4), "traffic": None},
+            "inference": {"patterns": 100, "ms": round(t_inf * 1e3, 3), "tflops": round(tf_inf, 1),
+                          "frac": round(tf_inf / 2500.0, 4)}}
+
+
 def run_warmstart(args, api, synth, dev):
     """Learned warm start on the small geometry with a 256^2 detector: train
     the U-Net (excluded from the timed comparison), then for ten test objects
@@ -575,8 +619,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=None, help="iterations per step (200 lab, 20 multiscan)")
-    ap.add_argument("--workload", choices=["lab", "multiscan", "warmstart", "batch-sweep", "fusion-compare"],
-                    default="lab")
+    ap.add_argument("--workload", choices=["lab", "multiscan", "warmstart", "batch-sweep", "fusion-compare",
+                                           "unet"], default="lab")
     ap.add_argument("--train-seconds", type=float, default=240.0, help="warm start: training time budget")
     ap.add_argument("--train-objects", type=int, default=500, help="warm start: training objects x 100 patterns")
     ap.add_argument("--epochs", type=float, default=100.0, help="warm start: epoch cap")
@@ -608,7 +652,7 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     run = {"lab": run_lab, "multiscan": run_multiscan, "warmstart": run_warmstart,
-           "batch-sweep": run_batch_sweep, "fusion-compare": run_fusion_compare}[args.workload]
+           "batch-sweep": run_batch_sweep, "fusion-compare": run_fusion_compare, "unet": run_unet}[args.workload]
     out = run(args, api, synth, dev)
     print(json.dumps(out))
     return 0
