@@ -214,14 +214,35 @@ def _elapsed(fn, device) -> float:
     return e0.elapsed_time(e1) * 1e-3
 
 
+def covering_subset(pos: np.ndarray, min_dist: float) -> np.ndarray:
+    """Indices of scan windows chosen by farthest-point sampling: start from the
+    window farthest from the scan's centroid, repeatedly add the window farthest
+    from those chosen, stop when every window lies within `min_dist` of a chosen
+    one.  The corners and edges of the scan are taken first, so the network can
+    run on these patterns only while the stitch still covers the scanned area
+    with overlapping windows.  Returned in scan order."""
+    p = np.asarray(pos, float)
+    first = int(np.argmax(np.hypot(*(p - p.mean(axis=0)).T)))
+    keep = [first]
+    d = np.hypot(*(p - p[first]).T)
+    while True:
+        j = int(np.argmax(d))
+        if d[j] < min_dist:
+            break
+        keep.append(j)
+        d = np.minimum(d, np.hypot(*(p - p[j]).T))
+    return np.sort(np.asarray(keep, np.int64))
+
+
 def time_to_threshold(S: Setup, data, params: Optional[torch.Tensor], tau: float = 1e-2,
                       max_plain: int = 200, max_warm: int = 50, alpha: float = 0.1,
-                      sync: bool = False) -> List[Dict[str, object]]:
+                      sync: bool = False, subset: Optional[np.ndarray] = None) -> List[Dict[str, object]]:
     """For every object of `data`: NRMSE per iteration from a flat start and
     from the network's stitched start, the iteration count at which each
     first reaches tau, and the timed cost of reaching it:
       plain: n_plain iterations;  warm: inference + stitching + n_warm iterations,
-    each timed as one event-bracketed run on the stream."""
+    each timed as one event-bracketed run on the stream.  With `subset`
+    (window indices), the network runs on those patterns only."""
     w = S.w
     dev = data["I"].device
     J = len(S.pos)
@@ -258,12 +279,15 @@ def time_to_threshold(S: Setup, data, params: Optional[torch.Tensor], tau: float
         Ox = flat.clone()
         r["t_iter"] = _elapsed(lambda: api.ptycho_iterate(Ox, Pk, I, S.pos, 10, **kw), dev) / 10
         if params is not None:
-            patches = torch.empty((J, w.Nw, w.Nw, 2), dtype=torch.float32, device=dev)
+            sub = np.arange(J) if subset is None else np.asarray(subset)
+            I_sub = I if subset is None else I.index_select(0, torch.from_numpy(sub).to(dev)).contiguous()
+            pos_sub = S.pos[sub]
+            patches = torch.empty((len(sub), w.Nw, w.Nw, 2), dtype=torch.float32, device=dev)
             P_unit = Pk / math.sqrt(s)
 
             def warm_start(out):
-                api.unet_forward(params, I, S.log_scale, H, WIDTHS, out=patches)
-                api.ptycho_stitch(patches, P_unit, S.pos, (w.M, w.M), sync=sync, out=out)
+                api.unet_forward(params, I_sub, S.log_scale, H, WIDTHS, out=patches)
+                api.ptycho_stitch(patches, P_unit, pos_sub, (w.M, w.M), sync=sync, out=out)
 
             O0 = torch.empty((w.M, w.M), dtype=torch.complex64, device=dev)
             warm_start(O0)

@@ -297,6 +297,13 @@ def test_rejects_bad_arguments(api):
     raw = torch.zeros((1, 2, 48, 48), dtype=torch.uint16, device=DEV)
     with pytest.raises(api.MnfError, match="multiples"):
         api.fuse_exposures(raw, [1.0, 2.0], 5)
+    # empty scans, a mini-batch beyond the launch limit, too many exposures
+    with pytest.raises(api.MnfError, match="MNF_EINVAL"):
+        api.ptycho_iterate(O, P, tf32(np.ones((0, 32, 32))), np.zeros((0, 2), np.int32), 1)
+    with pytest.raises(api.MnfError, match="batch"):
+        api.ptycho_iterate(O, P, I, [[0, 0], [1, 1]], 1, batch=513)
+    with pytest.raises(api.MnfError, match="MNF_EUNSUPPORTED"):
+        api.fuse_exposures(torch.zeros((1, 17, 32, 32), dtype=torch.uint16, device=DEV), [1.0] * 17, 2)
     # zero iterations leave the state untouched
     Oc = O.clone()
     api.ptycho_iterate(O, P, I, [[0, 0], [1, 1]], 0)
