@@ -272,6 +272,19 @@ int ptycho_stitch(mnf_ctx* ctx, const float* patches, const mnf_c64* P, int Nw, 
 int mnf_nrmse(mnf_ctx* ctx, const mnf_c64* O, const mnf_c64* O_true, const uint8_t* mask, long long n,
               double* out, void* stream);
 
+/* detector_resample: one line of a discrete-spectrum measurement (Methods 3.3,
+ * Eq. 4) from the reference-wavelength pattern, for an achromatic probe and
+ * object: the pattern at wavelength lambda is the reference pattern sampled
+ * at c + (k - c) * scale (scale = lambda_0 / lambda, c = Nd / 2, the centred
+ * zero frequency), bilinear between pixels, zero outside the detector, times
+ * scale^2 (which keeps the pattern's total):
+ *   out[j][k] = (accumulate ? out[j][k] : 0) + weight * scale^2 * I(c + (k - c) scale)
+ * I device float [J][Nd][Nd] (detector-centred); out device float [J][Nd][Nd],
+ * not aliasing I.  MNF_EINVAL for null pointers, sizes <= 0, scale <= 0 or
+ * aliasing buffers. */
+int detector_resample(mnf_ctx* ctx, const float* I, int J, int Nd, float scale, float weight, int accumulate,
+                      float* out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Launch-shape tuning.  Every pattern pass is compiled in two shapes (rows:
  * the default lines per block or half as many; columns: 32 columns per block

@@ -16,6 +16,7 @@ adjoint  Poisson / amplitude loss on the far-field intensity and its
          gradient with respect to object and probe
 unet     float64 reference of the warm-start network (forward, backward)
 baselines linear-integration and single-exposure fusion, image metrics
+broadband discrete-spectrum measurement (Eq. 4): resampling of a pattern per line
 
 Every function states the passage it follows; readings the paper leaves
 open are named where they are used.

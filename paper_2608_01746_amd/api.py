@@ -423,3 +423,36 @@ def nrmse(O: torch.Tensor, O_true: torch.Tensor, mask: Optional[torch.Tensor] = 
     rc = _L.load().mnf_nrmse(ctx, _ptr(O), _ptr(O_true), _ptr(mask), O.numel(), _ptr(out), _stream(O.device))
     _check(rc, ctx)
     return out
+
+
+def detector_resample(I: torch.Tensor, scale: float, weight: float = 1.0, out: Optional[torch.Tensor] = None,
+                      accumulate: bool = False) -> torch.Tensor:
+    """weight * scale^2 * I(c + (k - c) scale), bilinear, of detector-centred patterns I [J][Nd][Nd]."""
+    _dev(I, "I", torch.float32, 3)
+    J, Nd, _ = I.shape
+    if out is None:
+        out = torch.empty_like(I)
+        accumulate = False
+    else:
+        _dev(out, "out", torch.float32, 3)
+        if out.shape != I.shape:
+            raise ValueError("out must have I's shape")
+    ctx = _ctx(I.device)
+    rc = _L.load().detector_resample(ctx, _ptr(I), J, Nd, float(scale), float(weight), 1 if accumulate else 0,
+                                     _ptr(out), _stream(I.device))
+    _check(rc, ctx)
+    return out
+
+
+def broadband_forward(O: torch.Tensor, P: torch.Tensor, pos, Nd: int, scales: Sequence[float],
+                      weights: Sequence[float]) -> torch.Tensor:
+    """Discrete-spectrum far-field intensities (Eq. 4) of an achromatic probe and
+    object: sum_m w_m s_m^2 I_ref(c + (k - c) s_m), with I_ref the reference-wavelength
+    pattern of ptycho_forward and s_m = lambda_0 / lambda_m."""
+    if len(scales) != len(weights) or not scales:
+        raise ValueError("one weight per spectral line")
+    ref = ptycho_forward(O, P, pos, Nd)
+    out = torch.empty_like(ref)
+    for m, (s, w) in enumerate(zip(scales, weights)):
+        detector_resample(ref, s, w, out=out, accumulate=m > 0)
+    return out

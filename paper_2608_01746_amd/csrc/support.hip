@@ -1,6 +1,7 @@
 // Supporting kernels of the reconstruction workflow: detector exposures of a
 // clean intensity (synthetic data at scale), stitching of predicted object
-// patches into a starting object, and the object NRMSE.
+// patches into a starting object, the object NRMSE, and the resampling that
+// turns one far-field pattern into a discrete-spectrum measurement.
 #include <cmath>
 #include <vector>
 
@@ -220,6 +221,39 @@ __global__ void k_nrmse_final(const double* __restrict__ part, int nb, double* _
     *out = sqrt(r > 0.0 ? r : 0.0);
 }
 
+// Discrete-spectrum measurement: out (+)= w s^2 I(c + (k - c) s) per pixel,
+// bilinear between pixels, zero outside the detector (c = Nd / 2).
+__global__ void __launch_bounds__(256)
+k_resample_add(const float* __restrict__ I, int Nd, size_t total, float s, float w, int accumulate,
+               float* __restrict__ out) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= total) return;
+    const size_t npix = (size_t)Nd * Nd;
+    const size_t j = i / npix;
+    const int q = (int)(i % npix), ky = q / Nd, kx = q % Nd;
+    const int c = Nd / 2;
+    const float u = (float)c + (float)(ky - c) * s, v = (float)c + (float)(kx - c) * s;
+    const float fy0 = floorf(u), fx0 = floorf(v);
+    const int y0 = (int)fy0, x0 = (int)fx0;
+    const float fy = u - fy0, fx = v - fx0;
+    const float* Ij = I + j * npix;
+    float r = 0.f;
+#pragma unroll
+    for (int dy = 0; dy < 2; ++dy) {
+        const int yy = y0 + dy;
+        if (yy < 0 || yy >= Nd) continue;
+        const float wy = dy ? fy : 1.f - fy;
+#pragma unroll
+        for (int dx = 0; dx < 2; ++dx) {
+            const int xx = x0 + dx;
+            if (xx < 0 || xx >= Nd) continue;
+            r += wy * (dx ? fx : 1.f - fx) * Ij[(size_t)yy * Nd + xx];
+        }
+    }
+    const float v_out = w * s * s * r;
+    out[i] = accumulate ? out[i] + v_out : v_out;
+}
+
 }  // namespace
 
 extern "C" {
@@ -283,6 +317,20 @@ int mnf_nrmse(mnf_ctx* ctx, const mnf_c64* O, const mnf_c64* O_true, const uint8
     MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_nrmse_part, dim3(nb), dim3(256), (const float2*)O, (const float2*)O_true, mask,
                (size_t)n, (double*)part);
     MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_nrmse_final, dim3(1), dim3(64), (const double*)part, nb, out);
+    MNF_CHECK_LAUNCH(ctx);
+    return MNF_OK;
+}
+
+int detector_resample(mnf_ctx* ctx, const float* I, int J, int Nd, float scale, float weight, int accumulate,
+                      float* out, void* stream) {
+    MNF_TRY(begin(ctx));
+    if (!I || !out || J <= 0 || Nd <= 0) return set_error(ctx, MNF_EINVAL, "bad resampling arguments");
+    if (!(scale > 0.f)) return set_error(ctx, MNF_EINVAL, "scale must be positive");
+    if (I == out) return set_error(ctx, MNF_EINVAL, "input and output must not alias");
+    hipStream_t st = (hipStream_t)stream;
+    const size_t total = (size_t)J * Nd * Nd;
+    MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_resample_add, dim3((unsigned)((total + 255) / 256)), dim3(256), I, Nd, total,
+               scale, weight, accumulate, out);
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
 }

@@ -63,6 +63,7 @@ SIGNATURES = {
                                 c_float, c_float, ctypes.c_ulonglong, c_void_p, c_void_p]),
     "ptycho_stitch": (c_int, [c_void_p, c_void_p, c_void_p, c_int, POINTER(c_int32), c_int, c_int, c_void_p,
                               c_int, c_int, c_void_p]),
+    "detector_resample": (c_int, [c_void_p, c_void_p, c_int, c_int, c_float, c_float, c_int, c_void_p, c_void_p]),
     "mnf_nrmse": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, ctypes.c_longlong, c_void_p, c_void_p]),
     "unet_param_count": (ctypes.c_longlong, [POINTER(UnetShapeC)]),
     "unet_forward": (c_int, [c_void_p, POINTER(UnetShapeC), c_void_p, c_void_p, c_float, c_int, c_void_p,
