@@ -234,6 +234,45 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_gemm(ConvArgs a) {
     }
 }
 
+// First 3x3 layer (one input channel, bf16 output, no residual): one thread
+// per output pixel computes every output channel from the nine input taps,
+// loaded once; the bf16 weights (GEMM order Bt[co][tap], row length Kpad) and
+// the biases are staged in LDS as float.  Requires Nout <= 256, Nout a
+// multiple of 8 and 16-byte aligned output rows.
+__global__ void __launch_bounds__(256) k_conv3_c1(ConvArgs a) {
+    __shared__ float sw[256 * 9];
+    __shared__ float sb[256];
+    for (int i = threadIdx.x; i < a.Nout * 9; i += 256) sw[i] = bf2f(a.Bt[(size_t)(i / 9) * a.Kpad + i % 9]);
+    for (int i = threadIdx.x; i < a.Nout; i += 256) sb[i] = a.bias ? a.bias[i] : 0.f;
+    __syncthreads();
+    const int m = blockIdx.x * 256 + threadIdx.x;
+    if (m >= a.M) return;
+    const int x = m % a.Wout, t1 = m / a.Wout, y = t1 % a.Hout, img = t1 / a.Hout;
+    float v[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+        v[t] = (yy >= 0 && yy < a.Hin && xx >= 0 && xx < a.Win)
+                   ? bf2f(a.in[(((size_t)img * a.Hin + yy) * a.Win + xx) * a.in_cs + a.in_co])
+                   : 0.f;
+    }
+    uint16_t* orow = (uint16_t*)a.out + (size_t)m * a.out_cs + a.out_co;
+    for (int c0 = 0; c0 < a.Nout; c0 += 8) {
+        uint16_t o[8] __attribute__((aligned(16)));
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float* wq = sw + (c0 + q) * 9;
+            float acc = 0.f;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) acc += v[t] * wq[t];
+            float yv = acc + sb[c0 + q];
+            if (a.relu) yv = fmaxf(yv, 0.f);
+            o[q] = f2bf(yv);
+        }
+        *(uint4*)(orow + c0) = *(const uint4*)o;
+    }
+}
+
 // ------------------------------------------------------------ weight grad
 // dW[tap][ci][co] partials over pixel ranges: grid (ceil(Co/64), ceil(Ci/64), taps * splits).
 // Rows of the GEMM are input channels, columns output channels, the reduction

@@ -76,6 +76,12 @@ int launch_conv(mnf_ctx* ctx, int mode, bool mask, bool out_f32, const ConvArgs&
     if (a.M <= 0 || a.Nout <= 0) return MNF_OK;
     const bool vec = a.Cin % 8 == 0 && a.in_cs % 8 == 0 && a.in_co % 8 == 0 &&
                      (!mask || (a.mask_cs % 8 == 0 && a.mask_co % 8 == 0));
+    if (mode == CONV3 && a.Cin == 1 && !mask && !out_f32 && !a.resid && a.Nout % 8 == 0 && a.Nout <= 256 &&
+        a.out_cs % 8 == 0 && a.out_co % 8 == 0) {
+        // the one-channel first layer: direct, one thread per output pixel
+        hipLaunchKernelGGL(k_conv3_c1, dim3(g1((size_t)a.M)), dim3(256), 0, st, a);
+        return MNF_OK;
+    }
     const dim3 grid(g1((size_t)a.M, kGemmBM), g1((size_t)a.Nout, kGemmBN));
 #define MNF_CONV_BK(MD, MK, VC, OF)                                                                    \
     if (a.Kpad > 64) hipLaunchKernelGGL((k_conv_gemm<MD, MK, VC, OF, 64>), grid, dim3(kGemmThreads), 0, st, a); \
