@@ -82,6 +82,24 @@ int launch_conv(mnf_ctx* ctx, int mode, bool mask, bool out_f32, const ConvArgs&
         hipLaunchKernelGGL(k_conv3_c1, dim3(g1((size_t)a.M)), dim3(256), 0, st, a);
         return MNF_OK;
     }
+    if (mode == CONV3 && vec && a.Cin % kTileCh == 0 && a.Hin == a.Hout && a.Win == a.Wout) {
+        // direct tiled 3x3: tiles of 2 x 64 pixels, or 4 x 32 for narrow images
+        const int TW = a.Wout % 64 == 0 ? 64 : (a.Wout % 32 == 0 && a.Hout % 4 == 0 ? 32 : 0);
+        if (TW == 64 && a.Hout % 2 == 0) {
+            const dim3 gt((unsigned)(a.n * (a.Hout / 2) * (a.Wout / 64)), g1((size_t)a.Nout, kGemmBN));
+            if (mask) hipLaunchKernelGGL((k_conv3_tiled<true, false, 64>), gt, dim3(kGemmThreads), 0, st, a);
+            else if (out_f32) hipLaunchKernelGGL((k_conv3_tiled<false, true, 64>), gt, dim3(kGemmThreads), 0, st, a);
+            else hipLaunchKernelGGL((k_conv3_tiled<false, false, 64>), gt, dim3(kGemmThreads), 0, st, a);
+            return MNF_OK;
+        }
+        if (TW == 32) {
+            const dim3 gt((unsigned)(a.n * (a.Hout / 4) * (a.Wout / 32)), g1((size_t)a.Nout, kGemmBN));
+            if (mask) hipLaunchKernelGGL((k_conv3_tiled<true, false, 32>), gt, dim3(kGemmThreads), 0, st, a);
+            else if (out_f32) hipLaunchKernelGGL((k_conv3_tiled<false, true, 32>), gt, dim3(kGemmThreads), 0, st, a);
+            else hipLaunchKernelGGL((k_conv3_tiled<false, false, 32>), gt, dim3(kGemmThreads), 0, st, a);
+            return MNF_OK;
+        }
+    }
     const dim3 grid(g1((size_t)a.M, kGemmBM), g1((size_t)a.Nout, kGemmBN));
 #define MNF_CONV_BK(MD, MK, VC, OF)                                                                    \
     if (a.Kpad > 64) hipLaunchKernelGGL((k_conv_gemm<MD, MK, VC, OF, 64>), grid, dim3(kGemmThreads), 0, st, a); \

@@ -74,6 +74,22 @@ def test_conv_gradients(api, mode, n, H, Ci, Co, masked):
     assert np.all(np.abs(d - rdx) <= 2.0 ** -8 * np.abs(rdx) + 1e-6 * np.abs(rdx).max())
 
 
+# 3x3 shapes that take the direct tiled kernel (input channels a multiple of 32,
+# 64- or 32-pixel-wide tiles), forward and masked input gradient; a partial
+# output-channel tile in the last case
+TILED = [("conv3", 2, 64, 32, 64), ("conv3", 2, 32, 64, 96), ("conv3", 1, 128, 96, 40)]
+
+
+@pytest.mark.parametrize("mode,n,H,Ci,Co", TILED)
+def test_tiled_conv3_forward(api, mode, n, H, Ci, Co):
+    test_conv_forward(api, mode, n, H, Ci, Co)
+
+
+@pytest.mark.parametrize("mode,n,H,Ci,Co", TILED[:2])
+def test_tiled_conv3_gradients(api, mode, n, H, Ci, Co):
+    test_conv_gradients(api, mode, n, H, Ci, Co, True)
+
+
 # large layers (the full network's sizes at batch 4)
 LARGE = [("down", 4, 256, 32, 256), ("conv1", 4, 128, 64, 256), ("conv3", 4, 128, 32, 256)]
 
