@@ -17,6 +17,8 @@ adjoint  Poisson / amplitude loss on the far-field intensity and its
 unet     float64 reference of the warm-start network (forward, backward)
 baselines linear-integration and single-exposure fusion, image metrics
 broadband discrete-spectrum measurement (Eq. 4): resampling of a pattern per line
+subpixel real-valued scan positions: Fourier-translated probe, mini-batched
+         ePIE / rPIE at sub-pixel positions
 
 Every function states the passage it follows; readings the paper leaves
 open are named where they are used.
