@@ -148,6 +148,35 @@ int ptycho_iterate(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw,
                    double* err_out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Real-valued (sub-pixel) scan positions (Eq. 2 at positions such as the
+ * Fermat spiral of Methods 3.3, which the integer entry points take rounded).
+ * A position r = (y, x) is split into the nearest integer corner
+ * p = floor(r + 1/2) and the fraction d = r - p in [-1/2, 1/2) per axis; the
+ * fraction translates the probe: the exit wave is
+ *     psi = S_d[P] * O[p window],
+ *     S_d[P] = F^-1[ F[P](k) exp(-2 pi i (k_y d_y + k_x d_x) / Nw) ],
+ * an Nw-periodic Fourier translation with k in [-Nw/2, Nw/2), which has the
+ * far-field intensity of P(m) O(r + m) (translating the exit wave only adds
+ * a phase ramp to Eq. 3).  Nw must be a supported transform size.
+ * pos is host float [J][2]; the corners must satisfy the window bounds of the
+ * integer entry points; non-finite or |r| > 1e8 coordinates give MNF_EINVAL.
+ * Every other argument has the meaning, layout and ownership of ptycho_forward
+ * and ptycho_iterate.  Positions with zero fractions take no transform.
+ *
+ * ptycho_forward_subpixel: I_out[j] = fftshift |F_unitary(pad_Nd(psi_j))|^2.
+ * ptycho_iterate_subpixel: the ePIE / rPIE iteration of ptycho_iterate with
+ * P_j = S_{d_j}[P] in the exit wave and in the object numerator
+ * conj(P_j) dpsi_j, and probe numerators translated back to the untranslated
+ * probe, P += sum_j S_{-d_j}[conj(O_j) dpsi_j] / sum_j d_P,j.  The step
+ * denominators are those of ptycho_iterate (untranslated batch-start |P|^2,
+ * integer windows |O_j|^2).  One scan per call; params->graph is honoured. */
+int ptycho_forward_subpixel(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P, int Nw, int Nd,
+                            const float* pos, int J, float* I_out, void* stream);
+int ptycho_iterate_subpixel(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw, const float* I, int Nd,
+                            const float* pos, int J, const int32_t* order, int n_iter, const ptycho_params* params,
+                            double* err_out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Many independent scans of uneven sizes in one call (the same iteration as
  * ptycho_iterate, applied to every scan).  Scans are grouped by detector
  * size; each pass of each mini-batch round is one launch covering the
@@ -309,9 +338,10 @@ int mnf_get_variant(mnf_ctx* ctx, int Nd);
  * launch of kernel class c is bracketed by HIP events recorded on its
  * stream.  Classes: 0 rows_fwd (gather + row transforms), 1 cols_modulus
  * (column transforms + modulus projection + inverse column transforms),
- * 2 rows_inv (inverse row transforms + exit-wave difference), 3 probe_update,
- * 4 object_update, 5 small (copies, reductions), 6 fuse, 7 forward,
- * 8 grad_cols, 9 grad_scatter.  mask 0 disables timing.
+ * 2 rows_inv (inverse row transforms + exit-wave difference), 3 probe_update
+ * (the translated probe update of real positions), 4 object_update, 5 small
+ * (copies, reductions), 6 fuse, 7 forward, 8 grad_cols, 9 grad_scatter,
+ * 10 shift (Fourier translation of probes).  mask 0 disables timing.
  * mnf_profile_read waits for the recorded events and returns the launch
  * count and summed duration (ms) of class cls since the last reset. */
 int mnf_profile(mnf_ctx* ctx, uint32_t class_mask);

@@ -68,6 +68,17 @@ def _host_i32(a, shape_tail, name) -> np.ndarray:
     return arr
 
 
+def _host_f32(a, shape_tail, name) -> np.ndarray:
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if arr.ndim != 1 + len(shape_tail) or arr.shape[1:] != tuple(shape_tail):
+        raise ValueError(f"{name} must have shape [*]{list(shape_tail)}, got {arr.shape}")
+    return arr
+
+
+def _f32p(arr: np.ndarray):
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
 def _i32p(arr: Optional[np.ndarray]):
     if arr is None:
         return None
@@ -152,6 +163,25 @@ def ptycho_forward(O: torch.Tensor, P: torch.Tensor, pos, Nd: int,
     return out
 
 
+def ptycho_forward_subpixel(O: torch.Tensor, P: torch.Tensor, pos, Nd: int,
+                            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """As ptycho_forward at real positions pos [J][2] (float32): the fraction of
+    each position translates the probe in Fourier space."""
+    _dev(O, "O", torch.complex64, 2)
+    _dev(P, "P", torch.complex64, 2)
+    posa = _host_f32(pos, (2,), "pos")
+    J = posa.shape[0]
+    if out is None:
+        out = torch.empty((J, Nd, Nd), dtype=torch.float32, device=O.device)
+    else:
+        _dev(out, "out", torch.float32, 3)
+    ctx = _ctx(O.device)
+    rc = _L.load().ptycho_forward_subpixel(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], Nd,
+                                           _f32p(posa), J, _ptr(out), _stream(O.device))
+    _check(rc, ctx)
+    return out
+
+
 # ----------------------------------------------------------- reconstruction
 
 ALGS = {"epie": 0, "rpie": 1}
@@ -163,10 +193,26 @@ def ptycho_iterate(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_ite
                    err: bool = True, graph: bool = False) -> Optional[torch.Tensor]:
     """Run n_iter mini-batched ePIE/rPIE iterations, updating O and P in place.
     Returns the float64 error per iteration (device tensor) if err."""
+    return _iterate("ptycho_iterate", _host_i32(pos, (2,), "pos"), _i32p, O, P, I, n_iter, alg, alpha, beta,
+                    batch, update_probe, probe_start_iter, order, it0, err, graph)
+
+
+def ptycho_iterate_subpixel(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_iter: int,
+                            alg: str = "rpie", alpha: float = 0.1, beta: float = 0.1, batch: int = 1,
+                            update_probe: bool = False, probe_start_iter: int = 0, order=None, it0: int = 0,
+                            err: bool = True, graph: bool = False) -> Optional[torch.Tensor]:
+    """ptycho_iterate at real positions pos [J][2] (float32): translated
+    probes in the exit waves and object numerators, probe numerators
+    translated back."""
+    return _iterate("ptycho_iterate_subpixel", _host_f32(pos, (2,), "pos"), _f32p, O, P, I, n_iter, alg, alpha,
+                    beta, batch, update_probe, probe_start_iter, order, it0, err, graph)
+
+
+def _iterate(entry, posa, posp, O, P, I, n_iter, alg, alpha, beta, batch, update_probe, probe_start_iter, order,
+             it0, err, graph):
     _dev(O, "O", torch.complex64, 2)
     _dev(P, "P", torch.complex64, 2)
     _dev(I, "I", torch.float32, 3)
-    posa = _host_i32(pos, (2,), "pos")
     J = posa.shape[0]
     if I.shape[0] != J or I.shape[1] != I.shape[2]:
         raise ValueError("I must be [J][Nd][Nd]")
@@ -179,9 +225,9 @@ def ptycho_iterate(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_ite
                            1 if graph else 0)
     e = torch.empty(max(n_iter, 1), dtype=torch.float64, device=O.device) if err else None
     ctx = _ctx(O.device)
-    rc = _L.load().ptycho_iterate(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], _ptr(I),
-                                  I.shape[1], _i32p(posa), J, _i32p(orda), n_iter, ctypes.byref(prm),
-                                  _ptr(e), _stream(O.device))
+    rc = getattr(_L.load(), entry)(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], _ptr(I),
+                                   I.shape[1], posp(posa), J, _i32p(orda), n_iter, ctypes.byref(prm),
+                                   _ptr(e), _stream(O.device))
     _check(rc, ctx)
     return e[:n_iter] if err else None
 

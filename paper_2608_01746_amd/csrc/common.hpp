@@ -25,6 +25,7 @@ enum MnfKernelClass {
     MNF_K_FORWARD,        // forward-model column pass
     MNF_K_GRAD_COLS,      // gradient column pass
     MNF_K_GRAD_SCATTER,   // gradient object/probe scatter
+    MNF_K_SHIFT,          // Fourier translation of probes (real positions)
     MNF_K_NCLASS
 };
 

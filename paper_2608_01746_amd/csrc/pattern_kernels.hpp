@@ -21,11 +21,14 @@ namespace mnf {
 
 // -------------------------------------------------------------- rows_fwd
 // grid (ceil(maxNw / LINES), nslots).  Writes per-block maxima of |O_j|^2,
-// maxO2_part[slot][blockIdx.x] (when not NULL).
+// maxO2_part[slot][blockIdx.x] (when not NULL).  Pd (when not NULL) holds one
+// probe per slot, Pd[slot][Nw][Nw] (the probe translated to each slot's real
+// position), used in place of the scan's probe.
 template <int N, int RV>
 __global__ void __launch_bounds__((RowCfg<N, RV>::THREADS))
 k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
-           float2* __restrict__ S, float* __restrict__ maxO2_part, const float2* __restrict__ tw_g) {
+           float2* __restrict__ S, float* __restrict__ maxO2_part, const float2* __restrict__ Pd,
+           const float2* __restrict__ tw_g) {
     constexpr int T = RowCfg<N, RV>::T, LINES = RowCfg<N, RV>::LINES, V = PlanInfo<N>::V;
     __shared__ float2 lds[LINES * RowLds<N>::stride];
     __shared__ float2 tw[N];
@@ -42,7 +45,7 @@ k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
     float2 x[V];
     float mO = 0.f;
     const float2* Orow = sc.O + (size_t)(sd.py + (live ? y : 0)) * Mx + sd.px;
-    const float2* Prow = sc.P + (size_t)(live ? y : 0) * Nw;
+    const float2* Prow = (Pd ? Pd + (size_t)s * Nw * Nw : sc.P) + (size_t)(live ? y : 0) * Nw;
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int n = in_pos<N, false>(t, idx);
@@ -205,6 +208,12 @@ k_cols_intensity(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
 //       rPIE: d_P,s = (1 - beta)|O_s|^2 + beta max|O_s|^2;  ePIE: max|O_s|^2 / beta
 //   MODE 2 (gradient): g = upstream * psi';  S[s][r][n] = conj(P(r, n)) g and
 //     gP(r, n) += sum_s conj(O_s(r, n)) g  (when the scan has a gP).
+//   MODE 3, 4 (real positions): as MODE 0 with each slot's translated probe
+//     P_s = Pd[s] in place of P in dpsi and in the object numerator; P2 and
+//     maxP2_row still describe the untranslated batch-start probe.  MODE 4
+//     (probe updated) writes the probe numerators G[s][r][n] = conj(O_s) dpsi
+//     for the inverse translation and the float64 denominator sums
+//     DP[r][n] = sum_s d_P,s, and leaves P unchanged.
 template <int N, int RV = 0>
 struct UpdCfg {
     static constexpr int T = PlanInfo<N>::T;
@@ -219,12 +228,14 @@ __global__ void __launch_bounds__((UpdCfg<N, RV>::THREADS))
 k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
                   const GroupDev* __restrict__ groups, float2* __restrict__ S,
                   const float* __restrict__ maxO2_part, int nparts, int rpie, float beta,
-                  float upstream, const float2* __restrict__ tw_g) {
+                  float upstream, const float2* __restrict__ Pd, float2* __restrict__ G,
+                  double* __restrict__ DP, const float2* __restrict__ tw_g) {
     constexpr int T = UpdCfg<N, RV>::T, ULINES = UpdCfg<N, RV>::ULINES, V = PlanInfo<N>::V;
     constexpr int THREADS = UpdCfg<N, RV>::THREADS;
     constexpr int COLS = (N + THREADS - 1) / THREADS;  // probe columns owned per thread
-    constexpr bool ACC = MODE != 0;                     // probe-row sums over the batch
-    constexpr bool DEN = MODE == 1;
+    constexpr bool SUB = MODE >= 3;                     // per-slot translated probes
+    constexpr bool ACC = MODE == 1 || MODE == 2;        // probe-row sums over the batch
+    constexpr bool DEN = MODE == 1 || MODE == 4;
     // the transform's exchange buffer doubles as the per-line numerator buffer
     // once a round's transforms are done (both hold ULINES x N complex values)
     __shared__ float2 lds[ULINES * RowLds<N>::stride];
@@ -275,12 +286,14 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
         float2* row = S + ((size_t)(gd.s0 + kk) * N + r) * N;
         const float2* Orow = sc.O + (size_t)(s_py[kk] + r) * Mx + s_px[kk];
         // every global load of the round is issued before the transform
-        float2 x[V], o[V];
+        float2 x[V], o[V], pv[V];
+        const float2* Psrow = SUB ? Pd + ((size_t)(gd.s0 + kk) * Nw + r) * Nw : nullptr;
 #pragma unroll
         for (int idx = 0; idx < V; ++idx) {
             x[idx] = live ? row[in_pos<N, true>(t, idx)] : make_float2(0.f, 0.f);
             const int n = out_pos<N, true>(t, idx);
             o[idx] = live && n < Nw ? Orow[n] : make_float2(0.f, 0.f);
+            if constexpr (SUB) pv[idx] = live && n < Nw ? Psrow[n] : make_float2(0.f, 0.f);
         }
         fft_line<N, true>(x, t, lds, RowLds<N>(line), tw);
         if (live) {
@@ -290,10 +303,11 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             for (int idx = 0; idx < V; ++idx) {
                 const int n = out_pos<N, true>(t, idx);
                 if (n < Nw) {
-                    const float2 p = s_prow[n];
+                    const float2 p = SUB ? pv[idx] : s_prow[n];
                     const float2 d = MODE == 2 ? cscale(x[idx], scl) : csub(cscale(x[idx], scl), cmul(p, o[idx]));
                     row[n] = cconjmul(p, d);
                     if constexpr (ACC) c_num[line * N + n] = cconjmul(o[idx], d);
+                    if constexpr (MODE == 4) G[((size_t)(gd.s0 + k) * Nw + r) * Nw + n] = cconjmul(o[idx], d);
                     if constexpr (DEN) {
                         const float o2 = cabs2(o[idx]);
                         c_den[line * N + n] = rpie ? (1.f - beta) * o2 + beta * mO : mO / beta;
@@ -301,7 +315,7 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                 }
             }
         }
-        if constexpr (ACC) {
+        if constexpr (ACC || DEN) {
             __syncthreads();
             const int nl = min(ULINES, nb - k0);
 #pragma unroll
@@ -309,7 +323,7 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                 const int n = threadIdx.x + c * THREADS;
                 if (n < Nw) {
                     for (int l = 0; l < nl; ++l) {
-                        num[c] = cadd(num[c], c_num[l * N + n]);
+                        if constexpr (ACC) num[c] = cadd(num[c], c_num[l * N + n]);
                         if constexpr (DEN) den[c] += (double)c_den[l * N + n];
                     }
                 }
@@ -332,7 +346,8 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             const float p2 = cabs2(p);
             sc.P2[(size_t)r * Nw + n] = p2;
             pmax = fmaxf(pmax, p2);
-            if (DEN && den[c] > 0.0) {
+            if constexpr (MODE == 4) DP[(size_t)r * Nw + n] = den[c];
+            if (MODE == 1 && den[c] > 0.0) {
                 const double inv = 1.0 / den[c];
                 p.x = (float)((double)p.x + (double)num[c].x * inv);
                 p.y = (float)((double)p.y + (double)num[c].y * inv);

@@ -9,8 +9,11 @@
 #include <map>
 #include <vector>
 
+#include <cmath>
+
 #include "common.hpp"
 #include "pattern_kernels.hpp"
+#include "shift_kernels.hpp"
 #include "update_kernels.hpp"
 
 using namespace mnf;
@@ -24,6 +27,19 @@ bool size_supported(int N) {
         if (s == N) return true;
     return false;
 }
+
+#define MNF_DISPATCH(N, FN, ...)               \
+    switch (N) {                               \
+        case 16: return FN<16>(__VA_ARGS__);   \
+        case 32: return FN<32>(__VA_ARGS__);   \
+        case 64: return FN<64>(__VA_ARGS__);   \
+        case 128: return FN<128>(__VA_ARGS__); \
+        case 192: return FN<192>(__VA_ARGS__); \
+        case 256: return FN<256>(__VA_ARGS__); \
+        case 384: return FN<384>(__VA_ARGS__); \
+        case 512: return FN<512>(__VA_ARGS__); \
+        default: return MNF_EUNSUPPORTED;      \
+    }
 
 template <int RV>
 int row_lines_v(int N) {
@@ -61,6 +77,7 @@ struct ScanIn {
     double* err_out;
     float2* gO;
     float2* gP;
+    const float2* frac = nullptr;  // host [J] (d_y, d_x) fractions of real positions, or NULL
 };
 
 struct Box {
@@ -126,11 +143,23 @@ struct CallPlan {
     std::vector<GroupDev> groups;
     std::vector<Launch> launches;     // in issue order
     std::vector<int> iter_end;        // launches[iter_end[i-1] .. iter_end[i]) belong to iteration i
+    std::vector<float2> fracs;        // per slot (d_y, d_x) of real positions (sub-pixel plans)
     size_t max_S = 0;                 // bytes of pattern scratch
     size_t max_maxO2 = 0;             // floats of max partials
+    int max_slots = 0;                // slots of the largest launch
+    bool sub = false;                 // real (sub-pixel) positions: one scan, translated probes
     void* d_scans = nullptr;
     void* d_slots = nullptr;
     void* d_groups = nullptr;
+    void* d_fracs = nullptr;
+};
+
+// Per-slot translated probes Pd and probe numerators G ([slot][Nw][Nw]) and
+// the probe-update denominators DP ([Nw][Nw], float64) of a sub-pixel call.
+struct SubBufs {
+    float2* Pd;
+    float2* G;
+    double* DP;
 };
 
 void fill_scan_dev(ScanDev& d, const ScanIn& s, const Box& b) {
@@ -166,6 +195,7 @@ void plan_round(mnf_ctx* ctx, CallPlan& pl, const std::vector<ScanIn>& in, const
         for (int t = t0; t < t0 + nb; ++t) {
             const int j = s.order ? s.order[(size_t)i * s.J + t] : t;
             pl.slots.push_back(SlotDev{k, j, s.pos[2 * j], s.pos[2 * j + 1]});
+            pl.fracs.push_back(s.frac ? s.frac[j] : make_float2(0.f, 0.f));
         }
         pl.groups.push_back(g);
         L.nslots += nb;
@@ -175,6 +205,7 @@ void plan_round(mnf_ctx* ctx, CallPlan& pl, const std::vector<ScanIn>& in, const
     }
     if (L.nslots == 0) return;
     pl.max_S = std::max(pl.max_S, (size_t)L.nslots * N * N * sizeof(float2));
+    pl.max_slots = std::max(pl.max_slots, L.nslots);
     const int gr = (L.maxNw + row_lines(ctx, N) - 1) / row_lines(ctx, N);
     pl.max_maxO2 = std::max(pl.max_maxO2, (size_t)L.nslots * gr);
     pl.launches.push_back(L);
@@ -185,6 +216,8 @@ int upload_plan(mnf_ctx* ctx, CallPlan& pl, hipStream_t st) {
     MNF_TRY(upload(ctx, "plan_slots", pl.slots.data(), sizeof(SlotDev) * pl.slots.size(), st, &pl.d_slots));
     MNF_TRY(upload(ctx, "plan_groups", pl.groups.data(), sizeof(GroupDev) * std::max<size_t>(1, pl.groups.size()),
                    st, &pl.d_groups));
+    if (pl.sub)
+        MNF_TRY(upload(ctx, "plan_fracs", pl.fracs.data(), sizeof(float2) * pl.fracs.size(), st, &pl.d_fracs));
     return MNF_OK;
 }
 
@@ -192,11 +225,45 @@ int upload_plan(mnf_ctx* ctx, CallPlan& pl, hipStream_t st) {
 
 template <int N, int RV>
 int launch_rows_fwd(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ScanDev* scans, float2* S, float* mO,
-                    const float2* tw, hipStream_t st) {
+                    const float2* Pd, const float2* tw, hipStream_t st) {
     const int gr = (L.maxNw + RowCfg<N, RV>::LINES - 1) / RowCfg<N, RV>::LINES;
     MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, (k_rows_fwd<N, RV>), dim3(gr, L.nslots), dim3(RowCfg<N, RV>::THREADS),
-               scans, (const SlotDev*)pl.d_slots + L.slot_off, S, mO, tw);
+               scans, (const SlotDev*)pl.d_slots + L.slot_off, S, mO, Pd, tw);
     return MNF_OK;
+}
+
+// Translated probes of a launch's slots: Pd[s] = S_{d_s}[P] (rows, then columns).
+template <int NW>
+int shift_probe_n(mnf_ctx* ctx, const float2* P, float2* Pd, const float2* fr, int nslots, hipStream_t st) {
+    static_assert(NW % RowCfg<NW, 0>::LINES == 0 && NW % ColCfg<NW, 0>::C == 0, "whole blocks");
+    const float2* tw;
+    MNF_TRY(twiddles(ctx, NW, &tw));
+    MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_rows<NW>), dim3(NW / RowCfg<NW, 0>::LINES, nslots),
+               dim3(RowCfg<NW, 0>::THREADS), P, (size_t)0, Pd, fr, 1.f, tw);
+    MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_cols<NW>), dim3(NW / ColCfg<NW, 0>::C, nslots),
+               dim3(ColCfg<NW, 0>::THREADS), Pd, fr, tw);
+    return MNF_OK;
+}
+int shift_probe(mnf_ctx* ctx, int Nw, const float2* P, float2* Pd, const float2* fr, int nslots, hipStream_t st) {
+    MNF_DISPATCH(Nw, shift_probe_n, ctx, P, Pd, fr, nslots, st)
+}
+
+// Probe update of a sub-pixel launch: G[s] translated back by -d_s (rows in
+// place, then columns summed per group) and applied to P with DP.
+template <int NW>
+int shift_update_n(mnf_ctx* ctx, float2* G, const float2* fr, const GroupDev* groups, int nslots, int ngroups,
+                   float2* P, const double* DP, hipStream_t st) {
+    const float2* tw;
+    MNF_TRY(twiddles(ctx, NW, &tw));
+    MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_rows<NW>), dim3(NW / RowCfg<NW, 0>::LINES, nslots),
+               dim3(RowCfg<NW, 0>::THREADS), (const float2*)G, (size_t)NW * NW, G, fr, -1.f, tw);
+    MNF_LAUNCH(ctx, MNF_K_PROBE_UPDATE, st, (k_shift_cols_update<NW>), dim3(NW / ColCfg<NW, 0>::C, ngroups),
+               dim3(ColCfg<NW, 0>::THREADS), (const float2*)G, fr, groups, P, DP, tw);
+    return MNF_OK;
+}
+int shift_update(mnf_ctx* ctx, int Nw, float2* G, const float2* fr, const GroupDev* groups, int nslots, int ngroups,
+                 float2* P, const double* DP, hipStream_t st) {
+    MNF_DISPATCH(Nw, shift_update_n, ctx, G, fr, groups, nslots, ngroups, P, DP, st)
 }
 
 template <int N, int RV, int CV>
@@ -209,23 +276,70 @@ int issue_iterate_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, cons
     const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
     const int gr = (L.maxNw + RowCfg<N, RV>::LINES - 1) / RowCfg<N, RV>::LINES;
     const int rpie = p.alg == 1;
-    MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, tw, st)));
+    const float2* nP = nullptr;
+    float2* nG = nullptr;
+    double* nD = nullptr;
+    MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, nP, tw, st)));
     MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, CV, ColOp::Modulus>),
                dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, S, 0.f, tw);
     if (upd)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 1>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, tw);
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, nP,
+                   nG, nD, tw);
     else
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 0>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, tw);
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, nP,
+                   nG, nD, tw);
     MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
     return MNF_OK;
 }
 
+// The same mini-batch at real positions (one scan): translated probes, the
+// three pattern passes with per-slot probes, the object update and, when the
+// probe is updated, the inverse translation of its numerators.
+template <int N, int RV, int CV>
+int issue_subpixel_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd,
+                          float2* S, float* mO, const SubBufs& sb, hipStream_t st) {
+    const float2* tw;
+    MNF_TRY(twiddles(ctx, N, &tw));
+    const ScanDev* scans = (const ScanDev*)pl.d_scans;
+    const SlotDev* slots = (const SlotDev*)pl.d_slots + L.slot_off;
+    const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
+    const float2* fr = (const float2*)pl.d_fracs + L.slot_off;
+    const int Nw = pl.scans[0].Nw;
+    const int gr = (L.maxNw + RowCfg<N, RV>::LINES - 1) / RowCfg<N, RV>::LINES;
+    const int rpie = p.alg == 1;
+    const float2* Pd = sb.Pd;
+    MNF_TRY(shift_probe(ctx, Nw, pl.scans[0].P, sb.Pd, fr, L.nslots, st));
+    MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, Pd, tw, st)));
+    MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, CV, ColOp::Modulus>),
+               dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, S, 0.f, tw);
+    if (upd)
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 4>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, Pd,
+                   sb.G, sb.DP, tw);
+    else
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 3>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, Pd,
+                   (float2*)nullptr, (double*)nullptr, tw);
+    MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
+               groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
+    if (upd) MNF_TRY(shift_update(ctx, Nw, sb.G, fr, groups, L.nslots, L.ngroups, pl.scans[0].P, sb.DP, st));
+    return MNF_OK;
+}
+
 template <int N>
 int issue_iterate_n(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
-                    float* mO, hipStream_t st) {
+                    float* mO, const SubBufs* sb, hipStream_t st) {
+    if (sb) {
+        switch (variant_of(ctx, N)) {
+            case 1: return issue_subpixel_launch<N, 1, 0>(ctx, pl, L, p, upd, S, mO, *sb, st);
+            case 2: return issue_subpixel_launch<N, 0, 1>(ctx, pl, L, p, upd, S, mO, *sb, st);
+            case 3: return issue_subpixel_launch<N, 1, 1>(ctx, pl, L, p, upd, S, mO, *sb, st);
+            default: return issue_subpixel_launch<N, 0, 0>(ctx, pl, L, p, upd, S, mO, *sb, st);
+        }
+    }
     switch (variant_of(ctx, N)) {
         case 1: return issue_iterate_launch<N, 1, 0>(ctx, pl, L, p, upd, S, mO, st);
         case 2: return issue_iterate_launch<N, 0, 1>(ctx, pl, L, p, upd, S, mO, st);
@@ -235,18 +349,8 @@ int issue_iterate_n(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const pty
 }
 
 int issue_iterate_any(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
-                      float* mO, hipStream_t st) {
-    switch (L.N) {
-        case 16: return issue_iterate_n<16>(ctx, pl, L, p, upd, S, mO, st);
-        case 32: return issue_iterate_n<32>(ctx, pl, L, p, upd, S, mO, st);
-        case 64: return issue_iterate_n<64>(ctx, pl, L, p, upd, S, mO, st);
-        case 128: return issue_iterate_n<128>(ctx, pl, L, p, upd, S, mO, st);
-        case 192: return issue_iterate_n<192>(ctx, pl, L, p, upd, S, mO, st);
-        case 256: return issue_iterate_n<256>(ctx, pl, L, p, upd, S, mO, st);
-        case 384: return issue_iterate_n<384>(ctx, pl, L, p, upd, S, mO, st);
-        case 512: return issue_iterate_n<512>(ctx, pl, L, p, upd, S, mO, st);
-        default: return MNF_EUNSUPPORTED;
-    }
+                      float* mO, const SubBufs* sb, hipStream_t st) {
+    MNF_DISPATCH(L.N, issue_iterate_n, ctx, pl, L, p, upd, S, mO, sb, st)
 }
 
 // ----------------------------------------------------------------- iterate
@@ -271,7 +375,12 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
         classes[in[k].Nd].push_back(k);
         max_batches = std::max(max_batches, (in[k].J + p.batch - 1) / p.batch);
     }
+    const bool sub = in[0].frac != nullptr;
+    if (sub && ns != 1) return set_error(ctx, MNF_EINVAL, "real positions are supported for one scan per call");
+    if (sub && !size_supported(in[0].Nw))
+        return set_error(ctx, MNF_EUNSUPPORTED, "real positions need a probe window with an FFT plan (Nw=%d)", in[0].Nw);
     if (n_iter == 0) return MNF_OK;
+    pl.sub = sub;
 
     // per-scan scratch: P2 [Nw^2], maxP2_row [Nw], error partials [J][N/C], |A|^2 partials [J] and sum
     size_t f_need = 0, d_need = 0;
@@ -318,6 +427,21 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     MNF_TRY(upload(ctx, "plan_a2jobs", a2jobs.data(), sizeof(SumJob) * a2jobs.size(), st, &d_a2jobs));
     MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
     MNF_TRY(scratch(ctx, "maxO2", pl.max_maxO2 * sizeof(float), &mO));
+    SubBufs sbuf{nullptr, nullptr, nullptr};
+    const SubBufs* sb = nullptr;
+    if (sub) {
+        const size_t nw2 = (size_t)in[0].Nw * in[0].Nw;
+        void *pd, *g = nullptr, *dp = nullptr;
+        MNF_TRY(scratch(ctx, "sub_Pd", (size_t)pl.max_slots * nw2 * sizeof(float2), &pd));
+        if (p.update_probe) {
+            MNF_TRY(scratch(ctx, "sub_G", (size_t)pl.max_slots * nw2 * sizeof(float2), &g));
+            MNF_TRY(scratch(ctx, "sub_DP", nw2 * sizeof(double), &dp));
+        }
+        sbuf = SubBufs{(float2*)pd, (float2*)g, (double*)dp};
+        sb = &sbuf;
+        const float2* tw;
+        MNF_TRY(twiddles(ctx, in[0].Nw, &tw));
+    }
     bool any_err = false;
     for (int k = 0; k < ns; ++k) any_err |= in[k].err_out != nullptr;
     if (any_err) {
@@ -349,7 +473,7 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
         const int it = p.it0 + i;
         const bool upd = p.update_probe && it >= p.probe_start_iter;
         for (; li < (size_t)pl.iter_end[i] && rc == MNF_OK; ++li)
-            rc = issue_iterate_any(ctx, pl, pl.launches[li], p, upd, (float2*)S, (float*)mO, run);
+            rc = issue_iterate_any(ctx, pl, pl.launches[li], p, upd, (float2*)S, (float*)mO, sb, run);
         if (rc == MNF_OK && any_err) {
             hipLaunchKernelGGL(k_sum_jobs, dim3(ns), dim3(256), 0, run, (const SumJob*)d_jobs + (size_t)i * ns, 1.0);
         }
@@ -382,13 +506,20 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
 // ----------------------------------------------------------------- forward
 
 template <int N, int RV, int CV>
-int forward_v(mnf_ctx* ctx, const CallPlan& pl, float* I_out, hipStream_t st) {
+int forward_v(mnf_ctx* ctx, const CallPlan& pl, float* I_out, const SubBufs* sb, hipStream_t st) {
     const float2* tw;
     MNF_TRY(twiddles(ctx, N, &tw));
     void* S;
     MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
     for (const Launch& L : pl.launches) {
-        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, (const ScanDev*)pl.d_scans, (float2*)S, (float*)nullptr, tw, st)));
+        const float2* Pd = nullptr;
+        if (sb) {
+            MNF_TRY(shift_probe(ctx, pl.scans[0].Nw, pl.scans[0].P, sb->Pd, (const float2*)pl.d_fracs + L.slot_off,
+                                L.nslots, st));
+            Pd = sb->Pd;
+        }
+        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, (const ScanDev*)pl.d_scans, (float2*)S, (float*)nullptr, Pd, tw,
+                                        st)));
         MNF_LAUNCH(ctx, MNF_K_FORWARD, st, (k_cols_intensity<N, CV>), dim3(N / ColCfg<N, CV>::C, L.nslots),
                    dim3(ColCfg<N, CV>::THREADS), (const ScanDev*)pl.d_scans, (const SlotDev*)pl.d_slots + L.slot_off,
                    (const float2*)S, I_out, tw);
@@ -398,12 +529,12 @@ int forward_v(mnf_ctx* ctx, const CallPlan& pl, float* I_out, hipStream_t st) {
 }
 
 template <int N>
-int forward_n(mnf_ctx* ctx, const CallPlan& pl, float* I_out, hipStream_t st) {
+int forward_n(mnf_ctx* ctx, const CallPlan& pl, float* I_out, const SubBufs* sb, hipStream_t st) {
     switch (variant_of(ctx, N)) {
-        case 1: return forward_v<N, 1, 0>(ctx, pl, I_out, st);
-        case 2: return forward_v<N, 0, 1>(ctx, pl, I_out, st);
-        case 3: return forward_v<N, 1, 1>(ctx, pl, I_out, st);
-        default: return forward_v<N, 0, 0>(ctx, pl, I_out, st);
+        case 1: return forward_v<N, 1, 0>(ctx, pl, I_out, sb, st);
+        case 2: return forward_v<N, 0, 1>(ctx, pl, I_out, sb, st);
+        case 3: return forward_v<N, 1, 1>(ctx, pl, I_out, sb, st);
+        default: return forward_v<N, 0, 0>(ctx, pl, I_out, sb, st);
     }
 }
 
@@ -434,7 +565,8 @@ int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
     for (const Launch& L : pl.launches) {
         const SlotDev* slots = (const SlotDev*)pl.d_slots + L.slot_off;
         const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
-        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, (float2*)S, (float*)nullptr, tw, st)));
+        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, (float2*)S, (float*)nullptr, (const float2*)nullptr, tw,
+                                        st)));
         if (kind == 0)
             MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, CV, ColOp::PoissonGrad>),
                        dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, (float2*)S,
@@ -446,7 +578,7 @@ int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
         if (!s.gO && !s.gP) continue;
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 2>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, (float2*)S, (const float*)nullptr, 0, 0, 0.f,
-                   (float)upstream, tw);
+                   (float)upstream, (const float2*)nullptr, (float2*)nullptr, (double*)nullptr, tw);
         if (s.gO)
             MNF_LAUNCH(ctx, MNF_K_GRAD_SCATTER, st, k_grad_object, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                        groups, L.ngroups, (const float2*)S, N);
@@ -467,18 +599,24 @@ int grad_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
     }
 }
 
-#define MNF_DISPATCH(N, FN, ...)               \
-    switch (N) {                               \
-        case 16: return FN<16>(__VA_ARGS__);   \
-        case 32: return FN<32>(__VA_ARGS__);   \
-        case 64: return FN<64>(__VA_ARGS__);   \
-        case 128: return FN<128>(__VA_ARGS__); \
-        case 192: return FN<192>(__VA_ARGS__); \
-        case 256: return FN<256>(__VA_ARGS__); \
-        case 384: return FN<384>(__VA_ARGS__); \
-        case 512: return FN<512>(__VA_ARGS__); \
-        default: return MNF_EUNSUPPORTED;      \
+// Real positions host float [J][2] -> nearest integer corners (halves round up)
+// and the fractions r - corner in [-1/2, 1/2), exact in float.
+int split_positions(mnf_ctx* ctx, const float* pos, int J, std::vector<int32_t>& ip, std::vector<float2>& fr) {
+    if (!pos) return set_error(ctx, MNF_EINVAL, "null positions");
+    if (J <= 0) return set_error(ctx, MNF_EINVAL, "J must be positive (J=%d)", J);
+    ip.resize(2 * (size_t)J);
+    fr.resize(J);
+    for (int j = 0; j < J; ++j) {
+        const double y = pos[2 * j], x = pos[2 * j + 1];
+        if (!std::isfinite(y) || !std::isfinite(x) || std::fabs(y) > 1e8 || std::fabs(x) > 1e8)
+            return set_error(ctx, MNF_EINVAL, "position %d is not a finite coordinate", j);
+        const double py = std::floor(y + 0.5), px = std::floor(x + 0.5);
+        ip[2 * j] = (int32_t)py;
+        ip[2 * j + 1] = (int32_t)px;
+        fr[j] = make_float2((float)(y - py), (float)(x - px));
     }
+    return MNF_OK;
+}
 
 // Single-scan plan with the identity order in chunks of `chunk` positions.
 int plan_identity(mnf_ctx* ctx, const ScanIn& s, int chunk, CallPlan& pl, hipStream_t st) {
@@ -490,6 +628,7 @@ int plan_identity(mnf_ctx* ctx, const ScanIn& s, int chunk, CallPlan& pl, hipStr
     std::vector<ScanIn> in{s};
     const int nr = (s.J + chunk - 1) / chunk;
     for (int r = 0; r < nr; ++r) plan_round(ctx, pl, in, cls, 0, r, chunk, s.Nd);
+    pl.sub = s.frac != nullptr;
     return upload_plan(ctx, pl, st);
 }
 
@@ -592,7 +731,27 @@ int ptycho_forward(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64
     ScanIn s{(float2*)O, My, Mx, (float2*)P, Nw, I_out, Nd, pos, J, nullptr, nullptr, nullptr, nullptr};
     CallPlan pl;
     MNF_TRY(plan_identity(ctx, s, 64, pl, st));
-    MNF_DISPATCH(Nd, forward_n, ctx, pl, I_out, st)
+    MNF_DISPATCH(Nd, forward_n, ctx, pl, I_out, (const SubBufs*)nullptr, st)
+}
+
+int ptycho_forward_subpixel(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P, int Nw, int Nd,
+                            const float* pos, int J, float* I_out, void* stream) {
+    MNF_TRY(begin(ctx));
+    if (!I_out) return set_error(ctx, MNF_EINVAL, "null output");
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> ip;
+    std::vector<float2> fr;
+    MNF_TRY(split_positions(ctx, pos, J, ip, fr));
+    if (!size_supported(Nw))
+        return set_error(ctx, MNF_EUNSUPPORTED, "real positions need a probe window with an FFT plan (Nw=%d)", Nw);
+    ScanIn s{(float2*)O, My, Mx, (float2*)P, Nw, I_out, Nd, ip.data(), J, nullptr, nullptr, nullptr, nullptr,
+             fr.data()};
+    CallPlan pl;
+    MNF_TRY(plan_identity(ctx, s, 64, pl, st));
+    void* pd;
+    MNF_TRY(scratch(ctx, "sub_Pd", (size_t)pl.max_slots * Nw * Nw * sizeof(float2), &pd));
+    const SubBufs sb{(float2*)pd, nullptr, nullptr};
+    MNF_DISPATCH(Nd, forward_n, ctx, pl, I_out, &sb, st)
 }
 
 int ptycho_iterate(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw, const float* I, int Nd,
@@ -602,6 +761,19 @@ int ptycho_iterate(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw,
     if (!params) return set_error(ctx, MNF_EINVAL, "null params");
     std::vector<ScanIn> in{ScanIn{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, pos, J, order, err_out, nullptr,
                                   nullptr}};
+    return run_iterate(ctx, in, n_iter, *params, (hipStream_t)stream);
+}
+
+int ptycho_iterate_subpixel(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw, const float* I, int Nd,
+                            const float* pos, int J, const int32_t* order, int n_iter, const ptycho_params* params,
+                            double* err_out, void* stream) {
+    MNF_TRY(begin(ctx));
+    if (!params) return set_error(ctx, MNF_EINVAL, "null params");
+    std::vector<int32_t> ip;
+    std::vector<float2> fr;
+    MNF_TRY(split_positions(ctx, pos, J, ip, fr));
+    std::vector<ScanIn> in{ScanIn{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, ip.data(), J, order, err_out, nullptr,
+                                  nullptr, fr.data()}};
     return run_iterate(ctx, in, n_iter, *params, (hipStream_t)stream);
 }
 

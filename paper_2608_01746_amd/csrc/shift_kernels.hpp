@@ -1,0 +1,137 @@
+// Fourier translation of probe-sized fields for real-valued scan positions.
+//
+// A position r = p + d (p the nearest integer corner, d in [-1/2, 1/2) per
+// axis) is modelled by translating the probe by d: the exit wave
+// P(m - d) O(p + m) has the far-field intensity of P(m) O(p + m + d) (Eq. 2
+// at the real position; a translation only adds a phase ramp to Eq. 3).  The
+// translation over the Nw x Nw window is S_d = F^-1 diag(exp(-2 pi i k.d / Nw)) F
+// with frequencies k in [-Nw/2, Nw/2), applied as a row pass (x) and a column
+// pass (y), each forward transform -> ramp -> inverse transform in registers.
+// S_d is unitary with inverse S_-d, which carries the probe-update numerators
+// back to the untranslated probe.  Slots with a zero fraction on an axis skip
+// that axis's transforms, so whole-pixel positions keep the probe exactly.
+//
+// Fields are [slot][Nw][Nw] complex float, row-major; frac[slot] = (d_y, d_x).
+#pragma once
+
+#include "kernels_common.hpp"
+#include "tables.hpp"
+
+namespace mnf {
+
+// exp(-2 pi i k' d / N), k' the signed frequency of FFT-order index k
+template <int N>
+__device__ __forceinline__ float2 shift_ramp(int k, float d) {
+    const int ks = k < N / 2 ? k : k - N;
+    float s, c;
+    sincospif(-2.f * (float)ks * d / (float)N, &s, &c);
+    return make_float2(c, s);
+}
+
+// One line of N values (in[i * stride]) translated by d, left in x[] at the
+// positions out_pos<N, true>.  Loads for the transform use in_pos<N, false>;
+// d == 0 loads straight into the output positions (uniform over the block).
+template <int N, class ADDR>
+__device__ __forceinline__ void shift_line(float2* x, const float2* in, size_t stride, float d, int t,
+                                           float2* lds, const ADDR& addr, const float2* tw) {
+    constexpr int V = PlanInfo<N>::V;
+    if (d == 0.f) {
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) x[idx] = in[(size_t)out_pos<N, true>(t, idx) * stride];
+        return;
+    }
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) x[idx] = in[(size_t)in_pos<N, false>(t, idx) * stride];
+    fft_line<N, false>(x, t, lds, addr, tw);
+    const float inv = 1.f / (float)N;
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) x[idx] = cscale(cmul(x[idx], shift_ramp<N>(out_pos<N, false>(t, idx), d)), inv);
+    fft_line<N, true>(x, t, lds, addr, tw);
+}
+
+// grid (N / LINES, nslots).  dst[s][y][:] = row y of src[s] translated along x
+// by sign * d_x(s); src_stride 0 reads one shared field (the probe).  dst may
+// equal src (each line is read before any of it is written).
+template <int N>
+__global__ void __launch_bounds__((RowCfg<N, 0>::THREADS))
+k_shift_rows(const float2* src, size_t src_stride, float2* dst, const float2* __restrict__ frac, float sign,
+             const float2* __restrict__ tw_g) {
+    constexpr int T = RowCfg<N, 0>::T, LINES = RowCfg<N, 0>::LINES, V = PlanInfo<N>::V;
+    __shared__ float2 lds[LINES * RowLds<N>::stride];
+    __shared__ float2 tw[N];
+    const int s = blockIdx.y;
+    const int line = threadIdx.x / T, t = threadIdx.x % T;
+    const int y = blockIdx.x * LINES + line;  // N % LINES == 0
+    const float d = sign * frac[s].y;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
+    __syncthreads();
+    float2 x[V];
+    shift_line<N>(x, src + s * src_stride + (size_t)y * N, 1, d, t, lds, RowLds<N>(line), tw);
+    float2* row = dst + ((size_t)s * N + y) * N;
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) row[out_pos<N, true>(t, idx)] = x[idx];
+}
+
+// grid (N / C, nslots).  Column kx of f[s] translated along y by d_y(s), in place.
+template <int N>
+__global__ void __launch_bounds__((ColCfg<N, 0>::THREADS))
+k_shift_cols(float2* __restrict__ f, const float2* __restrict__ frac, const float2* __restrict__ tw_g) {
+    constexpr int C = ColCfg<N, 0>::C, T = ColCfg<N, 0>::T, V = PlanInfo<N>::V;
+    __shared__ float2 lds[C * N];
+    __shared__ float2 tw[N];
+    const int s = blockIdx.y;
+    const float d = frac[s].x;
+    if (d == 0.f) return;  // uniform over the block
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    float2* col = f + (size_t)s * N * N + blockIdx.x * C + c;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
+    __syncthreads();
+    float2 x[V];
+    shift_line<N>(x, col, N, d, t, lds, ColLds<C>(c), tw);
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) col[(size_t)out_pos<N, true>(t, idx) * N] = x[idx];
+}
+
+// grid (N / C, ngroups).  Probe update at real positions: G[s] holds the
+// numerators conj(O_s) dpsi_s with rows already translated by -d_x(s); column
+// kx is translated by -d_y(s) and summed over the group's slots in slot
+// order, then P[y][kx] += sum / DP[y][kx] (float64 quotient) where DP > 0.
+template <int N>
+__global__ void __launch_bounds__((ColCfg<N, 0>::THREADS))
+k_shift_cols_update(const float2* __restrict__ G, const float2* __restrict__ frac,
+                    const GroupDev* __restrict__ groups, float2* __restrict__ P, const double* __restrict__ DP,
+                    const float2* __restrict__ tw_g) {
+    constexpr int C = ColCfg<N, 0>::C, T = ColCfg<N, 0>::T, V = PlanInfo<N>::V;
+    __shared__ float2 lds[C * N];
+    __shared__ float2 tw[N];
+    const GroupDev gd = groups[blockIdx.y];
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int kx = blockIdx.x * C + c;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
+    __syncthreads();
+    float2 acc[V];
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) acc[idx] = make_float2(0.f, 0.f);
+    for (int k = 0; k < gd.nb; ++k) {
+        const int s = gd.s0 + k;
+        float2 x[V];
+        shift_line<N>(x, G + (size_t)s * N * N + kx, N, -frac[s].x, t, lds, ColLds<C>(c), tw);
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) acc[idx] = cadd(acc[idx], x[idx]);
+        __syncthreads();  // the next slot's transform reuses the exchange buffer
+    }
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) {
+        const size_t q = (size_t)out_pos<N, true>(t, idx) * N + kx;
+        const double den = DP[q];
+        if (den > 0.0) {
+            float2 p = P[q];
+            const double inv = 1.0 / den;
+            p.x = (float)((double)p.x + (double)acc[idx].x * inv);
+            p.y = (float)((double)p.y + (double)acc[idx].y * inv);
+            P[q] = p;
+        }
+    }
+}
+
+}  // namespace mnf

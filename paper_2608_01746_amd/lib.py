@@ -54,6 +54,11 @@ SIGNATURES = {
     "ptycho_iterate": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
                                POINTER(c_int32), c_int, POINTER(c_int32), c_int,
                                POINTER(PtychoParamsC), c_void_p, c_void_p]),
+    "ptycho_forward_subpixel": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_int,
+                                        POINTER(c_float), c_int, c_void_p, c_void_p]),
+    "ptycho_iterate_subpixel": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
+                                        POINTER(c_float), c_int, POINTER(c_int32), c_int,
+                                        POINTER(PtychoParamsC), c_void_p, c_void_p]),
     "ptycho_iterate_many": (c_int, [c_void_p, POINTER(PtychoScanC), c_int, c_int, POINTER(PtychoParamsC),
                                     c_void_p]),
     "ptycho_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
@@ -84,7 +89,7 @@ SIGNATURES = {
 }
 
 KERNEL_CLASSES = ["rows_fwd", "cols_modulus", "rows_inv", "probe_update", "object_update",
-                  "small", "fuse", "forward", "grad_cols", "grad_scatter"]
+                  "small", "fuse", "forward", "grad_cols", "grad_scatter", "shift"]
 
 _lib = None
 

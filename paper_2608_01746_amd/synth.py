@@ -90,6 +90,14 @@ def fermat_positions(J: int, c: float, centre: float) -> np.ndarray:
     return np.stack([y, x], axis=1).astype(np.int32)
 
 
+def fermat_positions_real(J: int, c: float, centre: float) -> np.ndarray:
+    """The Fermat spiral of fermat_positions without rounding, float32 [J][2]."""
+    n = np.arange(J, dtype=np.float64)
+    g = math.pi * (3.0 - math.sqrt(5.0))
+    r = c * np.sqrt(n)
+    return np.stack([centre + r * np.sin(n * g), centre + r * np.cos(n * g)], axis=1).astype(np.float32)
+
+
 def random_orders(J: int, n_iter: int, seed: int) -> np.ndarray:
     """One position permutation per iteration, int32 [n_iter][J]."""
     rng = np.random.default_rng(seed)
@@ -183,6 +191,15 @@ def lab_workload() -> Workload:
     return Workload("lab-256", 1024, 256, 256, 64.0, 3 * math.pi,
                     raster_positions(20, 32, 80, jitter=2, seed=2),
                     [1.0, 10.0, 100.0, 1e3, 1e4], 65535, 3.0, 6, 2, 32, 200, "rpie")
+
+
+def lab_subpixel_workload() -> Workload:
+    """lab-256 at real positions: 400 unrounded Fermat-spiral positions with
+    the raster's density (one position per 32^2 px, c = 32 / sqrt(pi))
+    around the object centre; everything else as lab-256."""
+    w = lab_workload()
+    pos = fermat_positions_real(400, 32.0 / math.sqrt(math.pi), (1024 - 256) / 2.0)
+    return dataclasses.replace(w, name="lab-256-subpixel", pos=pos)
 
 
 def gradient_workload() -> Workload:
