@@ -25,6 +25,10 @@ start (t_plain / t_warm), after training the network on 50,000 simulated
 fused patterns (training time reported separately, excluded).  Its roofline
 entry is the network's forward pass in TFLOP/s against the bf16 MFMA peak.
 
+--workload subpixel runs the lab job at 400 real (unrounded) Fermat-spiral
+positions with the same density, through the Fourier-translated-probe entry
+points (translation passes added to every mini-batch); traffic is null there
+(the stored counters describe the integer-position kernels).
 --workload unet times the network's training step and inference alone.
 --workload broadband runs two-harmonic (Eq. 4) data through fusion and the
 monochromatic reconstruction.
@@ -93,11 +97,12 @@ def measured_traffic(kernel: str):
     return (2.0 * f + w) * 1024.0
 
 
-def cpu_baseline(w, O_true, P, clean, scale, seconds: float):
-    """The float64 oracle on the host: rPIE mini-batches of the same workload,
-    repeated for about `seconds`; returns position updates per second."""
+def cpu_baseline(w, O_true, P, clean, scale, seconds: float, sub: bool = False):
+    """The float64 oracle on the host: rPIE mini-batches of the same workload
+    (at real positions with the sub-pixel oracle when `sub`), repeated for
+    about `seconds`; returns position updates per second."""
     import numpy as np
-    from oracle import ptycho
+    from oracle import ptycho, subpixel
 
     I = clean * scale  # noiseless intensities at the fused scale (same shapes as the job)
     A = ptycho.amplitudes(I)
@@ -110,7 +115,8 @@ def cpu_baseline(w, O_true, P, clean, scale, seconds: float):
     b = 0
     while time.perf_counter() - t0 < seconds:
         idx = order[(b * w.batch) % w.J:][:w.batch]
-        O, Pk, _ = ptycho.batch_update(O, Pk, A, w.pos, idx, prm, True)
+        upd = subpixel.batch_update if sub else ptycho.batch_update
+        O, Pk, _ = upd(O, Pk, A, w.pos.astype(np.float64) if sub else w.pos, idx, prm, True)
         n += len(idx)
         b += 1
     dt = time.perf_counter() - t0
@@ -132,11 +138,13 @@ def profile_dominant(api, run_step, classes):
     return dominant, ranks
 
 
-def roofline(dominant, nlaunch, kms, positions_per_launch, N, B):
+def roofline(dominant, nlaunch, kms, positions_per_launch, N, B, counters=True):
+    """`counters`: the stored counter readings describe this launch (the
+    integer-position lab workload)."""
     avg_us = kms / nlaunch * 1e3
     bytes_launch = algo_bytes_per_update(N, B) * positions_per_launch
     achieved = bytes_launch / (avg_us * 1e-6) / 1e9
-    traffic = measured_traffic(dominant)
+    traffic = measured_traffic(dominant) if counters else None
     return {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": None if traffic is None else round(traffic),
@@ -145,6 +153,7 @@ def roofline(dominant, nlaunch, kms, positions_per_launch, N, B):
 
 
 PASSES = ["rows_fwd", "cols_modulus", "rows_inv", "object_update", "fuse"]
+SUB_PASSES = PASSES + ["shift", "probe_update"]
 
 
 def tune_sizes(sizes, batch):
@@ -158,14 +167,17 @@ def run_lab(args, api, synth, dev):
     import numpy as np
     import torch
 
-    w = synth.lab_workload()
+    sub = args.workload == "subpixel"
+    w = synth.lab_subpixel_workload() if sub else synth.lab_workload()
+    forward = api.ptycho_forward_subpixel if sub else api.ptycho_forward
+    iterate = api.ptycho_iterate_subpixel if sub else api.ptycho_iterate
     n_iter = args.iters
     tuned = tune_sizes([w.Nd], w.batch) if args.tune else None
     O_true = w.object()
     P = w.probe()
     Ot = torch.from_numpy(O_true.astype(np.complex64)).to(dev)
     Pt = torch.from_numpy(P.astype(np.complex64)).to(dev)
-    clean_t = api.ptycho_forward(Ot, Pt, w.pos, w.Nd)
+    clean_t = forward(Ot, Pt, w.pos, w.Nd)
     torch.cuda.synchronize()
     clean = clean_t.cpu().numpy().astype(np.float64)
     del Ot, Pt, clean_t
@@ -187,11 +199,10 @@ def run_lab(args, api, synth, dev):
         O.copy_(O0)
         Pw.copy_(P0)
         api.fuse_exposures(raw, w.t, w.levels, sat=float(w.sat), delta=delta, out=fused)
-        state["err"] = api.ptycho_iterate(O, Pw, fused, w.pos, n_iter, alg="rpie", alpha=0.1, beta=0.1,
-                                          batch=w.batch, update_probe=True, probe_start_iter=5, order=order,
-                                          graph=graph)
+        state["err"] = iterate(O, Pw, fused, w.pos, n_iter, alg="rpie", alpha=0.1, beta=0.1,
+                               batch=w.batch, update_probe=True, probe_start_iter=5, order=order, graph=graph)
 
-    dominant, ranks = profile_dominant(api, step, PASSES)
+    dominant, ranks = profile_dominant(api, step, SUB_PASSES if sub else PASSES)
     graph = args.graph
     print("# per-class ms (warm-up step): " +
           ", ".join(f"{k} {v[1]:.2f} ({v[0]})" for k, v in ranks.items()), file=sys.stderr, flush=True)
@@ -214,8 +225,17 @@ def run_lab(args, api, synth, dev):
     dt = (t1 - t0) / args.steps
     value = w.J * n_iter / dt
     per_launch = w.J / math.ceil(w.J / w.batch)
+    if sub:
+        metric = ("scan-position updates/s at 256^2 FP32 (lab-scale rPIE at real Fermat-spiral positions, "
+                  "Fourier-translated probes, mini-batch 32, fusion included)")
+        wl = ("lab-256-subpixel: 1024^2 object, 256^2 probe, 400 real Fermat-spiral positions, 5 exposures, "
+              "6-level fusion, rPIE B=32, %d iterations" % n_iter)
+    else:
+        metric = "scan-position updates/s at 256^2 FP32 (lab-scale rPIE, mini-batch 32, fusion included)"
+        wl = ("lab-256: 1024^2 object, 256^2 probe, 400 positions, 5 exposures, "
+              "6-level fusion, rPIE B=32, %d iterations" % n_iter)
     out = {
-        "metric": "scan-position updates/s at 256^2 FP32 (lab-scale rPIE, mini-batch 32, fusion included)",
+        "metric": metric,
         "value": round(value, 1),
         "unit": "position-updates/s",
         "n_gpus": 1,
@@ -227,18 +247,16 @@ def run_lab(args, api, synth, dev):
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic (seeded object/probe, simulated Poisson+Gaussian exposures)",
-        "config": {"workload": "lab-256: 1024^2 object, 256^2 probe, 400 positions, 5 exposures, "
-                               "6-level fusion, rPIE B=32, %d iterations" % n_iter,
-                   "positions": w.J, "pattern": w.Nd, "batch": w.batch, "iterations": n_iter,
+        "config": {"workload": wl, "positions": w.J, "pattern": w.Nd, "batch": w.batch, "iterations": n_iter,
                    "exposures": len(w.t), "levels": w.levels},
-        "roofline": roofline(dominant, nlaunch, kms, per_launch, w.Nd, w.batch),
+        "roofline": roofline(dominant, nlaunch, kms, per_launch, w.Nd, w.batch, counters=not sub),
         "per_class_ms_one_step": {k: round(v[1], 3) for k, v in ranks.items()},
         "launch_variants": tuned,
         "graph": graph,
         "final_fourier_error": float(state["err"][-1].item()),
     }
     if not args.no_cpu:
-        v, n, sec = cpu_baseline(w, O_true, P, clean, scale, args.cpu_seconds)
+        v, n, sec = cpu_baseline(w, O_true, P, clean, scale, args.cpu_seconds, sub)
         out["cpu_baseline"] = {"value": round(v, 3), "unit": "position-updates/s", "cores": 1,
                                "kind": "oracle",
                                "sample": f"{n} rPIE position updates (mini-batches of {w.batch}) of the "
@@ -359,6 +377,34 @@ def run_batch_sweep(args, api, synth, dev):
             "sweep": rows}
 
 
+def _mtf(O_rec, O_true, mask, nbins=16):
+    """Modulation transfer of a reconstruction (host evaluation of a result):
+    on the largest centred square inside the illuminated mask, the
+    reconstruction's global factor matched by the squares' means, means
+    removed, H(f) = |sum R^ conj(T^)| / sum |T^|^2 over annuli of radial
+    frequency (cycles/pixel, nbins equal bins up to 0.5).  Returns H."""
+    import numpy as np
+    ys, xs = np.nonzero(mask)
+    cy, cx = (ys.min() + ys.max() + 1) // 2, (xs.min() + xs.max() + 1) // 2
+    h = 0
+    while (cy - h - 1 >= 0 and cx - h - 1 >= 0 and cy + h + 1 <= mask.shape[0] and cx + h + 1 <= mask.shape[1]
+           and mask[cy - h - 1:cy + h + 1, cx - h - 1:cx + h + 1].all()):
+        h += 1
+    T = np.asarray(O_true[cy - h:cy + h, cx - h:cx + h], np.complex128)
+    R = np.asarray(O_rec[cy - h:cy + h, cx - h:cx + h], np.complex128)
+    R = R * (T.mean() / R.mean())
+    Rh, Th = np.fft.fft2(R - R.mean()).ravel(), np.fft.fft2(T - T.mean()).ravel()
+    f = np.fft.fftfreq(2 * h)
+    fr = np.hypot(f[:, None], f[None, :]).ravel()
+    keep = fr <= 0.5
+    b = np.minimum((fr[keep] / 0.5 * nbins).astype(int), nbins - 1)
+    cross = np.bincount(b, (Rh[keep] * np.conj(Th[keep])).real, nbins) + \
+        1j * np.bincount(b, (Rh[keep] * np.conj(Th[keep])).imag, nbins)
+    power = np.bincount(b, np.abs(Th[keep]) ** 2, nbins)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.abs(cross) / power
+
+
 def run_fusion_compare(args, api, synth, dev):
     """MNF against the linear baselines on the small workload's simulated
     data at three flux levels: image metrics of each fused stack against the
@@ -373,9 +419,13 @@ def run_fusion_compare(args, api, synth, dev):
     P = w.probe()
     mask_np = None
     deltas = synth.default_deltas(w.levels, w.sigma_read)
-    # MNF with the default steps, with eight-fold steps (stronger quantisation),
-    # and with a narrower weight (sigma 0.1); the two linear baselines
-    methods = ("mnf", "mnf_delta8", "mnf_sigma0.1", "linear", "shortest")
+    # MNF with the default parameters and a stability sweep around them (no
+    # quantisation, eight-fold steps, weight width 0.1 / 0.3, weight centre
+    # 0.4 / 0.6); the two linear baselines
+    mnf_variants = {"mnf": {}, "mnf_delta0": {"delta": ()}, "mnf_delta8": {"delta": [8 * d for d in deltas]},
+                    "mnf_sigma0.1": {"sigma": 0.1}, "mnf_sigma0.3": {"sigma": 0.3},
+                    "mnf_mu0.4": {"mu": 0.4}, "mnf_mu0.6": {"mu": 0.6}}
+    methods = tuple(mnf_variants) + ("linear", "shortest")
     rows = []
     # the configured 1/10/100 bracket at three flux levels, and the paper's own
     # 1/2/4 s ratio (Results 2.3) at two
@@ -383,7 +433,8 @@ def run_fusion_compare(args, api, synth, dev):
                 ((1.0, 2.0, 4.0), 1.0), ((1.0, 2.0, 4.0), 0.1)]
     for tb, f in settings:
         w.t = list(tb)
-        per = {m: {"dev": [], "snr": [], "bgvar": [], "nrmse": [], "nrmse_best": []} for m in methods}
+        per = {m: {"dev": [], "snr": [], "bgvar": [], "nrmse": [], "nrmse_best": [], "mtf_nyquist": [],
+                   "mtf50": []} for m in methods}
         for seed in range(1, 5):
             O_true = w.object() if seed == 1 else synth.make_object(w.M, seed)
             Ot = torch.from_numpy(O_true.astype(np.complex64)).to(dev)
@@ -397,12 +448,9 @@ def run_fusion_compare(args, api, synth, dev):
                 mask = torch.from_numpy(mask_np.astype(np.uint8)).to(dev)
             Pk = torch.from_numpy((np.sqrt(s) * P).astype(np.complex64)).to(dev)
             for m in methods:
-                if m == "mnf":
-                    I = api.fuse_exposures(raw, w.t, w.levels, sat=float(w.sat), delta=deltas)
-                elif m == "mnf_delta8":
-                    I = api.fuse_exposures(raw, w.t, w.levels, sat=float(w.sat), delta=[8 * d for d in deltas])
-                elif m == "mnf_sigma0.1":
-                    I = api.fuse_exposures(raw, w.t, w.levels, sigma=0.1, sat=float(w.sat), delta=deltas)
+                if m in mnf_variants:
+                    kw = {"delta": deltas, **mnf_variants[m]}
+                    I = api.fuse_exposures(raw, w.t, w.levels, sat=float(w.sat), **kw)
                 else:
                     I = api.fuse_linear(raw, w.t, float(w.sat), mode=m)
                 F = I.cpu().numpy().astype(np.float64)
@@ -417,6 +465,10 @@ def run_fusion_compare(args, api, synth, dev):
                     best = min(best, api.nrmse(O, Ot, mask).item())
                 per[m]["nrmse"].append(api.nrmse(O, Ot, mask).item())
                 per[m]["nrmse_best"].append(best)
+                H = _mtf(O.cpu().numpy(), O_true, mask_np)
+                per[m]["mtf_nyquist"].append(float(H[-1]))
+                below = np.nonzero(H < 0.5)[0]
+                per[m]["mtf50"].append(float((below[0] + 0.5) / (2 * len(H))) if len(below) else 0.5)
         med = lambda xs: round(float(np.median(xs)), 4)
         rows.append({"bracket": list(tb), "flux": f, **{m: {k: med(v) for k, v in per[m].items()} for m in methods}})
         print(f"# t={tb} flux x{f}: " + "  ".join(f"{m} nrmse {rows[-1][m]['nrmse']} dev {rows[-1][m]['dev']} "
@@ -431,7 +483,9 @@ def run_fusion_compare(args, api, synth, dev):
                                    "shortest frame"},
             "comparison": rows,
             "metrics": "dev = ||F - C||/||C||; snr = 10 log10(sum C^2 / sum (F - C)^2) dB; bgvar = variance of F "
-                       "where C < 1e-3 max C; nrmse / nrmse_best = final / best over 50 iterations; medians"}
+                       "where C < 1e-3 max C; nrmse / nrmse_best = final / best over 50 iterations; "
+                       "mtf_nyquist = transfer of the final object in the last of 16 radial bins (0.47-0.5 "
+                       "cycles/px), mtf50 = centre of the first bin below 0.5 (0.5 if none); medians"}
 
 
 def run_broadband(args, api, synth, dev):
@@ -686,8 +740,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=None, help="iterations per step (200 lab, 20 multiscan)")
-    ap.add_argument("--workload", choices=["lab", "multiscan", "warmstart", "batch-sweep", "fusion-compare",
-                                           "unet", "broadband"], default="lab")
+    ap.add_argument("--workload", choices=["lab", "subpixel", "multiscan", "warmstart", "batch-sweep",
+                                           "fusion-compare", "unet", "broadband"], default="lab")
     ap.add_argument("--train-seconds", type=float, default=240.0, help="warm start: training time budget")
     ap.add_argument("--train-objects", type=int, default=500, help="warm start: training objects x 100 patterns")
     ap.add_argument("--epochs", type=float, default=100.0, help="warm start: epoch cap")
@@ -707,7 +761,7 @@ def main() -> int:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         return 2
     if args.iters is None:
-        args.iters = 200 if args.workload == "lab" else 20
+        args.iters = 200 if args.workload in ("lab", "subpixel") else 20
 
     import torch
 
@@ -720,7 +774,7 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    run = {"lab": run_lab, "multiscan": run_multiscan, "warmstart": run_warmstart,
+    run = {"lab": run_lab, "subpixel": run_lab, "multiscan": run_multiscan, "warmstart": run_warmstart,
            "batch-sweep": run_batch_sweep, "fusion-compare": run_fusion_compare, "unet": run_unet,
            "broadband": run_broadband}[args.workload]
     out = run(args, api, synth, dev)

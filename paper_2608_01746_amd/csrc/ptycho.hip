@@ -241,15 +241,16 @@ int shift_probe_n(mnf_ctx* ctx, const float2* P, float2* Pd, const float2* fr, i
     MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_rows<NW>), dim3(NW / RowCfg<NW, 0>::LINES, nslots),
                dim3(RowCfg<NW, 0>::THREADS), P, (size_t)0, Pd, fr, 1.f, tw);
     MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_cols<NW>), dim3(NW / ColCfg<NW, 0>::C, nslots),
-               dim3(ColCfg<NW, 0>::THREADS), Pd, fr, tw);
+               dim3(ColCfg<NW, 0>::THREADS), Pd, fr, 1.f, tw);
     return MNF_OK;
 }
 int shift_probe(mnf_ctx* ctx, int Nw, const float2* P, float2* Pd, const float2* fr, int nslots, hipStream_t st) {
     MNF_DISPATCH(Nw, shift_probe_n, ctx, P, Pd, fr, nslots, st)
 }
 
-// Probe update of a sub-pixel launch: G[s] translated back by -d_s (rows in
-// place, then columns summed per group) and applied to P with DP.
+// Probe update of a sub-pixel launch: G[s] translated back by -d_s in place
+// (rows, then columns, every slot in parallel), then summed per group and
+// applied to P with DP.
 template <int NW>
 int shift_update_n(mnf_ctx* ctx, float2* G, const float2* fr, const GroupDev* groups, int nslots, int ngroups,
                    float2* P, const double* DP, hipStream_t st) {
@@ -257,8 +258,10 @@ int shift_update_n(mnf_ctx* ctx, float2* G, const float2* fr, const GroupDev* gr
     MNF_TRY(twiddles(ctx, NW, &tw));
     MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_rows<NW>), dim3(NW / RowCfg<NW, 0>::LINES, nslots),
                dim3(RowCfg<NW, 0>::THREADS), (const float2*)G, (size_t)NW * NW, G, fr, -1.f, tw);
-    MNF_LAUNCH(ctx, MNF_K_PROBE_UPDATE, st, (k_shift_cols_update<NW>), dim3(NW / ColCfg<NW, 0>::C, ngroups),
-               dim3(ColCfg<NW, 0>::THREADS), (const float2*)G, fr, groups, P, DP, tw);
+    MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_cols<NW>), dim3(NW / ColCfg<NW, 0>::C, nslots),
+               dim3(ColCfg<NW, 0>::THREADS), G, fr, -1.f, tw);
+    MNF_LAUNCH(ctx, MNF_K_PROBE_UPDATE, st, (k_probe_sum_update<NW>), dim3((NW * NW + 255) / 256, ngroups),
+               dim3(256), (const float2*)G, groups, P, DP);
     return MNF_OK;
 }
 int shift_update(mnf_ctx* ctx, int Nw, float2* G, const float2* fr, const GroupDev* groups, int nslots, int ngroups,

@@ -72,15 +72,15 @@ k_shift_rows(const float2* src, size_t src_stride, float2* dst, const float2* __
     for (int idx = 0; idx < V; ++idx) row[out_pos<N, true>(t, idx)] = x[idx];
 }
 
-// grid (N / C, nslots).  Column kx of f[s] translated along y by d_y(s), in place.
+// grid (N / C, nslots).  Column kx of f[s] translated along y by sign * d_y(s), in place.
 template <int N>
 __global__ void __launch_bounds__((ColCfg<N, 0>::THREADS))
-k_shift_cols(float2* __restrict__ f, const float2* __restrict__ frac, const float2* __restrict__ tw_g) {
+k_shift_cols(float2* __restrict__ f, const float2* __restrict__ frac, float sign, const float2* __restrict__ tw_g) {
     constexpr int C = ColCfg<N, 0>::C, T = ColCfg<N, 0>::T, V = PlanInfo<N>::V;
     __shared__ float2 lds[C * N];
     __shared__ float2 tw[N];
     const int s = blockIdx.y;
-    const float d = frac[s].x;
+    const float d = sign * frac[s].x;
     if (d == 0.f) return;  // uniform over the block
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     float2* col = f + (size_t)s * N * N + blockIdx.x * C + c;
@@ -92,46 +92,27 @@ k_shift_cols(float2* __restrict__ f, const float2* __restrict__ frac, const floa
     for (int idx = 0; idx < V; ++idx) col[(size_t)out_pos<N, true>(t, idx) * N] = x[idx];
 }
 
-// grid (N / C, ngroups).  Probe update at real positions: G[s] holds the
-// numerators conj(O_s) dpsi_s with rows already translated by -d_x(s); column
-// kx is translated by -d_y(s) and summed over the group's slots in slot
-// order, then P[y][kx] += sum / DP[y][kx] (float64 quotient) where DP > 0.
+// grid (ceil(N^2 / 256), ngroups).  Probe update at real positions: G[s]
+// holds the numerators conj(O_s) dpsi_s translated back by -d_s; per probe
+// pixel q the group's slots are summed in slot order and
+// P[q] += sum / DP[q] (float64 quotient) where DP > 0.
 template <int N>
-__global__ void __launch_bounds__((ColCfg<N, 0>::THREADS))
-k_shift_cols_update(const float2* __restrict__ G, const float2* __restrict__ frac,
-                    const GroupDev* __restrict__ groups, float2* __restrict__ P, const double* __restrict__ DP,
-                    const float2* __restrict__ tw_g) {
-    constexpr int C = ColCfg<N, 0>::C, T = ColCfg<N, 0>::T, V = PlanInfo<N>::V;
-    __shared__ float2 lds[C * N];
-    __shared__ float2 tw[N];
+__global__ void __launch_bounds__(256)
+k_probe_sum_update(const float2* __restrict__ G, const GroupDev* __restrict__ groups, float2* __restrict__ P,
+                   const double* __restrict__ DP) {
     const GroupDev gd = groups[blockIdx.y];
-    const int c = threadIdx.x % C, t = threadIdx.x / C;
-    const int kx = blockIdx.x * C + c;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
-    __syncthreads();
-    float2 acc[V];
-#pragma unroll
-    for (int idx = 0; idx < V; ++idx) acc[idx] = make_float2(0.f, 0.f);
-    for (int k = 0; k < gd.nb; ++k) {
-        const int s = gd.s0 + k;
-        float2 x[V];
-        shift_line<N>(x, G + (size_t)s * N * N + kx, N, -frac[s].x, t, lds, ColLds<C>(c), tw);
-#pragma unroll
-        for (int idx = 0; idx < V; ++idx) acc[idx] = cadd(acc[idx], x[idx]);
-        __syncthreads();  // the next slot's transform reuses the exchange buffer
-    }
-#pragma unroll
-    for (int idx = 0; idx < V; ++idx) {
-        const size_t q = (size_t)out_pos<N, true>(t, idx) * N + kx;
-        const double den = DP[q];
-        if (den > 0.0) {
-            float2 p = P[q];
-            const double inv = 1.0 / den;
-            p.x = (float)((double)p.x + (double)acc[idx].x * inv);
-            p.y = (float)((double)p.y + (double)acc[idx].y * inv);
-            P[q] = p;
-        }
-    }
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= N * N) return;
+    const double den = DP[q];
+    if (!(den > 0.0)) return;
+    float2 acc = make_float2(0.f, 0.f);
+    const float2* g = G + (size_t)gd.s0 * N * N + q;
+    for (int k = 0; k < gd.nb; ++k) acc = cadd(acc, g[(size_t)k * N * N]);
+    float2 p = P[q];
+    const double inv = 1.0 / den;
+    p.x = (float)((double)p.x + (double)acc.x * inv);
+    p.y = (float)((double)p.y + (double)acc.y * inv);
+    P[q] = p;
 }
 
 }  // namespace mnf
