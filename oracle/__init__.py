@@ -19,6 +19,8 @@ baselines linear-integration and single-exposure fusion, image metrics
 broadband discrete-spectrum measurement (Eq. 4): resampling of a pattern per line
 subpixel real-valued scan positions: Fourier-translated probe, mini-batched
          ePIE / rPIE at sub-pixel positions
+mixed    mixed-state (multi-mode) probes: incoherent sum of modes, mini-batched
+         ePIE / rPIE with a shared projection
 
 Every function states the passage it follows; readings the paper leaves
 open are named where they are used.
