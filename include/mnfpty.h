@@ -177,6 +177,29 @@ int ptycho_iterate_subpixel(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P
                             double* err_out, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Mixed-state (multi-mode) probes for partially coherent illumination (the
+ * incoherent sum of Eq. 4, e.g. the two harmonics of the XUV source in
+ * Methods 3.2).  M mutually incoherent probe modes share one object:
+ *     I_j = sum_m |F_unitary(pad_Nd(P_m * O[pos_j window]))|^2.
+ * The iteration generalises ptycho_iterate (Thibault & Menzel 2013): each
+ * mode's far field is scaled by A_j / sqrt(sum_m |Psi_jm|^2) (where the sum
+ * is 0: A_j in mode 0, 0 in the others); the object takes
+ * sum_j sum_m conj(P_m) dpsi_jm over denominators of the total probe
+ * intensity Q = sum_m |P_m|^2 ((1-alpha) Q + alpha max Q for rPIE, max Q/alpha
+ * for ePIE); each mode P_m takes sum_j conj(O_j) dpsi_jm over the
+ * single-mode probe denominators; the error is sum (sqrt(sum_m |Psi|^2) - A)^2
+ * normalised by sum A^2.  No orthogonalisation of the modes.
+ * P     device c64 [M][Nw][Nw] (mode-major), 1 <= M <= 4, updated in place by
+ *       ptycho_iterate_modes when the probe is updated;
+ * batch * M <= 512; every other argument as for ptycho_forward / ptycho_iterate
+ * (one scan per call, integer positions).  M = 1 is the single-mode path. */
+int ptycho_forward_modes(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P, int M, int Nw, int Nd,
+                         const int32_t* pos, int J, float* I_out, void* stream);
+int ptycho_iterate_modes(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int M, int Nw, const float* I,
+                         int Nd, const int32_t* pos, int J, const int32_t* order, int n_iter,
+                         const ptycho_params* params, double* err_out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Many independent scans of uneven sizes in one call (the same iteration as
  * ptycho_iterate, applied to every scan).  Scans are grouped by detector
  * size; each pass of each mini-batch round is one launch covering the

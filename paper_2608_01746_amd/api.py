@@ -182,6 +182,26 @@ def ptycho_forward_subpixel(O: torch.Tensor, P: torch.Tensor, pos, Nd: int,
     return out
 
 
+def ptycho_forward_modes(O: torch.Tensor, P: torch.Tensor, pos, Nd: int,
+                         out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Detector-centred sum_m |F(P_m O_j)|^2 for probe modes P [M][Nw][Nw]."""
+    _dev(O, "O", torch.complex64, 2)
+    _dev(P, "P", torch.complex64, 3)
+    if P.shape[1] != P.shape[2]:
+        raise ValueError("probe modes must be [M][Nw][Nw]")
+    posa = _host_i32(pos, (2,), "pos")
+    J = posa.shape[0]
+    if out is None:
+        out = torch.empty((J, Nd, Nd), dtype=torch.float32, device=O.device)
+    else:
+        _dev(out, "out", torch.float32, 3)
+    ctx = _ctx(O.device)
+    rc = _L.load().ptycho_forward_modes(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], P.shape[1], Nd,
+                                        _i32p(posa), J, _ptr(out), _stream(O.device))
+    _check(rc, ctx)
+    return out
+
+
 # ----------------------------------------------------------- reconstruction
 
 ALGS = {"epie": 0, "rpie": 1}
@@ -208,10 +228,22 @@ def ptycho_iterate_subpixel(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, p
                     beta, batch, update_probe, probe_start_iter, order, it0, err, graph)
 
 
+def ptycho_iterate_modes(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_iter: int,
+                         alg: str = "rpie", alpha: float = 0.1, beta: float = 0.1, batch: int = 1,
+                         update_probe: bool = False, probe_start_iter: int = 0, order=None, it0: int = 0,
+                         err: bool = True, graph: bool = False) -> Optional[torch.Tensor]:
+    """ptycho_iterate with mixed-state probe modes P [M][Nw][Nw] (updated in
+    place with O)."""
+    return _iterate("ptycho_iterate_modes", _host_i32(pos, (2,), "pos"), _i32p, O, P, I, n_iter, alg, alpha,
+                    beta, batch, update_probe, probe_start_iter, order, it0, err, graph, modes=True)
+
+
 def _iterate(entry, posa, posp, O, P, I, n_iter, alg, alpha, beta, batch, update_probe, probe_start_iter, order,
-             it0, err, graph):
+             it0, err, graph, modes=False):
     _dev(O, "O", torch.complex64, 2)
-    _dev(P, "P", torch.complex64, 2)
+    _dev(P, "P", torch.complex64, 3 if modes else 2)
+    if modes and P.shape[1] != P.shape[2]:
+        raise ValueError("probe modes must be [M][Nw][Nw]")
     _dev(I, "I", torch.float32, 3)
     J = posa.shape[0]
     if I.shape[0] != J or I.shape[1] != I.shape[2]:
@@ -225,7 +257,8 @@ def _iterate(entry, posa, posp, O, P, I, n_iter, alg, alpha, beta, batch, update
                            1 if graph else 0)
     e = torch.empty(max(n_iter, 1), dtype=torch.float64, device=O.device) if err else None
     ctx = _ctx(O.device)
-    rc = getattr(_L.load(), entry)(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], _ptr(I),
+    psize = (P.shape[0], P.shape[1]) if modes else (P.shape[0],)
+    rc = getattr(_L.load(), entry)(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), *psize, _ptr(I),
                                    I.shape[1], posp(posa), J, _i32p(orda), n_iter, ctypes.byref(prm),
                                    _ptr(e), _stream(O.device))
     _check(rc, ctx)

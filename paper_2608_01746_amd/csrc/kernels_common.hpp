@@ -8,6 +8,7 @@
 namespace mnf {
 
 constexpr int kMaxBatch = 512;  // positions per mini-batch handled by one launch
+constexpr int kMaxModes = 4;    // probe modes of a mixed-state reconstruction
 constexpr int kColGroup = 32;   // adjacent columns per column-pass block (32 x 8 B = 256 B of S, 128 B of I per row)
 
 // Launch shapes.  Each pass has two compiled variants (0: the default, 1:

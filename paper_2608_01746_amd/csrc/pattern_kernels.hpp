@@ -21,13 +21,14 @@ namespace mnf {
 
 // -------------------------------------------------------------- rows_fwd
 // grid (ceil(maxNw / LINES), nslots).  Writes per-block maxima of |O_j|^2,
-// maxO2_part[slot][blockIdx.x] (when not NULL).  Pd (when not NULL) holds one
-// probe per slot, Pd[slot][Nw][Nw] (the probe translated to each slot's real
-// position), used in place of the scan's probe.
+// maxO2_part[slot][blockIdx.x] (when not NULL).  Pd (when not NULL) is a
+// table of probes [k][Nw][Nw] used in place of the scan's probe: slot s reads
+// Pd[s % pmod] (one translated probe per slot for real positions, pmod >=
+// nslots; probe mode s % M for mixed states, pmod = M).
 template <int N, int RV>
 __global__ void __launch_bounds__((RowCfg<N, RV>::THREADS))
 k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
-           float2* __restrict__ S, float* __restrict__ maxO2_part, const float2* __restrict__ Pd,
+           float2* __restrict__ S, float* __restrict__ maxO2_part, const float2* __restrict__ Pd, int pmod,
            const float2* __restrict__ tw_g) {
     constexpr int T = RowCfg<N, RV>::T, LINES = RowCfg<N, RV>::LINES, V = PlanInfo<N>::V;
     __shared__ float2 lds[LINES * RowLds<N>::stride];
@@ -45,7 +46,7 @@ k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
     float2 x[V];
     float mO = 0.f;
     const float2* Orow = sc.O + (size_t)(sd.py + (live ? y : 0)) * Mx + sd.px;
-    const float2* Prow = (Pd ? Pd + (size_t)s * Nw * Nw : sc.P) + (size_t)(live ? y : 0) * Nw;
+    const float2* Prow = (Pd ? Pd + (size_t)(s % pmod) * Nw * Nw : sc.P) + (size_t)(live ? y : 0) * Nw;
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int n = in_pos<N, false>(t, idx);
@@ -193,6 +194,132 @@ k_cols_intensity(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
     }
 }
 
+// ------------------------------------------------- mixed-state column passes
+// Slots come in runs of M (one per probe mode) for each position; grid
+// (N / C, nslots / M), block y owns the M slots of one position.
+//
+// cols_modulus_modes: the modes' column transforms Psi_m, the shared
+// projection Psi'_m = Psi_m A / sqrt(sum_m |Psi_m|^2) (where the sum is 0:
+// A in mode 0, 0 in the others), the inverse column transforms; error
+// (sqrt(sum_m |Psi_m|^2) - A)^2 into err_part[j][blockIdx.x].  Each mode's
+// transformed column is parked in S (every row, by the thread that reads it
+// back) while the intensity sum over the modes is formed.
+template <int N, int CV>
+__global__ void __launch_bounds__((ColCfg<N, CV>::THREADS))
+k_cols_modulus_modes(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
+                     float2* __restrict__ S, int M, const float2* __restrict__ tw_g) {
+    constexpr int C = ColCfg<N, CV>::C, T = ColCfg<N, CV>::T, V = PlanInfo<N>::V;
+    __shared__ float2 lds[C * N];
+    __shared__ float2 tw[N];
+    __shared__ double red[ColCfg<N, CV>::THREADS / 64 + 1];
+    const int s0 = blockIdx.y * M;
+    const ScanDev sc0 = scans[0];
+    const SlotDev sd = slots[s0];
+    const ScanDev sc = scan_desc(scans, sc0, sd.scan);
+    const int Nw = sc.Nw;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int kx = blockIdx.x * C + c;
+    const float* Ij = sc.I + (size_t)sd.j * N * N;
+    const int sx = (kx + N / 2) % N;
+    float a[V], tot[V];
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) {
+        const int ky = out_pos<N, false>(t, idx);
+        a[idx] = sqrtf(fmaxf(Ij[(size_t)((ky + N / 2) % N) * N + sx], 0.f));
+        tot[idx] = 0.f;
+    }
+    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
+    __syncthreads();
+    const float sc1 = 1.f / (float)N;
+    for (int m = 0; m < M; ++m) {
+        float2* col = S + (size_t)(s0 + m) * N * N + kx;
+        float2 x[V];
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) {
+            const int y = in_pos<N, false>(t, idx);
+            x[idx] = y < Nw ? col[(size_t)y * N] : make_float2(0.f, 0.f);
+        }
+        fft_line<N, false>(x, t, lds, ColLds<C>(c), tw);
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) {
+            const float2 v = cscale(x[idx], sc1);
+            tot[idx] += cabs2(v);
+            col[(size_t)out_pos<N, false>(t, idx) * N] = v;
+        }
+        __syncthreads();  // the next mode's transform reuses the exchange buffer
+    }
+    float accf = 0.f;
+    float f[V];
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) {
+        const float mag = sqrtf(tot[idx]);
+        const float d = mag - a[idx];
+        accf += d * d;
+        f[idx] = tot[idx] > 1e-30f ? a[idx] / mag : -1.f;  // -1: the all-zero case
+    }
+    for (int m = 0; m < M; ++m) {
+        float2* col = S + (size_t)(s0 + m) * N * N + kx;
+        float2 x[V];
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) {
+            const float2 v = col[(size_t)out_pos<N, false>(t, idx) * N];
+            x[idx] = f[idx] >= 0.f ? cscale(v, f[idx]) : make_float2(m == 0 ? a[idx] : 0.f, 0.f);
+        }
+        fft_line<N, true>(x, t, lds, ColLds<C>(c), tw);
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) {
+            const int y = out_pos<N, true>(t, idx);
+            if (y < Nw) col[(size_t)y * N] = x[idx];
+        }
+        __syncthreads();
+    }
+    const double acc = block_sum((double)accf, red);
+    if (threadIdx.x == 0) sc.err_part[(size_t)sd.j * gridDim.x + blockIdx.x] = acc;
+}
+
+// cols_intensity_modes: forward model only, I_out[j] = fftshift sum_m |Psi_m|^2.
+template <int N, int CV>
+__global__ void __launch_bounds__((ColCfg<N, CV>::THREADS))
+k_cols_intensity_modes(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
+                       const float2* __restrict__ S, int M, float* __restrict__ I_out,
+                       const float2* __restrict__ tw_g) {
+    constexpr int C = ColCfg<N, CV>::C, T = ColCfg<N, CV>::T, V = PlanInfo<N>::V;
+    __shared__ float2 lds[C * N];
+    __shared__ float2 tw[N];
+    const int s0 = blockIdx.y * M;
+    const ScanDev sc0 = scans[0];
+    const SlotDev sd = slots[s0];
+    const int Nw = scan_desc(scans, sc0, sd.scan).Nw;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int kx = blockIdx.x * C + c;
+    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
+    __syncthreads();
+    float tot[V];
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) tot[idx] = 0.f;
+    for (int m = 0; m < M; ++m) {
+        const float2* col = S + (size_t)(s0 + m) * N * N + kx;
+        float2 x[V];
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) {
+            const int y = in_pos<N, false>(t, idx);
+            x[idx] = y < Nw ? col[(size_t)y * N] : make_float2(0.f, 0.f);
+        }
+        fft_line<N, false>(x, t, lds, ColLds<C>(c), tw);
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) tot[idx] += cabs2(x[idx]);
+        __syncthreads();
+    }
+    const float sc2 = 1.f / ((float)N * (float)N);
+    float* Ij = I_out + (size_t)sd.j * N * N;
+    const int sx = (kx + N / 2) % N;
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) {
+        const int ky = out_pos<N, false>(t, idx);
+        Ij[(size_t)((ky + N / 2) % N) * N + sx] = tot[idx] * sc2;
+    }
+}
+
 // ------------------------------------------------------- rows_inv_update
 // grid (maxNw, ngroups): block (r, g) owns probe row r of group g's scan and
 // loops over the group's slots in rounds of ULINES.  For each slot s the
@@ -214,6 +341,14 @@ k_cols_intensity(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
 //     (probe updated) writes the probe numerators G[s][r][n] = conj(O_s) dpsi
 //     for the inverse translation and the float64 denominator sums
 //     DP[r][n] = sum_s d_P,s, and leaves P unchanged.
+//   MODE 5, 6 (mixed states): the group's slots come in runs of nmodes (one
+//     per probe mode, mode = slot index % nmodes, modes P[m][Nw][Nw]); as
+//     MODE 0, 1 with probe mode m in slot s's dpsi and object numerator.
+//     P2 = sum_m |P_m|^2 / nmodes and maxP2_row its row maximum, so the
+//     object update's per-slot denominators add up over a position's modes
+//     to those of the total probe intensity.  MODE 6 updates every mode's
+//     row, P_m += sum_s in mode m conj(O_s) dpsi_s / sum_j d_P,j, with one
+//     denominator term per position (its mode-0 slot).
 template <int N, int RV = 0>
 struct UpdCfg {
     static constexpr int T = PlanInfo<N>::T;
@@ -228,19 +363,21 @@ __global__ void __launch_bounds__((UpdCfg<N, RV>::THREADS))
 k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
                   const GroupDev* __restrict__ groups, float2* __restrict__ S,
                   const float* __restrict__ maxO2_part, int nparts, int rpie, float beta,
-                  float upstream, const float2* __restrict__ Pd, float2* __restrict__ G,
+                  float upstream, int nmodes, const float2* __restrict__ Pd, float2* __restrict__ G,
                   double* __restrict__ DP, const float2* __restrict__ tw_g) {
     constexpr int T = UpdCfg<N, RV>::T, ULINES = UpdCfg<N, RV>::ULINES, V = PlanInfo<N>::V;
     constexpr int THREADS = UpdCfg<N, RV>::THREADS;
     constexpr int COLS = (N + THREADS - 1) / THREADS;  // probe columns owned per thread
-    constexpr bool SUB = MODE >= 3;                     // per-slot translated probes
-    constexpr bool ACC = MODE == 1 || MODE == 2;        // probe-row sums over the batch
-    constexpr bool DEN = MODE == 1 || MODE == 4;
+    constexpr bool SUB = MODE == 3 || MODE == 4;                  // per-slot translated probes
+    constexpr bool MIX = MODE == 5 || MODE == 6;                  // probe modes
+    constexpr bool ACC = MODE == 1 || MODE == 2 || MODE == 6;     // probe-row sums over the batch
+    constexpr bool DEN = MODE == 1 || MODE == 4 || MODE == 6;
+    constexpr int NM = MIX ? kMaxModes : 1;                       // probe rows held
     // the transform's exchange buffer doubles as the per-line numerator buffer
     // once a round's transforms are done (both hold ULINES x N complex values)
     __shared__ float2 lds[ULINES * RowLds<N>::stride];
     __shared__ float2 tw[N];
-    __shared__ float2 s_prow[N];
+    __shared__ float2 s_prow[NM * N];
     __shared__ float c_den[DEN ? ULINES * N : 1];
     __shared__ float s_max[DEN ? kMaxBatch : 1];
     __shared__ int s_py[kMaxBatch], s_px[kMaxBatch];
@@ -255,9 +392,11 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
     const int line = threadIdx.x / T, t = threadIdx.x % T;
 
     const float2* Prow = sc.P + (size_t)r * Nw;
-    for (int i = threadIdx.x; i < N; i += THREADS) {
-        tw[i] = tw_g[i];
-        s_prow[i] = i < Nw ? Prow[i] : make_float2(0.f, 0.f);
+    for (int i = threadIdx.x; i < N; i += THREADS) tw[i] = tw_g[i];
+    const int nrow = MIX ? nmodes * N : N;
+    for (int i = threadIdx.x; i < nrow; i += THREADS) {
+        const int m = i / N, n = i % N;
+        s_prow[i] = n < Nw ? Prow[(size_t)m * Nw * Nw + n] : make_float2(0.f, 0.f);
     }
     for (int k = threadIdx.x; k < nb; k += THREADS) {
         const SlotDev sd = slots[gd.s0 + k];
@@ -269,11 +408,12 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             s_max[k] = m;
         }
     }
-    float2 num[COLS];
+    float2 num[NM][COLS];
     double den[COLS];
 #pragma unroll
     for (int c = 0; c < COLS; ++c) {
-        num[c] = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int q = 0; q < NM; ++q) num[q][c] = make_float2(0.f, 0.f);
         den[c] = 0.0;
     }
     __syncthreads();
@@ -303,7 +443,7 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             for (int idx = 0; idx < V; ++idx) {
                 const int n = out_pos<N, true>(t, idx);
                 if (n < Nw) {
-                    const float2 p = SUB ? pv[idx] : s_prow[n];
+                    const float2 p = SUB ? pv[idx] : s_prow[(MIX ? k % nmodes : 0) * N + n];
                     const float2 d = MODE == 2 ? cscale(x[idx], scl) : csub(cscale(x[idx], scl), cmul(p, o[idx]));
                     row[n] = cconjmul(p, d);
                     if constexpr (ACC) c_num[line * N + n] = cconjmul(o[idx], d);
@@ -323,8 +463,19 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                 const int n = threadIdx.x + c * THREADS;
                 if (n < Nw) {
                     for (int l = 0; l < nl; ++l) {
-                        if constexpr (ACC) num[c] = cadd(num[c], c_num[l * N + n]);
-                        if constexpr (DEN) den[c] += (double)c_den[l * N + n];
+                        if constexpr (MIX) {
+                            const int mm = (k0 + l) % nmodes;
+                            if constexpr (ACC) {
+#pragma unroll
+                                for (int q = 0; q < NM; ++q)
+                                    if (q == mm) num[q][c] = cadd(num[q][c], c_num[l * N + n]);
+                            }
+                            if constexpr (DEN)
+                                if (mm == 0) den[c] += (double)c_den[l * N + n];
+                        } else {
+                            if constexpr (ACC) num[0][c] = cadd(num[0][c], c_num[l * N + n]);
+                            if constexpr (DEN) den[c] += (double)c_den[l * N + n];
+                        }
                     }
                 }
             }
@@ -339,7 +490,24 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
         if constexpr (MODE == 2) {
             if (sc.gP) {
                 float2* g = sc.gP + (size_t)r * Nw + n;
-                *g = cadd(*g, num[c]);
+                *g = cadd(*g, num[0][c]);
+            }
+        } else if constexpr (MIX) {
+            float q2 = 0.f;
+            for (int q = 0; q < nmodes; ++q) q2 += cabs2(s_prow[q * N + n]);
+            const float p2 = q2 / (float)nmodes;
+            sc.P2[(size_t)r * Nw + n] = p2;
+            pmax = fmaxf(pmax, p2);
+            if (MODE == 6 && den[c] > 0.0) {
+                const double inv = 1.0 / den[c];
+#pragma unroll
+                for (int q = 0; q < NM; ++q) {
+                    if (q >= nmodes) break;
+                    float2 p = s_prow[q * N + n];
+                    p.x = (float)((double)p.x + (double)num[q][c].x * inv);
+                    p.y = (float)((double)p.y + (double)num[q][c].y * inv);
+                    sc.P[(size_t)q * Nw * Nw + (size_t)r * Nw + n] = p;
+                }
             }
         } else {
             float2 p = s_prow[n];
@@ -349,8 +517,8 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             if constexpr (MODE == 4) DP[(size_t)r * Nw + n] = den[c];
             if (MODE == 1 && den[c] > 0.0) {
                 const double inv = 1.0 / den[c];
-                p.x = (float)((double)p.x + (double)num[c].x * inv);
-                p.y = (float)((double)p.y + (double)num[c].y * inv);
+                p.x = (float)((double)p.x + (double)num[0][c].x * inv);
+                p.y = (float)((double)p.y + (double)num[0][c].y * inv);
                 sc.P[(size_t)r * Nw + n] = p;
             }
         }

@@ -78,6 +78,7 @@ struct ScanIn {
     float2* gO;
     float2* gP;
     const float2* frac = nullptr;  // host [J] (d_y, d_x) fractions of real positions, or NULL
+    int modes = 1;                 // probe modes (P holds [modes][Nw][Nw]); each position takes `modes` slots
 };
 
 struct Box {
@@ -148,6 +149,7 @@ struct CallPlan {
     size_t max_maxO2 = 0;             // floats of max partials
     int max_slots = 0;                // slots of the largest launch
     bool sub = false;                 // real (sub-pixel) positions: one scan, translated probes
+    int modes = 1;                    // probe modes (mixed states): one scan, `modes` slots per position
     void* d_scans = nullptr;
     void* d_slots = nullptr;
     void* d_groups = nullptr;
@@ -191,14 +193,16 @@ void plan_round(mnf_ctx* ctx, CallPlan& pl, const std::vector<ScanIn>& in, const
         const int t0 = b * B;
         if (t0 >= s.J) continue;
         const int nb = std::min(B, s.J - t0);
-        GroupDev g{k, L.nslots, nb, L.tiles};
+        GroupDev g{k, L.nslots, nb * s.modes, L.tiles};
         for (int t = t0; t < t0 + nb; ++t) {
             const int j = s.order ? s.order[(size_t)i * s.J + t] : t;
-            pl.slots.push_back(SlotDev{k, j, s.pos[2 * j], s.pos[2 * j + 1]});
-            pl.fracs.push_back(s.frac ? s.frac[j] : make_float2(0.f, 0.f));
+            for (int m = 0; m < s.modes; ++m) {
+                pl.slots.push_back(SlotDev{k, j, s.pos[2 * j], s.pos[2 * j + 1]});
+                pl.fracs.push_back(s.frac ? s.frac[j] : make_float2(0.f, 0.f));
+            }
         }
         pl.groups.push_back(g);
-        L.nslots += nb;
+        L.nslots += nb * s.modes;
         L.ngroups += 1;
         L.tiles += tiles_of(pl.scans[k]);
         L.maxNw = std::max(L.maxNw, s.Nw);
@@ -225,12 +229,14 @@ int upload_plan(mnf_ctx* ctx, CallPlan& pl, hipStream_t st) {
 
 template <int N, int RV>
 int launch_rows_fwd(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ScanDev* scans, float2* S, float* mO,
-                    const float2* Pd, const float2* tw, hipStream_t st) {
+                    const float2* Pd, int pmod, const float2* tw, hipStream_t st) {
     const int gr = (L.maxNw + RowCfg<N, RV>::LINES - 1) / RowCfg<N, RV>::LINES;
     MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, (k_rows_fwd<N, RV>), dim3(gr, L.nslots), dim3(RowCfg<N, RV>::THREADS),
-               scans, (const SlotDev*)pl.d_slots + L.slot_off, S, mO, Pd, tw);
+               scans, (const SlotDev*)pl.d_slots + L.slot_off, S, mO, Pd, pmod, tw);
     return MNF_OK;
 }
+
+constexpr int kOwnProbe = 1 << 30;  // pmod for one probe per slot
 
 // Translated probes of a launch's slots: Pd[s] = S_{d_s}[P] (rows, then columns).
 template <int NW>
@@ -282,17 +288,17 @@ int issue_iterate_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, cons
     const float2* nP = nullptr;
     float2* nG = nullptr;
     double* nD = nullptr;
-    MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, nP, tw, st)));
+    MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, nP, 1, tw, st)));
     MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, CV, ColOp::Modulus>),
                dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, S, 0.f, tw);
     if (upd)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 1>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, nP,
-                   nG, nD, tw);
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
+                   nP, nG, nD, tw);
     else
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 0>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, nP,
-                   nG, nD, tw);
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
+                   nP, nG, nD, tw);
     MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
     return MNF_OK;
@@ -315,26 +321,68 @@ int issue_subpixel_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, con
     const int rpie = p.alg == 1;
     const float2* Pd = sb.Pd;
     MNF_TRY(shift_probe(ctx, Nw, pl.scans[0].P, sb.Pd, fr, L.nslots, st));
-    MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, Pd, tw, st)));
+    MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, Pd, kOwnProbe, tw, st)));
     MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, CV, ColOp::Modulus>),
                dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, S, 0.f, tw);
     if (upd)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 4>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, Pd,
-                   sb.G, sb.DP, tw);
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
+                   Pd, sb.G, sb.DP, tw);
     else
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 3>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, Pd,
-                   (float2*)nullptr, (double*)nullptr, tw);
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
+                   Pd, (float2*)nullptr, (double*)nullptr, tw);
     MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
     if (upd) MNF_TRY(shift_update(ctx, Nw, sb.G, fr, groups, L.nslots, L.ngroups, pl.scans[0].P, sb.DP, st));
     return MNF_OK;
 }
 
+// The same mini-batch with probe modes (one scan): slots come in runs of M
+// per position; the exit-wave pass reads mode s % M, the column pass projects
+// the M modes of a position together, the inverse-row pass updates every
+// mode, the object update sums the modes' numerators.
+template <int N, int RV, int CV>
+int issue_modes_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd,
+                       float2* S, float* mO, hipStream_t st) {
+    const float2* tw;
+    MNF_TRY(twiddles(ctx, N, &tw));
+    const ScanDev* scans = (const ScanDev*)pl.d_scans;
+    const SlotDev* slots = (const SlotDev*)pl.d_slots + L.slot_off;
+    const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
+    const int M = pl.modes;
+    const int gr = (L.maxNw + RowCfg<N, RV>::LINES - 1) / RowCfg<N, RV>::LINES;
+    const int rpie = p.alg == 1;
+    const float2* nP = nullptr;
+    float2* nG = nullptr;
+    double* nD = nullptr;
+    MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, pl.scans[0].P, M, tw, st)));
+    MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_modulus_modes<N, CV>), dim3(N / ColCfg<N, CV>::C, L.nslots / M),
+               dim3(ColCfg<N, CV>::THREADS), scans, slots, S, M, tw);
+    if (upd)
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 6>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, M,
+                   nP, nG, nD, tw);
+    else
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 5>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, M,
+                   nP, nG, nD, tw);
+    MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
+               groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
+    return MNF_OK;
+}
+
 template <int N>
 int issue_iterate_n(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
                     float* mO, const SubBufs* sb, hipStream_t st) {
+    if (pl.modes > 1) {
+        switch (variant_of(ctx, N)) {
+            case 1: return issue_modes_launch<N, 1, 0>(ctx, pl, L, p, upd, S, mO, st);
+            case 2: return issue_modes_launch<N, 0, 1>(ctx, pl, L, p, upd, S, mO, st);
+            case 3: return issue_modes_launch<N, 1, 1>(ctx, pl, L, p, upd, S, mO, st);
+            default: return issue_modes_launch<N, 0, 0>(ctx, pl, L, p, upd, S, mO, st);
+        }
+    }
     if (sb) {
         switch (variant_of(ctx, N)) {
             case 1: return issue_subpixel_launch<N, 1, 0>(ctx, pl, L, p, upd, S, mO, *sb, st);
@@ -380,10 +428,18 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     }
     const bool sub = in[0].frac != nullptr;
     if (sub && ns != 1) return set_error(ctx, MNF_EINVAL, "real positions are supported for one scan per call");
+    const int modes = in[0].modes;
+    if (modes < 1 || modes > kMaxModes)
+        return set_error(ctx, MNF_EINVAL, "probe modes %d outside [1, %d]", modes, kMaxModes);
+    if (modes > 1 && (ns != 1 || sub))
+        return set_error(ctx, MNF_EINVAL, "probe modes are supported for one scan per call at integer positions");
+    if ((size_t)p.batch * modes > (size_t)kMaxBatch)
+        return set_error(ctx, MNF_EINVAL, "batch x modes = %d exceeds %d", p.batch * modes, kMaxBatch);
     if (sub && !size_supported(in[0].Nw))
         return set_error(ctx, MNF_EUNSUPPORTED, "real positions need a probe window with an FFT plan (Nw=%d)", in[0].Nw);
     if (n_iter == 0) return MNF_OK;
     pl.sub = sub;
+    pl.modes = modes;
 
     // per-scan scratch: P2 [Nw^2], maxP2_row [Nw], error partials [J][N/C], |A|^2 partials [J] and sum
     size_t f_need = 0, d_need = 0;
@@ -516,16 +572,27 @@ int forward_v(mnf_ctx* ctx, const CallPlan& pl, float* I_out, const SubBufs* sb,
     MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
     for (const Launch& L : pl.launches) {
         const float2* Pd = nullptr;
+        int pmod = 1;
         if (sb) {
             MNF_TRY(shift_probe(ctx, pl.scans[0].Nw, pl.scans[0].P, sb->Pd, (const float2*)pl.d_fracs + L.slot_off,
                                 L.nslots, st));
             Pd = sb->Pd;
+            pmod = kOwnProbe;
+        } else if (pl.modes > 1) {
+            Pd = pl.scans[0].P;
+            pmod = pl.modes;
         }
-        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, (const ScanDev*)pl.d_scans, (float2*)S, (float*)nullptr, Pd, tw,
-                                        st)));
-        MNF_LAUNCH(ctx, MNF_K_FORWARD, st, (k_cols_intensity<N, CV>), dim3(N / ColCfg<N, CV>::C, L.nslots),
-                   dim3(ColCfg<N, CV>::THREADS), (const ScanDev*)pl.d_scans, (const SlotDev*)pl.d_slots + L.slot_off,
-                   (const float2*)S, I_out, tw);
+        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, (const ScanDev*)pl.d_scans, (float2*)S, (float*)nullptr, Pd, pmod,
+                                        tw, st)));
+        if (pl.modes > 1)
+            MNF_LAUNCH(ctx, MNF_K_FORWARD, st, (k_cols_intensity_modes<N, CV>),
+                       dim3(N / ColCfg<N, CV>::C, L.nslots / pl.modes), dim3(ColCfg<N, CV>::THREADS),
+                       (const ScanDev*)pl.d_scans, (const SlotDev*)pl.d_slots + L.slot_off, (const float2*)S,
+                       pl.modes, I_out, tw);
+        else
+            MNF_LAUNCH(ctx, MNF_K_FORWARD, st, (k_cols_intensity<N, CV>), dim3(N / ColCfg<N, CV>::C, L.nslots),
+                       dim3(ColCfg<N, CV>::THREADS), (const ScanDev*)pl.d_scans,
+                       (const SlotDev*)pl.d_slots + L.slot_off, (const float2*)S, I_out, tw);
     }
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
@@ -568,8 +635,8 @@ int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
     for (const Launch& L : pl.launches) {
         const SlotDev* slots = (const SlotDev*)pl.d_slots + L.slot_off;
         const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
-        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, (float2*)S, (float*)nullptr, (const float2*)nullptr, tw,
-                                        st)));
+        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, (float2*)S, (float*)nullptr, (const float2*)nullptr, 1,
+                                        tw, st)));
         if (kind == 0)
             MNF_LAUNCH(ctx, MNF_K_GRAD_COLS, st, (k_cols_pointwise<N, CV, ColOp::PoissonGrad>),
                        dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, (float2*)S,
@@ -581,7 +648,7 @@ int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
         if (!s.gO && !s.gP) continue;
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 2>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, (float2*)S, (const float*)nullptr, 0, 0, 0.f,
-                   (float)upstream, (const float2*)nullptr, (float2*)nullptr, (double*)nullptr, tw);
+                   (float)upstream, 1, (const float2*)nullptr, (float2*)nullptr, (double*)nullptr, tw);
         if (s.gO)
             MNF_LAUNCH(ctx, MNF_K_GRAD_SCATTER, st, k_grad_object, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                        groups, L.ngroups, (const float2*)S, N);
@@ -632,6 +699,7 @@ int plan_identity(mnf_ctx* ctx, const ScanIn& s, int chunk, CallPlan& pl, hipStr
     const int nr = (s.J + chunk - 1) / chunk;
     for (int r = 0; r < nr; ++r) plan_round(ctx, pl, in, cls, 0, r, chunk, s.Nd);
     pl.sub = s.frac != nullptr;
+    pl.modes = s.modes;
     return upload_plan(ctx, pl, st);
 }
 
@@ -777,6 +845,28 @@ int ptycho_iterate_subpixel(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P
     MNF_TRY(split_positions(ctx, pos, J, ip, fr));
     std::vector<ScanIn> in{ScanIn{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, ip.data(), J, order, err_out, nullptr,
                                   nullptr, fr.data()}};
+    return run_iterate(ctx, in, n_iter, *params, (hipStream_t)stream);
+}
+
+int ptycho_forward_modes(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P, int M, int Nw, int Nd,
+                         const int32_t* pos, int J, float* I_out, void* stream) {
+    MNF_TRY(begin(ctx));
+    if (!I_out) return set_error(ctx, MNF_EINVAL, "null output");
+    if (M < 1 || M > kMaxModes) return set_error(ctx, MNF_EINVAL, "probe modes %d outside [1, %d]", M, kMaxModes);
+    hipStream_t st = (hipStream_t)stream;
+    ScanIn s{(float2*)O, My, Mx, (float2*)P, Nw, I_out, Nd, pos, J, nullptr, nullptr, nullptr, nullptr, nullptr, M};
+    CallPlan pl;
+    MNF_TRY(plan_identity(ctx, s, 64, pl, st));
+    MNF_DISPATCH(Nd, forward_n, ctx, pl, I_out, (const SubBufs*)nullptr, st)
+}
+
+int ptycho_iterate_modes(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int M, int Nw, const float* I,
+                         int Nd, const int32_t* pos, int J, const int32_t* order, int n_iter,
+                         const ptycho_params* params, double* err_out, void* stream) {
+    MNF_TRY(begin(ctx));
+    if (!params) return set_error(ctx, MNF_EINVAL, "null params");
+    std::vector<ScanIn> in{ScanIn{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, pos, J, order, err_out, nullptr,
+                                  nullptr, nullptr, M}};
     return run_iterate(ctx, in, n_iter, *params, (hipStream_t)stream);
 }
 

@@ -59,6 +59,11 @@ SIGNATURES = {
     "ptycho_iterate_subpixel": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
                                         POINTER(c_float), c_int, POINTER(c_int32), c_int,
                                         POINTER(PtychoParamsC), c_void_p, c_void_p]),
+    "ptycho_forward_modes": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_int, c_int,
+                                     POINTER(c_int32), c_int, c_void_p, c_void_p]),
+    "ptycho_iterate_modes": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_int, c_void_p, c_int,
+                                     POINTER(c_int32), c_int, POINTER(c_int32), c_int,
+                                     POINTER(PtychoParamsC), c_void_p, c_void_p]),
     "ptycho_iterate_many": (c_int, [c_void_p, POINTER(PtychoScanC), c_int, c_int, POINTER(PtychoParamsC),
                                     c_void_p]),
     "ptycho_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
