@@ -485,7 +485,8 @@ __device__ __forceinline__ void wgrad_load(const WgradArgs& a, int p, int p_end,
 // VEC: 16-byte loads of 8 channels; needs channel strides and offsets that are
 // multiples of 8 (the partial last group of channels falls back to scalar loads).
 // Each thread loads two adjacent pixels per round trip, so the transposition
-// into the [channel][pixel] LDS tiles writes 32-bit pixel pairs.
+// into the [channel][pixel] LDS tiles writes 32-bit pixel pairs.  The next
+// chunk's global loads are issued before the current chunk's MFMAs.
 template <int MODE, bool VEC>
 __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
     __shared__ __attribute__((aligned(16))) uint16_t sA[64 * kWgLds];  // [ci][pixel]
@@ -504,11 +505,11 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
     // (every tap for UP, whose taps cover disjoint output pixels; tap 0 otherwise).
     const bool do_bias = blockIdx.y == 0 && (MODE == UP || tap == 0);
     float bsum[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint16_t va0[8] __attribute__((aligned(16))), vb0[8] __attribute__((aligned(16)));
+    uint16_t va1[8] __attribute__((aligned(16))), vb1[8] __attribute__((aligned(16)));
+    wgrad_load<MODE, VEC>(a, p_begin + 2 * lp, p_end, tap, ci0 + lc, co0 + lc, va0, vb0);
+    wgrad_load<MODE, VEC>(a, p_begin + 2 * lp + 1, p_end, tap, ci0 + lc, co0 + lc, va1, vb1);
     for (int p0 = p_begin; p0 < p_end; p0 += kWgK) {
-        uint16_t va0[8] __attribute__((aligned(16))), vb0[8] __attribute__((aligned(16)));
-        uint16_t va1[8] __attribute__((aligned(16))), vb1[8] __attribute__((aligned(16)));
-        wgrad_load<MODE, VEC>(a, p0 + 2 * lp, p_end, tap, ci0 + lc, co0 + lc, va0, vb0);
-        wgrad_load<MODE, VEC>(a, p0 + 2 * lp + 1, p_end, tap, ci0 + lc, co0 + lc, va1, vb1);
         if (do_bias) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) bsum[q] += bf2f(vb0[q]) + bf2f(vb1[q]);
@@ -520,6 +521,10 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
             *(uint32_t*)(sB + (lc + q) * kWgLds + 2 * lp) = (uint32_t)vb0[q] | ((uint32_t)vb1[q] << 16);
         }
         __syncthreads();
+        if (p0 + kWgK < p_end) {  // uniform over the block
+            wgrad_load<MODE, VEC>(a, p0 + kWgK + 2 * lp, p_end, tap, ci0 + lc, co0 + lc, va0, vb0);
+            wgrad_load<MODE, VEC>(a, p0 + kWgK + 2 * lp + 1, p_end, tap, ci0 + lc, co0 + lc, va1, vb1);
+        }
 #pragma unroll
         for (int s = 0; s < kWgK / 16; ++s) {
             const int kk = s * 16 + 8 * (lane >> 5);
@@ -547,6 +552,156 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_wgrad(WgradArgs a) {
             for (int l = 0; l < kGemmThreads / 8; ++l) r += bred[((l << 3) + gi) * 8 + q];
             const int bt = MODE == UP ? tap : 0;
             a.bpart[((size_t)split * (MODE == UP ? 4 : 1) + bt) * a.Cout + co0 + tid] = r;
+        }
+    }
+}
+
+// Weight and bias gradient of a 3x3 convolution, all nine taps per block:
+// grid (Cout / (32 NCT), Cin / 32, splits), three waves, wave w owns the taps
+// of kernel row dy = w (dx = 0, 1, 2) for a 32-input x 32 NCT-output channel
+// tile.  The reduction runs over chunks of 64 output pixels (TR = 64 / TWC
+// rows of TWC pixels; chunks [z * per, (z + 1) * per) for grid z).  Per chunk
+// the block stages the masked output gradient as [co][pixel] and the TR + 2
+// input rows the taps touch as [row][ci][x0 - 8 .. x0 + TWC + 16), once, so
+// an input pixel is read once per chunk instead of once per tap.  A lane's
+// eight K values of tap (dy, dx) are input columns x + dx - 1 .. + 7: two
+// aligned 16-byte LDS reads and one 4-byte read serve all three dx, the
+// shifts by one bf16 taken with v_alignbyte.  part [splits][9][Ci][Co]; the
+// bias partials bpart [splits][Co] come from the blocks of the first input
+// tile.  Needs 16-byte aligned channel groups, Cin % 32 == 0, Cout % (32 NCT)
+// == 0, Wout % TWC == 0 and Hout % TR == 0 (stride 1, same size).
+constexpr int kWtThreads = 192;
+
+__device__ __forceinline__ uint32_t bf_shift1(uint32_t hi, uint32_t lo) { return __builtin_amdgcn_alignbyte(hi, lo, 2); }
+
+template <int NCT, int TWC>
+__global__ void __launch_bounds__(kWtThreads) k_wgrad3_tiled(WgradArgs a, int per) {
+    constexpr int TR = 64 / TWC;
+    constexpr int XS = TWC + 24;        // sX row (bf16): columns x0 - 8 .. x0 + TWC + 9 used, padded
+    constexpr int NCO = 32 * NCT;
+    constexpr int GS = 64 + 8;          // sG row (bf16)
+    constexpr int NPAIR = TWC / 2 + 2;  // input pixel pairs per row: x0 - 2 .. x0 + TWC + 1
+    constexpr int XT = (TR + 2) * NPAIR * 4;
+    constexpr int GT = 32 * (NCO / 8);
+    constexpr int GPER = (GT + kWtThreads - 1) / kWtThreads;
+    __shared__ __attribute__((aligned(16))) uint16_t sX[(TR + 2) * 32 * XS];
+    __shared__ __attribute__((aligned(16))) uint16_t sG[NCO * GS];
+    __shared__ float bred[GT * 8];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int co0 = blockIdx.x * NCO, ci0 = blockIdx.y * 32;
+    const int rows = a.Hout / TR, tiles_x = a.Wout / TWC;
+    const int nchunks = a.n * rows * tiles_x;
+    const int c_begin = blockIdx.z * per, c_end = min(nchunks, c_begin + per);
+    const bool do_bias = blockIdx.y == 0;
+    f32x16_t acc[3][NCT];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) acc[d][c] = f32x16_t{};
+    float bsum[GPER][8];
+#pragma unroll
+    for (int u = 0; u < GPER; ++u)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bsum[u][q] = 0.f;
+    const uint4 z4 = make_uint4(0, 0, 0, 0);
+    for (int ch = c_begin; ch < c_end; ++ch) {
+        const int img = ch / (rows * tiles_x), rem = ch % (rows * tiles_x);
+        const int y0 = (rem / tiles_x) * TR, x0 = (rem % tiles_x) * TWC;
+        __syncthreads();  // the previous chunk's operand reads are done
+        for (int t = tid; t < XT; t += kWtThreads) {
+            const int g = t & 3, q = (t >> 2) % NPAIR, r = (t >> 2) / NPAIR;
+            const int yy = y0 + r - 1, xx = x0 - 2 + 2 * q;
+            uint4 v0 = z4, v1 = z4;
+            if (yy >= 0 && yy < a.Hin) {
+                const size_t rowp = ((size_t)img * a.Hin + yy) * a.Win;
+                const uint16_t* base = a.in + a.in_co + ci0 + 8 * g;
+                if (xx >= 0 && xx < a.Win) v0 = *(const uint4*)(base + (rowp + xx) * a.in_cs);
+                if (xx + 1 >= 0 && xx + 1 < a.Win) v1 = *(const uint4*)(base + (rowp + xx + 1) * a.in_cs);
+            }
+            const uint16_t* e0 = (const uint16_t*)&v0;
+            const uint16_t* e1 = (const uint16_t*)&v1;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                *(uint32_t*)(sX + (r * 32 + 8 * g + k) * XS + 6 + 2 * q) = (uint32_t)e0[k] | ((uint32_t)e1[k] << 16);
+        }
+#pragma unroll
+        for (int u = 0; u < GPER; ++u) {
+            const int t = tid + u * kWtThreads;
+            if (t >= GT) break;
+            const int g = t % (NCO / 8), q = t / (NCO / 8);
+            uint16_t gv[2][8] __attribute__((aligned(16)));
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int k = 2 * q + e, ry = k / TWC, xk = k % TWC;
+                const size_t gp = ((size_t)img * a.Hout + y0 + ry) * a.Wout + x0 + xk;
+                *(uint4*)gv[e] = *(const uint4*)(a.dout + gp * a.dout_cs + co0 + 8 * g);
+                if (a.act) {
+                    const uint4 h4 = *(const uint4*)(a.act + gp * a.act_cs + a.act_co + co0 + 8 * g);
+                    const uint16_t* h = (const uint16_t*)&h4;
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk)
+                        if (h[kk] == 0 || (h[kk] & 0x8000u)) gv[e][kk] = 0;
+                }
+            }
+            if (do_bias) {
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) bsum[u][kk] += bf2f(gv[0][kk]) + bf2f(gv[1][kk]);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+                *(uint32_t*)(sG + (8 * g + kk) * GS + 2 * q) = (uint32_t)gv[0][kk] | ((uint32_t)gv[1][kk] << 16);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kb = s * 16 + 8 * (lane >> 5);
+            const int ry = kb / TWC, xj = kb % TWC;
+            const uint16_t* xr = sX + ((ry + w) * 32 + (lane & 31)) * XS + xj;
+            const uint4 E0 = *(const uint4*)xr;
+            const uint4 E1 = *(const uint4*)(xr + 8);
+            const uint32_t E2 = *(const uint32_t*)(xr + 16);
+            const uint4 A0 = make_uint4(bf_shift1(E1.x, E0.w), bf_shift1(E1.y, E1.x), bf_shift1(E1.z, E1.y),
+                                        bf_shift1(E1.w, E1.z));
+            const uint4 A2 = make_uint4(bf_shift1(E1.y, E1.x), bf_shift1(E1.z, E1.y), bf_shift1(E1.w, E1.z),
+                                        bf_shift1(E2, E1.w));
+            const bf16x8_t av[3] = {__builtin_bit_cast(bf16x8_t, A0), __builtin_bit_cast(bf16x8_t, E1),
+                                    __builtin_bit_cast(bf16x8_t, A2)};
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                const bf16x8_t bv = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sG + (c * 32 + (lane & 31)) * GS + kb));
+#pragma unroll
+                for (int d = 0; d < 3; ++d) acc[d][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av[d], bv, acc[d][c], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const int tap = 3 * w + d;
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) {
+            const int j = co0 + c * 32 + (lane & 31);
+#pragma unroll
+            for (int v = 0; v < 16; ++v) {
+                const int i = ci0 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+                a.part[(((size_t)blockIdx.z * 9 + tap) * a.Cin + i) * a.Cout + j] = acc[d][c][v];
+            }
+        }
+    }
+    if (do_bias) {
+        // per output channel, the 32 pixel-pair tasks summed in a fixed order
+#pragma unroll
+        for (int u = 0; u < GPER; ++u) {
+            const int t = tid + u * kWtThreads;
+            if (t < GT)
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) bred[t * 8 + kk] = bsum[u][kk];
+        }
+        __syncthreads();
+        if (tid < NCO) {
+            const int g = tid / 8, kk = tid % 8;
+            float r = 0.f;
+            for (int q = 0; q < 32; ++q) r += bred[(q * (NCO / 8) + g) * 8 + kk];
+            a.bpart[(size_t)blockIdx.z * a.Cout + co0 + tid] = r;
         }
     }
 }

@@ -292,6 +292,31 @@ int layer_wgrad(mnf_ctx* ctx, const LayerDesc& L, View x, int n, int Hin, View d
         return MNF_OK;
     }
     const int target_blocks = 1024;
+    // 3x3 layers with 32-channel tiles: all nine taps per block from LDS-staged rows
+    const int twc = Hout % 64 == 0 ? 64 : (Hout % 32 == 0 && Hout % 2 == 0 ? 32 : 0);
+    if (L.mode == CONV3 && vec && L.ci % 32 == 0 && L.co % 32 == 0 && twc) {
+        const int nct = L.co % 64 == 0 ? 2 : 1;
+        const int gxy = (L.co / (32 * nct)) * (L.ci / 32);
+        const int nchunks = n * Hout * Hout / 64;
+        int splits = std::max(1, std::min(target_blocks / gxy, nchunks));
+        const int per = (nchunks + splits - 1) / splits;
+        splits = (nchunks + per - 1) / per;
+        void* part;
+        void* bpart;
+        MNF_TRY(scratch(ctx, "unet_wpart", (size_t)splits * count * sizeof(float), &part));
+        MNF_TRY(scratch(ctx, "unet_bpart", (size_t)splits * L.co * sizeof(float), &bpart));
+        a.part = (float*)part;
+        a.bpart = (float*)bpart;
+        a.splits = splits;
+        const dim3 grid((unsigned)(L.co / (32 * nct)), (unsigned)(L.ci / 32), (unsigned)splits);
+        if (nct == 2 && twc == 64) hipLaunchKernelGGL((k_wgrad3_tiled<2, 64>), grid, dim3(kWtThreads), 0, st, a, per);
+        else if (nct == 2) hipLaunchKernelGGL((k_wgrad3_tiled<2, 32>), grid, dim3(kWtThreads), 0, st, a, per);
+        else if (twc == 64) hipLaunchKernelGGL((k_wgrad3_tiled<1, 64>), grid, dim3(kWtThreads), 0, st, a, per);
+        else hipLaunchKernelGGL((k_wgrad3_tiled<1, 32>), grid, dim3(kWtThreads), 0, st, a, per);
+        reduce_partials((const float*)part, splits, count, dW, st);
+        reduce_partials((const float*)bpart, splits, (size_t)L.co, db, st);
+        return MNF_OK;
+    }
     const int tiles = g1((size_t)L.co, 64) * g1((size_t)L.ci, 64) * taps;
     a.splits = std::max(1, std::min(target_blocks / std::max(1, tiles), (a.P + 4095) / 4096));
     const int btaps = L.mode == UP ? 4 : 1;

@@ -90,6 +90,19 @@ def test_tiled_conv3_gradients(api, mode, n, H, Ci, Co):
     test_conv_gradients(api, mode, n, H, Ci, Co, True)
 
 
+# 3x3 weight gradients through the all-taps tiled kernel: 32- and 64-channel
+# output tiles, 64-pixel rows and pairs of 32-pixel rows, two input-channel
+# tiles (the bias from the first only), masked and unmasked
+WGRAD_TILED = [("conv3", 1, 64, 32, 32), ("conv3", 1, 32, 32, 64), ("conv3", 2, 32, 64, 96),
+               ("conv3", 2, 128, 64, 32), ("conv3", 1, 64, 96, 128)]
+
+
+@pytest.mark.parametrize("mode,n,H,Ci,Co", WGRAD_TILED)
+@pytest.mark.parametrize("masked", [False, True])
+def test_tiled_weight_gradients(api, mode, n, H, Ci, Co, masked):
+    test_conv_gradients(api, mode, n, H, Ci, Co, masked)
+
+
 # large layers (the full network's sizes at batch 4)
 LARGE = [("down", 4, 256, 32, 256), ("conv1", 4, 128, 64, 256), ("conv3", 4, 128, 32, 256)]
 
