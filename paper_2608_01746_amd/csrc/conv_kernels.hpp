@@ -604,10 +604,51 @@ __global__ void __launch_bounds__(kWtThreads) k_wgrad3_tiled(WgradArgs a, int pe
 #pragma unroll
         for (int q = 0; q < 8; ++q) bsum[u][q] = 0.f;
     const uint4 z4 = make_uint4(0, 0, 0, 0);
-    for (int ch = c_begin; ch < c_end; ++ch) {
+    constexpr int XPER = (XT + kWtThreads - 1) / kWtThreads;
+    // Staging, chosen per variant by measurement: 0 each task loads and writes
+    // in turn (one 32-channel output tile, 64-pixel rows); 1 all of a chunk's
+    // loads into registers first, then the LDS writes (two tiles, 64-pixel
+    // rows); 2 as 1 with the next chunk's loads in flight during the current
+    // chunk's MFMAs (two-row chunks).
+    constexpr int STYLE = TWC == 32 ? 2 : (NCT == 2 ? 1 : 0);
+    uint4 rx[XPER][2], rg[GPER][2], ra[GPER][2];
+    auto fetch = [&](int ch) {
         const int img = ch / (rows * tiles_x), rem = ch % (rows * tiles_x);
         const int y0 = (rem / tiles_x) * TR, x0 = (rem % tiles_x) * TWC;
-        __syncthreads();  // the previous chunk's operand reads are done
+#pragma unroll
+        for (int u = 0; u < XPER; ++u) {
+            const int t = tid + u * kWtThreads;
+            rx[u][0] = rx[u][1] = z4;
+            if (t >= XT) continue;
+            const int g = t & 3, q = (t >> 2) % NPAIR, r = (t >> 2) / NPAIR;
+            const int yy = y0 + r - 1, xx = x0 - 2 + 2 * q;
+            if (yy >= 0 && yy < a.Hin) {
+                const size_t rowp = ((size_t)img * a.Hin + yy) * a.Win;
+                const uint16_t* base = a.in + a.in_co + ci0 + 8 * g;
+                if (xx >= 0 && xx < a.Win) rx[u][0] = *(const uint4*)(base + (rowp + xx) * a.in_cs);
+                if (xx + 1 >= 0 && xx + 1 < a.Win) rx[u][1] = *(const uint4*)(base + (rowp + xx + 1) * a.in_cs);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < GPER; ++u) {
+            const int t = tid + u * kWtThreads;
+            rg[u][0] = rg[u][1] = ra[u][0] = ra[u][1] = z4;
+            if (t >= GT) continue;
+            const int g = t % (NCO / 8), q = t / (NCO / 8);
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int k = 2 * q + e, ry = k / TWC, xk = k % TWC;
+                const size_t gp = ((size_t)img * a.Hout + y0 + ry) * a.Wout + x0 + xk;
+                rg[u][e] = *(const uint4*)(a.dout + gp * a.dout_cs + co0 + 8 * g);
+                if (a.act) ra[u][e] = *(const uint4*)(a.act + gp * a.act_cs + a.act_co + co0 + 8 * g);
+            }
+        }
+    };
+    // staging straight from global memory (no prefetch): each task loads and
+    // writes its pieces in turn
+    auto stage_direct = [&](int ch) {
+        const int img = ch / (rows * tiles_x), rem = ch % (rows * tiles_x);
+        const int y0 = (rem / tiles_x) * TR, x0 = (rem % tiles_x) * TWC;
         for (int t = tid; t < XT; t += kWtThreads) {
             const int g = t & 3, q = (t >> 2) % NPAIR, r = (t >> 2) / NPAIR;
             const int yy = y0 + r - 1, xx = x0 - 2 + 2 * q;
@@ -651,7 +692,53 @@ __global__ void __launch_bounds__(kWtThreads) k_wgrad3_tiled(WgradArgs a, int pe
             for (int kk = 0; kk < 8; ++kk)
                 *(uint32_t*)(sG + (8 * g + kk) * GS + 2 * q) = (uint32_t)gv[0][kk] | ((uint32_t)gv[1][kk] << 16);
         }
+    };
+    if constexpr (STYLE == 2) {
+        if (c_begin < c_end) fetch(c_begin);
+    }
+    for (int ch = c_begin; ch < c_end; ++ch) {
+        if constexpr (STYLE == 1) fetch(ch);
+        __syncthreads();  // the previous chunk's operand reads are done
+        if constexpr (STYLE == 0) stage_direct(ch);
+#pragma unroll
+        for (int u = 0; u < (STYLE ? XPER : 0); ++u) {
+            const int t = tid + u * kWtThreads;
+            if (t >= XT) continue;
+            const int g = t & 3, q = (t >> 2) % NPAIR, r = (t >> 2) / NPAIR;
+            const uint16_t* e0 = (const uint16_t*)&rx[u][0];
+            const uint16_t* e1 = (const uint16_t*)&rx[u][1];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                *(uint32_t*)(sX + (r * 32 + 8 * g + k) * XS + 6 + 2 * q) = (uint32_t)e0[k] | ((uint32_t)e1[k] << 16);
+        }
+#pragma unroll
+        for (int u = 0; u < (STYLE ? GPER : 0); ++u) {
+            const int t = tid + u * kWtThreads;
+            if (t >= GT) continue;
+            const int g = t % (NCO / 8), q = t / (NCO / 8);
+            uint16_t gv[2][8] __attribute__((aligned(16)));
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                *(uint4*)gv[e] = rg[u][e];
+                if (a.act) {
+                    const uint16_t* h = (const uint16_t*)&ra[u][e];
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk)
+                        if (h[kk] == 0 || (h[kk] & 0x8000u)) gv[e][kk] = 0;
+                }
+            }
+            if (do_bias) {
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) bsum[u][kk] += bf2f(gv[0][kk]) + bf2f(gv[1][kk]);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+                *(uint32_t*)(sG + (8 * g + kk) * GS + 2 * q) = (uint32_t)gv[0][kk] | ((uint32_t)gv[1][kk] << 16);
+        }
         __syncthreads();
+        if constexpr (STYLE == 2) {
+            if (ch + 1 < c_end) fetch(ch + 1);
+        }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int kb = s * 16 + 8 * (lane >> 5);

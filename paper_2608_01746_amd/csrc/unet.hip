@@ -298,7 +298,9 @@ int layer_wgrad(mnf_ctx* ctx, const LayerDesc& L, View x, int n, int Hin, View d
         const int nct = L.co % 64 == 0 ? 2 : 1;
         const int gxy = (L.co / (32 * nct)) * (L.ci / 32);
         const int nchunks = n * Hout * Hout / 64;
-        int splits = std::max(1, std::min(target_blocks / gxy, nchunks));
+        // 64-channel output tiles: two resident blocks per CU on 256 CUs (fewer
+        // splits also shrink the partials); 32-channel tiles run lighter blocks
+        int splits = std::max(1, std::min((nct == 2 ? 512 : 1024) / gxy, nchunks));
         const int per = (nchunks + splits - 1) / splits;
         splits = (nchunks + per - 1) / per;
         void* part;
