@@ -15,6 +15,7 @@
 #pragma once
 
 #include "kernels_common.hpp"
+#include "shift_kernels.hpp"
 #include "tables.hpp"
 
 namespace mnf {
@@ -24,12 +25,15 @@ namespace mnf {
 // maxO2_part[slot][blockIdx.x] (when not NULL).  Pd (when not NULL) is a
 // table of probes [k][Nw][Nw] used in place of the scan's probe: slot s reads
 // Pd[s % pmod] (one translated probe per slot for real positions, pmod >=
-// nslots; probe mode s % M for mixed states, pmod = M).
-template <int N, int RV>
+// nslots; probe mode s % M for mixed states, pmod = M).  SUBX (real
+// positions, Nw == N): Pd[s] holds the probe translated along y only; each
+// row is translated along x by d_x(s) = frac[s].y here, in registers, and the
+// fully translated row is stored back to Pd[s] for the inverse row pass.
+template <int N, int RV, bool SUBX = false>
 __global__ void __launch_bounds__((RowCfg<N, RV>::THREADS))
 k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
-           float2* __restrict__ S, float* __restrict__ maxO2_part, const float2* __restrict__ Pd, int pmod,
-           const float2* __restrict__ tw_g) {
+           float2* __restrict__ S, float* __restrict__ maxO2_part, float2* Pd, int pmod,
+           const float2* __restrict__ frac, const float2* __restrict__ tw_g) {
     constexpr int T = RowCfg<N, RV>::T, LINES = RowCfg<N, RV>::LINES, V = PlanInfo<N>::V;
     __shared__ float2 lds[LINES * RowLds<N>::stride];
     __shared__ float2 tw[N];
@@ -46,20 +50,41 @@ k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
     float2 x[V];
     float mO = 0.f;
     const float2* Orow = sc.O + (size_t)(sd.py + (live ? y : 0)) * Mx + sd.px;
-    const float2* Prow = (Pd ? Pd + (size_t)(s % pmod) * Nw * Nw : sc.P) + (size_t)(live ? y : 0) * Nw;
+    if constexpr (SUBX) {
+        float2* Pw = Pd + ((size_t)s * N + (live ? y : 0)) * N;
+        const float dx = frac[s].y;  // uniform over the block
+        for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
+        __syncthreads();
+        float2 p[V];
+        shift_line<N>(p, Pw, 1, dx, t, lds, RowLds<N>(line), tw);
 #pragma unroll
-    for (int idx = 0; idx < V; ++idx) {
-        const int n = in_pos<N, false>(t, idx);
-        float2 v = make_float2(0.f, 0.f);
-        if (live && n < Nw) {
-            const float2 o = Orow[n];
-            v = cmul(Prow[n], o);
-            mO = fmaxf(mO, cabs2(o));
+        for (int idx = 0; idx < V; ++idx) {
+            const int n = in_pos<N, false>(t, idx);
+            if (live && dx != 0.f) Pw[n] = p[idx];
+            float2 v = make_float2(0.f, 0.f);
+            if (live) {
+                const float2 o = Orow[n];
+                v = cmul(p[idx], o);
+                mO = fmaxf(mO, cabs2(o));
+            }
+            x[idx] = v;
         }
-        x[idx] = v;
+    } else {
+        const float2* Prow = (Pd ? Pd + (size_t)(s % pmod) * Nw * Nw : sc.P) + (size_t)(live ? y : 0) * Nw;
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) {
+            const int n = in_pos<N, false>(t, idx);
+            float2 v = make_float2(0.f, 0.f);
+            if (live && n < Nw) {
+                const float2 o = Orow[n];
+                v = cmul(Prow[n], o);
+                mO = fmaxf(mO, cabs2(o));
+            }
+            x[idx] = v;
+        }
+        for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
+        __syncthreads();
     }
-    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
-    __syncthreads();
     fft_line<N, false>(x, t, lds, RowLds<N>(line), tw);
     if (live) {
         float2* row = S + ((size_t)s * N + y) * N;
@@ -340,7 +365,9 @@ k_cols_intensity_modes(const ScanDev* __restrict__ scans, const SlotDev* __restr
 //     maxP2_row still describe the untranslated batch-start probe.  MODE 4
 //     (probe updated) writes the probe numerators G[s][r][n] = conj(O_s) dpsi
 //     for the inverse translation and the float64 denominator sums
-//     DP[r][n] = sum_s d_P,s, and leaves P unchanged.
+//     DP[r][n] = sum_s d_P,s, and leaves P unchanged.  With gfrac (Nw == N)
+//     the numerator rows are translated back along x by -d_x(s) =
+//     -gfrac[s].y in registers before they are stored.
 //   MODE 5, 6 (mixed states): the group's slots come in runs of nmodes (one
 //     per probe mode, mode = slot index % nmodes, modes P[m][Nw][Nw]); as
 //     MODE 0, 1 with probe mode m in slot s's dpsi and object numerator.
@@ -364,7 +391,7 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                   const GroupDev* __restrict__ groups, float2* __restrict__ S,
                   const float* __restrict__ maxO2_part, int nparts, int rpie, float beta,
                   float upstream, int nmodes, const float2* __restrict__ Pd, float2* __restrict__ G,
-                  double* __restrict__ DP, const float2* __restrict__ tw_g) {
+                  double* __restrict__ DP, const float2* __restrict__ gfrac, const float2* __restrict__ tw_g) {
     constexpr int T = UpdCfg<N, RV>::T, ULINES = UpdCfg<N, RV>::ULINES, V = PlanInfo<N>::V;
     constexpr int THREADS = UpdCfg<N, RV>::THREADS;
     constexpr int COLS = (N + THREADS - 1) / THREADS;  // probe columns owned per thread
@@ -447,11 +474,27 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                     const float2 d = MODE == 2 ? cscale(x[idx], scl) : csub(cscale(x[idx], scl), cmul(p, o[idx]));
                     row[n] = cconjmul(p, d);
                     if constexpr (ACC) c_num[line * N + n] = cconjmul(o[idx], d);
-                    if constexpr (MODE == 4) G[((size_t)(gd.s0 + k) * Nw + r) * Nw + n] = cconjmul(o[idx], d);
+                    if constexpr (MODE == 4) {
+                        if (gfrac) x[idx] = cconjmul(o[idx], d);  // translated below, then stored
+                        else G[((size_t)(gd.s0 + k) * Nw + r) * Nw + n] = cconjmul(o[idx], d);
+                    }
                     if constexpr (DEN) {
                         const float o2 = cabs2(o[idx]);
                         c_den[line * N + n] = rpie ? (1.f - beta) * o2 + beta * mO : mO / beta;
                     }
+                }
+            }
+        }
+        if constexpr (MODE == 4) {
+            if (gfrac) {  // uniform: every line of the round takes part in the transforms
+#pragma unroll
+                for (int idx = 0; idx < V; ++idx)
+                    if (!live) x[idx] = make_float2(0.f, 0.f);
+                shift_regs<N>(x, live ? -gfrac[gd.s0 + kk].y : 0.f, t, lds, RowLds<N>(line), tw);
+                if (live) {
+                    float2* grow = G + ((size_t)(gd.s0 + k) * Nw + r) * Nw;
+#pragma unroll
+                    for (int idx = 0; idx < V; ++idx) grow[out_pos<N, true>(t, idx)] = x[idx];
                 }
             }
         }

@@ -227,12 +227,12 @@ int upload_plan(mnf_ctx* ctx, CallPlan& pl, hipStream_t st) {
 
 // ---------------------------------------------------------- launch helpers
 
-template <int N, int RV>
+template <int N, int RV, bool SUBX = false>
 int launch_rows_fwd(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ScanDev* scans, float2* S, float* mO,
-                    const float2* Pd, int pmod, const float2* tw, hipStream_t st) {
+                    const float2* Pd, int pmod, const float2* tw, hipStream_t st, const float2* frac = nullptr) {
     const int gr = (L.maxNw + RowCfg<N, RV>::LINES - 1) / RowCfg<N, RV>::LINES;
-    MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, (k_rows_fwd<N, RV>), dim3(gr, L.nslots), dim3(RowCfg<N, RV>::THREADS),
-               scans, (const SlotDev*)pl.d_slots + L.slot_off, S, mO, Pd, pmod, tw);
+    MNF_LAUNCH(ctx, MNF_K_ROWS_FWD, st, (k_rows_fwd<N, RV, SUBX>), dim3(gr, L.nslots), dim3(RowCfg<N, RV>::THREADS),
+               scans, (const SlotDev*)pl.d_slots + L.slot_off, S, mO, (float2*)Pd, pmod, frac, tw);
     return MNF_OK;
 }
 
@@ -247,11 +247,22 @@ int shift_probe_n(mnf_ctx* ctx, const float2* P, float2* Pd, const float2* fr, i
     MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_rows<NW>), dim3(NW / RowCfg<NW, 0>::LINES, nslots),
                dim3(RowCfg<NW, 0>::THREADS), P, (size_t)0, Pd, fr, 1.f, tw);
     MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_cols<NW>), dim3(NW / ColCfg<NW, 0>::C, nslots),
-               dim3(ColCfg<NW, 0>::THREADS), Pd, fr, 1.f, tw);
+               dim3(ColCfg<NW, 0>::THREADS), (const float2*)Pd, (size_t)NW * NW, Pd, fr, 1.f, tw);
     return MNF_OK;
 }
 int shift_probe(mnf_ctx* ctx, int Nw, const float2* P, float2* Pd, const float2* fr, int nslots, hipStream_t st) {
     MNF_DISPATCH(Nw, shift_probe_n, ctx, P, Pd, fr, nslots, st)
+}
+
+// The probe translated along y only, Pd[s] = S_{(d_y, 0)}[P] (one column pass
+// from the shared probe); the row pass that reads it adds the x translation.
+template <int NW>
+int shift_probe_y(mnf_ctx* ctx, const float2* P, float2* Pd, const float2* fr, int nslots, hipStream_t st) {
+    const float2* tw;
+    MNF_TRY(twiddles(ctx, NW, &tw));
+    MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_cols<NW>), dim3(NW / ColCfg<NW, 0>::C, nslots),
+               dim3(ColCfg<NW, 0>::THREADS), P, (size_t)0, Pd, fr, 1.f, tw);
+    return MNF_OK;
 }
 
 // Probe update of a sub-pixel launch: G[s] translated back by -d_s in place
@@ -265,7 +276,7 @@ int shift_update_n(mnf_ctx* ctx, float2* G, const float2* fr, const GroupDev* gr
     MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_rows<NW>), dim3(NW / RowCfg<NW, 0>::LINES, nslots),
                dim3(RowCfg<NW, 0>::THREADS), (const float2*)G, (size_t)NW * NW, G, fr, -1.f, tw);
     MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_cols<NW>), dim3(NW / ColCfg<NW, 0>::C, nslots),
-               dim3(ColCfg<NW, 0>::THREADS), G, fr, -1.f, tw);
+               dim3(ColCfg<NW, 0>::THREADS), (const float2*)G, (size_t)NW * NW, G, fr, -1.f, tw);
     MNF_LAUNCH(ctx, MNF_K_PROBE_UPDATE, st, (k_probe_sum_update<NW>), dim3((NW * NW + 255) / 256, ngroups),
                dim3(256), (const float2*)G, groups, P, DP);
     return MNF_OK;
@@ -294,11 +305,11 @@ int issue_iterate_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, cons
     if (upd)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 1>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
-                   nP, nG, nD, tw);
+                   nP, nG, nD, (const float2*)nullptr, tw);
     else
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 0>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
-                   nP, nG, nD, tw);
+                   nP, nG, nD, (const float2*)nullptr, tw);
     MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
     return MNF_OK;
@@ -320,21 +331,38 @@ int issue_subpixel_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, con
     const int gr = (L.maxNw + RowCfg<N, RV>::LINES - 1) / RowCfg<N, RV>::LINES;
     const int rpie = p.alg == 1;
     const float2* Pd = sb.Pd;
-    MNF_TRY(shift_probe(ctx, Nw, pl.scans[0].P, sb.Pd, fr, L.nslots, st));
-    MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, Pd, kOwnProbe, tw, st)));
+    // Nw == N: the x translations run inside the row passes (forward probe
+    // rows in the exit-wave pass, probe numerators in the inverse-row pass)
+    const bool fused = Nw == N;
+    if (fused) {
+        MNF_TRY(shift_probe_y<N>(ctx, pl.scans[0].P, sb.Pd, fr, L.nslots, st));
+        MNF_TRY((launch_rows_fwd<N, RV, true>(ctx, pl, L, scans, S, mO, Pd, kOwnProbe, tw, st, fr)));
+    } else {
+        MNF_TRY(shift_probe(ctx, Nw, pl.scans[0].P, sb.Pd, fr, L.nslots, st));
+        MNF_TRY((launch_rows_fwd<N, RV>(ctx, pl, L, scans, S, mO, Pd, kOwnProbe, tw, st)));
+    }
     MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, CV, ColOp::Modulus>),
                dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, S, 0.f, tw);
     if (upd)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 4>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
-                   Pd, sb.G, sb.DP, tw);
+                   Pd, sb.G, sb.DP, fused ? fr : (const float2*)nullptr, tw);
     else
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 3>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
-                   Pd, (float2*)nullptr, (double*)nullptr, tw);
+                   Pd, (float2*)nullptr, (double*)nullptr, (const float2*)nullptr, tw);
     MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
-    if (upd) MNF_TRY(shift_update(ctx, Nw, sb.G, fr, groups, L.nslots, L.ngroups, pl.scans[0].P, sb.DP, st));
+    if (upd) {
+        if (fused) {
+            MNF_LAUNCH(ctx, MNF_K_SHIFT, st, (k_shift_cols<N>), dim3(N / ColCfg<N, 0>::C, L.nslots),
+                       dim3(ColCfg<N, 0>::THREADS), (const float2*)sb.G, (size_t)N * N, sb.G, fr, -1.f, tw);
+            MNF_LAUNCH(ctx, MNF_K_PROBE_UPDATE, st, (k_probe_sum_update<N>), dim3((N * N + 255) / 256, L.ngroups),
+                       dim3(256), (const float2*)sb.G, groups, pl.scans[0].P, (const double*)sb.DP);
+        } else {
+            MNF_TRY(shift_update(ctx, Nw, sb.G, fr, groups, L.nslots, L.ngroups, pl.scans[0].P, sb.DP, st));
+        }
+    }
     return MNF_OK;
 }
 
@@ -362,11 +390,11 @@ int issue_modes_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const 
     if (upd)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 6>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, M,
-                   nP, nG, nD, tw);
+                   nP, nG, nD, (const float2*)nullptr, tw);
     else
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 5>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, M,
-                   nP, nG, nD, tw);
+                   nP, nG, nD, (const float2*)nullptr, tw);
     MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
     return MNF_OK;
@@ -573,9 +601,18 @@ int forward_v(mnf_ctx* ctx, const CallPlan& pl, float* I_out, const SubBufs* sb,
     for (const Launch& L : pl.launches) {
         const float2* Pd = nullptr;
         int pmod = 1;
+        const float2* fr = sb ? (const float2*)pl.d_fracs + L.slot_off : nullptr;
+        if (sb && pl.scans[0].Nw == N) {  // x translation inside the exit-wave pass
+            MNF_TRY(shift_probe_y<N>(ctx, pl.scans[0].P, sb->Pd, fr, L.nslots, st));
+            MNF_TRY((launch_rows_fwd<N, RV, true>(ctx, pl, L, (const ScanDev*)pl.d_scans, (float2*)S, (float*)nullptr,
+                                                  sb->Pd, kOwnProbe, tw, st, fr)));
+            MNF_LAUNCH(ctx, MNF_K_FORWARD, st, (k_cols_intensity<N, CV>), dim3(N / ColCfg<N, CV>::C, L.nslots),
+                       dim3(ColCfg<N, CV>::THREADS), (const ScanDev*)pl.d_scans,
+                       (const SlotDev*)pl.d_slots + L.slot_off, (const float2*)S, I_out, tw);
+            continue;
+        }
         if (sb) {
-            MNF_TRY(shift_probe(ctx, pl.scans[0].Nw, pl.scans[0].P, sb->Pd, (const float2*)pl.d_fracs + L.slot_off,
-                                L.nslots, st));
+            MNF_TRY(shift_probe(ctx, pl.scans[0].Nw, pl.scans[0].P, sb->Pd, fr, L.nslots, st));
             Pd = sb->Pd;
             pmod = kOwnProbe;
         } else if (pl.modes > 1) {
@@ -648,7 +685,8 @@ int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
         if (!s.gO && !s.gP) continue;
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 2>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, (float2*)S, (const float*)nullptr, 0, 0, 0.f,
-                   (float)upstream, 1, (const float2*)nullptr, (float2*)nullptr, (double*)nullptr, tw);
+                   (float)upstream, 1, (const float2*)nullptr, (float2*)nullptr, (double*)nullptr,
+                   (const float2*)nullptr, tw);
         if (s.gO)
             MNF_LAUNCH(ctx, MNF_K_GRAD_SCATTER, st, k_grad_object, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                        groups, L.ngroups, (const float2*)S, N);

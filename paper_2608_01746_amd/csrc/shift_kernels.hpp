@@ -28,6 +28,20 @@ __device__ __forceinline__ float2 shift_ramp(int k, float d) {
     return make_float2(c, s);
 }
 
+// A line held in registers at the positions in_pos<N, false> (the same as
+// out_pos<N, true>) translated by d in place; every thread of the block
+// takes part (the transforms synchronise), d may differ between lines.
+template <int N, class ADDR>
+__device__ __forceinline__ void shift_regs(float2* x, float d, int t, float2* lds, const ADDR& addr,
+                                           const float2* tw) {
+    constexpr int V = PlanInfo<N>::V;
+    fft_line<N, false>(x, t, lds, addr, tw);
+    const float inv = 1.f / (float)N;
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) x[idx] = cscale(cmul(x[idx], shift_ramp<N>(out_pos<N, false>(t, idx), d)), inv);
+    fft_line<N, true>(x, t, lds, addr, tw);
+}
+
 // One line of N values (in[i * stride]) translated by d, left in x[] at the
 // positions out_pos<N, true>.  Loads for the transform use in_pos<N, false>;
 // d == 0 loads straight into the output positions (uniform over the block).
@@ -42,11 +56,7 @@ __device__ __forceinline__ void shift_line(float2* x, const float2* in, size_t s
     }
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) x[idx] = in[(size_t)in_pos<N, false>(t, idx) * stride];
-    fft_line<N, false>(x, t, lds, addr, tw);
-    const float inv = 1.f / (float)N;
-#pragma unroll
-    for (int idx = 0; idx < V; ++idx) x[idx] = cscale(cmul(x[idx], shift_ramp<N>(out_pos<N, false>(t, idx), d)), inv);
-    fft_line<N, true>(x, t, lds, addr, tw);
+    shift_regs<N>(x, d, t, lds, addr, tw);
 }
 
 // grid (N / LINES, nslots).  dst[s][y][:] = row y of src[s] translated along x
@@ -72,22 +82,26 @@ k_shift_rows(const float2* src, size_t src_stride, float2* dst, const float2* __
     for (int idx = 0; idx < V; ++idx) row[out_pos<N, true>(t, idx)] = x[idx];
 }
 
-// grid (N / C, nslots).  Column kx of f[s] translated along y by sign * d_y(s), in place.
+// grid (N / C, nslots).  dst[s] column kx = column kx of src[s] translated
+// along y by sign * d_y(s); src_stride 0 reads one shared field (the probe).
+// dst may equal src (in place; then a zero fraction leaves the column).
 template <int N>
 __global__ void __launch_bounds__((ColCfg<N, 0>::THREADS))
-k_shift_cols(float2* __restrict__ f, const float2* __restrict__ frac, float sign, const float2* __restrict__ tw_g) {
+k_shift_cols(const float2* src, size_t src_stride, float2* dst, const float2* __restrict__ frac, float sign,
+             const float2* __restrict__ tw_g) {
     constexpr int C = ColCfg<N, 0>::C, T = ColCfg<N, 0>::T, V = PlanInfo<N>::V;
     __shared__ float2 lds[C * N];
     __shared__ float2 tw[N];
     const int s = blockIdx.y;
     const float d = sign * frac[s].x;
-    if (d == 0.f) return;  // uniform over the block
+    if (d == 0.f && src == dst) return;  // uniform over the block
     const int c = threadIdx.x % C, t = threadIdx.x / C;
-    float2* col = f + (size_t)s * N * N + blockIdx.x * C + c;
+    const float2* in = src + s * src_stride + blockIdx.x * C + c;
+    float2* col = dst + (size_t)s * N * N + blockIdx.x * C + c;
     for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
     __syncthreads();
     float2 x[V];
-    shift_line<N>(x, col, N, d, t, lds, ColLds<C>(c), tw);
+    shift_line<N>(x, in, N, d, t, lds, ColLds<C>(c), tw);
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) col[(size_t)out_pos<N, true>(t, idx) * N] = x[idx];
 }
