@@ -274,34 +274,35 @@ __global__ void __launch_bounds__(256) k_conv3_c1(ConvArgs a) {
 }
 
 // 3x3 convolution (forward, or input gradient with flipped taps) as a direct
-// tiled kernel: a block computes TH x TW = 128 output pixels of one image x 64
-// output channels.  Per chunk of 32 input channels it stages the input patch
-// ((TH + 2) x (TW + 2) pixels, zero padded, ReLU-masked for MASK) and the 9 x 64
-// x 32 weights in LDS once, then every wave runs its 32 pixels x 64 channels
-// through 9 taps x 2 K16 steps x 2 MFMA tiles from LDS, so each input pixel is
-// fetched once per chunk instead of once per tap.  Same MFMA lane layout and
-// epilogue as k_conv_gemm.  Needs Cin % 32 == 0, 16-byte aligned channel
-// offsets, W % TW == 0 and H % TH == 0.
+// tiled kernel: a block computes TH x TW = 128 output pixels of one image x
+// 32 NB output channels (NB = 1 for layers with at most 32).  Per chunk of 32
+// input channels it stages the input patch ((TH + 2) x (TW + 2) pixels, zero
+// padded, ReLU-masked for MASK) and the 9 x 32 NB x 32 weights in LDS once,
+// then every wave runs its 32 pixels x 32 NB channels through 9 taps x 2 K16
+// steps x NB MFMA tiles from LDS, so each input pixel is fetched once per
+// chunk instead of once per tap.  Same MFMA lane layout and epilogue as
+// k_conv_gemm.  Needs Cin % 32 == 0, 16-byte aligned channel offsets,
+// W % TW == 0 and H % TH == 0.
 constexpr int kTileCh = 32;               // input channels per chunk
 constexpr int kTileLds = kTileCh + 8;     // padded LDS row (bf16) per pixel / weight row
 
-template <bool MASK, bool OUT_F32, int TW>
+template <bool MASK, bool OUT_F32, int TW, int NB = 2>
 __global__ void __launch_bounds__(kGemmThreads) k_conv3_tiled(ConvArgs a) {
     constexpr int TH = kGemmBM / TW;
+    constexpr int BN = 32 * NB;  // output channels of the block
     constexpr int PW = TW + 2, PH = TH + 2, NPIX = PW * PH;
     constexpr int A_LOADS = NPIX * (kTileCh / 8);        // 16-byte pieces of the patch
-    constexpr int B_LOADS = 9 * kGemmBN * (kTileCh / 8); // 16-byte pieces of the weights
+    constexpr int B_LOADS = 9 * BN * (kTileCh / 8);      // 16-byte pieces of the weights
     constexpr int A_PER = (A_LOADS + kGemmThreads - 1) / kGemmThreads;
-    constexpr int B_PER = B_LOADS / kGemmThreads;
-    static_assert(B_LOADS % kGemmThreads == 0, "weight pieces per thread");
+    constexpr int B_PER = (B_LOADS + kGemmThreads - 1) / kGemmThreads;
     __shared__ __attribute__((aligned(16))) uint16_t sA[NPIX * kTileLds];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[9 * kGemmBN * kTileLds];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[9 * BN * kTileLds];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int tiles_x = a.Wout / TW, tiles_y = a.Hout / TH;
     const int tile = blockIdx.x;
     const int img = tile / (tiles_x * tiles_y), tr = tile % (tiles_x * tiles_y);
     const int y0 = (tr / tiles_x) * TH, x0 = (tr % tiles_x) * TW;
-    const int n0 = blockIdx.y * kGemmBN;
+    const int n0 = blockIdx.y * BN;
     f32x16_t acc0 = {}, acc1 = {};
     uint4 ra[A_PER], rb[B_PER];
     auto fetch = [&](int c0) {
@@ -333,10 +334,11 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv3_tiled(ConvArgs a) {
 #pragma unroll
         for (int q = 0; q < B_PER; ++q) {
             const int e = tid + q * kGemmThreads;
-            const int row = e / (kTileCh / 8), piece = e % (kTileCh / 8);  // row = tap * 64 + co
-            const int t = row / kGemmBN, n = n0 + row % kGemmBN;
-            rb[q] = n < a.Nout ? *(const uint4*)(a.Bt + (size_t)n * a.Kpad + t * a.Cin + c0 + 8 * piece)
-                               : make_uint4(0, 0, 0, 0);
+            const int row = e / (kTileCh / 8), piece = e % (kTileCh / 8);  // row = tap * BN + co
+            const int t = row / BN, n = n0 + row % BN;
+            rb[q] = e < B_LOADS && n < a.Nout
+                        ? *(const uint4*)(a.Bt + (size_t)n * a.Kpad + t * a.Cin + c0 + 8 * piece)
+                        : make_uint4(0, 0, 0, 0);
         }
     };
     // this wave's 32 output pixels: row py, columns px0 .. px0 + 31 of the tile
@@ -352,7 +354,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv3_tiled(ConvArgs a) {
 #pragma unroll
         for (int q = 0; q < B_PER; ++q) {
             const int e = tid + q * kGemmThreads;
-            *(uint4*)(sB + (e / (kTileCh / 8)) * kTileLds + 8 * (e % (kTileCh / 8))) = rb[q];
+            if (e < B_LOADS) *(uint4*)(sB + (e / (kTileCh / 8)) * kTileLds + 8 * (e % (kTileCh / 8))) = rb[q];
         }
         __syncthreads();
         if (c0 + kTileCh < a.Cin) fetch(c0 + kTileCh);  // next chunk in flight during the MFMAs
@@ -364,17 +366,19 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv3_tiled(ConvArgs a) {
                 const int kk = s * 16 + 8 * (lane >> 5);
                 const bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sA + pix * kTileLds + kk));
                 const bf16x8_t b0 =
-                    __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (t * kGemmBN + (lane & 31)) * kTileLds + kk));
-                const bf16x8_t b1 = __builtin_bit_cast(
-                    bf16x8_t, *(const uint4*)(sB + (t * kGemmBN + 32 + (lane & 31)) * kTileLds + kk));
+                    __builtin_bit_cast(bf16x8_t, *(const uint4*)(sB + (t * BN + (lane & 31)) * kTileLds + kk));
                 acc0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b0, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
+                if constexpr (NB == 2) {
+                    const bf16x8_t b1 = __builtin_bit_cast(
+                        bf16x8_t, *(const uint4*)(sB + (t * BN + 32 + (lane & 31)) * kTileLds + kk));
+                    acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
+                }
             }
         }
     }
     // epilogue: accumulator row i is pixel 32 w + i of the tile
 #pragma unroll
-    for (int nb = 0; nb < 2; ++nb) {
+    for (int nb = 0; nb < NB; ++nb) {
         const int j = n0 + 32 * nb + (lane & 31);
         if (j >= a.Nout) continue;
         const float bj = a.bias ? a.bias[j] : 0.f;

@@ -85,6 +85,14 @@ int launch_conv(mnf_ctx* ctx, int mode, bool mask, bool out_f32, const ConvArgs&
     if (mode == CONV3 && vec && a.Cin % kTileCh == 0 && a.Hin == a.Hout && a.Win == a.Wout) {
         // direct tiled 3x3: tiles of 2 x 64 pixels, or 4 x 32 for narrow images
         const int TW = a.Wout % 64 == 0 ? 64 : (a.Wout % 32 == 0 && a.Hout % 4 == 0 ? 32 : 0);
+        if (TW == 64 && a.Hout % 2 == 0 && a.Nout <= 32) {  // one 32-channel output tile
+            const dim3 gt((unsigned)(a.n * (a.Hout / 2) * (a.Wout / 64)), 1);
+            if (mask) hipLaunchKernelGGL((k_conv3_tiled<true, false, 64, 1>), gt, dim3(kGemmThreads), 0, st, a);
+            else if (out_f32)
+                hipLaunchKernelGGL((k_conv3_tiled<false, true, 64, 1>), gt, dim3(kGemmThreads), 0, st, a);
+            else hipLaunchKernelGGL((k_conv3_tiled<false, false, 64, 1>), gt, dim3(kGemmThreads), 0, st, a);
+            return MNF_OK;
+        }
         if (TW == 64 && a.Hout % 2 == 0) {
             const dim3 gt((unsigned)(a.n * (a.Hout / 2) * (a.Wout / 64)), g1((size_t)a.Nout, kGemmBN));
             if (mask) hipLaunchKernelGGL((k_conv3_tiled<true, false, 64>), gt, dim3(kGemmThreads), 0, st, a);

@@ -77,7 +77,8 @@ def test_conv_gradients(api, mode, n, H, Ci, Co, masked):
 # 3x3 shapes that take the direct tiled kernel (input channels a multiple of 32,
 # 64- or 32-pixel-wide tiles), forward and masked input gradient; a partial
 # output-channel tile in the last case
-TILED = [("conv3", 2, 64, 32, 64), ("conv3", 2, 32, 64, 96), ("conv3", 1, 128, 96, 40)]
+TILED = [("conv3", 2, 64, 32, 64), ("conv3", 2, 32, 64, 96), ("conv3", 1, 128, 96, 40), ("conv3", 2, 64, 32, 32),
+         ("conv3", 1, 64, 64, 24)]
 
 
 @pytest.mark.parametrize("mode,n,H,Ci,Co", TILED)
@@ -85,7 +86,7 @@ def test_tiled_conv3_forward(api, mode, n, H, Ci, Co):
     test_conv_forward(api, mode, n, H, Ci, Co)
 
 
-@pytest.mark.parametrize("mode,n,H,Ci,Co", TILED[:2])
+@pytest.mark.parametrize("mode,n,H,Ci,Co", TILED[:2] + TILED[3:])
 def test_tiled_conv3_gradients(api, mode, n, H, Ci, Co):
     test_conv_gradients(api, mode, n, H, Ci, Co, True)
 
