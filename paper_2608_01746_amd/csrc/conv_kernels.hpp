@@ -797,6 +797,125 @@ __global__ void __launch_bounds__(kWtThreads) k_wgrad3_tiled(WgradArgs a, int pe
     }
 }
 
+// Weight and bias gradient of the 2x2 stride-2 convolution, all four taps per
+// block: grid (Cout / (32 NCT), Cin / 32, splits), four waves, wave w owns tap
+// (w / 2, w % 2) for a 32-input x 32 NCT-output channel tile.  The reduction
+// runs over chunks of 64 output pixels (TR = 64 / TWC rows of TWC pixels;
+// chunks [z * per, (z + 1) * per)).  Every input pixel belongs to one tap, so
+// per chunk the block stages each tap's input pixels as [tap][ci][pixel]
+// (pixel-contiguous, no halo) and the masked output gradient as [co][pixel]
+// once; the gradient and its ReLU mask are read once per chunk instead of
+// once per tap.  part [splits][4][Ci][Co], bpart [splits][Co] from the blocks
+// of the first input tile.  Needs 16-byte aligned channel groups,
+// Cin % 32 == 0, Cout % (32 NCT) == 0, Wout % TWC == 0, Hout % TR == 0.
+template <int NCT, int TWC>
+__global__ void __launch_bounds__(kGemmThreads) k_wgrad_down_tiled(WgradArgs a, int per) {
+    constexpr int TR = 64 / TWC;
+    constexpr int XS = 64 + 8, GS = 64 + 8;
+    constexpr int NCO = 32 * NCT;
+    constexpr int XT = 4 * 32 * 4;        // (tap, pixel pair, channel group) tasks
+    constexpr int GT = 32 * (NCO / 8);    // (pixel pair, channel group) tasks
+    constexpr int GPER = (GT + kGemmThreads - 1) / kGemmThreads;
+    __shared__ __attribute__((aligned(16))) uint16_t sX[4 * 32 * XS];
+    __shared__ __attribute__((aligned(16))) uint16_t sG[NCO * GS];
+    __shared__ float bred[GT * 8];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int co0 = blockIdx.x * NCO, ci0 = blockIdx.y * 32;
+    const int rows = a.Hout / TR, tiles_x = a.Wout / TWC;
+    const int nchunks = a.n * rows * tiles_x;
+    const int c_begin = blockIdx.z * per, c_end = min(nchunks, c_begin + per);
+    const bool do_bias = blockIdx.y == 0;
+    f32x16_t acc[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) acc[c] = f32x16_t{};
+    float bsum[GPER][8];
+#pragma unroll
+    for (int u = 0; u < GPER; ++u)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) bsum[u][q] = 0.f;
+    for (int ch = c_begin; ch < c_end; ++ch) {
+        const int img = ch / (rows * tiles_x), rem = ch % (rows * tiles_x);
+        const int y0 = (rem / tiles_x) * TR, x0 = (rem % tiles_x) * TWC;
+        __syncthreads();  // the previous chunk's operand reads are done
+        for (int t = tid; t < XT; t += kGemmThreads) {
+            const int g = t & 3, q = (t >> 2) & 31, tap = t >> 7;
+            const int ry = (2 * q) / TWC, xk = (2 * q) % TWC;
+            const int iy = 2 * (y0 + ry) + tap / 2, ix = 2 * (x0 + xk) + tap % 2;
+            const uint16_t* base = a.in + (((size_t)img * a.Hin + iy) * a.Win + ix) * a.in_cs + a.in_co + ci0 + 8 * g;
+            const uint4 v0 = *(const uint4*)base;
+            const uint4 v1 = *(const uint4*)(base + 2 * (size_t)a.in_cs);
+            const uint16_t* e0 = (const uint16_t*)&v0;
+            const uint16_t* e1 = (const uint16_t*)&v1;
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                *(uint32_t*)(sX + (tap * 32 + 8 * g + k) * XS + 2 * q) = (uint32_t)e0[k] | ((uint32_t)e1[k] << 16);
+        }
+#pragma unroll
+        for (int u = 0; u < GPER; ++u) {
+            const int t = tid + u * kGemmThreads;
+            if (t >= GT) break;
+            const int g = t % (NCO / 8), q = t / (NCO / 8);
+            uint16_t gv[2][8] __attribute__((aligned(16)));
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                const int k = 2 * q + e, ry = k / TWC, xk = k % TWC;
+                const size_t gp = ((size_t)img * a.Hout + y0 + ry) * a.Wout + x0 + xk;
+                *(uint4*)gv[e] = *(const uint4*)(a.dout + gp * a.dout_cs + co0 + 8 * g);
+                if (a.act) {
+                    const uint4 h4 = *(const uint4*)(a.act + gp * a.act_cs + a.act_co + co0 + 8 * g);
+                    const uint16_t* h = (const uint16_t*)&h4;
+#pragma unroll
+                    for (int kk = 0; kk < 8; ++kk)
+                        if (h[kk] == 0 || (h[kk] & 0x8000u)) gv[e][kk] = 0;
+                }
+            }
+            if (do_bias) {
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) bsum[u][kk] += bf2f(gv[0][kk]) + bf2f(gv[1][kk]);
+            }
+#pragma unroll
+            for (int kk = 0; kk < 8; ++kk)
+                *(uint32_t*)(sG + (8 * g + kk) * GS + 2 * q) = (uint32_t)gv[0][kk] | ((uint32_t)gv[1][kk] << 16);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kb = s * 16 + 8 * (lane >> 5);
+            const bf16x8_t av = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sX + (w * 32 + (lane & 31)) * XS + kb));
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) {
+                const bf16x8_t bv = __builtin_bit_cast(bf16x8_t, *(const uint4*)(sG + (c * 32 + (lane & 31)) * GS + kb));
+                acc[c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[c], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) {
+        const int j = co0 + c * 32 + (lane & 31);
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int i = ci0 + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+            a.part[(((size_t)blockIdx.z * 4 + w) * a.Cin + i) * a.Cout + j] = acc[c][v];
+        }
+    }
+    if (do_bias) {
+#pragma unroll
+        for (int u = 0; u < GPER; ++u) {
+            const int t = tid + u * kGemmThreads;
+            if (t < GT)
+#pragma unroll
+                for (int kk = 0; kk < 8; ++kk) bred[t * 8 + kk] = bsum[u][kk];
+        }
+        __syncthreads();
+        if (tid < NCO) {
+            const int g = tid / 8, kk = tid % 8;
+            float r = 0.f;
+            for (int q = 0; q < 32; ++q) r += bred[(q * (NCO / 8) + g) * 8 + kk];
+            a.bpart[(size_t)blockIdx.z * a.Cout + co0 + tid] = r;
+        }
+    }
+}
+
 // dW = sum over splits (fixed order); grid ceil(taps*Ci*Co / 256).
 __global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, size_t count, float* __restrict__ dW) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -327,6 +327,31 @@ int layer_wgrad(mnf_ctx* ctx, const LayerDesc& L, View x, int n, int Hin, View d
         reduce_partials((const float*)bpart, splits, (size_t)L.co, db, st);
         return MNF_OK;
     }
+    // 2x2 stride-2 layers with 32-channel tiles: all four taps per block
+    const int twd = Hout % 64 == 0 ? 64 : (Hout % 32 == 0 && Hout % 2 == 0 ? 32 : 0);
+    if (L.mode == DOWN && vec && L.ci % 32 == 0 && L.co % 32 == 0 && twd) {
+        const int nct = L.co % 64 == 0 ? 2 : 1;
+        const int gxy = (L.co / (32 * nct)) * (L.ci / 32);
+        const int nchunks = n * Hout * Hout / 64;
+        int splits = std::max(1, std::min(1024 / gxy, nchunks));
+        const int per = (nchunks + splits - 1) / splits;
+        splits = (nchunks + per - 1) / per;
+        void* part;
+        void* bpart;
+        MNF_TRY(scratch(ctx, "unet_wpart", (size_t)splits * count * sizeof(float), &part));
+        MNF_TRY(scratch(ctx, "unet_bpart", (size_t)splits * L.co * sizeof(float), &bpart));
+        a.part = (float*)part;
+        a.bpart = (float*)bpart;
+        a.splits = splits;
+        const dim3 grid((unsigned)(L.co / (32 * nct)), (unsigned)(L.ci / 32), (unsigned)splits);
+        if (nct == 2 && twd == 64) hipLaunchKernelGGL((k_wgrad_down_tiled<2, 64>), grid, dim3(kGemmThreads), 0, st, a, per);
+        else if (nct == 2) hipLaunchKernelGGL((k_wgrad_down_tiled<2, 32>), grid, dim3(kGemmThreads), 0, st, a, per);
+        else if (twd == 64) hipLaunchKernelGGL((k_wgrad_down_tiled<1, 64>), grid, dim3(kGemmThreads), 0, st, a, per);
+        else hipLaunchKernelGGL((k_wgrad_down_tiled<1, 32>), grid, dim3(kGemmThreads), 0, st, a, per);
+        reduce_partials((const float*)part, splits, count, dW, st);
+        reduce_partials((const float*)bpart, splits, (size_t)L.co, db, st);
+        return MNF_OK;
+    }
     const int tiles = g1((size_t)L.co, 64) * g1((size_t)L.ci, 64) * taps;
     a.splits = std::max(1, std::min(target_blocks / std::max(1, tiles), (a.P + 4095) / 4096));
     const int btaps = L.mode == UP ? 4 : 1;

@@ -95,7 +95,9 @@ def test_tiled_conv3_gradients(api, mode, n, H, Ci, Co):
 # output tiles, 64-pixel rows and pairs of 32-pixel rows, two input-channel
 # tiles (the bias from the first only), masked and unmasked
 WGRAD_TILED = [("conv3", 1, 64, 32, 32), ("conv3", 1, 32, 32, 64), ("conv3", 2, 32, 64, 96),
-               ("conv3", 2, 128, 64, 32), ("conv3", 1, 64, 96, 128)]
+               ("conv3", 2, 128, 64, 32), ("conv3", 1, 64, 96, 128),
+               # 2x2 stride-2 layers through the all-taps kernel (output 64 or 32 wide)
+               ("down", 1, 128, 32, 64), ("down", 2, 64, 64, 32), ("down", 1, 128, 64, 96)]
 
 
 @pytest.mark.parametrize("mode,n,H,Ci,Co", WGRAD_TILED)
