@@ -96,6 +96,8 @@ def run(api, O0, P0, I, pos, prm, order, n_iter, graph=False):
     (32, 32, 80, 25, 2, "rpie", 32, True),       # whole scan in one batch
     (256, 256, 360, 6, 2, "rpie", 4, True),
     (16, 16, 40, 7, 4, "epie", 3, True),
+    (512, 512, 560, 3, 2, "rpie", 2, True),      # the largest detector
+    (384, 384, 440, 4, 3, "rpie", 3, True),
 ])
 def test_iterations_match_oracle(api, Nd, Nw, Mo, J, M, alg, B, upd):
     O, P, pos, I = scan(Mo, Nw, Nd, J, M, Nd + J)

@@ -54,7 +54,7 @@ def real_positions(J, lo, hi, seed):
 # ---------------------------------------------------------------- forward
 
 @pytest.mark.parametrize("Nd,Nw,M", [(16, 16, 40), (32, 32, 64), (64, 64, 96), (128, 64, 120),
-                                     (192, 192, 224), (256, 256, 288)])
+                                     (192, 192, 224), (256, 256, 288), (384, 384, 416), (512, 512, 544)])
 def test_forward_matches_oracle(api, Nd, Nw, M):
     O = c64(synth.make_object(M, Nd + Nw))
     P = c64(soft_probe(synth.make_probe(Nw, Nw / 3, 2.0), 3))
@@ -113,6 +113,9 @@ def one_iter(api, O0, P0, I, pos, prm, order, n_iter):
     (32, 32, 80, 25, "rpie", 32, True),      # whole scan in one batch
     (256, 256, 360, 6, "rpie", 4, True),
     (16, 16, 40, 7, "epie", 3, True),
+    (384, 384, 440, 4, "rpie", 3, True),     # the largest sizes, translations inside the row passes
+    (512, 512, 560, 3, "rpie", 2, True),
+    (192, 192, 240, 5, "epie", 2, True),
 ])
 def test_iterations_match_oracle(api, Nd, Nw, M, J, alg, B, upd):
     O, P, pos, I = scan(M, Nw, Nd, J, Nd + J)
