@@ -29,6 +29,8 @@ entry is the network's forward pass in TFLOP/s against the bf16 MFMA peak.
 positions with the same density, through the Fourier-translated-probe entry
 points (translation passes added to every mini-batch); traffic is null there
 (the stored counters describe the integer-position kernels).
+--workload grad times the loss gradient (the adjoint) on the 2048^2 /
+512^2 / 1000-position gradient workload in position-gradients/s.
 --workload unet times the network's training step and inference alone.
 --workload broadband runs two-harmonic (Eq. 4) data through fusion and the
 monochromatic reconstruction.
@@ -262,6 +264,96 @@ def run_lab(args, api, synth, dev):
                                "kind": "oracle",
                                "sample": f"{n} rPIE position updates (mini-batches of {w.batch}) of the "
                                          f"same workload in float64 NumPy, {sec:.1f} s"}
+    return out
+
+
+def run_grad(args, api, synth, dev):
+    """Loss gradient (the adjoint of Eqs. 2-3) on the gradient workload: 2048^2
+    object, 512^2 probe, 1000 Fermat-spiral positions, MNF-fused data from
+    exposures simulated on the GPU (5 exposures, 16 bit, read noise 3,
+    6 levels).  A step is the Poisson loss and the object and probe gradients
+    over every position (exit waves recomputed in batches of 32), at a
+    perturbed start so the gradient is not zero.  value = positions / s."""
+    import numpy as np
+    import torch
+
+    w = synth.gradient_workload()
+    O_true = w.object()
+    P = w.probe()
+    Ot = torch.from_numpy(O_true.astype(np.complex64)).to(dev)
+    Pt = torch.from_numpy(P.astype(np.complex64)).to(dev)
+    clean = api.ptycho_forward(Ot, Pt, w.pos, w.Nd)
+    s = synth.flux_scale(float(clean.max().item()), w.sat)
+    print(f"# simulating {w.J} x {len(w.t)} exposures of {w.Nd}^2 on the GPU", file=sys.stderr, flush=True)
+    raw = api.detector_expose(clean, w.t, s, w.sat, w.sigma_read, seed=4004)
+    del clean
+    fused = api.fuse_exposures(raw, w.t, w.levels, sat=float(w.sat), delta=synth.default_deltas(w.levels, w.sigma_read))
+    del raw
+    torch.cuda.synchronize()
+    O0 = torch.from_numpy((synth.make_object(w.M, 44) * 0.2 + O_true * 0.8).astype(np.complex64)).to(dev)
+    Pk = torch.from_numpy((np.sqrt(s) * P).astype(np.complex64)).to(dev)
+    state = {}
+
+    def step():
+        state["out"] = api.ptycho_grad(O0, Pk, fused, w.pos, "poisson", eps=1e-6, batch=w.batch)
+
+    classes = ["rows_fwd", "grad_cols", "rows_inv", "grad_scatter"]
+    api.profile(classes)
+    api.profile_reset()
+    step()
+    torch.cuda.synchronize()
+    ranks = api.profile_read()
+    api.profile([])
+    dominant = max(classes, key=lambda k: ranks[k][1])
+    for _ in range(args.warmup - 1):
+        step()
+    api.profile([dominant])
+    api.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = api.profile_read()
+    api.profile([])
+    nlaunch, kms = prof[dominant]
+    dt = (t1 - t0) / args.steps
+    N, B = w.Nd, w.batch
+    per_launch = w.J / math.ceil(w.J / B)
+    # algorithmic bytes per position gradient: intensity 4 N^2, object window
+    # read 8 N^2, object-gradient window write 8 N^2, probe read and probe
+    # gradient write 16 N^2 amortised over the batch
+    bytes_pos = 20.0 * N * N + 16.0 * N * N / B
+    avg_us = kms / nlaunch * 1e3
+    achieved = bytes_pos * per_launch / (avg_us * 1e-6) / 1e9
+    out = {
+        "metric": "position-gradients/s at 512^2 FP32 (Poisson loss and object/probe gradients, batches of 32)",
+        "value": round(w.J / dt, 1), "unit": "position-gradients/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic (seeded object/probe, exposures simulated on the GPU, MNF-fused)",
+        "config": {"workload": "grad-512: 2048^2 object, 512^2 probe, 1000 Fermat-spiral positions, 5 exposures, "
+                               "6-level fusion, Poisson loss, recompute batches of 32"},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": round(avg_us, 2), "launches": nlaunch,
+                     "algorithmic_bytes_per_launch": round(bytes_pos * per_launch)},
+        "per_class_ms_one_step": {k: round(v[1], 3) for k, v in ranks.items()},
+        "loss": float(state["out"][0].item()),
+    }
+    if not args.no_cpu:
+        from oracle import adjoint
+        O_np, P_np = O0.cpu().numpy().astype(np.complex128), Pk.cpu().numpy().astype(np.complex128)
+        I_np = fused.cpu().numpy().astype(np.float64)
+        n, t_start = 0, time.perf_counter()
+        while time.perf_counter() - t_start < args.cpu_seconds and n < w.J:
+            adjoint.loss_and_grad(O_np, P_np, I_np[n:n + 1], w.pos[n:n + 1], "poisson", 1e-6)
+            n += 1
+        sec = time.perf_counter() - t_start
+        out["cpu_baseline"] = {"value": round(n / sec, 3), "unit": "position-gradients/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"{n} positions' Poisson loss and gradients in float64 NumPy, {sec:.1f} s"}
     return out
 
 
@@ -758,7 +850,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=None, help="iterations per step (200 lab, 20 multiscan)")
-    ap.add_argument("--workload", choices=["lab", "subpixel", "multiscan", "warmstart", "batch-sweep",
+    ap.add_argument("--workload", choices=["lab", "subpixel", "multiscan", "grad", "warmstart", "batch-sweep",
                                            "fusion-compare", "unet", "broadband"], default="lab")
     ap.add_argument("--train-seconds", type=float, default=240.0, help="warm start: training time budget")
     ap.add_argument("--train-objects", type=int, default=500, help="warm start: training objects x 100 patterns")
@@ -792,7 +884,7 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    run = {"lab": run_lab, "subpixel": run_lab, "multiscan": run_multiscan, "warmstart": run_warmstart,
+    run = {"lab": run_lab, "subpixel": run_lab, "multiscan": run_multiscan, "grad": run_grad, "warmstart": run_warmstart,
            "batch-sweep": run_batch_sweep, "fusion-compare": run_fusion_compare, "unet": run_unet,
            "broadband": run_broadband}[args.workload]
     out = run(args, api, synth, dev)
