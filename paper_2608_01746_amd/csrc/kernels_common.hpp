@@ -32,6 +32,40 @@ struct ColCfg {
     static constexpr int THREADS = C * T;
 };
 
+// Loads through a global-address-space view of a device pointer.  A pointer
+// read out of a descriptor is generic to the compiler, which then emits flat
+// loads; those also count against the LDS counter, so every wait for an LDS
+// value would wait for them too.  Only for memory of the device heap.
+template <class T>
+using gptr = const __attribute__((address_space(1))) T*;
+__device__ __forceinline__ float ldg(const float* p, size_t i) { return ((gptr<float>)p)[i]; }
+__device__ __forceinline__ float2 ldg(const float2* p, size_t i) {
+    typedef float v2 __attribute__((ext_vector_type(2)));
+    const v2 v = ((gptr<v2>)p)[i];
+    return make_float2(v.x, v.y);
+}
+
+// The twiddle table staged through registers: load() with a prologue's
+// other loads, store() to LDS just before the barrier that precedes the first
+// transform, so the table's load needs no wait of its own (a load-to-LDS
+// loop waits for every load issued before it).
+template <int N, int THREADS>
+struct TwRegs {
+    static constexpr int K = (N + THREADS - 1) / THREADS;
+    float2 v[K];
+    __device__ __forceinline__ void load(const float2* tw_g) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) v[k] = tw_g[min((int)threadIdx.x + k * THREADS, N - 1)];
+    }
+    __device__ __forceinline__ void store(float2* tw) const {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = (int)threadIdx.x + k * THREADS;
+            if (i < N) tw[i] = v[k];
+        }
+    }
+};
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));

@@ -50,40 +50,45 @@ k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
     float2 x[V];
     float mO = 0.f;
     const float2* Orow = sc.O + (size_t)(sd.py + (live ? y : 0)) * Mx + sd.px;
+    // Every load is issued unconditionally (row and column clamped into the
+    // window) and masked afterwards, so a thread's loads are all in flight
+    // together instead of one guarded load after another.
     if constexpr (SUBX) {
         float2* Pw = Pd + ((size_t)s * N + (live ? y : 0)) * N;
         const float dx = frac[s].y;  // uniform over the block
+        float2 o[V];
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) o[idx] = ldg(Orow, in_pos<N, false>(t, idx));  // Nw == N
         for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
         __syncthreads();
         float2 p[V];
         shift_line<N>(p, Pw, 1, dx, t, lds, RowLds<N>(line), tw);
+        if (live && dx != 0.f) {
+#pragma unroll
+            for (int idx = 0; idx < V; ++idx) Pw[in_pos<N, false>(t, idx)] = p[idx];
+        }
 #pragma unroll
         for (int idx = 0; idx < V; ++idx) {
-            const int n = in_pos<N, false>(t, idx);
-            if (live && dx != 0.f) Pw[n] = p[idx];
-            float2 v = make_float2(0.f, 0.f);
-            if (live) {
-                const float2 o = Orow[n];
-                v = cmul(p[idx], o);
-                mO = fmaxf(mO, cabs2(o));
-            }
-            x[idx] = v;
+            x[idx] = live ? cmul(p[idx], o[idx]) : make_float2(0.f, 0.f);
+            mO = fmaxf(mO, live ? cabs2(o[idx]) : 0.f);
         }
     } else {
         const float2* Prow = (Pd ? Pd + (size_t)(s % pmod) * Nw * Nw : sc.P) + (size_t)(live ? y : 0) * Nw;
+        float2 o[V], p[V];
 #pragma unroll
         for (int idx = 0; idx < V; ++idx) {
-            const int n = in_pos<N, false>(t, idx);
-            float2 v = make_float2(0.f, 0.f);
-            if (live && n < Nw) {
-                const float2 o = Orow[n];
-                v = cmul(Prow[n], o);
-                mO = fmaxf(mO, cabs2(o));
-            }
-            x[idx] = v;
+            const int n = min(in_pos<N, false>(t, idx), Nw - 1);
+            o[idx] = ldg(Orow, n);
+            p[idx] = ldg(Prow, n);
         }
         for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
         __syncthreads();
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) {
+            const bool in = live && in_pos<N, false>(t, idx) < Nw;
+            x[idx] = in ? cmul(p[idx], o[idx]) : make_float2(0.f, 0.f);
+            mO = fmaxf(mO, in ? cabs2(o[idx]) : 0.f);
+        }
     }
     fft_line<N, false>(x, t, lds, RowLds<N>(line), tw);
     if (live) {
@@ -143,28 +148,36 @@ k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
     __shared__ float2 tw[N];
     __shared__ double red[ColCfg<N, CV>::THREADS / 64 + 1];
     const int s = blockIdx.y;
+    const int c = threadIdx.x % C, t = threadIdx.x / C;
+    const int kx = blockIdx.x * C + c;
+    float2* col = S + (size_t)s * N * N + kx;
+    // The column and the twiddles need no descriptor: their loads go out
+    // before the descriptors are read (rows at and beyond Nw hold stale
+    // values and are zeroed once Nw is known).
+    float2 x[V];
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) x[idx] = col[(size_t)in_pos<N, false>(t, idx) * N];
+    TwRegs<N, ColCfg<N, CV>::THREADS> twr;
+    twr.load(tw_g);
     const ScanDev sc0 = scans[0];
     const SlotDev sd = slots[s];
     const ScanDev sc = scan_desc(scans, sc0, sd.scan);
     const int Nw = sc.Nw;
-    const int c = threadIdx.x % C, t = threadIdx.x / C;
-    const int kx = blockIdx.x * C + c;
-    float2* col = S + (size_t)s * N * N + kx;
 
     // the fused intensity at this thread's output frequencies is loaded with
     // the column, before the transform
     const float* Ij = sc.I + (size_t)sd.j * N * N;
     const int sx = (kx + N / 2) % N;
-    float2 x[V];
     float Iq[V];
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
-        const int y = in_pos<N, false>(t, idx);
-        x[idx] = y < Nw ? col[(size_t)y * N] : make_float2(0.f, 0.f);
         const int ky = out_pos<N, false>(t, idx);
-        Iq[idx] = Ij[(size_t)((ky + N / 2) % N) * N + sx];
+        Iq[idx] = ldg(Ij, (size_t)((ky + N / 2) % N) * N + sx);
     }
-    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx)
+        if (in_pos<N, false>(t, idx) >= Nw) x[idx] = make_float2(0.f, 0.f);
+    twr.store(tw);
     __syncthreads();
     fft_line<N, false>(x, t, lds, ColLds<C>(c), tw);
 
@@ -250,7 +263,7 @@ k_cols_modulus_modes(const ScanDev* __restrict__ scans, const SlotDev* __restric
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int ky = out_pos<N, false>(t, idx);
-        a[idx] = sqrtf(fmaxf(Ij[(size_t)((ky + N / 2) % N) * N + sx], 0.f));
+        a[idx] = sqrtf(fmaxf(ldg(Ij, (size_t)((ky + N / 2) % N) * N + sx), 0.f));
         tot[idx] = 0.f;
     }
     for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
@@ -260,10 +273,10 @@ k_cols_modulus_modes(const ScanDev* __restrict__ scans, const SlotDev* __restric
         float2* col = S + (size_t)(s0 + m) * N * N + kx;
         float2 x[V];
 #pragma unroll
-        for (int idx = 0; idx < V; ++idx) {
-            const int y = in_pos<N, false>(t, idx);
-            x[idx] = y < Nw ? col[(size_t)y * N] : make_float2(0.f, 0.f);
-        }
+        for (int idx = 0; idx < V; ++idx) x[idx] = col[(size_t)min(in_pos<N, false>(t, idx), Nw - 1) * N];
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx)
+            if (in_pos<N, false>(t, idx) >= Nw) x[idx] = make_float2(0.f, 0.f);
         fft_line<N, false>(x, t, lds, ColLds<C>(c), tw);
 #pragma unroll
         for (int idx = 0; idx < V; ++idx) {
@@ -417,23 +430,61 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
     const int r = blockIdx.x;
     if (r >= Nw) return;  // uniform over the block
     const int line = threadIdx.x / T, t = threadIdx.x % T;
+    // Inverse-transform input of a round: row r of slot k0 + line (slot 0 of
+    // the group for lines past the end, zeroed after the loads).  The first
+    // round's loads go out before the prologue below.
+    float2 x[V];
+    auto load_rows = [&](int k0) {
+        const int k = k0 + line;
+        const float2* row = S + ((size_t)(gd.s0 + (k < nb ? k : 0)) * N + r) * N;
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) x[idx] = row[in_pos<N, true>(t, idx)];
+    };
+    load_rows(0);
 
+    // Prologue: the twiddles, probe row(s) and slot table are loaded into
+    // registers (indices clamped) and stored to LDS afterwards, so their
+    // loads are in flight together rather than one loop's after another's.
     const float2* Prow = sc.P + (size_t)r * Nw;
-    for (int i = threadIdx.x; i < N; i += THREADS) tw[i] = tw_g[i];
+    TwRegs<N, THREADS> twr;
+    twr.load(tw_g);
+    constexpr int PK = (NM * N + THREADS - 1) / THREADS;
     const int nrow = MIX ? nmodes * N : N;
-    for (int i = threadIdx.x; i < nrow; i += THREADS) {
-        const int m = i / N, n = i % N;
-        s_prow[i] = n < Nw ? Prow[(size_t)m * Nw * Nw + n] : make_float2(0.f, 0.f);
+    float2 prv[PK];
+#pragma unroll
+    for (int q = 0; q < PK; ++q) {
+        const int i = min((int)threadIdx.x + q * THREADS, nrow - 1);
+        prv[q] = ldg(Prow, (size_t)(i / N) * Nw * Nw + min(i % N, Nw - 1));
     }
-    for (int k = threadIdx.x; k < nb; k += THREADS) {
-        const SlotDev sd = slots[gd.s0 + k];
-        s_py[k] = sd.py;
-        s_px[k] = sd.px;
-        if constexpr (DEN) {
-            float m = 0.f;
-            for (int i = 0; i < nparts; ++i) m = fmaxf(m, maxO2_part[(size_t)(gd.s0 + k) * nparts + i]);
-            s_max[k] = m;
+    constexpr int SK = (kMaxBatch + THREADS - 1) / THREADS;
+#pragma unroll
+    for (int q = 0; q < SK; ++q) {
+        const int k = (int)threadIdx.x + q * THREADS;
+        if (k < nb) {
+            const SlotDev sd = slots[gd.s0 + k];
+            if constexpr (DEN) {
+                // the slot's row-pass maxima, 16 loads at a time (the last
+                // index repeated past the end leaves the maximum unchanged)
+                const float* part = maxO2_part + (size_t)(gd.s0 + k) * nparts;
+                float m = 0.f;
+                for (int i0 = 0; i0 < nparts; i0 += 16) {
+                    float v[16];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) v[u] = part[min(i0 + u, nparts - 1)];
+#pragma unroll
+                    for (int u = 0; u < 16; ++u) m = fmaxf(m, v[u]);
+                }
+                s_max[k] = m;
+            }
+            s_py[k] = sd.py;
+            s_px[k] = sd.px;
         }
+    }
+    twr.store(tw);
+#pragma unroll
+    for (int q = 0; q < PK; ++q) {
+        const int i = (int)threadIdx.x + q * THREADS;
+        if (i < nrow) s_prow[i] = i % N < Nw ? prv[q] : make_float2(0.f, 0.f);
     }
     float2 num[NM][COLS];
     double den[COLS];
@@ -453,11 +504,12 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
         float2* row = S + ((size_t)(gd.s0 + kk) * N + r) * N;
         const float2* Orow = sc.O + (size_t)(s_py[kk] + r) * Mx + s_px[kk];
         // every global load of the round is issued before the transform
-        float2 x[V], o[V], pv[V];
+        float2 o[V], pv[V];
         const float2* Psrow = SUB ? Pd + ((size_t)(gd.s0 + kk) * Nw + r) * Nw : nullptr;
+        if (k0 > 0) load_rows(k0);
 #pragma unroll
         for (int idx = 0; idx < V; ++idx) {
-            x[idx] = live ? row[in_pos<N, true>(t, idx)] : make_float2(0.f, 0.f);
+            if (!live) x[idx] = make_float2(0.f, 0.f);
             const int n = out_pos<N, true>(t, idx);
             o[idx] = live && n < Nw ? Orow[n] : make_float2(0.f, 0.f);
             if constexpr (SUB) pv[idx] = live && n < Nw ? Psrow[n] : make_float2(0.f, 0.f);

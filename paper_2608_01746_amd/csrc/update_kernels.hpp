@@ -83,12 +83,12 @@ k_object_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ s
     const int cnt = tile_window_list(slots, gd, Nw, ty0, tx0, l_slot, l_py, l_px);
     if (cnt == 0) return;
     float mp = 0.f;
-    for (int i = threadIdx.x; i < Nw; i += kObjThreads) mp = fmaxf(mp, sc.maxP2_row[i]);
+    for (int i = threadIdx.x; i < Nw; i += kObjThreads) mp = fmaxf(mp, ldg(sc.maxP2_row, i));
     mp = block_max(mp, red);
-    const float a = rpie ? 1.f - alpha : 0.f;
-    const double cst = rpie ? (double)alpha * (double)mp : (double)mp / (double)alpha;
     const int xx = tx0 + (threadIdx.x % kObjTileX);
     const int yb = ty0 + (threadIdx.x / kObjTileX) * kObjRows;
+    const float a = rpie ? 1.f - alpha : 0.f;
+    const double cst = rpie ? (double)alpha * (double)mp : (double)mp / (double)alpha;
     const float* P2 = sc.P2;
     float2 num[kObjRows];
     double den[kObjRows];
@@ -114,7 +114,7 @@ k_object_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ s
                 in[c][q] = inx && uy >= 0 && uy < Nw;
                 const int uyc = min(max(uy, 0), Nw - 1);
                 w[c][q] = Sk[(size_t)uyc * N];
-                p2[c][q] = P2[(size_t)uyc * Nw + uxc];
+                p2[c][q] = ldg(P2, (size_t)uyc * Nw + uxc);
             }
         }
 #pragma unroll
@@ -127,16 +127,20 @@ k_object_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ s
                 }
     }
     if (xx >= sc.bx0 + sc.bw) return;
+    // the object values are read together (rows clamped into the box), then
+    // the rows inside the box with a positive denominator are written
+    float2 ov[kObjRows];
+#pragma unroll
+    for (int q = 0; q < kObjRows; ++q) ov[q] = ldg(sc.O, (size_t)min(yb + q, sc.by0 + sc.bh - 1) * sc.Mx + xx);
 #pragma unroll
     for (int q = 0; q < kObjRows; ++q) {
         const int yy = yb + q;
         if (yy < sc.by0 + sc.bh && den[q] > 0.0) {
-            float2* o = sc.O + (size_t)yy * sc.Mx + xx;
             const double inv = 1.0 / den[q];
-            float2 v = *o;
+            float2 v = ov[q];
             v.x = (float)((double)v.x + (double)num[q].x * inv);
             v.y = (float)((double)v.y + (double)num[q].y * inv);
-            *o = v;
+            sc.O[(size_t)yy * sc.Mx + xx] = v;
         }
     }
 }
@@ -191,13 +195,13 @@ k_grad_object(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slo
                 }
     }
     if (xx >= sc.bx0 + sc.bw) return;
+    float2 gv[kObjRows];
+#pragma unroll
+    for (int q = 0; q < kObjRows; ++q) gv[q] = ldg(sc.gO, (size_t)min(yb + q, sc.by0 + sc.bh - 1) * sc.Mx + xx);
 #pragma unroll
     for (int q = 0; q < kObjRows; ++q) {
         const int yy = yb + q;
-        if (yy < sc.by0 + sc.bh && any[q]) {
-            float2* g = sc.gO + (size_t)yy * sc.Mx + xx;
-            *g = cadd(*g, acc[q]);
-        }
+        if (yy < sc.by0 + sc.bh && any[q]) sc.gO[(size_t)yy * sc.Mx + xx] = cadd(gv[q], acc[q]);
     }
 }
 
