@@ -70,7 +70,7 @@ def algo_bytes_per_update(N: int, B: int) -> float:
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["fft.hpp", "kernels_common.hpp", "pattern_kernels.hpp", "shift_kernels.hpp", "update_kernels.hpp",
-                  "tables.hpp", "ptycho.hip"]
+                  "tables.hpp", "ptycho.hip", "../build.py"]  # build.py: the compiler flags
 
 
 def kernel_source_hash() -> str:
