@@ -56,13 +56,15 @@ k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
     if constexpr (SUBX) {
         float2* Pw = Pd + ((size_t)s * N + (live ? y : 0)) * N;
         const float dx = frac[s].y;  // uniform over the block
-        float2 o[V];
+        float2 o[V], p[V];
+        line_load<N>(p, Pw, 1, t);
 #pragma unroll
         for (int idx = 0; idx < V; ++idx) o[idx] = ldg(Orow, in_pos<N, false>(t, idx));  // Nw == N
-        for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
+        TwRegs<N, RowCfg<N, RV>::THREADS> twr;
+        twr.load(tw_g);
+        twr.store(tw);
         __syncthreads();
-        float2 p[V];
-        shift_line<N>(p, Pw, 1, dx, t, lds, RowLds<N>(line), tw);
+        if (dx != 0.f) shift_regs<N>(p, dx, t, lds, RowLds<N>(line), tw);
         if (live && dx != 0.f) {
 #pragma unroll
             for (int idx = 0; idx < V; ++idx) Pw[in_pos<N, false>(t, idx)] = p[idx];

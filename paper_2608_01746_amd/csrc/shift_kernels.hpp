@@ -42,21 +42,14 @@ __device__ __forceinline__ void shift_regs(float2* x, float d, int t, float2* ld
     fft_line<N, true>(x, t, lds, addr, tw);
 }
 
-// One line of N values (in[i * stride]) translated by d, left in x[] at the
-// positions out_pos<N, true>.  Loads for the transform use in_pos<N, false>;
-// d == 0 loads straight into the output positions (uniform over the block).
-template <int N, class ADDR>
-__device__ __forceinline__ void shift_line(float2* x, const float2* in, size_t stride, float d, int t,
-                                           float2* lds, const ADDR& addr, const float2* tw) {
+// One line of N values (in[i * stride]) loaded into x[] at the positions
+// in_pos<N, false>, which are also where a translation (shift_regs) leaves
+// them (out_pos<N, true>): a zero fraction needs no transform at all.
+template <int N>
+__device__ __forceinline__ void line_load(float2* x, const float2* in, size_t stride, int t) {
     constexpr int V = PlanInfo<N>::V;
-    if (d == 0.f) {
-#pragma unroll
-        for (int idx = 0; idx < V; ++idx) x[idx] = in[(size_t)out_pos<N, true>(t, idx) * stride];
-        return;
-    }
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) x[idx] = in[(size_t)in_pos<N, false>(t, idx) * stride];
-    shift_regs<N>(x, d, t, lds, addr, tw);
 }
 
 // grid (N / LINES, nslots).  dst[s][y][:] = row y of src[s] translated along x
@@ -72,11 +65,14 @@ k_shift_rows(const float2* src, size_t src_stride, float2* dst, const float2* __
     const int s = blockIdx.y;
     const int line = threadIdx.x / T, t = threadIdx.x % T;
     const int y = blockIdx.x * LINES + line;  // N % LINES == 0
-    const float d = sign * frac[s].y;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
-    __syncthreads();
     float2 x[V];
-    shift_line<N>(x, src + s * src_stride + (size_t)y * N, 1, d, t, lds, RowLds<N>(line), tw);
+    line_load<N>(x, src + s * src_stride + (size_t)y * N, 1, t);
+    TwRegs<N, RowCfg<N, 0>::THREADS> twr;
+    twr.load(tw_g);
+    const float d = sign * frac[s].y;  // uniform over the block
+    twr.store(tw);
+    __syncthreads();
+    if (d != 0.f) shift_regs<N>(x, d, t, lds, RowLds<N>(line), tw);
     float2* row = dst + ((size_t)s * N + y) * N;
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) row[out_pos<N, true>(t, idx)] = x[idx];
@@ -98,10 +94,13 @@ k_shift_cols(const float2* src, size_t src_stride, float2* dst, const float2* __
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const float2* in = src + s * src_stride + blockIdx.x * C + c;
     float2* col = dst + (size_t)s * N * N + blockIdx.x * C + c;
-    for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
-    __syncthreads();
     float2 x[V];
-    shift_line<N>(x, in, N, d, t, lds, ColLds<C>(c), tw);
+    line_load<N>(x, in, N, t);
+    TwRegs<N, ColCfg<N, 0>::THREADS> twr;
+    twr.load(tw_g);
+    twr.store(tw);
+    __syncthreads();
+    if (d != 0.f) shift_regs<N>(x, d, t, lds, ColLds<C>(c), tw);
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) col[(size_t)out_pos<N, true>(t, idx) * N] = x[idx];
 }
@@ -118,11 +117,20 @@ k_probe_sum_update(const float2* __restrict__ G, const GroupDev* __restrict__ gr
     const int q = blockIdx.x * 256 + threadIdx.x;
     if (q >= N * N) return;
     const double den = DP[q];
-    if (!(den > 0.0)) return;
+    float2 p = P[q];
+    // the slots' numerators, eight loads at a time (slot index clamped),
+    // summed in slot order
     float2 acc = make_float2(0.f, 0.f);
     const float2* g = G + (size_t)gd.s0 * N * N + q;
-    for (int k = 0; k < gd.nb; ++k) acc = cadd(acc, g[(size_t)k * N * N]);
-    float2 p = P[q];
+    for (int k0 = 0; k0 < gd.nb; k0 += 8) {
+        float2 v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = g[(size_t)min(k0 + u, gd.nb - 1) * N * N];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (k0 + u < gd.nb) acc = cadd(acc, v[u]);
+    }
+    if (!(den > 0.0)) return;
     const double inv = 1.0 / den;
     p.x = (float)((double)p.x + (double)acc.x * inv);
     p.y = (float)((double)p.y + (double)acc.y * inv);
