@@ -52,16 +52,24 @@ __device__ __forceinline__ float binom5(int m) {
 
 // Level 0 of every exposure at one pixel: I_tilde_k and the weight W_k
 // normalised over the K frames of the pixel.  KM >= K is a compile-time bound
-// so that the per-exposure values stay in registers.
+// so that the per-exposure values stay in registers.  Split into the loads of
+// the K raw counts (exposure index clamped to K - 1 past the end, so every
+// load is issued unconditionally and a caller can issue several pixels'
+// loads before the first wait) and the pointwise evaluation.
 template <int KM>
-__device__ __forceinline__ void level0_at(const uint16_t* __restrict__ px, size_t npix, int K, const FuseConsts& c,
-                                          float* gi, float* gw) {
+__device__ __forceinline__ void level0_load(const uint16_t* __restrict__ px, size_t npix, int K, float* cnt) {
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) cnt[kk] = (float)px[(size_t)min(kk, K - 1) * npix];
+}
+
+template <int KM>
+__device__ __forceinline__ void level0_eval(const float* cnt, int K, const FuseConsts& c, float* gi, float* gw) {
     float wsum = 0.f;
 #pragma unroll
     for (int kk = 0; kk < KM; ++kk) {
         gi[kk] = gw[kk] = 0.f;
         if (kk < K) {
-            const float I = (float)px[(size_t)kk * npix];
+            const float I = cnt[kk];
             const float Ib = fminf(fmaxf((I - c.dark) * c.inv_range, 0.f), 1.f);
             const float d = Ib - c.mu;
             const float w = __expf(-d * d * c.inv_2s2);  // hardware exp2 path: a few ulp, far inside the 1e-6 weight bound
@@ -96,14 +104,18 @@ k_fuse_level1(const uint16_t* __restrict__ raw, int K, int H, int W, size_t tota
 #pragma unroll 1
     for (int a = 0; a < 5; ++a) {
         const int yy = reflect101(2 * oy + a - 2, H);
+        // the counts of the row's five taps are loaded before any is used
+        float cnt[5][KM];
+#pragma unroll
+        for (int b = 0; b < 5; ++b)
+            level0_load<KM>(base + (size_t)yy * W + reflect101(2 * ox + b - 2, W), npix, K, cnt[b]);
         float ri[KM], rw[KM];
 #pragma unroll
         for (int kk = 0; kk < KM; ++kk) ri[kk] = rw[kk] = 0.f;
-#pragma unroll 1
+#pragma unroll
         for (int b = 0; b < 5; ++b) {
-            const int xx = reflect101(2 * ox + b - 2, W);
             float gi[KM], gw[KM];
-            level0_at<KM>(base + (size_t)yy * W + xx, npix, K, c, gi, gw);
+            level0_eval<KM>(cnt[b], K, c, gi, gw);
 #pragma unroll
             for (int kk = 0; kk < KM; ++kk) {
                 ri[kk] += binom5(b) * gi[kk];
@@ -161,34 +173,59 @@ k_fuse_reduce(const float* __restrict__ GI, const float* __restrict__ GW, int h,
 // neighbouring lanes of alternating parity run the same instructions.
 //   even: taps (c-1, c, c+1) weights (1/8, 3/4, 1/8), c-1 -> 1 at the border
 //   odd : taps (c, c+1, -)   weights (1/2, 1/2, 0),   c+1 -> hc-1 at the border
-__device__ __forceinline__ float expand_at(const float* __restrict__ g, int hc, int wc, int y, int x) {
+// The taps depend only on the grid and the pixel, so several coarse images
+// sampled at one pixel share them; loads and the weighted sum are separate
+// so that a caller can issue all the loads first.
+struct ExpandTaps {
+    int iy[3], ix[3];
+    float wy[3], wx[3];
+};
+
+__device__ __forceinline__ ExpandTaps expand_taps(int hc, int wc, int y, int x) {
     const int cy = y >> 1, cx = x >> 1;
     const bool ey = (y & 1) == 0, ex = (x & 1) == 0;
     const int up = cy + 1 >= hc ? hc - 1 : cy + 1, rt = cx + 1 >= wc ? wc - 1 : cx + 1;
-    const int iy0 = ey ? (cy - 1 < 0 ? 1 : cy - 1) : cy, iy1 = ey ? cy : up, iy2 = up;
-    const int ix0 = ex ? (cx - 1 < 0 ? 1 : cx - 1) : cx, ix1 = ex ? cx : rt, ix2 = rt;
-    const float wy0 = ey ? 0.125f : 0.5f, wy1 = ey ? 0.75f : 0.5f, wy2 = ey ? 0.125f : 0.f;
-    const float wx0 = ex ? 0.125f : 0.5f, wx1 = ex ? 0.75f : 0.5f, wx2 = ex ? 0.125f : 0.f;
-    const float* r0 = g + (size_t)iy0 * wc;
-    const float* r1 = g + (size_t)iy1 * wc;
-    const float* r2 = g + (size_t)iy2 * wc;
-    float s = 0.f, r;
-    r = 0.f;
-    r += wx0 * r0[ix0];
-    r += wx1 * r0[ix1];
-    r += wx2 * r0[ix2];
-    s += wy0 * r;
-    r = 0.f;
-    r += wx0 * r1[ix0];
-    r += wx1 * r1[ix1];
-    r += wx2 * r1[ix2];
-    s += wy1 * r;
-    r = 0.f;
-    r += wx0 * r2[ix0];
-    r += wx1 * r2[ix1];
-    r += wx2 * r2[ix2];
-    s += wy2 * r;
+    ExpandTaps e;
+    e.iy[0] = ey ? (cy - 1 < 0 ? 1 : cy - 1) : cy;
+    e.iy[1] = ey ? cy : up;
+    e.iy[2] = up;
+    e.ix[0] = ex ? (cx - 1 < 0 ? 1 : cx - 1) : cx;
+    e.ix[1] = ex ? cx : rt;
+    e.ix[2] = rt;
+    e.wy[0] = ey ? 0.125f : 0.5f;
+    e.wy[1] = ey ? 0.75f : 0.5f;
+    e.wy[2] = ey ? 0.125f : 0.f;
+    e.wx[0] = ex ? 0.125f : 0.5f;
+    e.wx[1] = ex ? 0.75f : 0.5f;
+    e.wx[2] = ex ? 0.125f : 0.f;
+    return e;
+}
+
+__device__ __forceinline__ void expand_load(const float* __restrict__ g, int wc, const ExpandTaps& e, float* v) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int q = 0; q < 3; ++q) v[3 * r + q] = g[(size_t)e.iy[r] * wc + e.ix[q]];
+}
+
+__device__ __forceinline__ float expand_sum(const ExpandTaps& e, const float* v) {
+    float s = 0.f;
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        float t = 0.f;
+        t += e.wx[0] * v[3 * r];
+        t += e.wx[1] * v[3 * r + 1];
+        t += e.wx[2] * v[3 * r + 2];
+        s += e.wy[r] * t;
+    }
     return s;
+}
+
+__device__ __forceinline__ float expand_at(const float* __restrict__ g, int hc, int wc, int y, int x) {
+    const ExpandTaps e = expand_taps(hc, wc, y, x);
+    float v[9];
+    expand_load(g, wc, e, v);
+    return expand_sum(e, v);
 }
 
 // Band level l < L: F_l (+)= Q(G_l[W] (G_l[I] - U(G_{l+1}[I]))); base l = L:
@@ -245,8 +282,24 @@ k_fuse_final(const uint16_t* __restrict__ raw, int K, int H, int W, size_t total
     const size_t npix = (size_t)H * W;
     const int jj = i / (H * W), pq = i - jj * (H * W);
     const int y = pq / W, x = pq - y * W;
+    float cnt[KM];
+    level0_load<KM>(raw + (size_t)jj * K * npix + pq, npix, K, cnt);
+    // with K <= 8 the expand taps of every exposure's level 1 and of the
+    // collapsed level 1 are loaded together with the counts
+    const int h1 = H >> 1, w1 = W >> 1;
+    const size_t n1 = (total / npix) * (size_t)h1 * w1;  // level-1 pixels of the chunk
+    constexpr bool BATCH = KM <= 8;
+    ExpandTaps e{};
+    float ev[BATCH ? KM : 1][9], rv[9];
+    if (BATCH && L > 0) {
+        e = expand_taps(h1, w1, y, x);
+#pragma unroll
+        for (int kk = 0; kk < (BATCH ? KM : 1); ++kk)
+            expand_load(GI1 + (size_t)min(kk, K - 1) * n1 + (size_t)jj * h1 * w1, w1, e, ev[kk]);
+        expand_load(R1 + (size_t)jj * h1 * w1, w1, e, rv);
+    }
     float gi[KM], gw[KM];
-    level0_at<KM>(raw + (size_t)jj * K * npix + pq, npix, K, c, gi, gw);
+    level0_eval<KM>(cnt, K, c, gi, gw);
     if (weights_out) {
 #pragma unroll
         for (int kk = 0; kk < KM; ++kk)
@@ -263,18 +316,18 @@ k_fuse_final(const uint16_t* __restrict__ raw, int K, int H, int W, size_t total
         out[i] = F;
         return;
     }
-    const int h1 = H >> 1, w1 = W >> 1;
-    const size_t n1 = (total / npix) * (size_t)h1 * w1;  // level-1 pixels of the chunk
 #pragma unroll
     for (int kk = 0; kk < KM; ++kk)
         if (kk < K) {
-            const float lap = gi[kk] - expand_at(GI1 + (size_t)kk * n1 + (size_t)jj * h1 * w1, h1, w1, y, x);
+            const float up = BATCH ? expand_sum(e, ev[BATCH ? kk : 0])
+                                   : expand_at(GI1 + (size_t)kk * n1 + (size_t)jj * h1 * w1, h1, w1, y, x);
+            const float lap = gi[kk] - up;
             float v = gw[kk] * lap;
             const float st = q.step[kk];
             if (st > 0.f) v = st * rintf(v / st);
             F = kk == 0 ? v : F + v;
         }
-    out[i] = F + expand_at(R1 + (size_t)jj * h1 * w1, h1, w1, y, x);
+    out[i] = F + (BATCH ? expand_sum(e, rv) : expand_at(R1 + (size_t)jj * h1 * w1, h1, w1, y, x));
 }
 
 inline dim3 grid1d(size_t n) { return dim3((unsigned)((n + 255) / 256)); }

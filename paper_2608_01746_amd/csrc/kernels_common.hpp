@@ -39,6 +39,7 @@ struct ColCfg {
 template <class T>
 using gptr = const __attribute__((address_space(1))) T*;
 __device__ __forceinline__ float ldg(const float* p, size_t i) { return ((gptr<float>)p)[i]; }
+__device__ __forceinline__ double ldg(const double* p, size_t i) { return ((gptr<double>)p)[i]; }
 __device__ __forceinline__ float2 ldg(const float2* p, size_t i) {
     typedef float v2 __attribute__((ext_vector_type(2)));
     const v2 v = ((gptr<v2>)p)[i];

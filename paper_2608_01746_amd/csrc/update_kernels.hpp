@@ -233,8 +233,16 @@ __global__ void __launch_bounds__(256)
 k_sum_jobs(const SumJob* __restrict__ jobs, double scale) {
     __shared__ double red[4];
     const SumJob jb = jobs[blockIdx.x];
+    // a thread's terms in index order, loaded eight at a time (index clamped)
     double a = 0.0;
-    for (size_t i = threadIdx.x; i < jb.n; i += 256) a += jb.in[i];
+    for (size_t i0 = threadIdx.x; i0 < jb.n; i0 += 8 * 256) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = ldg(jb.in, min(i0 + (size_t)u * 256, jb.n - 1));
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + (size_t)u * 256 < jb.n) a += v[u];
+    }
     a = block_sum(a, red);
     if (threadIdx.x == 0 && jb.out) {
         double r = a * scale;
@@ -249,7 +257,14 @@ k_sum_amplitude2(const float* __restrict__ I, size_t npix, double* __restrict__ 
     __shared__ double red[4];
     const float* Ij = I + (size_t)blockIdx.x * npix;
     double a = 0.0;
-    for (size_t i = threadIdx.x; i < npix; i += 256) a += (double)fmaxf(Ij[i], 0.f);
+    for (size_t i0 = threadIdx.x; i0 < npix; i0 += 8 * 256) {
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = Ij[min(i0 + (size_t)u * 256, npix - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            if (i0 + (size_t)u * 256 < npix) a += (double)fmaxf(v[u], 0.f);
+    }
     a = block_sum(a, red);
     if (threadIdx.x == 0) part[blockIdx.x] = a;
 }
