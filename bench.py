@@ -421,7 +421,8 @@ def run_multiscan(args, api, synth, dev):
         "config": {"workload": "multiscan: 64 scans, N in {128,192,256,384,512}, 50-1000 Fermat-spiral "
                                "positions, rPIE B=32, %d iterations" % n_iter,
                    "scans": len(ws), "positions": total_J, "iterations": n_iter},
-        "roofline": dict(roofline(dominant, nlaunch, kms, per_launch, Nbar, 32),
+        # the stored counters describe the lab-256 launches, not these
+        "roofline": dict(roofline(dominant, nlaunch, kms, per_launch, Nbar, 32, counters=False),
                          note="per-launch events from one step with direct launches; N = rms pattern size"),
         "per_class_ms_direct_step": {k: round(v[1], 3) for k, v in ranks.items()},
         "launch_variants": tuned,
