@@ -136,12 +136,103 @@ k_fuse_level1(const uint16_t* __restrict__ raw, int K, int H, int W, size_t tota
         }
 }
 
-// G_{l+1} = D(G_l * w_G) for the image and the weight pyramids together.
+// Level 1 as above with each level-0 value evaluated once: a block owns a
+// kL1TY x kL1TX tile of level-1 pixels of one pattern, evaluates level 0 of
+// all K exposures over the tile's (2 kL1TY + 3) x (2 kL1TX + 3) footprint into
+// LDS (reflected coordinates, clamped into the image beyond the single
+// reflection that only pixels past the edge would need), then reduces from
+// LDS with the taps in the untiled kernel's order, so the results are the
+// same.  grid (tiles_x * tiles_y * nj), 256 threads; K <= KM.
+constexpr int kL1TY = 8, kL1TX = 32;
+constexpr int kL1RY = 2 * kL1TY + 3, kL1RX = 2 * kL1TX + 3, kL1R = kL1RY * kL1RX;
+
+template <int KM>
+__global__ void __launch_bounds__(kL1TY * kL1TX)
+k_fuse_level1_tiled(const uint16_t* __restrict__ raw, int K, int H, int W, size_t total, FuseConsts c,
+                    float* __restrict__ GI1, float* __restrict__ GW1) {
+    constexpr int THREADS = kL1TY * kL1TX, PER = (kL1R + THREADS - 1) / THREADS;
+    __shared__ float LI[KM * kL1R], LW[KM * kL1R];
+    const int h1 = H >> 1, w1 = W >> 1;
+    const int tiles_x = (w1 + kL1TX - 1) / kL1TX, tiles_y = (h1 + kL1TY - 1) / kL1TY;
+    const int b = blockIdx.x;
+    const int jj = b / (tiles_x * tiles_y);
+    const int tb = b - jj * (tiles_x * tiles_y);
+    const int oy0 = (tb / tiles_x) * kL1TY, ox0 = (tb % tiles_x) * kL1TX;
+    const int y0 = 2 * oy0 - 2, x0 = 2 * ox0 - 2;
+    const size_t npix = (size_t)H * W;
+    const uint16_t* base = raw + (size_t)jj * K * npix;
+    float cnt[PER][KM];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int p = min((int)threadIdx.x + u * THREADS, kL1R - 1);
+        const int ry = p / kL1RX, rx = p - ry * kL1RX;
+        const int yy = min(max(reflect101(y0 + ry, H), 0), H - 1);
+        const int xx = min(max(reflect101(x0 + rx, W), 0), W - 1);
+        level0_load<KM>(base + (size_t)yy * W + xx, npix, K, cnt[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int p = (int)threadIdx.x + u * THREADS;
+        if (p < kL1R) {
+            float gi[KM], gw[KM];
+            level0_eval<KM>(cnt[u], K, c, gi, gw);
+#pragma unroll
+            for (int kk = 0; kk < KM; ++kk)
+                if (kk < K) {
+                    LI[kk * kL1R + p] = gi[kk];
+                    LW[kk * kL1R + p] = gw[kk];
+                }
+        }
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / kL1TX, tx = threadIdx.x % kL1TX;
+    const int oy = oy0 + ty, ox = ox0 + tx;
+    if (oy >= h1 || ox >= w1) return;
+    float si[KM], sw[KM];
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) si[kk] = sw[kk] = 0.f;
+#pragma unroll
+    for (int a = 0; a < 5; ++a) {
+        float ri[KM], rw[KM];
+#pragma unroll
+        for (int kk = 0; kk < KM; ++kk) ri[kk] = rw[kk] = 0.f;
+#pragma unroll
+        for (int bb = 0; bb < 5; ++bb) {
+            const int p = (2 * ty + a) * kL1RX + 2 * tx + bb;
+#pragma unroll
+            for (int kk = 0; kk < KM; ++kk)
+                if (kk < K) {
+                    ri[kk] += binom5(bb) * LI[kk * kL1R + p];
+                    rw[kk] += binom5(bb) * LW[kk * kL1R + p];
+                }
+        }
+#pragma unroll
+        for (int kk = 0; kk < KM; ++kk) {
+            si[kk] += binom5(a) * ri[kk];
+            sw[kk] += binom5(a) * rw[kk];
+        }
+    }
+    const size_t i = (size_t)jj * h1 * w1 + (size_t)oy * w1 + ox;
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk)
+        if (kk < K) {
+            GI1[(size_t)kk * total + i] = si[kk];
+            GW1[(size_t)kk * total + i] = sw[kk];
+        }
+}
+
+// G_{l+1} = D(G_l * w_G) for the image and the weight pyramids together, for
+// every exposure at once: blockIdx.y is the exposure, whose level-l arrays
+// start at k * in_stride and level-(l+1) arrays at k * out_stride.
 __global__ void __launch_bounds__(256)
-k_fuse_reduce(const float* __restrict__ GI, const float* __restrict__ GW, int h, int w, size_t total,
-              float* __restrict__ GI1, float* __restrict__ GW1) {
+k_fuse_reduce(const float* __restrict__ GI, const float* __restrict__ GW, size_t in_stride, int h, int w,
+              size_t total, float* __restrict__ GI1, float* __restrict__ GW1, size_t out_stride) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
+    GI += blockIdx.y * in_stride;
+    GW += blockIdx.y * in_stride;
+    GI1 += blockIdx.y * out_stride;
+    GW1 += blockIdx.y * out_stride;
     const int h2 = h >> 1, w2 = w >> 1;
     const size_t jj = i / ((size_t)h2 * w2);
     const int r = (int)(i % ((size_t)h2 * w2));
@@ -228,26 +319,66 @@ __device__ __forceinline__ float expand_at(const float* __restrict__ g, int hc, 
     return expand_sum(e, v);
 }
 
-// Band level l < L: F_l (+)= Q(G_l[W] (G_l[I] - U(G_{l+1}[I]))); base l = L:
-// F_L (+)= G_L[W] G_L[I].  `first` starts the sum over exposures.
+// Band level l < L: F_l = sum_k Q_k(G_l[W_k] (G_l[I_k] - U(G_{l+1}[I_k])));
+// base l = L: F_L = sum_k G_L[W_k] G_L[I_k].  Every exposure in one thread,
+// summed in exposure order; exposure k's level-l arrays start at k * stride,
+// its level-(l+1) image at k * stride_c.  The loads of four exposures are
+// issued before their terms are formed.
+struct BandSteps {
+    float step[kMaxK];  // quantisation step of each exposure at this level (0 = none)
+};
+
 __global__ void __launch_bounds__(256)
-k_fuse_band(const float* __restrict__ GI, const float* __restrict__ GW, const float* __restrict__ GIc,
-            int h, int w, size_t total, float step, int base, int first, float* __restrict__ F) {
+k_fuse_band(const float* __restrict__ GI, const float* __restrict__ GW, size_t stride,
+            const float* __restrict__ GIc, size_t stride_c, int K, int h, int w, size_t total, BandSteps q,
+            int base, float* __restrict__ F) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
-    float v;
+    constexpr int G = 4;
+    float acc = 0.f;
     if (base) {
-        v = GW[i] * GI[i];
+        for (int k0 = 0; k0 < K; k0 += G) {
+            float vi[G], vw[G];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const size_t o = (size_t)min(k0 + u, K - 1) * stride + i;
+                vi[u] = GI[o];
+                vw[u] = GW[o];
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+                if (k0 + u < K) {
+                    const float v = vw[u] * vi[u];
+                    acc = k0 + u == 0 ? v : acc + v;
+                }
+        }
     } else {
         const size_t jj = i / ((size_t)h * w);
         const int r = (int)(i % ((size_t)h * w));
         const int y = r / w, x = r % w;
         const int hc = h >> 1, wc = w >> 1;
-        const float lap = GI[i] - expand_at(GIc + jj * (size_t)hc * wc, hc, wc, y, x);
-        v = GW[i] * lap;
-        if (step > 0.f) v = step * rintf(v / step);
+        const ExpandTaps e = expand_taps(hc, wc, y, x);
+        for (int k0 = 0; k0 < K; k0 += G) {
+            float vi[G], vw[G], ev[G][9];
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                const int k = min(k0 + u, K - 1);
+                vi[u] = GI[(size_t)k * stride + i];
+                vw[u] = GW[(size_t)k * stride + i];
+                expand_load(GIc + (size_t)k * stride_c + jj * (size_t)hc * wc, wc, e, ev[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < G; ++u)
+                if (k0 + u < K) {
+                    const float lap = vi[u] - expand_sum(e, ev[u]);
+                    float v = vw[u] * lap;
+                    const float st = q.step[k0 + u];
+                    if (st > 0.f) v = st * rintf(v / st);
+                    acc = k0 + u == 0 ? v : acc + v;
+                }
+        }
     }
-    F[i] = first ? v : F[i] + v;
+    F[i] = acc;
 }
 
 // Collapse step: R_l = U(R_{l+1}) + F_l, written to out (F_l in place, or the
@@ -402,13 +533,13 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
 
     const size_t npix_all = (size_t)H * W;
     if (npix_all > (size_t)(INT32_MAX / 2)) return set_error(ctx, MNF_EUNSUPPORTED, "pattern of %d x %d too large", H, W);
-    // per-position scratch (floats): level 1 of all K image and weight
-    // pyramids, levels 2..L of one exposure's pyramids, fused levels 1..L
+    // per-position scratch (floats): levels 1..L of all K image and weight
+    // pyramids (level 1 in GI1 / GW1, levels 2..L in SI / SW), fused levels 1..L
     std::vector<size_t> offF(L + 2, 0), offS(L + 2, 0);
     for (int l = 1; l <= L; ++l) offF[l + 1] = offF[l] + (size_t)(H >> l) * (W >> l);
     for (int l = 2; l <= L; ++l) offS[l + 1] = offS[l] + (size_t)(H >> l) * (W >> l);
     const size_t n1pos = L >= 1 ? (size_t)(H >> 1) * (W >> 1) : 0;
-    const size_t per_pos = 2 * (size_t)K * n1pos + 2 * offS[L + 1] + offF[L + 1];
+    const size_t per_pos = 2 * (size_t)K * n1pos + 2 * (size_t)K * offS[L + 1] + offF[L + 1];
     const size_t budget = (size_t)1 << 30;
     size_t chunk_cap = per_pos == 0 ? (size_t)J : budget / (per_pos * sizeof(float));
     chunk_cap = std::min(chunk_cap, (size_t)(INT32_MAX / 2) / npix_all);  // 32-bit pixel indices in a chunk
@@ -418,8 +549,8 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
         void *a1, *a2, *a3, *a4, *a5;
         MNF_TRY(scratch(ctx, "fuseGI1", (size_t)chunk * K * n1pos * sizeof(float), &a1));
         MNF_TRY(scratch(ctx, "fuseGW1", (size_t)chunk * K * n1pos * sizeof(float), &a2));
-        MNF_TRY(scratch(ctx, "fuseSI", std::max<size_t>(1, (size_t)chunk * offS[L + 1]) * sizeof(float), &a3));
-        MNF_TRY(scratch(ctx, "fuseSW", std::max<size_t>(1, (size_t)chunk * offS[L + 1]) * sizeof(float), &a4));
+        MNF_TRY(scratch(ctx, "fuseSI", std::max<size_t>(1, (size_t)chunk * K * offS[L + 1]) * sizeof(float), &a3));
+        MNF_TRY(scratch(ctx, "fuseSW", std::max<size_t>(1, (size_t)chunk * K * offS[L + 1]) * sizeof(float), &a4));
         MNF_TRY(scratch(ctx, "fuseF", (size_t)chunk * offF[L + 1] * sizeof(float), &a5));
         GI1 = (float*)a1;
         GW1 = (float*)a2;
@@ -437,30 +568,35 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
         const uint16_t* rawc = raw + (size_t)j0 * K * npix;
         const size_t n1 = (size_t)nj * n1pos;
         if (L >= 1) {
-            if (small_k)
+            if (K <= 5) {
+                const size_t tiles = (size_t)((W / 2 + kL1TX - 1) / kL1TX) * ((H / 2 + kL1TY - 1) / kL1TY) * nj;
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level1_tiled<5>, dim3((unsigned)tiles), dim3(kL1TY * kL1TX),
+                           rawc, K, H, W, n1, c, GI1, GW1);
+            } else if (small_k)
                 MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level1<8>, grid1d(n1), dim3(256), rawc, K, H, W, n1, c, GI1, GW1);
             else
                 MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level1<kMaxK>, grid1d(n1), dim3(256), rawc, K, H, W, n1, c, GI1,
                            GW1);
-            // level-l arrays (l >= 1) of exposure k and of the fused pyramid
-            auto lvlI = [&](int k, int l) { return l == 1 ? GI1 + (size_t)k * n1 : SI + (size_t)nj * offS[l]; };
-            auto lvlW = [&](int k, int l) { return l == 1 ? GW1 + (size_t)k * n1 : SW + (size_t)nj * offS[l]; };
+            // level-l arrays (l >= 1) of exposure k and of the fused pyramid;
+            // exposure k's arrays of level l sit at k * sstride(l) from exposure 0's
+            const size_t sS = (size_t)nj * offS[L + 1];
+            auto lvlI = [&](int l) { return l == 1 ? GI1 : SI + (size_t)nj * offS[l]; };
+            auto lvlW = [&](int l) { return l == 1 ? GW1 : SW + (size_t)nj * offS[l]; };
+            auto sstride = [&](int l) { return l == 1 ? n1 : sS; };
             auto lvlF = [&](int l) { return F + (size_t)nj * offF[l]; };
-            for (int k = 0; k < K; ++k) {
-                for (int l = 1; l < L; ++l) {
-                    const int h = H >> l, w = W >> l;
-                    const size_t nn = (size_t)nj * (h >> 1) * (w >> 1);
-                    MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_reduce, grid1d(nn), dim3(256), lvlI(k, l), lvlW(k, l), h, w,
-                               nn, lvlI(k, l + 1), lvlW(k, l + 1));
-                }
-                for (int l = 1; l <= L; ++l) {
-                    const int h = H >> l, w = W >> l;
-                    const size_t nn = (size_t)nj * h * w;
-                    const float sl = l < L ? step[(size_t)l * K + k] : 0.f;
-                    MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_band, grid1d(nn), dim3(256), lvlI(k, l), lvlW(k, l),
-                               l < L ? lvlI(k, l + 1) : (const float*)nullptr, h, w, nn, sl, l == L ? 1 : 0,
-                               k == 0 ? 1 : 0, lvlF(l));
-                }
+            for (int l = 1; l < L; ++l) {
+                const int h = H >> l, w = W >> l;
+                const size_t nn = (size_t)nj * (h >> 1) * (w >> 1);
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_reduce, dim3(grid1d(nn).x, K), dim3(256), lvlI(l), lvlW(l),
+                           sstride(l), h, w, nn, lvlI(l + 1), lvlW(l + 1), sS);
+            }
+            for (int l = 1; l <= L; ++l) {
+                const int h = H >> l, w = W >> l;
+                const size_t nn = (size_t)nj * h * w;
+                BandSteps bs{};
+                for (int k = 0; k < K; ++k) bs.step[k] = l < L ? step[(size_t)l * K + k] : 0.f;
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_band, grid1d(nn), dim3(256), lvlI(l), lvlW(l), sstride(l),
+                           l < L ? lvlI(l + 1) : (const float*)nullptr, sS, K, h, w, nn, bs, l == L ? 1 : 0, lvlF(l));
             }
             for (int l = L - 1; l >= 1; --l) {
                 const int h = H >> l, w = W >> l;

@@ -69,7 +69,12 @@ def test_forward_model_matches_oracle(api, Nd, Nw, M):
 # ----------------------------------------------------------------- fusion
 
 @pytest.mark.parametrize("H,W,K,L,J", [(64, 64, 3, 4, 7), (256, 256, 5, 6, 3), (48, 80, 2, 3, 4),
-                                       (32, 32, 1, 0, 2), (128, 64, 4, 5, 3)])
+                                       (32, 32, 1, 0, 2), (128, 64, 4, 5, 3),
+                                       # level-1 tiles cut by the edge in both axes; a pattern
+                                       # smaller than one tile's footprint
+                                       (20, 44, 5, 2, 3), (8, 8, 3, 1, 2),
+                                       # more exposures than the tiled level-1 kernel takes
+                                       (32, 48, 7, 3, 2), (32, 32, 10, 2, 2)])
 def test_fusion_without_quantisation_matches_oracle(api, H, W, K, L, J):
     rng = np.random.default_rng(H * W + K)
     t = [3.0 ** k for k in range(K)]
