@@ -4,11 +4,13 @@
 // normalised over the K frames) are pointwise functions of the K raw counts
 // of a pixel, cheaper to recompute from the 2-byte counts than to write and
 // re-read as 4-byte pyramids:
-//   1. k_fuse_level1: level 1 of every exposure's image and weight pyramid
-//      straight from the raw counts (reduce of the recomputed level 0);
-//   2. per exposure, levels 2..L by reduce, and the modulated, quantised
-//      band-pass coefficients of levels 1..L-1 plus the weighted base of
-//      level L accumulated over exposures into one fused pyramid F_l;
+//   1. k_fuse_level1_tiled (K <= 5; k_fuse_level1 beyond): level 1 of every
+//      exposure's image and weight pyramid straight from the raw counts
+//      (reduce of the recomputed level 0);
+//   2. levels 2..L of every exposure by reduce (one launch per level), and
+//      the modulated, quantised band-pass coefficients of levels 1..L-1
+//      plus the weighted base of level L summed over exposures, in exposure
+//      order, into one fused pyramid F_l (one launch per level);
 //   3. collapse of F down to level 1;
 //   4. k_fuse_final: per level-0 pixel, the level-0 coefficients of all
 //      exposures (recomputed level 0 minus the expanded level 1), quantised
