@@ -170,7 +170,10 @@ def test_small_workload_one_iteration(api, alg, B, upd):
 @pytest.mark.parametrize("Nd,Nw,M,n_side,step,B", [(256, 256, 384, 3, 48, 4), (128, 128, 200, 4, 20, 5),
                                                    (192, 192, 260, 3, 30, 4), (256, 64, 120, 4, 16, 5),
                                                    (512, 512, 600, 2, 60, 3), (384, 384, 440, 2, 40, 3),
-                                                   (16, 12, 40, 5, 6, 8), (32, 32, 60, 3, 12, 16)])
+                                                   (16, 12, 40, 5, 6, 8), (32, 32, 60, 3, 12, 16),
+                                                   # mini-batches longer than one round of the inverse
+                                                   # row pass (8 lines per block at 512, 16 at 384)
+                                                   (512, 512, 600, 3, 40, 9), (384, 384, 440, 5, 12, 17)])
 def test_sizes_one_iteration(api, Nd, Nw, M, n_side, step, B):
     O, P, pos, I = tiny_scan(M, Nw, Nd, n_side, step, 2, seed=Nd + Nw, jitter=1)
     O0 = c64(np.ones_like(O))
