@@ -29,10 +29,13 @@ __device__ __forceinline__ int find_group(const GroupDev* __restrict__ groups, i
 
 // Ordered list (in slot order) of the group's windows overlapping the tile
 // [ty0, ty0 + kObjTileY) x [tx0, tx0 + kObjTileX).  Wave 0 builds it with
-// ballots; every thread returns the count.
+// ballots; every thread returns the count.  `before_barrier` runs in every
+// thread after wave 0's loads are issued and before the barrier that
+// publishes the list, so LDS values it writes are published with it.
+template <class F>
 __device__ __forceinline__ int tile_window_list(const SlotDev* __restrict__ slots, const GroupDev& gd,
                                                 int Nw, int ty0, int tx0, int* l_slot, int* l_py,
-                                                int* l_px) {
+                                                int* l_px, F&& before_barrier) {
     __shared__ int count;
     if (threadIdx.x < 64) {
         int cnt = 0;
@@ -57,8 +60,15 @@ __device__ __forceinline__ int tile_window_list(const SlotDev* __restrict__ slot
         }
         if (threadIdx.x == 0) count = cnt;
     }
+    before_barrier();
     __syncthreads();
     return count;
+}
+
+__device__ __forceinline__ int tile_window_list(const SlotDev* __restrict__ slots, const GroupDev& gd,
+                                                int Nw, int ty0, int tx0, int* l_slot, int* l_py,
+                                                int* l_px) {
+    return tile_window_list(slots, gd, Nw, ty0, tx0, l_slot, l_py, l_px, [] {});
 }
 
 // O[x] += sum_s W_s(u_s) / sum_s d_O(u_s),  u_s = x - p_s, over the windows
@@ -80,11 +90,22 @@ k_object_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ s
     const int tile = blockIdx.x - gd.tile0;
     const int ty0 = sc.by0 + (tile / sc.tiles_x) * kObjTileY;
     const int tx0 = sc.bx0 + (tile % sc.tiles_x) * kObjTileX;
-    const int cnt = tile_window_list(slots, gd, Nw, ty0, tx0, l_slot, l_py, l_px);
+    // The probe's row maxima (Nw <= 512: two per thread) are loaded with the
+    // slot table and reduced per wave before the window list's barrier,
+    // which also publishes the wave maxima.
+    static_assert(2 * kObjThreads >= 512, "two row maxima per thread cover the largest probe");
+    const int i0 = (int)threadIdx.x, i1 = i0 + kObjThreads;
+    const float v0 = ldg(sc.maxP2_row, min(i0, Nw - 1));
+    const float v1 = ldg(sc.maxP2_row, min(i1, Nw - 1));
+    const int cnt = tile_window_list(slots, gd, Nw, ty0, tx0, l_slot, l_py, l_px, [&] {
+        float m = fmaxf(0.f, i0 < Nw ? v0 : 0.f);
+        m = wave_max(fmaxf(m, i1 < Nw ? v1 : 0.f));
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    });
     if (cnt == 0) return;
-    float mp = 0.f;
-    for (int i = threadIdx.x; i < Nw; i += kObjThreads) mp = fmaxf(mp, ldg(sc.maxP2_row, i));
-    mp = block_max(mp, red);
+    float mp = red[0];
+#pragma unroll
+    for (int w = 1; w < kObjThreads / 64; ++w) mp = fmaxf(mp, red[w]);
     const int xx = tx0 + (threadIdx.x % kObjTileX);
     const int yb = ty0 + (threadIdx.x / kObjTileX) * kObjRows;
     const float a = rpie ? 1.f - alpha : 0.f;
