@@ -80,20 +80,22 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Block-wide max / sum in a fixed order (waves combined in index order).
 // `red` must hold blockDim.x / 64 elements.  Result valid in every thread.
-__device__ __forceinline__ float block_max(float v, float* red) {
+// `reuse`: `red` was read earlier in the block, so a leading barrier keeps
+// those reads ahead of the new writes; a block's first use needs none.
+__device__ __forceinline__ float block_max(float v, float* red, bool reuse = true) {
     v = wave_max(v);
     const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-    __syncthreads();
+    if (reuse) __syncthreads();
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
     float r = red[0];
     for (int i = 1; i < nw; ++i) r = fmaxf(r, red[i]);
     return r;
 }
-__device__ __forceinline__ double block_sum(double v, double* red) {
+__device__ __forceinline__ double block_sum(double v, double* red, bool reuse = true) {
     v = wave_sum(v);
     const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-    __syncthreads();
+    if (reuse) __syncthreads();
     if ((threadIdx.x & 63) == 0) red[w] = v;
     __syncthreads();
     double r = red[0];

@@ -99,7 +99,7 @@ k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
         for (int idx = 0; idx < V; ++idx) row[out_pos<N, false>(t, idx)] = x[idx];
     }
     if (maxO2_part) {
-        mO = block_max(mO, red);
+        mO = block_max(mO, red, false);
         if (threadIdx.x == 0) maxO2_part[(size_t)s * gridDim.x + blockIdx.x] = mO;
     }
 }
@@ -195,7 +195,7 @@ k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
         const int y = out_pos<N, true>(t, idx);
         if (y < Nw) col[(size_t)y * N] = x[idx];  // the 1/N of the unitary inverse is applied by the row pass
     }
-    acc = block_sum(acc, red);
+    acc = block_sum(acc, red, false);
     if (threadIdx.x == 0) sc.err_part[(size_t)sd.j * gridDim.x + blockIdx.x] = acc;
 }
 
@@ -313,7 +313,7 @@ k_cols_modulus_modes(const ScanDev* __restrict__ scans, const SlotDev* __restric
         }
         __syncthreads();
     }
-    const double acc = block_sum((double)accf, red);
+    const double acc = block_sum((double)accf, red, false);
     if (threadIdx.x == 0) sc.err_part[(size_t)sd.j * gridDim.x + blockIdx.x] = acc;
 }
 
@@ -621,7 +621,7 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
         }
     }
     if constexpr (MODE != 2) {
-        pmax = block_max(pmax, red);
+        pmax = block_max(pmax, red, false);
         if (threadIdx.x == 0) sc.maxP2_row[r] = pmax;
     }
 }
