@@ -89,6 +89,25 @@ def test_fusion_without_quantisation_matches_oracle(api, H, W, K, L, J):
     np.testing.assert_allclose(wts.sum(1).cpu().numpy(), 1.0, atol=2e-6)
 
 
+@pytest.mark.parametrize("K,radiometric", [(5, False), (7, False), (4, True)])
+def test_fusion_parameters_match_oracle(api, K, radiometric):
+    # a dark level, a weight centre and width off the defaults, both readings of
+    # the fused quantity; level-1 tiles cut by the pattern edge in both axes;
+    # five exposures take the tiled level-1 kernel, seven the untiled one
+    rng = np.random.default_rng(40 + K)
+    H, W, L, J, dark = 40, 24, 3, 3, 12.0
+    t = [2.0 ** k for k in range(K)]
+    base = rng.gamma(0.8, 300.0, size=(J, 1, H, W))
+    raw = np.clip(rng.poisson(base * np.array(t)[None, :, None, None]) + dark, 0, 4095).astype(np.uint16)
+    p = mnf.FuseParams(levels=L, mu=0.4, sigma=0.3, sat=4095.0, dark=dark, radiometric=radiometric)
+    ref = mnf.fuse(raw, t, p)
+    Wref = mnf.weights(raw, p)
+    out, wts = api.fuse_exposures(torch.from_numpy(raw).to(DEV), t, L, mu=0.4, sigma=0.3, sat=4095.0, dark=dark,
+                                  radiometric=radiometric, return_weights=True)
+    assert rel(out.cpu().numpy(), ref) < 1e-5
+    assert rel(wts.cpu().numpy(), Wref) < 1e-6
+
+
 def test_fusion_identical_exposures_returns_input(api):
     rng = np.random.default_rng(5)
     img = rng.integers(0, 4096, size=(3, 64, 96)).astype(np.uint16)
