@@ -225,39 +225,66 @@ k_fuse_level1_tiled(const uint16_t* __restrict__ raw, int K, int H, int W, size_
 
 // G_{l+1} = D(G_l * w_G) for the image and the weight pyramids together, for
 // every exposure at once: blockIdx.y is the exposure, whose level-l arrays
-// start at k * in_stride and level-(l+1) arrays at k * out_stride.
-__global__ void __launch_bounds__(256)
+// start at k * in_stride and level-(l+1) arrays at k * out_stride.  A block
+// owns a kL1TY x kL1TX tile of level-(l+1) pixels of one pattern, stages the
+// tile's footprint of both level-l arrays in LDS (reflected coordinates,
+// clamped into the level beyond the single reflection that only pixels past
+// the edge would need) and reduces from LDS with the taps in row-then-column
+// order, so each level-l value is read from memory once.
+// grid (tiles_x * tiles_y * nj, K), kL1TY * kL1TX threads.
+__global__ void __launch_bounds__(kL1TY * kL1TX)
 k_fuse_reduce(const float* __restrict__ GI, const float* __restrict__ GW, size_t in_stride, int h, int w,
-              size_t total, float* __restrict__ GI1, float* __restrict__ GW1, size_t out_stride) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    GI += blockIdx.y * in_stride;
-    GW += blockIdx.y * in_stride;
-    GI1 += blockIdx.y * out_stride;
-    GW1 += blockIdx.y * out_stride;
+              float* __restrict__ GI1, float* __restrict__ GW1, size_t out_stride) {
+    constexpr int THREADS = kL1TY * kL1TX, PER = (kL1R + THREADS - 1) / THREADS;
+    __shared__ float LI[kL1R], LW[kL1R];
     const int h2 = h >> 1, w2 = w >> 1;
-    const size_t jj = i / ((size_t)h2 * w2);
-    const int r = (int)(i % ((size_t)h2 * w2));
-    const int oy = r / w2, ox = r % w2;
+    const int tiles_x = (w2 + kL1TX - 1) / kL1TX, tiles_y = (h2 + kL1TY - 1) / kL1TY;
+    const int b = blockIdx.x;
+    const int jj = b / (tiles_x * tiles_y);
+    const int tb = b - jj * (tiles_x * tiles_y);
+    const int oy0 = (tb / tiles_x) * kL1TY, ox0 = (tb % tiles_x) * kL1TX;
+    const int y0 = 2 * oy0 - 2, x0 = 2 * ox0 - 2;
+    const float* gi = GI + blockIdx.y * in_stride + (size_t)jj * h * w;
+    const float* gw = GW + blockIdx.y * in_stride + (size_t)jj * h * w;
+    float vi[PER], vw[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int p = min((int)threadIdx.x + u * THREADS, kL1R - 1);
+        const int ry = p / kL1RX, rx = p - ry * kL1RX;
+        const int yy = min(max(reflect101(y0 + ry, h), 0), h - 1);
+        const int xx = min(max(reflect101(x0 + rx, w), 0), w - 1);
+        vi[u] = gi[(size_t)yy * w + xx];
+        vw[u] = gw[(size_t)yy * w + xx];
+    }
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int p = (int)threadIdx.x + u * THREADS;
+        if (p < kL1R) {
+            LI[p] = vi[u];
+            LW[p] = vw[u];
+        }
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / kL1TX, tx = threadIdx.x % kL1TX;
+    const int oy = oy0 + ty, ox = ox0 + tx;
+    if (oy >= h2 || ox >= w2) return;
     const float wt[5] = {0.0625f, 0.25f, 0.375f, 0.25f, 0.0625f};
-    const float* gi = GI + jj * (size_t)h * w;
-    const float* gw = GW + jj * (size_t)h * w;
     float si = 0.f, sw = 0.f;
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
-        const int yy = reflect101(2 * oy + a - 2, h);
         float ri = 0.f, rw = 0.f;
 #pragma unroll
-        for (int b = 0; b < 5; ++b) {
-            const int xx = reflect101(2 * ox + b - 2, w);
-            ri += wt[b] * gi[(size_t)yy * w + xx];
-            rw += wt[b] * gw[(size_t)yy * w + xx];
+        for (int bb = 0; bb < 5; ++bb) {
+            const int p = (2 * ty + a) * kL1RX + 2 * tx + bb;
+            ri += wt[bb] * LI[p];
+            rw += wt[bb] * LW[p];
         }
         si += wt[a] * ri;
         sw += wt[a] * rw;
     }
-    GI1[i] = si;
-    GW1[i] = sw;
+    const size_t o = blockIdx.y * out_stride + (size_t)jj * h2 * w2 + (size_t)oy * w2 + ox;
+    GI1[o] = si;
+    GW1[o] = sw;
 }
 
 // Expand of a coarse image g (hc x wc) evaluated at fine pixel (y, x),
@@ -588,9 +615,9 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
             auto lvlF = [&](int l) { return F + (size_t)nj * offF[l]; };
             for (int l = 1; l < L; ++l) {
                 const int h = H >> l, w = W >> l;
-                const size_t nn = (size_t)nj * (h >> 1) * (w >> 1);
-                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_reduce, dim3(grid1d(nn).x, K), dim3(256), lvlI(l), lvlW(l),
-                           sstride(l), h, w, nn, lvlI(l + 1), lvlW(l + 1), sS);
+                const size_t tiles = (size_t)((w / 2 + kL1TX - 1) / kL1TX) * ((h / 2 + kL1TY - 1) / kL1TY) * nj;
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_reduce, dim3((unsigned)tiles, K), dim3(kL1TY * kL1TX), lvlI(l),
+                           lvlW(l), sstride(l), h, w, lvlI(l + 1), lvlW(l + 1), sS);
             }
             for (int l = 1; l <= L; ++l) {
                 const int h = H >> l, w = W >> l;
