@@ -7,7 +7,7 @@
 //   1. k_fuse_level1_tiled (K <= 5; k_fuse_level1 beyond): level 1 of every
 //      exposure's image and weight pyramid straight from the raw counts
 //      (reduce of the recomputed level 0);
-//   2. levels 2..L of every exposure by reduce (one launch per level), and
+//   2. levels 2..L of every exposure by LDS-tiled reduce (one launch per level), and
 //      the modulated, quantised band-pass coefficients of levels 1..L-1
 //      plus the weighted base of level L summed over exposures, in exposure
 //      order, into one fused pyramid F_l (one launch per level);
