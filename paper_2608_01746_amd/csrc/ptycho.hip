@@ -343,7 +343,16 @@ int issue_subpixel_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, con
     }
     MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, CV, ColOp::Modulus>),
                dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, S, 0.f, tw);
-    if (upd)
+    // With the probe updated, each round of the inverse row pass also runs the
+    // numerators' translation, so full-height row blocks are used whenever
+    // half-height ones would need more rounds (one scan: the group is the
+    // launch's slot list).
+    const bool full_rows = RV == 1 && L.nslots > UpdCfg<N, 1>::ULINES;
+    if (upd && full_rows)
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 0, 4>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N, 0>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
+                   Pd, sb.G, sb.DP, fused ? fr : (const float2*)nullptr, tw);
+    else if (upd)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 4>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
                    Pd, sb.G, sb.DP, fused ? fr : (const float2*)nullptr, tw);

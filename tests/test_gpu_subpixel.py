@@ -129,6 +129,27 @@ def test_iterations_match_oracle(api, Nd, Nw, M, J, alg, B, upd):
     np.testing.assert_allclose(eg, er, rtol=1e-5)
 
 
+@pytest.mark.parametrize("variant", [1, 3])
+def test_half_height_row_shapes_with_long_batches(api, variant):
+    # the launch shapes with half-height row blocks: batches of 20 exceed
+    # their 16 lines per block at 64^2, so the probe-updating inverse row pass
+    # runs with full-height blocks while the forward row pass keeps the shape
+    from paper_2608_01746_amd import tune
+    O, P, pos, I = scan(160, 64, 64, 40, 23)
+    O0 = c64(np.ones_like(O) * (0.9 + 0.1j))
+    P0 = c64(soft_probe(P, 2) * np.exp(0.1j))
+    prm = ptycho.PtychoParams("rpie", 0.2, 0.3, 20, True)
+    order = synth.random_orders(40, 2, 7)
+    tune.set_variant(64, variant)
+    try:
+        Og, Pg, eg, Or, Pr, er = one_iter(api, O0, P0, I, pos, prm, order, 2)
+    finally:
+        tune.set_variant(64, 0)
+    assert rel(Og, Or) < 1e-5
+    assert rel(Pg, Pr) < 1e-5
+    np.testing.assert_allclose(eg, er, rtol=1e-5)
+
+
 def test_probe_start_iteration_and_graph_replay(api):
     O, P, pos, I = scan(128, 64, 64, 12, 9)
     O0 = c64(np.ones_like(O))
