@@ -81,23 +81,82 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel: str):
-    """Counter-measured bytes per launch (fetch x 2.0 + write x 1.0) of `kernel`
-    from profiles/lab256_counters.txt, if taken with the current kernel sources."""
+RECON_PASSES = ("rows_fwd", "cols_modulus", "rows_inv", "object_update")
+
+
+def measured_traffic_all():
+    """Counter-measured bytes per launch (fetch x 2.0 + write x 1.0) of every
+    reconstruction pass from profiles/lab256_counters.txt, if taken with the
+    current kernel sources; {} otherwise."""
     path = os.path.join(ROOT, "profiles", "lab256_counters.txt")
     if not os.path.exists(path):
-        return None
+        return {}
     src_hash, rows = None, {}
     for line in open(path):
         parts = line.split()
         if len(parts) >= 2 and parts[0] == "source_hash":
             src_hash = parts[1]
-        elif len(parts) == 3 and parts[0] in ("rows_fwd", "cols_modulus", "rows_inv", "object_update"):
-            rows[parts[0]] = (float(parts[1]), float(parts[2]))
-    if src_hash != kernel_source_hash() or kernel not in rows:
-        return None
-    f, w = rows[kernel]
-    return (2.0 * f + w) * 1024.0
+        elif len(parts) == 3 and parts[0] in RECON_PASSES:
+            rows[parts[0]] = (2.0 * float(parts[1]) + float(parts[2])) * 1024.0
+    return rows if src_hash == kernel_source_hash() else {}
+
+
+def measured_traffic(kernel: str):
+    return measured_traffic_all().get(kernel)
+
+
+def host_cpu():
+    """(model name, usable host cores) of this machine."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return model, len(os.sched_getaffinity(0))
+
+
+def batch_update_all_cores(O, P, A, pos, idx, alpha, beta, update_probe, workers):
+    """The float64 rPIE mini-batch update of the oracle (same formulas, same
+    batch-start semantics), written batched so that every host core works:
+    the batch's exit waves are transformed together by scipy.fft with
+    `workers` threads.  A CPU throughput reference for the benchmark only;
+    its agreement with the oracle is tested."""
+    import numpy as np
+    import scipy.fft as sfft
+
+    Nw, Nd = P.shape[0], A.shape[-1]
+    idx = np.asarray(idx)
+    Oj = np.stack([O[y:y + Nw, x:x + Nw] for y, x in pos[idx]])
+    psi = np.zeros((len(idx), Nd, Nd), np.complex128)
+    psi[:, :Nw, :Nw] = P * Oj
+    Psi = sfft.fft2(psi, norm="ortho", workers=workers)
+    mag = np.abs(Psi)
+    Aj = A[idx]
+    err = float(np.sum((mag - Aj) ** 2))
+    nz = mag > 0
+    Psi_p = np.where(nz, Aj * Psi / np.where(nz, mag, 1.0), Aj)
+    dpsi = sfft.ifft2(Psi_p, norm="ortho", workers=workers)[:, :Nw, :Nw] - psi[:, :Nw, :Nw]
+    P2 = np.abs(P) ** 2
+    numO = np.zeros_like(O)
+    denO = np.zeros(O.shape)
+    dO = (1.0 - alpha) * P2 + alpha * float(P2.max())
+    for k, (y, x) in enumerate(pos[idx]):
+        numO[y:y + Nw, x:x + Nw] += np.conj(P) * dpsi[k]
+        denO[y:y + Nw, x:x + Nw] += dO
+    O_new = O.copy()
+    cov = denO > 0
+    O_new[cov] += numO[cov] / denO[cov]
+    P_new = P.copy()
+    if update_probe:
+        O2 = np.abs(Oj) ** 2
+        numP = np.sum(np.conj(Oj) * dpsi, axis=0)
+        denP = np.sum((1.0 - beta) * O2 + beta * O2.max(axis=(1, 2), keepdims=True), axis=0)
+        okp = denP > 0
+        P_new[okp] += numP[okp] / denP[okp]
+    return O_new, P_new, err
 
 
 def cpu_baseline(w, O_true, P, clean, scale, seconds: float, sub: bool = False):
@@ -126,6 +185,29 @@ def cpu_baseline(w, O_true, P, clean, scale, seconds: float, sub: bool = False):
     return n / dt, n, dt
 
 
+def cpu_baseline_all_cores(w, O_true, P, clean, scale, seconds: float):
+    """The batched float64 update on every usable host core (FFTs threaded),
+    repeated for about `seconds`; returns (position updates/s, n, s, cores)."""
+    import numpy as np
+    from oracle import ptycho
+
+    _, cores = host_cpu()
+    workers = min(cores, 16)
+    A = ptycho.amplitudes(clean * scale)
+    O = np.ones_like(O_true)
+    Pk = P * math.sqrt(scale)
+    order = np.random.default_rng(0).permutation(w.J)
+    n, b = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        idx = order[(b * w.batch) % w.J:][:w.batch]
+        O, Pk, _ = batch_update_all_cores(O, Pk, A, w.pos, idx, 0.1, 0.1, True, workers)
+        n += len(idx)
+        b += 1
+    dt = time.perf_counter() - t0
+    return n / dt, n, dt, workers
+
+
 def profile_dominant(api, run_step, classes):
     """Time one step with events around every launch of `classes`; return the
     dominant class and the per-class (launches, ms)."""
@@ -141,18 +223,31 @@ def profile_dominant(api, run_step, classes):
     return dominant, ranks
 
 
-def roofline(dominant, nlaunch, kms, positions_per_launch, N, B, counters=True):
+def roofline(dominant, nlaunch, kms, positions_per_launch, N, B, counters=True, updates_per_step=None,
+             ms_per_step=None):
     """`counters`: the stored counter readings describe this launch (the
-    integer-position lab workload)."""
+    integer-position lab workload).  With the step's updates and duration the
+    entry also carries pipeline_frac: the whole step's algorithmic bytes per
+    second (every pass, fusion and launch gaps included) against the HBM peak;
+    traffic_ratio: the reconstruction passes' counter-measured bytes per
+    mini-batch against the algorithmic bytes of that mini-batch."""
     avg_us = kms / nlaunch * 1e3
     bytes_launch = algo_bytes_per_update(N, B) * positions_per_launch
     achieved = bytes_launch / (avg_us * 1e-6) / 1e9
     traffic = measured_traffic(dominant) if counters else None
-    return {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None if traffic is None else round(traffic),
-            "avg_launch_us": round(avg_us, 2), "launches": nlaunch,
-            "algorithmic_bytes_per_launch": round(bytes_launch)}
+    out = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+           "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": None if traffic is None else round(traffic),
+           "avg_launch_us": round(avg_us, 2), "launches": nlaunch,
+           "algorithmic_bytes_per_launch": round(bytes_launch)}
+    if updates_per_step and ms_per_step:
+        gbs = algo_bytes_per_update(N, B) * updates_per_step / (ms_per_step * 1e-3) / 1e9
+        out["pipeline_achieved"] = round(gbs, 1)
+        out["pipeline_frac"] = round(gbs / HBM_PEAK_GBS, 4)
+    allt = measured_traffic_all() if counters else {}
+    out["traffic_ratio"] = (round(sum(allt.values()) / bytes_launch, 3)
+                            if len(allt) == len(RECON_PASSES) else None)
+    return out
 
 
 PASSES = ["rows_fwd", "cols_modulus", "rows_inv", "object_update", "fuse"]
@@ -252,7 +347,8 @@ def run_lab(args, api, synth, dev):
         "data": "synthetic (seeded object/probe, simulated Poisson+Gaussian exposures)",
         "config": {"workload": wl, "positions": w.J, "pattern": w.Nd, "batch": w.batch, "iterations": n_iter,
                    "exposures": len(w.t), "levels": w.levels},
-        "roofline": roofline(dominant, nlaunch, kms, per_launch, w.Nd, w.batch, counters=not sub),
+        "roofline": roofline(dominant, nlaunch, kms, per_launch, w.Nd, w.batch, counters=not sub,
+                             updates_per_step=w.J * n_iter, ms_per_step=dt * 1e3),
         "per_class_ms_one_step": {k: round(v[1], 3) for k, v in ranks.items()},
         "launch_variants": tuned,
         "graph": graph,
@@ -260,10 +356,18 @@ def run_lab(args, api, synth, dev):
     }
     if not args.no_cpu:
         v, n, sec = cpu_baseline(w, O_true, P, clean, scale, args.cpu_seconds, sub)
+        model, _ = host_cpu()
         out["cpu_baseline"] = {"value": round(v, 3), "unit": "position-updates/s", "cores": 1,
-                               "kind": "oracle",
+                               "kind": "oracle", "host": model,
                                "sample": f"{n} rPIE position updates (mini-batches of {w.batch}) of the "
                                          f"same workload in float64 NumPy, {sec:.1f} s"}
+        if not sub:
+            v2, n2, sec2, cores = cpu_baseline_all_cores(w, O_true, P, clean, scale, args.cpu_seconds)
+            out["cpu_baseline_all_cores"] = {
+                "value": round(v2, 3), "unit": "position-updates/s", "cores": cores,
+                "kind": "batched float64 update, scipy.fft over all usable host cores", "host": model,
+                "sample": f"{n2} rPIE position updates (mini-batches of {w.batch}) of the same workload, "
+                          f"{sec2:.1f} s"}
     return out
 
 

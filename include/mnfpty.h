@@ -34,6 +34,8 @@ extern "C" {
 #define MNF_EUNSUPPORTED -2   /* detector size without a compiled FFT plan, too many levels/exposures */
 #define MNF_EHIP         -3   /* a HIP runtime call failed; the message holds hipGetErrorString */
 #define MNF_ENOMEM       -4   /* scratch allocation failed */
+#define MNF_ENONFINITE   -5   /* a call produced a non-finite error, loss, object or probe value (from mnf_status) */
+#define MNF_EDIVERGED    -6   /* an iteration's Fourier error exceeded max(10 x the call's first, 1e-6) (from mnf_status) */
 
 typedef struct { float re, im; } mnf_c64;
 typedef struct mnf_ctx mnf_ctx;
@@ -45,8 +47,21 @@ int mnf_create(mnf_ctx** out, int hip_device);
 /* Release a context and its scratch.  Waits for the device first.  NULL is a no-op. */
 void mnf_destroy(mnf_ctx* ctx);
 
-/* Message of the last failing call on ctx ("" if none).  Valid until the next call on ctx. */
+/* Message of the last failing call on ctx ("" if none).  Valid until the next call on ctx.
+ * With ctx == NULL: the message of the last failed mnf_create on the calling thread. */
 const char* mnf_last_error(const mnf_ctx* ctx);
+
+/* Numerical status of the work issued on ctx (a guard the paper does not
+ * discuss; iterative phase retrieval can blow up on inconsistent data).
+ * Kernels record, without synchronising, (1) a non-finite per-iteration
+ * Fourier error or loss, or a non-finite object or probe element at the end
+ * of a reconstruction call, and (2) divergence: an iteration whose Fourier
+ * error (when err_out is given) exceeds max(10 x the first iteration of the
+ * same call, 1e-6).  mnf_status waits for `stream`, returns MNF_ENONFINITE
+ * (which takes precedence) or MNF_EDIVERGED if either was recorded since the
+ * previous mnf_status on ctx, MNF_OK otherwise, and clears the record.  Work
+ * still running on other streams may be reported by a later call. */
+int mnf_status(mnf_ctx* ctx, void* stream);
 
 /* Detector sizes with a compiled FFT plan: writes up to `cap` sizes to
  * `sizes` (host int32) and returns how many exist. */
@@ -221,18 +236,21 @@ int ptycho_iterate_many(mnf_ctx* ctx, const ptycho_scan* scans, int n_scans, int
                         const ptycho_params* params, void* stream);
 
 /* ------------------------------------------------------------------------
- * Loss on fused intensities and its gradient (the adjoint of Eqs. 2-3),
- * exit waves recomputed per chunk of `batch` positions:
+ * Loss on fused intensities and its gradient (the adjoint of Eqs. 2-3; the
+ * Poisson model of the Introduction), exit waves recomputed per chunk of
+ * `batch` positions:
  *   loss = sum_j sum_q l(Psi_j, I_j),  Psi_j = F_unitary(pad(P O_j)),
  *   Poisson (kind 0): l = |Psi|^2 - I ln(|Psi|^2 + eps), I = max(I, 0)
  *   amplitude (kind 1): l = (|Psi| - sqrt(I))^2
  * Gradients use g = dL/dRe + i dL/dIm (PyTorch's complex convention),
- * scaled by *upstream (host double).
+ * scaled by *upstream: a device double scalar read by the kernels (so an
+ * autograd backward needs no device-to-host copy), or NULL for 1.
  * gO device c64 [My][Mx] and gP device c64 [Nw][Nw] are overwritten (either may be NULL).
- * loss_out device double [1] (may be NULL). */
+ * loss_out device double [1] (may be NULL).  A non-finite loss is recorded
+ * for mnf_status. */
 int ptycho_grad(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P, int Nw,
                 const float* I, int Nd, const int32_t* pos, int J,
-                int kind, float eps, int batch, double upstream,
+                int kind, float eps, int batch, const double* upstream,
                 double* loss_out, mnf_c64* gO, mnf_c64* gP, void* stream);
 
 /* ------------------------------------------------------------------------

@@ -33,7 +33,7 @@ def _ctx(device: torch.device) -> ctypes.c_void_p:
             c = ctypes.c_void_p()
             rc = lib.mnf_create(ctypes.byref(c), idx)
             if rc != 0:
-                raise MnfError(rc, f"mnf_create({idx}) failed")
+                raise MnfError(rc, f"mnf_create({idx}) failed: {lib.mnf_last_error(None).decode()}")
             _contexts[idx] = c
         return c
 
@@ -311,9 +311,11 @@ LOSSES = {"poisson": 0, "amplitude": 1}
 
 
 def ptycho_grad(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, kind: str = "poisson",
-                eps: float = 1e-6, batch: int = 32, upstream: float = 1.0, need_gO: bool = True,
+                eps: float = 1e-6, batch: int = 32, upstream=None, need_gO: bool = True,
                 need_gP: bool = True):
-    """(loss float64 device scalar, gO or None, gP or None)."""
+    """(loss float64 device scalar, gO or None, gP or None).  `upstream` scales
+    the gradients: None (1), a float, or a float64 device scalar tensor that
+    the kernels read in place (no device-to-host copy)."""
     _dev(O, "O", torch.complex64, 2)
     _dev(P, "P", torch.complex64, 2)
     _dev(I, "I", torch.float32, 3)
@@ -322,12 +324,37 @@ def ptycho_grad(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, kind: st
     loss = torch.empty((), dtype=torch.float64, device=O.device)
     gO = torch.empty_like(O) if need_gO else None
     gP = torch.empty_like(P) if need_gP else None
+    if upstream is not None and not isinstance(upstream, torch.Tensor):
+        upstream = torch.tensor(float(upstream), dtype=torch.float64, device=O.device)
+    if upstream is not None:
+        if upstream.device != O.device or upstream.dtype != torch.float64 or upstream.numel() != 1:
+            raise ValueError("upstream must be a float64 scalar on the device of O")
+        upstream = upstream.contiguous()
     ctx = _ctx(O.device)
     rc = _L.load().ptycho_grad(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], _ptr(I),
-                               I.shape[1], _i32p(posa), J, LOSSES[kind], eps, batch, float(upstream),
+                               I.shape[1], _i32p(posa), J, LOSSES[kind], eps, batch, _ptr(upstream),
                                _ptr(loss), _ptr(gO), _ptr(gP), _stream(O.device))
     _check(rc, ctx)
     return loss, gO, gP
+
+
+def status(device="cuda:0") -> int:
+    """Wait for the device's current stream and return the numerical status
+    recorded since the last call (0, MNF_ENONFINITE or MNF_EDIVERGED); the
+    record is cleared."""
+    dev = torch.device(device)
+    ctx = _ctx(dev)
+    rc = _L.load().mnf_status(ctx, _stream(dev))
+    if rc not in (0, _L.MNF_ENONFINITE, _L.MNF_EDIVERGED):
+        _check(rc, ctx)
+    return rc
+
+
+def check_status(device="cuda:0") -> None:
+    """Raise MnfError if a non-finite value or divergence was recorded."""
+    dev = torch.device(device)
+    ctx = _ctx(dev)
+    _check(_L.load().mnf_status(ctx, _stream(dev)), ctx)
 
 
 # ------------------------------------------------------------ launch timing

@@ -15,7 +15,7 @@ from . import api
 class PtychoLoss(torch.autograd.Function):
     @staticmethod
     def forward(ctx, O, P, I, pos, kind="poisson", eps=1e-6, batch=32):
-        loss, _, _ = api.ptycho_grad(O.detach(), P.detach(), I, pos, kind, eps, batch, 1.0,
+        loss, _, _ = api.ptycho_grad(O.detach(), P.detach(), I, pos, kind, eps, batch, None,
                                      need_gO=False, need_gP=False)
         ctx.save_for_backward(O, P, I)
         ctx.pos, ctx.kind, ctx.eps, ctx.batch = pos, kind, eps, batch
@@ -27,7 +27,8 @@ class PtychoLoss(torch.autograd.Function):
         need_O, need_P = ctx.needs_input_grad[0], ctx.needs_input_grad[1]
         if not (need_O or need_P):
             return (None,) * 7
-        up = float(g.item())  # the adjoint takes the upstream factor as a host scalar
+        # the upstream factor stays on the device: the kernels read it in place
+        up = g.detach().to(device=O.device, dtype=torch.float64).reshape(())
         _, gO, gP = api.ptycho_grad(O.detach(), P.detach(), I, ctx.pos, ctx.kind, ctx.eps, ctx.batch, up,
                                     need_gO=need_O, need_gP=need_P)
         return gO, gP, None, None, None, None, None

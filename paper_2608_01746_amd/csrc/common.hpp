@@ -52,9 +52,15 @@ struct mnf_ctx {
     hipEvent_t pinned_done = nullptr;
     // launch-shape variant per detector size: bit 0 rows, bit 1 columns (0 = defaults)
     std::map<int, int> variant;
-    // stream used to capture graphs and the last instantiated graph
+    // stream used to capture graphs; the last instantiated graph and the key
+    // of the launch sequence it holds (a call whose sequence hashes to the same
+    // key replays it instead of capturing again)
     hipStream_t capture_stream = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    uint64_t graph_key = 0;
+    // status bits set by kernels (non-finite values, divergence), read and
+    // cleared by mnf_status
+    unsigned* d_status = nullptr;
 };
 
 namespace mnf {
@@ -106,6 +112,37 @@ void prof_push(mnf_ctx* ctx, int cls, hipEvent_t e0, hipEvent_t e1);
             hipLaunchKernelGGL(kernel, grid, block, 0, st, __VA_ARGS__);                     \
         }                                                                                    \
     } while (0)
+
+// 64-bit hash of byte ranges (FNV-1a over 8-byte words plus a final mix),
+// for keys of cached launch sequences.
+struct KeyHash {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void* p, size_t n) {
+        const unsigned char* b = (const unsigned char*)p;
+        size_t i = 0;
+        for (; i + 8 <= n; i += 8) {
+            uint64_t w;
+            __builtin_memcpy(&w, b + i, 8);
+            h = (h ^ w) * 1099511628211ull;
+        }
+        for (; i < n; ++i) h = (h ^ b[i]) * 1099511628211ull;
+    }
+    template <class T>
+    void add(const T& v) { add(&v, sizeof v); }
+    template <class T>
+    void add_vec(const std::vector<T>& v) {
+        const size_t n = v.size();
+        add(n);
+        if (n) add(v.data(), n * sizeof(T));
+    }
+    uint64_t value() const {
+        uint64_t x = h;
+        x ^= x >> 33;
+        x *= 0xff51afd7ed558ccdull;
+        x ^= x >> 33;
+        return x ? x : 1;
+    }
+};
 
 inline int begin(mnf_ctx* ctx) {
     if (!ctx) return MNF_EINVAL;

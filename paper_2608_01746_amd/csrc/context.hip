@@ -3,6 +3,7 @@
 #include <cstring>
 
 #include "common.hpp"
+#include "tables.hpp"
 
 namespace mnf {
 
@@ -153,19 +154,61 @@ const char* mnf_kernel_class_name(int cls) {
     return (cls >= 0 && cls < MNF_K_NCLASS) ? kClassNames[cls] : "";
 }
 
+// message of the last failed mnf_create on this thread (mnf_last_error(NULL))
+static thread_local std::string g_create_error;
+
+static int create_failed(int code, const std::string& msg) {
+    g_create_error = msg;
+    return code;
+}
+
 int mnf_create(mnf_ctx** out, int hip_device) {
-    if (!out) return MNF_EINVAL;
+    if (!out) return create_failed(MNF_EINVAL, "null output pointer");
     *out = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
         (void)hipGetLastError();
-        return MNF_EINVAL;
+        return create_failed(MNF_EINVAL, "no HIP device " + std::to_string(hip_device));
     }
-    if (hipSetDevice(hip_device) != hipSuccess) return MNF_EHIP;
+    hipError_t e = hipSetDevice(hip_device);
+    if (e != hipSuccess) return create_failed(MNF_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
     mnf_ctx* c = new mnf_ctx();
     c->device = hip_device;
+    e = hipMalloc(&c->d_status, 256);
+    if (e == hipSuccess) e = hipMemset(c->d_status, 0, 256);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        mnf_destroy(c);
+        return create_failed(MNF_ENOMEM, std::string("status word: ") + hipGetErrorString(e));
+    }
+    // twiddle tables of every supported size up front, so that no later call
+    // needs to allocate one
+    int32_t sizes[16];
+    const int ns = mnf_supported_sizes(sizes, 16);
+    for (int i = 0; i < ns; ++i) {
+        const float2* tw;
+        const int rc = mnf::twiddles(c, sizes[i], &tw);
+        if (rc != MNF_OK) {
+            const std::string msg = "twiddle table: " + c->err;
+            mnf_destroy(c);
+            return create_failed(rc, msg);
+        }
+    }
+    g_create_error.clear();
     *out = c;
     return MNF_OK;
+}
+
+int mnf_status(mnf_ctx* ctx, void* stream) {
+    MNF_TRY(mnf::begin(ctx));
+    MNF_HIP(ctx, hipStreamSynchronize((hipStream_t)stream));
+    unsigned h = 0;
+    MNF_HIP(ctx, hipMemcpy(&h, ctx->d_status, sizeof h, hipMemcpyDeviceToHost));
+    if (h == 0) return MNF_OK;
+    MNF_HIP(ctx, hipMemset(ctx->d_status, 0, sizeof h));
+    if (h & mnf::kStatusNonFinite)
+        return mnf::set_error(ctx, MNF_ENONFINITE, "a non-finite error, loss, object or probe value was produced");
+    return mnf::set_error(ctx, MNF_EDIVERGED, "the Fourier error grew above 10x its first value within one call");
 }
 
 void mnf_destroy(mnf_ctx* ctx) {
@@ -183,9 +226,10 @@ void mnf_destroy(mnf_ctx* ctx) {
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->pinned_done) (void)hipEventDestroy(ctx->pinned_done);
+    if (ctx->d_status) (void)hipFree(ctx->d_status);
     delete ctx;
 }
 
-const char* mnf_last_error(const mnf_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* mnf_last_error(const mnf_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"

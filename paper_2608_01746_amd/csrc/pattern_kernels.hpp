@@ -114,13 +114,16 @@ template <ColOp OP>
 __device__ __forceinline__ float2 col_pointwise(float2 v, float Iq, float eps, float& accf, double& acc) {
     const float m2 = cabs2(v);
     if constexpr (OP == ColOp::Modulus) {
-        // Fourier-modulus projection against A = sqrt(max(I, 0)); error (|Psi| - A)^2.
-        // Correctly rounded square root and quotient: sequential updates amplify rounding.
-        const float a = sqrtf(fmaxf(Iq, 0.f));
-        const float mag = sqrtf(m2);
-        const float d = mag - a;
+        // Fourier-modulus projection against the amplitude a = Iq (A = sqrt(max(I, 0)),
+        // precomputed once per call); error (|Psi| - A)^2.  One hardware reciprocal
+        // square root r ~ 1/|Psi| (about 1 ulp) gives both |Psi| = m2 r and the
+        // scale A r, in place of a correctly rounded root and quotient per value.
+        const float a = Iq;
+        const bool nz = m2 > 1e-30f;
+        const float r = __builtin_amdgcn_rsqf(nz ? m2 : 1.f);
+        const float d = (nz ? m2 * r : 0.f) - a;
         accf += d * d;  // a thread's V terms in float32, then float64 across threads
-        return m2 > 1e-30f ? cscale(v, a / mag) : make_float2(a, 0.f);
+        return nz ? cscale(v, a * r) : make_float2(a, 0.f);
     } else if constexpr (OP == ColOp::PoissonGrad) {
         // l = |Psi|^2 - I ln(|Psi|^2 + eps); g = 2 (1 - I / (|Psi|^2 + eps)) Psi
         const float I = fmaxf(Iq, 0.f);
@@ -166,15 +169,23 @@ k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
     const ScanDev sc = scan_desc(scans, sc0, sd.scan);
     const int Nw = sc.Nw;
 
-    // the fused intensity at this thread's output frequencies is loaded with
-    // the column, before the transform
-    const float* Ij = sc.I + (size_t)sd.j * N * N;
-    const int sx = (kx + N / 2) % N;
+    // the amplitude (projection) or fused intensity (losses) at this thread's
+    // output frequencies is loaded with the column, before the transform; the
+    // amplitudes are stored in FFT order, the intensities detector-centred
     float Iq[V];
+    const bool from_I = OP != ColOp::Modulus || !sc.A;  // no amplitude buffer: square roots below
+    if (!from_I) {
+        const float* Aj = sc.A + (size_t)sd.j * N * N + kx;
 #pragma unroll
-    for (int idx = 0; idx < V; ++idx) {
-        const int ky = out_pos<N, false>(t, idx);
-        Iq[idx] = ldg(Ij, (size_t)((ky + N / 2) % N) * N + sx);
+        for (int idx = 0; idx < V; ++idx) Iq[idx] = ldg(Aj, (size_t)out_pos<N, false>(t, idx) * N);
+    } else {
+        const float* Ij = sc.I + (size_t)sd.j * N * N;
+        const int sx = (kx + N / 2) % N;
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) {
+            const int ky = out_pos<N, false>(t, idx);
+            Iq[idx] = ldg(Ij, (size_t)((ky + N / 2) % N) * N + sx);
+        }
     }
 #pragma unroll
     for (int idx = 0; idx < V; ++idx)
@@ -182,6 +193,16 @@ k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
     twr.store(tw);
     __syncthreads();
     fft_line<N, false>(x, t, lds, ColLds<C>(c), tw);
+    if (from_I) {  // uniform: intensities read directly are checked, square roots taken here
+        bool bad = false;
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) bad |= !isfinite(Iq[idx]);
+        if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(sc.status, kStatusNonFinite);
+        if constexpr (OP == ColOp::Modulus) {
+#pragma unroll
+            for (int idx = 0; idx < V; ++idx) Iq[idx] = sqrtf(fmaxf(Iq[idx], 0.f));
+        }
+    }
 
     const float sc1 = 1.f / (float)N;
     double acc = 0.0;
@@ -259,15 +280,22 @@ k_cols_modulus_modes(const ScanDev* __restrict__ scans, const SlotDev* __restric
     const int Nw = sc.Nw;
     const int c = threadIdx.x % C, t = threadIdx.x / C;
     const int kx = blockIdx.x * C + c;
-    const float* Ij = sc.I + (size_t)sd.j * N * N;
-    const int sx = (kx + N / 2) % N;
     float a[V], tot[V];
+    if (sc.A) {  // amplitudes in FFT order
+        const float* Aj = sc.A + (size_t)sd.j * N * N + kx;
 #pragma unroll
-    for (int idx = 0; idx < V; ++idx) {
-        const int ky = out_pos<N, false>(t, idx);
-        a[idx] = sqrtf(fmaxf(ldg(Ij, (size_t)((ky + N / 2) % N) * N + sx), 0.f));
-        tot[idx] = 0.f;
+        for (int idx = 0; idx < V; ++idx) a[idx] = ldg(Aj, (size_t)out_pos<N, false>(t, idx) * N);
+    } else {  // from the detector-centred intensities
+        const float* Ij = sc.I + (size_t)sd.j * N * N;
+        const int sx = (kx + N / 2) % N;
+#pragma unroll
+        for (int idx = 0; idx < V; ++idx) {
+            const int ky = out_pos<N, false>(t, idx);
+            a[idx] = sqrtf(fmaxf(ldg(Ij, (size_t)((ky + N / 2) % N) * N + sx), 0.f));
+        }
     }
+#pragma unroll
+    for (int idx = 0; idx < V; ++idx) tot[idx] = 0.f;
     for (int i = threadIdx.x; i < N; i += blockDim.x) tw[i] = tw_g[i];
     __syncthreads();
     const float sc1 = 1.f / (float)N;
@@ -292,10 +320,11 @@ k_cols_modulus_modes(const ScanDev* __restrict__ scans, const SlotDev* __restric
     float f[V];
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
-        const float mag = sqrtf(tot[idx]);
-        const float d = mag - a[idx];
+        const bool nz = tot[idx] > 1e-30f;
+        const float r = __builtin_amdgcn_rsqf(nz ? tot[idx] : 1.f);  // ~1 / sqrt(sum_m |Psi_m|^2)
+        const float d = (nz ? tot[idx] * r : 0.f) - a[idx];
         accf += d * d;
-        f[idx] = tot[idx] > 1e-30f ? a[idx] / mag : -1.f;  // -1: the all-zero case
+        f[idx] = nz ? a[idx] * r : -1.f;  // -1: the all-zero case
     }
     for (int m = 0; m < M; ++m) {
         float2* col = S + (size_t)(s0 + m) * N * N + kx;
@@ -373,7 +402,7 @@ k_cols_intensity_modes(const ScanDev* __restrict__ scans, const SlotDev* __restr
 //     place from the batch sums (slot order, float64 denominators):
 //       P(r, n) += sum_s conj(O_s) dpsi / sum_s d_P,s
 //       rPIE: d_P,s = (1 - beta)|O_s|^2 + beta max|O_s|^2;  ePIE: max|O_s|^2 / beta
-//   MODE 2 (gradient): g = upstream * psi';  S[s][r][n] = conj(P(r, n)) g and
+//   MODE 2 (gradient): g = *upstream * psi' (1 when upstream is NULL);  S[s][r][n] = conj(P(r, n)) g and
 //     gP(r, n) += sum_s conj(O_s(r, n)) g  (when the scan has a gP).
 //   MODE 3, 4 (real positions): as MODE 0 with each slot's translated probe
 //     P_s = Pd[s] in place of P in dpsi and in the object numerator; P2 and
@@ -405,7 +434,7 @@ __global__ void __launch_bounds__((UpdCfg<N, RV>::THREADS))
 k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
                   const GroupDev* __restrict__ groups, float2* __restrict__ S,
                   const float* __restrict__ maxO2_part, int nparts, int rpie, float beta,
-                  float upstream, int nmodes, const float2* __restrict__ Pd, float2* __restrict__ G,
+                  const double* __restrict__ upstream, int nmodes, const float2* __restrict__ Pd, float2* __restrict__ G,
                   double* __restrict__ DP, const float2* __restrict__ gfrac, const float2* __restrict__ tw_g) {
     constexpr int T = UpdCfg<N, RV>::T, ULINES = UpdCfg<N, RV>::ULINES, V = PlanInfo<N>::V;
     constexpr int THREADS = UpdCfg<N, RV>::THREADS;
@@ -498,7 +527,7 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
     }
     __syncthreads();
 
-    const float scl = (MODE == 2 ? upstream : 1.f) / (float)N;
+    const float scl = (MODE == 2 && upstream ? (float)*upstream : 1.f) / (float)N;
     for (int k0 = 0; k0 < nb; k0 += ULINES) {
         const int k = k0 + line;
         const bool live = k < nb;
@@ -596,13 +625,13 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             sc.P2[(size_t)r * Nw + n] = p2;
             pmax = fmaxf(pmax, p2);
             if (MODE == 6 && den[c] > 0.0) {
-                const double inv = 1.0 / den[c];
+                const float inv = (float)(1.0 / den[c]);  // the float64 denominator, inverted once
 #pragma unroll
                 for (int q = 0; q < NM; ++q) {
                     if (q >= nmodes) break;
                     float2 p = s_prow[q * N + n];
-                    p.x = (float)((double)p.x + (double)num[q][c].x * inv);
-                    p.y = (float)((double)p.y + (double)num[q][c].y * inv);
+                    p.x += num[q][c].x * inv;
+                    p.y += num[q][c].y * inv;
                     sc.P[(size_t)q * Nw * Nw + (size_t)r * Nw + n] = p;
                 }
             }
@@ -613,9 +642,9 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             pmax = fmaxf(pmax, p2);
             if constexpr (MODE == 4) DP[(size_t)r * Nw + n] = den[c];
             if (MODE == 1 && den[c] > 0.0) {
-                const double inv = 1.0 / den[c];
-                p.x = (float)((double)p.x + (double)num[0][c].x * inv);
-                p.y = (float)((double)p.y + (double)num[0][c].y * inv);
+                const float inv = (float)(1.0 / den[c]);  // the float64 denominator, inverted once
+                p.x += num[0][c].x * inv;
+                p.y += num[0][c].y * inv;
                 sc.P[(size_t)r * Nw + n] = p;
             }
         }

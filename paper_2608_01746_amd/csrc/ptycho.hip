@@ -164,13 +164,14 @@ struct SubBufs {
     double* DP;
 };
 
-void fill_scan_dev(ScanDev& d, const ScanIn& s, const Box& b) {
+void fill_scan_dev(ScanDev& d, const ScanIn& s, const Box& b, unsigned* status) {
     d = ScanDev{};
     d.O = s.O;
     d.P = s.P;
     d.I = s.I;
     d.gO = s.gO;
     d.gP = s.gP;
+    d.status = status;
     d.My = s.My;
     d.Mx = s.Mx;
     d.Nw = s.Nw;
@@ -304,11 +305,11 @@ int issue_iterate_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, cons
                dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, S, 0.f, tw);
     if (upd)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 1>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, (const double*)nullptr, 1,
                    nP, nG, nD, (const float2*)nullptr, tw);
     else
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 0>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, (const double*)nullptr, 1,
                    nP, nG, nD, (const float2*)nullptr, tw);
     MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
@@ -350,15 +351,15 @@ int issue_subpixel_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, con
     const bool full_rows = RV == 1 && L.nslots > UpdCfg<N, 1>::ULINES;
     if (upd && full_rows)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, 0, 4>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, 0>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
+                   dim3(UpdCfg<N, 0>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, (const double*)nullptr, 1,
                    Pd, sb.G, sb.DP, fused ? fr : (const float2*)nullptr, tw);
     else if (upd)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 4>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, (const double*)nullptr, 1,
                    Pd, sb.G, sb.DP, fused ? fr : (const float2*)nullptr, tw);
     else
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 3>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, 1,
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, (const double*)nullptr, 1,
                    Pd, (float2*)nullptr, (double*)nullptr, (const float2*)nullptr, tw);
     MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
@@ -398,11 +399,11 @@ int issue_modes_launch(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const 
                dim3(ColCfg<N, CV>::THREADS), scans, slots, S, M, tw);
     if (upd)
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 6>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, M,
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, (const double*)nullptr, M,
                    nP, nG, nD, (const float2*)nullptr, tw);
     else
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 5>), dim3(L.maxNw, L.ngroups),
-                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, 1.f, M,
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, gr, rpie, p.beta, (const double*)nullptr, M,
                    nP, nG, nD, (const float2*)nullptr, tw);
     MNF_LAUNCH(ctx, MNF_K_OBJECT_UPDATE, st, k_object_update, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                groups, L.ngroups, (const float2*)S, N, rpie, p.alpha);
@@ -459,7 +460,7 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
         Box b;
         MNF_TRY(check_scan(ctx, in[k], k, &b));
         MNF_TRY(check_order(ctx, in[k].order, n_iter, in[k].J, k));
-        fill_scan_dev(pl.scans[k], in[k], b);
+        fill_scan_dev(pl.scans[k], in[k], b, ctx->d_status);
         classes[in[k].Nd].push_back(k);
         max_batches = std::max(max_batches, (in[k].J + p.batch - 1) / p.batch);
     }
@@ -478,15 +479,17 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     pl.sub = sub;
     pl.modes = modes;
 
-    // per-scan scratch: P2 [Nw^2], maxP2_row [Nw], error partials [J][N/C], |A|^2 partials [J] and sum
+    // per-scan scratch: P2 [Nw^2], maxP2_row [Nw], amplitudes [J][Nd][Nd] (FFT order),
+    // error partials [J][N/C], |A|^2 partials [J] and sum
+    const bool amp = true;
     size_t f_need = 0, d_need = 0;
     for (int k = 0; k < ns; ++k) {
-        f_need += (size_t)in[k].Nw * in[k].Nw + in[k].Nw;
+        f_need += (size_t)in[k].Nw * in[k].Nw + in[k].Nw + (amp ? (size_t)in[k].J * in[k].Nd * in[k].Nd : 0);
         d_need += (size_t)in[k].J * col_groups(ctx, in[k].Nd) + in[k].J + 1;
     }
     void *fbuf, *dbuf;
-    MNF_TRY(scratch(ctx, "scan_f32", f_need * sizeof(float), &fbuf));
-    MNF_TRY(scratch(ctx, "scan_f64", d_need * sizeof(double), &dbuf));
+    MNF_TRY(mnf::scratch(ctx, "scan_f32", f_need * sizeof(float), &fbuf));
+    MNF_TRY(mnf::scratch(ctx, "scan_f64", d_need * sizeof(double), &dbuf));
     std::vector<double*> sA2p(ns), sA2(ns);
     {
         float* f = (float*)fbuf;
@@ -496,6 +499,8 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
             f += (size_t)in[k].Nw * in[k].Nw;
             pl.scans[k].maxP2_row = f;
             f += in[k].Nw;
+            pl.scans[k].A = amp ? f : nullptr;
+            if (amp) f += (size_t)in[k].J * in[k].Nd * in[k].Nd;
             pl.scans[k].err_part = d;
             d += (size_t)in[k].J * col_groups(ctx, in[k].Nd);
             sA2p[k] = d;
@@ -510,34 +515,50 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
         pl.iter_end.push_back((int)pl.launches.size());
     }
     MNF_TRY(upload_plan(ctx, pl, st));
-    // error reduction jobs, one per scan per iteration
+    // error reduction jobs, one per scan per iteration.  A graph writes the
+    // errors to an internal buffer [ns][n_iter], copied to err_out after each
+    // replay, so that the caller's output addresses are not part of the graph.
+    const bool graph_req = p.graph != 0 && ctx->prof.mask == 0;
+    double* err_buf = nullptr;
+    if (graph_req) {
+        void* eb;
+        MNF_TRY(mnf::scratch(ctx, "err_buf", (size_t)ns * std::max(n_iter, 1) * sizeof(double), &eb));
+        err_buf = (double*)eb;
+    }
+    auto err_dst = [&](int k) { return graph_req ? err_buf + (size_t)k * n_iter : in[k].err_out; };
     std::vector<SumJob> jobs;
     for (int i = 0; i < n_iter; ++i)
         for (int k = 0; k < ns; ++k)
             jobs.push_back(SumJob{pl.scans[k].err_part, (size_t)in[k].J * col_groups(ctx, in[k].Nd), sA2[k],
-                                  in[k].err_out ? in[k].err_out + i : nullptr});
+                                  in[k].err_out ? err_dst(k) + i : nullptr,
+                                  in[k].err_out && i > 0 ? err_dst(k) : nullptr, ctx->d_status});
     std::vector<SumJob> a2jobs;
-    for (int k = 0; k < ns; ++k) a2jobs.push_back(SumJob{sA2p[k], (size_t)in[k].J, nullptr, sA2[k]});
+    for (int k = 0; k < ns; ++k) a2jobs.push_back(SumJob{sA2p[k], (size_t)in[k].J, nullptr, sA2[k], nullptr, nullptr});
     void *d_jobs, *d_a2jobs, *S, *mO;
     MNF_TRY(upload(ctx, "plan_jobs", jobs.data(), sizeof(SumJob) * jobs.size(), st, &d_jobs));
     MNF_TRY(upload(ctx, "plan_a2jobs", a2jobs.data(), sizeof(SumJob) * a2jobs.size(), st, &d_a2jobs));
-    MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
-    MNF_TRY(scratch(ctx, "maxO2", pl.max_maxO2 * sizeof(float), &mO));
+    MNF_TRY(mnf::scratch(ctx, "S", pl.max_S, &S));
+    MNF_TRY(mnf::scratch(ctx, "maxO2", pl.max_maxO2 * sizeof(float), &mO));
     SubBufs sbuf{nullptr, nullptr, nullptr};
     const SubBufs* sb = nullptr;
     if (sub) {
         const size_t nw2 = (size_t)in[0].Nw * in[0].Nw;
         void *pd, *g = nullptr, *dp = nullptr;
-        MNF_TRY(scratch(ctx, "sub_Pd", (size_t)pl.max_slots * nw2 * sizeof(float2), &pd));
+        MNF_TRY(mnf::scratch(ctx, "sub_Pd", (size_t)pl.max_slots * nw2 * sizeof(float2), &pd));
         if (p.update_probe) {
-            MNF_TRY(scratch(ctx, "sub_G", (size_t)pl.max_slots * nw2 * sizeof(float2), &g));
-            MNF_TRY(scratch(ctx, "sub_DP", nw2 * sizeof(double), &dp));
+            MNF_TRY(mnf::scratch(ctx, "sub_G", (size_t)pl.max_slots * nw2 * sizeof(float2), &g));
+            MNF_TRY(mnf::scratch(ctx, "sub_DP", nw2 * sizeof(double), &dp));
         }
         sbuf = SubBufs{(float2*)pd, (float2*)g, (double*)dp};
         sb = &sbuf;
         const float2* tw;
         MNF_TRY(twiddles(ctx, in[0].Nw, &tw));
     }
+    // the amplitudes every iteration projects onto, once per call
+    for (int k = 0; k < ns && amp; ++k)
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_amplitude_prep,
+                   dim3((unsigned)((in[k].Nd * in[k].Nd + 255) / 256), (unsigned)in[k].J), dim3(256), in[k].I,
+                   in[k].Nd, (float*)pl.scans[k].A, ctx->d_status);
     bool any_err = false;
     for (int k = 0; k < ns; ++k) any_err |= in[k].err_out != nullptr;
     if (any_err) {
@@ -553,14 +574,57 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
         const float2* tw;
         MNF_TRY(twiddles(ctx, kv.first, &tw));
     }
-    // the iterations, optionally captured into one graph
+    // the iterations, optionally as one graph.  Launch timing needs direct
+    // launches, so a context with timing enabled does not use graphs.
     hipStream_t run = st;
-    const bool graph = p.graph != 0;
-    const uint32_t saved_mask = ctx->prof.mask;
+    const bool graph = graph_req;
+    uint64_t key = 0;
+    // copies of the graph's errors to the caller's outputs (after a replay)
+    auto copy_errs = [&]() -> int {
+        for (int k = 0; k < ns; ++k)
+            if (in[k].err_out)
+                MNF_HIP(ctx, hipMemcpyAsync(in[k].err_out, err_buf + (size_t)k * n_iter, n_iter * sizeof(double),
+                                            hipMemcpyDeviceToDevice, st));
+        return MNF_OK;
+    };
     if (graph) {
+        // Everything the launch sequence depends on: plan tables (their device
+        // copies are re-uploaded above on every call), scratch addresses,
+        // parameters, launch shapes.  The same key replays the cached graph.
+        KeyHash kh;
+        kh.add_vec(pl.scans);
+        kh.add_vec(pl.slots);
+        kh.add_vec(pl.groups);
+        for (const Launch& L : pl.launches) {  // field by field: the struct has padding
+            const long long f[] = {L.N, (long long)L.slot_off, L.nslots, (long long)L.group_off, L.ngroups, L.tiles,
+                                   L.maxNw};
+            kh.add(f, sizeof f);
+        }
+        kh.add_vec(pl.iter_end);
+        kh.add_vec(pl.fracs);
+        kh.add_vec(jobs);
+        kh.add(p);
+        kh.add(n_iter);
+        const void* ptrs[] = {pl.d_scans, pl.d_slots, pl.d_groups, pl.d_fracs, d_jobs, S, mO,
+                              sbuf.Pd, sbuf.G, sbuf.DP};
+        kh.add(ptrs, sizeof ptrs);
+        for (auto& kv : classes) {
+            const float2* tw;
+            MNF_TRY(twiddles(ctx, kv.first, &tw));
+            const int v = variant_of(ctx, kv.first);
+            kh.add(kv.first);
+            kh.add(v);
+            kh.add(tw);
+        }
+        kh.add(pl.sub);
+        kh.add(pl.modes);
+        key = kh.value();
+        if (ctx->graph_exec && ctx->graph_key == key) {
+            MNF_HIP(ctx, hipGraphLaunch(ctx->graph_exec, st));
+            return copy_errs();
+        }
         if (!ctx->capture_stream) MNF_HIP(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
         run = ctx->capture_stream;
-        ctx->prof.mask = 0;  // no timing events inside a capture
         MNF_HIP(ctx, hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal));
     }
     int rc = MNF_OK;
@@ -574,8 +638,15 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
             hipLaunchKernelGGL(k_sum_jobs, dim3(ns), dim3(256), 0, run, (const SumJob*)d_jobs + (size_t)i * ns, 1.0);
         }
     }
+    // non-finite objects and probes are reported by mnf_status
+    for (int k = 0; k < ns && rc == MNF_OK; ++k) {
+        const size_t no = (size_t)in[k].My * in[k].Mx, np = (size_t)in[k].modes * in[k].Nw * in[k].Nw;
+        hipLaunchKernelGGL(k_check_finite, dim3((unsigned)std::min<size_t>((no + 255) / 256, 1024)), dim3(256), 0, run,
+                           (const float2*)in[k].O, no, ctx->d_status);
+        hipLaunchKernelGGL(k_check_finite, dim3((unsigned)std::min<size_t>((np + 255) / 256, 1024)), dim3(256), 0, run,
+                           (const float2*)in[k].P, np, ctx->d_status);
+    }
     if (graph) {
-        ctx->prof.mask = saved_mask;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(run, &g);
         if (rc != MNF_OK) {
@@ -587,12 +658,14 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
             MNF_HIP(ctx, hipStreamSynchronize(st));
             MNF_HIP(ctx, hipGraphExecDestroy(ctx->graph_exec));
             ctx->graph_exec = nullptr;
+            ctx->graph_key = 0;
         }
         e = hipGraphInstantiate(&ctx->graph_exec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
         if (e != hipSuccess) return set_error(ctx, MNF_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        ctx->graph_key = key;
         MNF_HIP(ctx, hipGraphLaunch(ctx->graph_exec, st));
-        return MNF_OK;
+        return copy_errs();
     }
     if (rc != MNF_OK) return rc;
     MNF_CHECK_LAUNCH(ctx);
@@ -606,7 +679,7 @@ int forward_v(mnf_ctx* ctx, const CallPlan& pl, float* I_out, const SubBufs* sb,
     const float2* tw;
     MNF_TRY(twiddles(ctx, N, &tw));
     void* S;
-    MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
+    MNF_TRY(mnf::scratch(ctx, "S", pl.max_S, &S));
     for (const Launch& L : pl.launches) {
         const float2* Pd = nullptr;
         int pmod = 1;
@@ -657,19 +730,19 @@ int forward_n(mnf_ctx* ctx, const CallPlan& pl, float* I_out, const SubBufs* sb,
 // ------------------------------------------------------------------ grad
 
 template <int N, int RV, int CV>
-int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, double upstream, double* loss_out,
+int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, const double* upstream, double* loss_out,
            hipStream_t st) {
     const float2* tw;
     MNF_TRY(twiddles(ctx, N, &tw));
     void *S, *lossp, *d_job;
-    MNF_TRY(scratch(ctx, "S", pl.max_S, &S));
-    MNF_TRY(scratch(ctx, "losspart", (size_t)s.J * col_groups(ctx, N) * sizeof(double), &lossp));
+    MNF_TRY(mnf::scratch(ctx, "S", pl.max_S, &S));
+    MNF_TRY(mnf::scratch(ctx, "losspart", (size_t)s.J * col_groups(ctx, N) * sizeof(double), &lossp));
     // the scan's partials live in the loss buffer
     std::vector<ScanDev> sd = pl.scans;
     sd[0].err_part = (double*)lossp;
     void* d_scans;
     MNF_TRY(upload(ctx, "plan_scans", sd.data(), sizeof(ScanDev), st, &d_scans));
-    SumJob job{(const double*)lossp, (size_t)s.J * col_groups(ctx, N), nullptr, loss_out};
+    SumJob job{(const double*)lossp, (size_t)s.J * col_groups(ctx, N), nullptr, loss_out, nullptr, ctx->d_status};
     MNF_TRY(upload(ctx, "plan_lossjob", &job, sizeof job, st, &d_job));
     if (s.gO)
         MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_zero_c64, dim3((unsigned)(((size_t)s.My * s.Mx + 255) / 256)), dim3(256),
@@ -694,19 +767,19 @@ int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
         if (!s.gO && !s.gP) continue;
         MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 2>), dim3(L.maxNw, L.ngroups),
                    dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, (float2*)S, (const float*)nullptr, 0, 0, 0.f,
-                   (float)upstream, 1, (const float2*)nullptr, (float2*)nullptr, (double*)nullptr,
+                   upstream, 1, (const float2*)nullptr, (float2*)nullptr, (double*)nullptr,
                    (const float2*)nullptr, tw);
         if (s.gO)
             MNF_LAUNCH(ctx, MNF_K_GRAD_SCATTER, st, k_grad_object, dim3(L.tiles), dim3(kObjThreads), scans, slots,
                        groups, L.ngroups, (const float2*)S, N);
     }
-    if (loss_out) MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_jobs, dim3(1), dim3(256), (const SumJob*)d_job, 1.0);
+    MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_jobs, dim3(1), dim3(256), (const SumJob*)d_job, 1.0);  // loss, status
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
 }
 
 template <int N>
-int grad_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, double upstream, double* loss_out,
+int grad_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, const double* upstream, double* loss_out,
            hipStream_t st) {
     switch (variant_of(ctx, N)) {
         case 1: return grad_v<N, 1, 0>(ctx, pl, s, kind, eps, upstream, loss_out, st);
@@ -740,7 +813,7 @@ int plan_identity(mnf_ctx* ctx, const ScanIn& s, int chunk, CallPlan& pl, hipStr
     Box b;
     MNF_TRY(check_scan(ctx, s, 0, &b));
     pl.scans.resize(1);
-    fill_scan_dev(pl.scans[0], s, b);
+    fill_scan_dev(pl.scans[0], s, b, ctx->d_status);
     std::vector<int> cls{0};
     std::vector<ScanIn> in{s};
     const int nr = (s.J + chunk - 1) / chunk;
@@ -761,9 +834,9 @@ int autotune_impl(mnf_ctx* ctx, int N, int nslots, int reps, double* times_us, h
     const int step = N / 4 > 0 ? N / 4 : 1;
     const int M = N + (side - 1) * step;
     void *O, *P, *I;
-    MNF_TRY(scratch(ctx, "tune_O", (size_t)M * M * sizeof(float2), &O));
-    MNF_TRY(scratch(ctx, "tune_P", (size_t)N * N * sizeof(float2), &P));
-    MNF_TRY(scratch(ctx, "tune_I", (size_t)nslots * N * N * sizeof(float), &I));
+    MNF_TRY(mnf::scratch(ctx, "tune_O", (size_t)M * M * sizeof(float2), &O));
+    MNF_TRY(mnf::scratch(ctx, "tune_P", (size_t)N * N * sizeof(float2), &P));
+    MNF_TRY(mnf::scratch(ctx, "tune_I", (size_t)nslots * N * N * sizeof(float), &I));
     hipLaunchKernelGGL(k_fill_c64, dim3((unsigned)(((size_t)M * M + 255) / 256)), dim3(256), 0, st, (float2*)O,
                        (size_t)M * M, make_float2(1.f, 0.f));
     hipLaunchKernelGGL(k_fill_c64, dim3((unsigned)(((size_t)N * N + 255) / 256)), dim3(256), 0, st, (float2*)P,
@@ -867,7 +940,7 @@ int ptycho_forward_subpixel(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, cons
     CallPlan pl;
     MNF_TRY(plan_identity(ctx, s, 64, pl, st));
     void* pd;
-    MNF_TRY(scratch(ctx, "sub_Pd", (size_t)pl.max_slots * Nw * Nw * sizeof(float2), &pd));
+    MNF_TRY(mnf::scratch(ctx, "sub_Pd", (size_t)pl.max_slots * Nw * Nw * sizeof(float2), &pd));
     const SubBufs sb{(float2*)pd, nullptr, nullptr};
     MNF_DISPATCH(Nd, forward_n, ctx, pl, I_out, &sb, st)
 }
@@ -932,7 +1005,7 @@ int ptycho_iterate_many(mnf_ctx* ctx, const ptycho_scan* scans, int n_scans, int
 }
 
 int ptycho_grad(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P, int Nw, const float* I, int Nd,
-                const int32_t* pos, int J, int kind, float eps, int batch, double upstream, double* loss_out,
+                const int32_t* pos, int J, int kind, float eps, int batch, const double* upstream, double* loss_out,
                 mnf_c64* gO, mnf_c64* gP, void* stream) {
     MNF_TRY(begin(ctx));
     if (kind != 0 && kind != 1) return set_error(ctx, MNF_EINVAL, "kind must be 0 (Poisson) or 1 (amplitude)");

@@ -131,9 +131,9 @@ k_probe_sum_update(const float2* __restrict__ G, const GroupDev* __restrict__ gr
             if (k0 + u < gd.nb) acc = cadd(acc, v[u]);
     }
     if (!(den > 0.0)) return;
-    const double inv = 1.0 / den;
-    p.x = (float)((double)p.x + (double)acc.x * inv);
-    p.y = (float)((double)p.y + (double)acc.y * inv);
+    const float inv = (float)(1.0 / den);  // the float64 denominator, inverted once
+    p.x += acc.x * inv;
+    p.y += acc.y * inv;
     P[q] = p;
 }
 

@@ -157,10 +157,10 @@ k_object_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ s
     for (int q = 0; q < kObjRows; ++q) {
         const int yy = yb + q;
         if (yy < sc.by0 + sc.bh && den[q] > 0.0) {
-            const double inv = 1.0 / den[q];
+            const float inv = (float)(1.0 / den[q]);  // the float64 denominator, inverted once
             float2 v = ov[q];
-            v.x = (float)((double)v.x + (double)num[q].x * inv);
-            v.y = (float)((double)v.y + (double)num[q].y * inv);
+            v.x += num[q].x * inv;
+            v.y += num[q].y * inv;
             sc.O[(size_t)yy * sc.Mx + xx] = v;
         }
     }
@@ -242,12 +242,17 @@ __global__ void k_zero_c64(float2* __restrict__ dst, size_t n) {
 }
 
 // One block per job: out = scale * sum(in[0..n)) in a fixed order, divided by
-// *div when div is given (0 when *div == 0).
+// *div when div is given (0 when *div == 0).  With `status`, a non-finite
+// result sets kStatusNonFinite, and with `first` a result above
+// max(10 * *first, 1e-6) sets kStatusDiverged (the floor keeps runs that
+// converge to rounding level from being flagged).
 struct SumJob {
     const double* in;
     size_t n;
     const double* div;
     double* out;
+    const double* first;
+    unsigned* status;
 };
 
 __global__ void __launch_bounds__(256)
@@ -265,11 +270,45 @@ k_sum_jobs(const SumJob* __restrict__ jobs, double scale) {
             if (i0 + (size_t)u * 256 < jb.n) a += v[u];
     }
     a = block_sum(a, red);
-    if (threadIdx.x == 0 && jb.out) {
+    if (threadIdx.x == 0) {
         double r = a * scale;
         if (jb.div) r = *jb.div > 0.0 ? r / *jb.div : 0.0;
-        *jb.out = r;
+        if (jb.out) *jb.out = r;
+        if (jb.status) {
+            if (!isfinite(r)) atomicOr(jb.status, kStatusNonFinite);
+            else if (jb.first && r > fmax(10.0 * *jb.first, 1e-6)) atomicOr(jb.status, kStatusDiverged);
+        }
     }
+}
+
+// Sets kStatusNonFinite when any of the n complex values is not finite.
+__global__ void __launch_bounds__(256)
+k_check_finite(const float2* __restrict__ a, size_t n, unsigned* __restrict__ status) {
+    bool bad = false;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float2 v = ldg(a, i);
+        bad |= !isfinite(v.x) || !isfinite(v.y);
+    }
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, kStatusNonFinite);
+}
+
+// Amplitudes of the fused intensities in FFT order (the detector-centred
+// patterns shifted by N/2 along both axes):
+//   A[j][ky][kx] = sqrt(max(I[j][(ky + N/2) mod N][(kx + N/2) mod N], 0)).
+// grid (ceil(N*N / 256), J).
+// A non-finite intensity sets kStatusNonFinite (its amplitude becomes 0).
+__global__ void __launch_bounds__(256)
+k_amplitude_prep(const float* __restrict__ I, int N, float* __restrict__ A, unsigned* __restrict__ status) {
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    bool bad = false;
+    if (q < N * N) {
+        const int ky = q / N, kx = q % N;
+        const size_t base = (size_t)blockIdx.y * N * N;
+        const float v = I[base + (size_t)((ky + N / 2) % N) * N + (kx + N / 2) % N];
+        bad = !isfinite(v);
+        A[base + q] = sqrtf(fmaxf(v, 0.f));
+    }
+    if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, kStatusNonFinite);
 }
 
 // part[j] = sum_q max(I[j][q], 0) (the squared amplitudes), one block per position.

@@ -13,9 +13,12 @@ MNF_EINVAL = -1
 MNF_EUNSUPPORTED = -2
 MNF_EHIP = -3
 MNF_ENOMEM = -4
+MNF_ENONFINITE = -5
+MNF_EDIVERGED = -6
 
 ERROR_NAMES = {MNF_EINVAL: "MNF_EINVAL", MNF_EUNSUPPORTED: "MNF_EUNSUPPORTED",
-               MNF_EHIP: "MNF_EHIP", MNF_ENOMEM: "MNF_ENOMEM"}
+               MNF_EHIP: "MNF_EHIP", MNF_ENOMEM: "MNF_ENOMEM", MNF_ENONFINITE: "MNF_ENONFINITE",
+               MNF_EDIVERGED: "MNF_EDIVERGED"}
 
 
 class FuseParamsC(ctypes.Structure):
@@ -44,6 +47,7 @@ SIGNATURES = {
     "mnf_create": (c_int, [POINTER(c_void_p), c_int]),
     "mnf_destroy": (None, [c_void_p]),
     "mnf_last_error": (ctypes.c_char_p, [c_void_p]),
+    "mnf_status": (c_int, [c_void_p, c_void_p]),
     "mnf_supported_sizes": (c_int, [POINTER(c_int32), c_int]),
     "fuse_exposures": (c_int, [c_void_p, c_void_p, POINTER(c_float), c_int, c_int, c_int, c_int,
                                POINTER(FuseParamsC), c_void_p, c_void_p, c_void_p]),
@@ -67,7 +71,7 @@ SIGNATURES = {
     "ptycho_iterate_many": (c_int, [c_void_p, POINTER(PtychoScanC), c_int, c_int, POINTER(PtychoParamsC),
                                     c_void_p]),
     "ptycho_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
-                            POINTER(c_int32), c_int, c_int, c_float, c_int, c_double,
+                            POINTER(c_int32), c_int, c_int, c_float, c_int, c_void_p,
                             c_void_p, c_void_p, c_void_p, c_void_p]),
     "detector_expose": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(c_float), c_int, c_float,
                                 c_float, c_float, ctypes.c_ulonglong, c_void_p, c_void_p]),

@@ -84,3 +84,20 @@ def test_create_without_device_fails_cleanly(lib):
     c = ctypes.c_void_p()
     assert lib.load().mnf_create(ctypes.byref(c), 0) == lib.MNF_EINVAL
     assert not c.value
+
+
+def test_error_codes_match_header(lib):
+    text = open(HEADER).read()
+    codes = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define\s+(MNF_\w+)\s+(-?\d+)", text)}
+    for name in ["MNF_OK", "MNF_EINVAL", "MNF_EUNSUPPORTED", "MNF_EHIP", "MNF_ENOMEM", "MNF_ENONFINITE",
+                 "MNF_EDIVERGED"]:
+        assert getattr(lib, name) == codes[name], name
+    assert set(lib.ERROR_NAMES.values()) == {n for n in codes if n != "MNF_OK"}
+
+
+def test_host_paths_reject_a_null_context(lib):
+    # argument checks run before any device call
+    L = lib.load()
+    assert L.mnf_status(None, None) == lib.MNF_EINVAL
+    assert L.ptycho_grad(None, None, 1, 1, None, 1, None, 16, None, 1, 0, 1e-6, 1, None, None, None, None,
+                         None) == lib.MNF_EINVAL

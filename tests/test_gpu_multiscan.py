@@ -136,3 +136,22 @@ def test_many_rejects_bad_scan(api):
     ts[2]["pos"] = np.array(ts[2]["pos"]) + 1000
     with pytest.raises(api.MnfError, match="scan 2"):
         api.ptycho_iterate_many(ts, 1)
+
+
+def test_cached_graph_replays_and_recaptures(api):
+    # the same call three times on the same buffers (the second and third
+    # replay the cached graph), then another order (a new capture); every
+    # result equals direct launches, and each call's errors reach its own
+    # output tensor
+    O, P, pos, I = tiny_scan(300, 128, 128, 4, 50, 2, seed=7)
+    It = tf32(I)
+    kw = dict(alg="rpie", batch=5, update_probe=True, probe_start_iter=1)
+    Og, Pg = tc64(np.ones_like(O)), tc64(P * 0.8)
+    for seed in (1, 1, 1, 2):
+        order = synth.random_orders(len(pos), 3, seed)
+        Og.copy_(tc64(np.ones_like(O)))
+        Pg.copy_(tc64(P * 0.8))
+        eg = api.ptycho_iterate(Og, Pg, It, pos, 3, order=order, graph=True, **kw)
+        Od, Pd = tc64(np.ones_like(O)), tc64(P * 0.8)
+        ed = api.ptycho_iterate(Od, Pd, It, pos, 3, order=order, **kw)
+        assert torch.equal(Og, Od) and torch.equal(Pg, Pd) and torch.equal(eg, ed), seed

@@ -183,6 +183,32 @@ def test_adam_steps_reduce_the_loss(api):
     assert losses[-1] < 0.5 * losses[0]
 
 
+def test_full_size_network_forward_matches_oracle(api):
+    # the warm-start network at its real size (256^2 input, widths 32..256),
+    # one sample, bf16-representable weights and input: only the float32
+    # accumulation order and the bf16 rounding of activations between layers
+    # differ from the float64 oracle (the same bar as the small network)
+    W = (32, 64, 128, 256)
+    rng = np.random.default_rng(7)
+    p = unet.init_params(W, 11)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.05
+        p[k] = torch.from_numpy(p[k].astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    names = [nm for L in unet.layer_specs(W) for nm in (L[0] + ".W", L[0] + ".b")]
+    flat = np.concatenate([p[k].ravel() for k in names])
+    assert flat.size == api.unet_param_count(256, W)
+    I = rng.gamma(0.5, 50.0, size=(1, 256, 256))
+    scale = 1.0 / np.log1p(I.max())
+    out = api.unet_forward(torch.from_numpy(flat.astype(np.float32)).to(DEV),
+                           torch.from_numpy(I.astype(np.float32)).to(DEV), scale, 256, W).cpu().numpy()
+    x = np.log1p(I.astype(np.float32).astype(np.float64)) * np.float32(scale)
+    x = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()[..., None]
+    ref, _ = unet.forward(p, x, W)
+    assert out.shape == ref.shape == (1, 64, 64, 2)
+    assert rel(out, ref) < 2e-2
+
+
 def test_full_size_network_runs(api):
     # the warm-start network at its real size: 256^2 input, widths 32..256
     W = (32, 64, 128, 256)

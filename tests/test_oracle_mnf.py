@@ -199,3 +199,35 @@ def test_literal_mode_fuses_normalised_images():
     raw = np.repeat(img[None], 2, axis=0)
     p = mnf.FuseParams(levels=2, sat=4095.0, radiometric=False)
     np.testing.assert_allclose(mnf.fuse_position(raw, [1.0, 1.0], p), img / 4095.0, rtol=1e-13)
+
+
+def test_literal_mode_step_is_in_normalised_units():
+    # Literal reading (radiometric = 0): the fused quantity is I_bar in [0, 1],
+    # so a step of delta ADU is delta / (sat - dark) there (Eq. 8 applied to
+    # the normalised images).  K = 1: the weight is 1, so every deviation comes
+    # from quantisation and stays within sum_l delta_l / (2 (sat - dark)).
+    # A step left in ADU (delta itself) would round every band coefficient of
+    # a [0, 1] image to 0 and miss this bound by orders of magnitude; a step of
+    # zero would leave no deviation at all.
+    rng = np.random.default_rng(31)
+    sat, dark = 4095.0, 15.0
+    raw = np.clip(rng.gamma(2.0, 600.0, size=(1, 48, 40)) + dark, 0, sat)
+    d = [3.0, 2.0, 1.5]
+    pq = mnf.FuseParams(levels=3, sat=sat, dark=dark, delta=d, radiometric=False)
+    p0 = mnf.FuseParams(levels=3, sat=sat, dark=dark, radiometric=False)
+    assert mnf.step_size(pq, 1, [1.0], 0) == pytest.approx(2.0 / (sat - dark), rel=1e-15)
+    out = mnf.fuse_position(raw, [1.0], pq)
+    Ibar = np.clip((raw[0] - dark) / (sat - dark), 0.0, 1.0)
+    np.testing.assert_allclose(mnf.fuse_position(raw, [1.0], p0), Ibar, rtol=0, atol=1e-12)
+    dev = np.abs(out - Ibar)
+    assert dev.max() <= sum(d) / (2 * (sat - dark)) + 1e-12
+    assert dev.max() > 0.1 * min(d) / (sat - dark)
+
+
+def test_literal_mode_step_ignores_exposure_times():
+    # in the literal reading every exposure is quantised in the same units
+    p = mnf.FuseParams(levels=2, sat=4095.0, dark=0.0, delta=[4.0, 2.0], radiometric=False)
+    t = [1.0, 10.0, 100.0]
+    for k in range(3):
+        assert mnf.step_size(p, 0, t, k) == 4.0 / 4095.0
+        assert mnf.step_size(p, 1, t, k) == 2.0 / 4095.0

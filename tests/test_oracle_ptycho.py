@@ -254,3 +254,31 @@ def test_phase_sync_gram_is_hermitian_psd_by_brute_force():
     # leading eigenvector of [[4, 2e^{i.5}], [2e^{-i.5}, 4]] is (e^{i.5}, 1)/sqrt 2
     want = np.array([np.exp(0.25j), np.exp(-0.25j)])
     assert np.abs(c - want).max() < 1e-12
+
+
+def test_conditioning_record_reproduces():
+    # the spreads recorded in tests/golden (written by make_conditioning.py from
+    # the oracle) are what the oracle gives now; the GPU bars scale with them
+    import json
+    import os
+    from _cases import SMALL_ONE_ITER_CASES, small_one_iter_spread
+    rec = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "conditioning_spreads.json")))
+    for alg, B, upd in SMALL_ONE_ITER_CASES:
+        sO, sP = small_one_iter_spread(alg, B, upd)
+        r = rec[f"{alg}-{B}-{upd}"]
+        assert sO == pytest.approx(r["spread_object"], rel=1e-9)
+        assert sP == pytest.approx(r["spread_probe"], rel=1e-9, abs=1e-15)
+
+
+def test_illumination_mask_by_hand():
+    # |P|^2 = [[1, 0], [0, 4]] at corners (0, 0) and (1, 1) of a 3 x 3 object:
+    # summed intensity [[1, 0, 0], [0, 5, 0], [0, 0, 4]], maximum 5
+    P = np.array([[1.0, 0.0], [0.0, 2.0j]])
+    pos = np.array([[0, 0], [1, 1]])
+    m = ptycho.illumination_mask(P, pos, (3, 3))          # threshold 0.5
+    np.testing.assert_array_equal(m, np.eye(3, dtype=bool))
+    m = ptycho.illumination_mask(P, pos, (3, 3), frac=0.3)  # threshold 1.5
+    np.testing.assert_array_equal(m, np.diag([False, True, True]))
+    m = ptycho.illumination_mask(P, pos, (3, 3), frac=0.9)  # threshold 4.5
+    np.testing.assert_array_equal(m, np.diag([False, True, False]))
