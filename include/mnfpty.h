@@ -162,6 +162,26 @@ int ptycho_iterate(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw,
                    const int32_t* order, int n_iter, const ptycho_params* params,
                    double* err_out, void* stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ptycho_iterate without
+ * any allocation.  Arguments, layouts, ownership and results are those of
+ * ptycho_iterate, except that params->graph must be 0 (MNF_EINVAL
+ * otherwise) and launch timing (mnf_profile) is suspended for the call.
+ * Every scratch buffer and staged host table of the call lives in one static
+ * device array of 48 MiB per GPU, held from the context's creation until the
+ * process ends; a call needing more (roughly batch x Nd^2 x 8 bytes of
+ * pattern scratch plus 16 bytes per position per iteration of tables) fails
+ * with MNF_EINVAL before any work is issued.  The fused intensities are
+ * read directly (square roots taken in the column pass) instead of through
+ * a per-call amplitude buffer.  All calls on one GPU share the array and it
+ * keeps the last call's contents: calls that overlap in time on one GPU
+ * (several streams, threads or contexts) race and must be serialised by
+ * the caller.  Nothing in the array needs to start at zero. */
+int ptycho_iterate_noalloc(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw,
+                           const float* I, int Nd, const int32_t* pos, int J,
+                           const int32_t* order, int n_iter, const ptycho_params* params,
+                           double* err_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Real-valued (sub-pixel) scan positions (Eq. 2 at positions such as the
  * Fermat spiral of Methods 3.3, which the integer entry points take rounded).

@@ -217,6 +217,17 @@ def ptycho_iterate(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_ite
                     batch, update_probe, probe_start_iter, order, it0, err, graph)
 
 
+def ptycho_iterate_noalloc(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_iter: int,
+                           alg: str = "rpie", alpha: float = 0.1, beta: float = 0.1, batch: int = 1,
+                           update_probe: bool = False, probe_start_iter: int = 0, order=None, it0: int = 0,
+                           err: bool = True) -> Optional[torch.Tensor]:
+    """ptycho_iterate through the entry point that allocates no device memory
+    (its scratch is the library's static 48 MiB array).  The returned error
+    tensor, when requested, is allocated here by torch, not by the library."""
+    return _iterate("ptycho_iterate_noalloc", _host_i32(pos, (2,), "pos"), _i32p, O, P, I, n_iter, alg, alpha,
+                    beta, batch, update_probe, probe_start_iter, order, it0, err, False)
+
+
 def ptycho_iterate_subpixel(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_iter: int,
                             alg: str = "rpie", alpha: float = 0.1, beta: float = 0.1, batch: int = 1,
                             update_probe: bool = False, probe_start_iter: int = 0, order=None, it0: int = 0,

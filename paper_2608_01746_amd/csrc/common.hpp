@@ -38,6 +38,15 @@ struct MnfProfile {
     double ms[MNF_K_NCLASS] = {};
 };
 
+// Bump allocator over caller-free memory (the library's static scratch):
+// while a context has one set, scratch buffers and staged host copies come
+// from it instead of device allocations.
+struct MnfArena {
+    char* base = nullptr;
+    size_t cap = 0;
+    size_t used = 0;
+};
+
 struct mnf_ctx {
     int device = 0;
     MnfProfile prof;
@@ -61,6 +70,10 @@ struct mnf_ctx {
     // status bits set by kernels (non-finite values, divergence), read and
     // cleared by mnf_status
     unsigned* d_status = nullptr;
+    // device address of this device's static scratch (see ptycho_iterate_noalloc)
+    void* noalloc_ptr = nullptr;
+    // set only for the duration of a call that must not allocate
+    MnfArena* arena = nullptr;
 };
 
 namespace mnf {
@@ -93,6 +106,10 @@ int upload(mnf_ctx* ctx, const char* name, const void* host, size_t bytes,
 
 // Device twiddle table for length N (computed in float64, rounded to float).
 int twiddles(mnf_ctx* ctx, int N, const float2** out);
+
+// Device address of the static scratch array of the context's device
+// (defined beside ptycho_iterate_noalloc); called once per context at creation.
+int noalloc_setup(mnf_ctx* ctx);
 
 // Launch timing: a pair of timing events for one launch of class `cls`,
 // passed to the launch itself (hipExtLaunchKernel records them at the start

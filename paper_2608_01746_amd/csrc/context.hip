@@ -21,6 +21,18 @@ int set_error(mnf_ctx* ctx, int code, const char* fmt, ...) {
 
 int scratch(mnf_ctx* ctx, const char* name, size_t bytes, void** out) {
     if (bytes == 0) bytes = 256;
+    if (ctx->arena) {
+        // 256-byte aligned pieces of the static scratch, in request order
+        MnfArena& a = *ctx->arena;
+        const size_t off = (a.used + 255) & ~(size_t)255;
+        if (off > a.cap || bytes > a.cap - off)
+            return set_error(ctx, MNF_EINVAL,
+                             "scratch '%s': this call needs more than the %zu bytes of static scratch (%zu used, "
+                             "%zu more requested)", name, a.cap, off, bytes);
+        *out = a.base + off;
+        a.used = off + bytes;
+        return MNF_OK;
+    }
     auto it = ctx->scratch.find(name);
     if (it != ctx->scratch.end() && it->second.second >= bytes) {
         *out = it->second.first;
@@ -49,6 +61,12 @@ int upload(mnf_ctx* ctx, const char* name, const void* host, size_t bytes, hipSt
            void** dev_out) {
     MNF_TRY(scratch(ctx, name, bytes, dev_out));
     if (bytes == 0) return MNF_OK;
+    if (ctx->arena) {
+        // no pinned staging: a copy from pageable memory, which the runtime
+        // stages before returning (so the host array may go out of scope)
+        MNF_HIP(ctx, hipMemcpyAsync(*dev_out, host, bytes, hipMemcpyHostToDevice, stream));
+        return MNF_OK;
+    }
     // the previous staged copy must have left the pinned buffer
     if (ctx->pinned_done) MNF_HIP(ctx, hipEventSynchronize(ctx->pinned_done));
     if (ctx->pinned_size < bytes) {
@@ -182,7 +200,7 @@ int mnf_create(mnf_ctx** out, int hip_device) {
         return create_failed(MNF_ENOMEM, std::string("status word: ") + hipGetErrorString(e));
     }
     // twiddle tables of every supported size up front, so that no later call
-    // needs to allocate one
+    // needs to allocate one; the static scratch's device address
     int32_t sizes[16];
     const int ns = mnf_supported_sizes(sizes, 16);
     for (int i = 0; i < ns; ++i) {
@@ -193,6 +211,12 @@ int mnf_create(mnf_ctx** out, int hip_device) {
             mnf_destroy(c);
             return create_failed(rc, msg);
         }
+    }
+    const int rc = mnf::noalloc_setup(c);
+    if (rc != MNF_OK) {
+        const std::string msg = "static scratch: " + c->err;
+        mnf_destroy(c);
+        return create_failed(rc, msg);
     }
     g_create_error.clear();
     *out = c;

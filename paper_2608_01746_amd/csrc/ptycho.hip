@@ -7,6 +7,7 @@
 // current mini-batch of every scan of one detector size.
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <vector>
 
 #include <cmath>
@@ -479,9 +480,10 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     pl.sub = sub;
     pl.modes = modes;
 
-    // per-scan scratch: P2 [Nw^2], maxP2_row [Nw], amplitudes [J][Nd][Nd] (FFT order),
-    // error partials [J][N/C], |A|^2 partials [J] and sum
-    const bool amp = true;
+    // per-scan scratch: P2 [Nw^2], maxP2_row [Nw], amplitudes [J][Nd][Nd] (FFT order;
+    // a call without allocations takes the square roots in the column pass
+    // instead), error partials [J][N/C], |A|^2 partials [J] and sum
+    const bool amp = ctx->arena == nullptr;
     size_t f_need = 0, d_need = 0;
     for (int k = 0; k < ns; ++k) {
         f_need += (size_t)in[k].Nw * in[k].Nw + in[k].Nw + (amp ? (size_t)in[k].J * in[k].Nd * in[k].Nd : 0);
@@ -518,7 +520,7 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     // error reduction jobs, one per scan per iteration.  A graph writes the
     // errors to an internal buffer [ns][n_iter], copied to err_out after each
     // replay, so that the caller's output addresses are not part of the graph.
-    const bool graph_req = p.graph != 0 && ctx->prof.mask == 0;
+    const bool graph_req = p.graph != 0 && ctx->prof.mask == 0 && ctx->arena == nullptr;
     double* err_buf = nullptr;
     if (graph_req) {
         void* eb;
@@ -887,7 +889,61 @@ int autotune_impl(mnf_ctx* ctx, int N, int nslots, int reps, double* times_us, h
 
 }  // namespace
 
+// ------------------------------------------------------ without allocations
+//
+// Static scratch of ptycho_iterate_noalloc: a file-scope device array that
+// every GPU the library runs on holds until the process ends.  Host code
+// never passes its name to a kernel (on the host the name stands for a host
+// object): the device address comes from hipGetSymbolAddress, once per
+// device at context creation, and only that address is used.
+constexpr size_t kNoAllocScratchBytes = (size_t)48 << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mutex;
+void* g_noalloc_ptr[kMaxDevices] = {};
+}  // namespace
+
+int mnf::noalloc_setup(mnf_ctx* ctx) {
+    if (ctx->device < 0 || ctx->device >= kMaxDevices)
+        return set_error(ctx, MNF_EINVAL, "device %d beyond the %d the static scratch table holds", ctx->device,
+                         kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_noalloc_mutex);
+    if (!g_noalloc_ptr[ctx->device]) {
+        void* ptr = nullptr;
+        // the context's device is current (mnf_create set it)
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(::scratch));
+        if (e != hipSuccess || !ptr)
+            return set_error(ctx, MNF_EHIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_noalloc_ptr[ctx->device] = ptr;
+    }
+    ctx->noalloc_ptr = g_noalloc_ptr[ctx->device];
+    return MNF_OK;
+}
+
 extern "C" {
+
+int ptycho_iterate_noalloc(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw, const float* I, int Nd,
+                           const int32_t* pos, int J, const int32_t* order, int n_iter, const ptycho_params* params,
+                           double* err_out, void* stream) {
+    MNF_TRY(begin(ctx));
+    if (!params) return set_error(ctx, MNF_EINVAL, "null params");
+    if (params->graph) return set_error(ctx, MNF_EINVAL, "graph = 1 is not available without allocations");
+    if (!ctx->noalloc_ptr) return set_error(ctx, MNF_EHIP, "the static scratch of device %d is not set up", ctx->device);
+    // every scratch piece and staged table of this call comes from the static
+    // scratch; launch timing (which creates events) is suspended
+    MnfArena arena{(char*)ctx->noalloc_ptr, kNoAllocScratchBytes, 0};
+    const uint32_t mask = ctx->prof.mask;
+    ctx->arena = &arena;
+    ctx->prof.mask = 0;
+    std::vector<ScanIn> in{ScanIn{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, pos, J, order, err_out, nullptr,
+                                  nullptr}};
+    const int rc = run_iterate(ctx, in, n_iter, *params, (hipStream_t)stream);
+    ctx->arena = nullptr;
+    ctx->prof.mask = mask;
+    return rc;
+}
 
 int mnf_autotune(mnf_ctx* ctx, int Nd, int nslots, int reps, double* times_us, void* stream) {
     MNF_TRY(begin(ctx));

@@ -60,6 +60,9 @@ SIGNATURES = {
                                POINTER(PtychoParamsC), c_void_p, c_void_p]),
     "ptycho_forward_subpixel": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_int,
                                         POINTER(c_float), c_int, c_void_p, c_void_p]),
+    "ptycho_iterate_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
+                                       POINTER(c_int32), c_int, POINTER(c_int32), c_int,
+                                       POINTER(PtychoParamsC), c_void_p, c_void_p]),
     "ptycho_iterate_subpixel": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
                                         POINTER(c_float), c_int, POINTER(c_int32), c_int,
                                         POINTER(PtychoParamsC), c_void_p, c_void_p]),

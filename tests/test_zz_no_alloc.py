@@ -1,0 +1,65 @@
+"""The entry point that allocates nothing (ptycho_iterate_noalloc, static
+scratch) against ptycho_iterate through the C ABI: two calls in a row on one
+GPU, the second with a smaller scan, each equal to the allocating entry
+point's result."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2608_01746_amd import synth
+
+from _cases import tiny_scan
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def api():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_01746_amd import api as _api
+    return _api
+
+
+def _both(api, M, Nw, Nd, n_side, step, B, n_iter, seed):
+    O, P, pos, I = tiny_scan(M, Nw, Nd, n_side, step, 2, seed=seed, jitter=1)
+    order = synth.random_orders(len(pos), n_iter, seed)
+    kw = dict(alg="rpie", alpha=0.2, beta=0.3, batch=B, update_probe=True, probe_start_iter=1, order=order)
+    It = torch.from_numpy(I.astype(np.float32)).to(DEV)
+    out = []
+    for fn in (api.ptycho_iterate, api.ptycho_iterate_noalloc):
+        Og = torch.ones((M, M), dtype=torch.complex64, device=DEV)
+        Pg = torch.from_numpy((P * 0.9).astype(np.complex64)).to(DEV)
+        e = fn(Og, Pg, It, pos, n_iter, **kw)
+        out.append((Og.cpu().numpy(), Pg.cpu().numpy(), e.cpu().numpy()))
+    return out
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def test_noalloc_matches_allocating_entry_point(api):
+    # a 256^2 scan first, then a smaller 64^2 one: the static scratch is reused
+    for args in [(520, 256, 256, 3, 120, 8, 3, 21), (160, 48, 64, 4, 30, 5, 4, 22)]:
+        (Oa, Pa, ea), (Ob, Pb, eb) = _both(api, *args)
+        assert _rel(Ob, Oa) <= 1e-6 and _rel(Pb, Pa) <= 1e-6, args
+        np.testing.assert_allclose(eb, ea, rtol=1e-6)
+
+
+def test_noalloc_rejects_graphs_and_oversize(api):
+    O, P, pos, I = tiny_scan(96, 32, 32, 3, 20, 2, seed=3)
+    Og = torch.ones((96, 96), dtype=torch.complex64, device=DEV)
+    Pg = torch.from_numpy(P.astype(np.complex64)).to(DEV)
+    It = torch.from_numpy(I.astype(np.float32)).to(DEV)
+    with pytest.raises(TypeError):
+        api.ptycho_iterate_noalloc(Og, Pg, It, pos, 1, graph=True)
+    # 512 positions of 512^2 in one mini-batch: 1 GiB of pattern scratch
+    M, N = 520, 512
+    pos = np.zeros((512, 2), np.int32)
+    Ob = torch.ones((M, M), dtype=torch.complex64, device=DEV)
+    Pb = torch.ones((N, N), dtype=torch.complex64, device=DEV)
+    Ib = torch.ones((512, N, N), dtype=torch.float32, device=DEV)
+    with pytest.raises(api.MnfError, match="static scratch"):
+        api.ptycho_iterate_noalloc(Ob, Pb, Ib, pos, 1, batch=512)
