@@ -271,6 +271,10 @@ def run_lab(args, api, synth, dev):
     iterate = api.ptycho_iterate_subpixel if sub else api.ptycho_iterate
     n_iter = args.iters
     tuned = tune_sizes([w.Nd], w.batch) if args.tune else None
+    if getattr(args, "three_launch", False):
+        from paper_2608_01746_amd import tune
+        tune.set_variant(w.Nd, tune.get_variant(w.Nd) | 4)
+        tuned = {str(w.Nd): tune.get_variant(w.Nd)}
     O_true = w.object()
     P = w.probe()
     Ot = torch.from_numpy(O_true.astype(np.complex64)).to(dev)
@@ -969,6 +973,8 @@ def main() -> int:
     ap.add_argument("--no-tune", dest="tune", action="store_false",
                     help="keep the default launch shapes instead of the tuned ones")
     ap.add_argument("--graph", action="store_true", help="lab: capture each step's iterations in a hipGraph")
+    ap.add_argument("--three-launch", action="store_true",
+                    help="lab: three launches per mini-batch (object update fused with the next exit waves)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 256 MiB device copy (a known-size reference for HBM counters)")
     args = ap.parse_args()

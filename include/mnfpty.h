@@ -378,18 +378,23 @@ int detector_resample(mnf_ctx* ctx, const float* I, int J, int Nd, float scale, 
 /* ------------------------------------------------------------------------
  * Launch-shape tuning.  Every pattern pass is compiled in two shapes (rows:
  * the default lines per block or half as many; columns: 32 columns per block
- * or 16), giving four variants per detector size: bit 0 selects the row
- * shape, bit 1 the column shape.  Variants change only launch geometry, never
- * the algorithm or the mini-batch, and give identical results up to the
- * order of float64 partial sums of the error.
+ * or 16); bit 0 of a variant selects the row shape, bit 1 the column shape.
+ * Bit 2 selects the pass structure of a single-scan, integer-position,
+ * single-mode reconstruction whose object box is at most 1024 pixels wide:
+ * three launches per mini-batch (the object update fused with the next
+ * mini-batch's exit-wave rows) instead of four.  Eight variants per detector
+ * size; they change only launch geometry and pass structure, never the
+ * algorithm or the mini-batch, and give identical results up to the order of
+ * float64 partial sums of the error.
  *
- * mnf_autotune times the four variants on a synthetic scan of `nslots`
- * positions (one mini-batch of that size per iteration, `reps` iterations),
- * keeps the fastest for size Nd on this context and returns its index
- * (0..3), or a negative error.  times_us (host double[4] or NULL) receives
- * the mean time of one iteration per variant.  It synchronises the stream.
- * mnf_set_variant / mnf_get_variant store or read a variant (e.g. from a
- * tuning cache kept by the caller). */
+ * mnf_autotune times the eight variants on a synthetic scan of `nslots`
+ * positions (one mini-batch of that size per iteration, `reps` iterations)
+ * in three interleaved rounds, keeps for size Nd on this context the variant
+ * with the lowest median time if it beats variant 0 by at least 3 % (else 0)
+ * and returns its index (0..7), or a negative error.  times_us (host
+ * double[8] or NULL) receives each variant's median time of one iteration.
+ * It synchronises the stream.  mnf_set_variant / mnf_get_variant store or
+ * read a variant (e.g. from a tuning cache kept by the caller). */
 int mnf_autotune(mnf_ctx* ctx, int Nd, int nslots, int reps, double* times_us, void* stream);
 int mnf_set_variant(mnf_ctx* ctx, int Nd, int variant);
 int mnf_get_variant(mnf_ctx* ctx, int Nd);

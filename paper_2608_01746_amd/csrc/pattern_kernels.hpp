@@ -493,22 +493,31 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
         const int k = (int)threadIdx.x + q * THREADS;
         if (k < nb) {
             const SlotDev sd = slots[gd.s0 + k];
-            if constexpr (DEN) {
-                // the slot's row-pass maxima, 16 loads at a time (the last
-                // index repeated past the end leaves the maximum unchanged)
-                const float* part = maxO2_part + (size_t)(gd.s0 + k) * nparts;
-                float m = 0.f;
-                for (int i0 = 0; i0 < nparts; i0 += 16) {
-                    float v[16];
-#pragma unroll
-                    for (int u = 0; u < 16; ++u) v[u] = part[min(i0 + u, nparts - 1)];
-#pragma unroll
-                    for (int u = 0; u < 16; ++u) m = fmaxf(m, v[u]);
-                }
-                s_max[k] = m;
-            }
             s_py[k] = sd.py;
             s_px[k] = sd.px;
+        }
+    }
+    if constexpr (DEN) {
+        // each slot's maximum of |O_s|^2 from the exit-wave pass's partial
+        // maxima (nparts per slot: 16 row blocks, or one per window row):
+        // G lanes of one wave per slot, 8 loads each in flight (the index
+        // clamped to the slot's last part, which leaves the maximum unchanged)
+        int G = 64;
+        while (G > 1 && G * nb > THREADS) G >>= 1;
+        const int lane = (int)threadIdx.x % G;
+        for (int kb = 0; kb < nb; kb += THREADS / G) {
+            const int k = kb + (int)threadIdx.x / G;
+            const float* part = maxO2_part + (size_t)(gd.s0 + min(k, nb - 1)) * nparts;
+            float m = 0.f;
+            for (int i0 = lane; i0 < nparts; i0 += 8 * G) {
+                float v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = part[min(i0 + u * G, nparts - 1)];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) m = fmaxf(m, v[u]);
+            }
+            for (int o = G / 2; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+            if (k < nb && lane == 0) s_max[k] = m;
         }
     }
     twr.store(tw);

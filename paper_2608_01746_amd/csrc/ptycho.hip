@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "objrow_kernels.hpp"
 #include "pattern_kernels.hpp"
 #include "shift_kernels.hpp"
 #include "update_kernels.hpp"
@@ -60,6 +61,9 @@ int variant_of(mnf_ctx* ctx, int N) {
     return it == ctx->variant.end() ? 0 : it->second;
 }
 int row_lines(mnf_ctx* ctx, int N) { return (variant_of(ctx, N) & 1) ? row_lines_v<1>(N) : row_lines_v<0>(N); }
+// variant bit 2: three launches per mini-batch where the object update can be
+// fused with the next mini-batch's exit-wave rows (k_obj_rows)
+bool three_launch(mnf_ctx* ctx, int N) { return (variant_of(ctx, N) & 4) != 0; }
 int col_groups(mnf_ctx* ctx, int N) {
     const int c0 = kColGroup < N ? kColGroup : N;
     return N / ((variant_of(ctx, N) & 2) ? c0 / 2 : c0);
@@ -415,7 +419,7 @@ template <int N>
 int issue_iterate_n(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
                     float* mO, const SubBufs* sb, hipStream_t st) {
     if (pl.modes > 1) {
-        switch (variant_of(ctx, N)) {
+        switch (variant_of(ctx, N) & 3) {
             case 1: return issue_modes_launch<N, 1, 0>(ctx, pl, L, p, upd, S, mO, st);
             case 2: return issue_modes_launch<N, 0, 1>(ctx, pl, L, p, upd, S, mO, st);
             case 3: return issue_modes_launch<N, 1, 1>(ctx, pl, L, p, upd, S, mO, st);
@@ -423,14 +427,14 @@ int issue_iterate_n(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const pty
         }
     }
     if (sb) {
-        switch (variant_of(ctx, N)) {
+        switch (variant_of(ctx, N) & 3) {
             case 1: return issue_subpixel_launch<N, 1, 0>(ctx, pl, L, p, upd, S, mO, *sb, st);
             case 2: return issue_subpixel_launch<N, 0, 1>(ctx, pl, L, p, upd, S, mO, *sb, st);
             case 3: return issue_subpixel_launch<N, 1, 1>(ctx, pl, L, p, upd, S, mO, *sb, st);
             default: return issue_subpixel_launch<N, 0, 0>(ctx, pl, L, p, upd, S, mO, *sb, st);
         }
     }
-    switch (variant_of(ctx, N)) {
+    switch (variant_of(ctx, N) & 3) {
         case 1: return issue_iterate_launch<N, 1, 0>(ctx, pl, L, p, upd, S, mO, st);
         case 2: return issue_iterate_launch<N, 0, 1>(ctx, pl, L, p, upd, S, mO, st);
         case 3: return issue_iterate_launch<N, 1, 1>(ctx, pl, L, p, upd, S, mO, st);
@@ -441,6 +445,74 @@ int issue_iterate_n(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const pty
 int issue_iterate_any(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
                       float* mO, const SubBufs* sb, hipStream_t st) {
     MNF_DISPATCH(L.N, issue_iterate_n, ctx, pl, L, p, upd, S, mO, sb, st)
+}
+
+// ---- three launches per mini-batch (one scan, integer positions, one mode)
+//
+// columns + inverse rows of mini-batch L on S (whose rows the previous
+// k_obj_rows launch wrote, with one |O|^2 maximum per window row)
+template <int N, int RV, int CV>
+int issue_cols_inv(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
+                   float* mO, hipStream_t st) {
+    const float2* tw;
+    MNF_TRY(twiddles(ctx, N, &tw));
+    const ScanDev* scans = (const ScanDev*)pl.d_scans;
+    const SlotDev* slots = (const SlotDev*)pl.d_slots + L.slot_off;
+    const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
+    const int nparts = pl.scans[0].Nw;
+    const int rpie = p.alg == 1;
+    const float2* nP = nullptr;
+    float2* nG = nullptr;
+    double* nD = nullptr;
+    MNF_LAUNCH(ctx, MNF_K_COLS_MODULUS, st, (k_cols_pointwise<N, CV, ColOp::Modulus>),
+               dim3(N / ColCfg<N, CV>::C, L.nslots), dim3(ColCfg<N, CV>::THREADS), scans, slots, S, 0.f, tw);
+    if (upd)
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 1>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, nparts, rpie, p.beta,
+                   (const double*)nullptr, 1, nP, nG, nD, (const float2*)nullptr, tw);
+    else
+        MNF_LAUNCH(ctx, MNF_K_ROWS_INV, st, (k_rows_inv_update<N, RV, 0>), dim3(L.maxNw, L.ngroups),
+                   dim3(UpdCfg<N, RV>::THREADS), scans, slots, groups, S, (const float*)mO, nparts, rpie, p.beta,
+                   (const double*)nullptr, 1, nP, nG, nD, (const float2*)nullptr, tw);
+    return MNF_OK;
+}
+
+template <int N>
+int issue_cols_inv_n(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
+                     float* mO, hipStream_t st) {
+    switch (variant_of(ctx, N) & 3) {
+        case 1: return issue_cols_inv<N, 1, 0>(ctx, pl, L, p, upd, S, mO, st);
+        case 2: return issue_cols_inv<N, 0, 1>(ctx, pl, L, p, upd, S, mO, st);
+        case 3: return issue_cols_inv<N, 1, 1>(ctx, pl, L, p, upd, S, mO, st);
+        default: return issue_cols_inv<N, 0, 0>(ctx, pl, L, p, upd, S, mO, st);
+    }
+}
+
+// object update of mini-batch Lu (from S_u; none for the call's first) and
+// exit-wave rows of mini-batch Lf (to S_f; none after the call's last)
+template <int N>
+int issue_obj_rows_n(mnf_ctx* ctx, const CallPlan& pl, const Launch* Lu, const Launch* Lf, const float2* S_u,
+                     float2* S_f, float* mO, const ptycho_params& p, hipStream_t st) {
+    const float2* tw;
+    MNF_TRY(twiddles(ctx, N, &tw));
+    const ScanDev& sc = pl.scans[0];
+    const SlotDev* d_slots = (const SlotDev*)pl.d_slots;
+    const int kind = Lf ? MNF_K_ROWS_FWD : MNF_K_OBJECT_UPDATE;
+    MNF_LAUNCH(ctx, kind, st, k_obj_rows<N>, dim3((unsigned)((sc.bh + kObjRowsPerBlock - 1) / kObjRowsPerBlock)),
+               dim3(kObjRowThreads), (const ScanDev*)pl.d_scans, Lu ? d_slots + Lu->slot_off : d_slots,
+               Lu ? Lu->nslots : 0, S_u, Lf ? d_slots + Lf->slot_off : d_slots, Lf ? Lf->nslots : 0, S_f, mO,
+               p.alg == 1 ? 1 : 0, p.alpha, tw);
+    return MNF_OK;
+}
+
+int issue_cols_inv_any(mnf_ctx* ctx, const CallPlan& pl, const Launch& L, const ptycho_params& p, bool upd, float2* S,
+                       float* mO, hipStream_t st) {
+    MNF_DISPATCH(L.N, issue_cols_inv_n, ctx, pl, L, p, upd, S, mO, st)
+}
+
+int issue_obj_rows_any(mnf_ctx* ctx, const CallPlan& pl, int N, const Launch* Lu, const Launch* Lf, const float2* S_u,
+                       float2* S_f, float* mO, const ptycho_params& p, hipStream_t st) {
+    MNF_DISPATCH(N, issue_obj_rows_n, ctx, pl, Lu, Lf, S_u, S_f, mO, p, st)
 }
 
 // ----------------------------------------------------------------- iterate
@@ -539,8 +611,22 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     void *d_jobs, *d_a2jobs, *S, *mO;
     MNF_TRY(upload(ctx, "plan_jobs", jobs.data(), sizeof(SumJob) * jobs.size(), st, &d_jobs));
     MNF_TRY(upload(ctx, "plan_a2jobs", a2jobs.data(), sizeof(SumJob) * a2jobs.size(), st, &d_a2jobs));
-    MNF_TRY(mnf::scratch(ctx, "S", pl.max_S, &S));
-    MNF_TRY(mnf::scratch(ctx, "maxO2", pl.max_maxO2 * sizeof(float), &mO));
+    // With launch-shape bit 2, one scan at integer positions with one probe
+    // mode takes three launches per mini-batch (object update fused with the
+    // next mini-batch's exit-wave rows, k_obj_rows) when its object box fits
+    // the pass's LDS rows; the pattern scratch is then double-buffered (the
+    // fused pass reads one mini-batch's numerators and writes the next one's
+    // rows) and the |O|^2 maxima are kept per window row.  The results are
+    // bit-identical to four launches; which is faster is left to the tuner
+    // (at 32 patterns of 256^2 the fused pass, one block's chain of loads,
+    // update, transforms and stores, is slower than the two passes it joins).
+    const bool fused = ns == 1 && !sub && modes == 1 && pl.scans[0].bw <= kObjRowMaxWidth &&
+                       three_launch(ctx, in[0].Nd);
+    const size_t sS = pl.max_S / sizeof(float2);  // complex values of one pattern buffer
+    MNF_TRY(mnf::scratch(ctx, "S", pl.max_S * (fused ? 2 : 1), &S));
+    MNF_TRY(mnf::scratch(ctx, "maxO2",
+                         std::max(pl.max_maxO2, fused ? (size_t)pl.max_slots * in[0].Nw : (size_t)0) * sizeof(float),
+                         &mO));
     SubBufs sbuf{nullptr, nullptr, nullptr};
     const SubBufs* sb = nullptr;
     if (sub) {
@@ -631,11 +717,24 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     }
     int rc = MNF_OK;
     size_t li = 0;
+    const size_t nL = pl.launches.size();
+    auto Sbuf = [&](size_t b) { return (float2*)S + (fused ? (b % 2) * sS : 0); };
     for (int i = 0; i < n_iter && rc == MNF_OK; ++i) {
         const int it = p.it0 + i;
         const bool upd = p.update_probe && it >= p.probe_start_iter;
-        for (; li < (size_t)pl.iter_end[i] && rc == MNF_OK; ++li)
-            rc = issue_iterate_any(ctx, pl, pl.launches[li], p, upd, (float2*)S, (float*)mO, sb, run);
+        for (; li < (size_t)pl.iter_end[i] && rc == MNF_OK; ++li) {
+            if (!fused) {
+                rc = issue_iterate_any(ctx, pl, pl.launches[li], p, upd, (float2*)S, (float*)mO, sb, run);
+                continue;
+            }
+            const Launch& L = pl.launches[li];
+            if (li == 0)
+                rc = issue_obj_rows_any(ctx, pl, L.N, nullptr, &L, nullptr, Sbuf(0), (float*)mO, p, run);
+            if (rc == MNF_OK) rc = issue_cols_inv_any(ctx, pl, L, p, upd, Sbuf(li), (float*)mO, run);
+            if (rc == MNF_OK)
+                rc = issue_obj_rows_any(ctx, pl, L.N, &L, li + 1 < nL ? &pl.launches[li + 1] : nullptr, Sbuf(li),
+                                        Sbuf(li + 1), (float*)mO, p, run);
+        }
         if (rc == MNF_OK && any_err) {
             hipLaunchKernelGGL(k_sum_jobs, dim3(ns), dim3(256), 0, run, (const SumJob*)d_jobs + (size_t)i * ns, 1.0);
         }
@@ -721,7 +820,7 @@ int forward_v(mnf_ctx* ctx, const CallPlan& pl, float* I_out, const SubBufs* sb,
 
 template <int N>
 int forward_n(mnf_ctx* ctx, const CallPlan& pl, float* I_out, const SubBufs* sb, hipStream_t st) {
-    switch (variant_of(ctx, N)) {
+    switch (variant_of(ctx, N) & 3) {
         case 1: return forward_v<N, 1, 0>(ctx, pl, I_out, sb, st);
         case 2: return forward_v<N, 0, 1>(ctx, pl, I_out, sb, st);
         case 3: return forward_v<N, 1, 1>(ctx, pl, I_out, sb, st);
@@ -783,7 +882,7 @@ int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
 template <int N>
 int grad_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, const double* upstream, double* loss_out,
            hipStream_t st) {
-    switch (variant_of(ctx, N)) {
+    switch (variant_of(ctx, N) & 3) {
         case 1: return grad_v<N, 1, 0>(ctx, pl, s, kind, eps, upstream, loss_out, st);
         case 2: return grad_v<N, 0, 1>(ctx, pl, s, kind, eps, upstream, loss_out, st);
         case 3: return grad_v<N, 1, 1>(ctx, pl, s, kind, eps, upstream, loss_out, st);
@@ -857,32 +956,43 @@ int autotune_impl(mnf_ctx* ctx, int N, int nslots, int reps, double* times_us, h
     MNF_HIP(ctx, hipEventCreate(&e0));
     MNF_HIP(ctx, hipEventCreate(&e1));
     const int saved = variant_of(ctx, N);
-    int best = 0;
-    double best_t = 1e300;
+    // Three interleaved rounds over the variants (launch shapes x pass
+    // structure), the median time of each kept; a variant replaces the default
+    // only when it is faster by at least kMargin, so run-to-run noise does not
+    // flip the pick.
+    constexpr int kVariants = 8, kRounds = 3;
+    constexpr double kMargin = 0.03;
+    std::vector<double> t((size_t)kVariants * kRounds, 0.0);
     int rc = MNF_OK;
-    for (int v = 0; v < 4 && rc == MNF_OK; ++v) {
-        ctx->variant[N] = v;
-        rc = run_iterate(ctx, in, 1, p, st);  // warm-up (also sizes the scratch)
-        if (rc != MNF_OK) break;
-        if (hipEventRecord(e0, st) != hipSuccess) { rc = MNF_EHIP; break; }
-        rc = run_iterate(ctx, in, reps, p, st);
-        if (rc != MNF_OK) break;
-        if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = MNF_EHIP; break; }
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const double us = 1e3 * ms / reps;
-        if (times_us) times_us[v] = us;
-        if (us < best_t) {
-            best_t = us;
-            best = v;
+    for (int r = 0; r < kRounds && rc == MNF_OK; ++r)
+        for (int v = 0; v < kVariants && rc == MNF_OK; ++v) {
+            ctx->variant[N] = v;
+            if (r == 0) rc = run_iterate(ctx, in, 1, p, st);  // warm-up (also sizes the scratch)
+            if (rc != MNF_OK) break;
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = MNF_EHIP; break; }
+            rc = run_iterate(ctx, in, reps, p, st);
+            if (rc != MNF_OK) break;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) { rc = MNF_EHIP; break; }
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            t[(size_t)v * kRounds + r] = 1e3 * ms / reps;
         }
-    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (rc != MNF_OK) {
         ctx->variant[N] = saved;
         return rc == MNF_EHIP ? set_error(ctx, MNF_EHIP, "event timing failed during tuning") : rc;
     }
+    double med[kVariants];
+    for (int v = 0; v < kVariants; ++v) {
+        double* x = &t[(size_t)v * kRounds];
+        std::sort(x, x + kRounds);
+        med[v] = x[kRounds / 2];
+        if (times_us) times_us[v] = med[v];
+    }
+    int best = 0;
+    for (int v = 1; v < kVariants; ++v)
+        if (med[v] < med[best] && med[v] < (1.0 - kMargin) * med[0]) best = v;
     ctx->variant[N] = best;
     return best;
 }
@@ -953,7 +1063,7 @@ int mnf_autotune(mnf_ctx* ctx, int Nd, int nslots, int reps, double* times_us, v
 int mnf_set_variant(mnf_ctx* ctx, int Nd, int variant) {
     MNF_TRY(begin(ctx));
     if (!size_supported(Nd)) return set_error(ctx, MNF_EUNSUPPORTED, "detector size %d has no FFT plan", Nd);
-    if (variant < 0 || variant > 3) return set_error(ctx, MNF_EINVAL, "variant must be 0..3");
+    if (variant < 0 || variant > 7) return set_error(ctx, MNF_EINVAL, "variant must be 0..7");
     ctx->variant[Nd] = variant;
     return MNF_OK;
 }

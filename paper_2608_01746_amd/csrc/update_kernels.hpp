@@ -159,8 +159,8 @@ k_object_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ s
         if (yy < sc.by0 + sc.bh && den[q] > 0.0) {
             const float inv = (float)(1.0 / den[q]);  // the float64 denominator, inverted once
             float2 v = ov[q];
-            v.x += num[q].x * inv;
-            v.y += num[q].y * inv;
+            v.x = fmaf(num[q].x, inv, v.x);
+            v.y = fmaf(num[q].y, inv, v.y);
             sc.O[(size_t)yy * sc.Mx + xx] = v;
         }
     }

@@ -61,7 +61,7 @@ def autotune(sizes: Iterable[int], batch: int = 32, reps: int = 10, device="cuda
         key = f"{arch}:{int(N)}:{int(batch)}"
         entry = data.get(key)
         if entry is None or force:
-            times = (ctypes.c_double * 4)()
+            times = (ctypes.c_double * 8)()
             v = lib.mnf_autotune(ctx, int(N), int(batch), int(reps), times,
                                  ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
             _api._check(v if v < 0 else 0, ctx)

@@ -6,7 +6,7 @@ import pytest
 import torch
 
 from oracle import ptycho
-from paper_2608_01746_amd import synth
+from paper_2608_01746_amd import synth, tune
 
 from _cases import c64, f32, soft_probe, tiny_scan
 
@@ -155,3 +155,25 @@ def test_cached_graph_replays_and_recaptures(api):
         Od, Pd = tc64(np.ones_like(O)), tc64(P * 0.8)
         ed = api.ptycho_iterate(Od, Pd, It, pos, 3, order=order, **kw)
         assert torch.equal(Og, Od) and torch.equal(Pg, Pd) and torch.equal(eg, ed), seed
+
+
+@pytest.mark.parametrize("Nd,Nw,M,B,n_side,step", [(256, 256, 520, 8, 3, 120), (64, 48, 300, 7, 6, 40),
+                                                   (128, 100, 400, 5, 5, 60), (512, 512, 900, 4, 2, 300)])
+def test_three_launch_path_equals_four_launch_path(api, Nd, Nw, M, B, n_side, step):
+    # one scan at integer positions takes the fused object-update / exit-wave
+    # pass (three launches per mini-batch); launch-shape bit 2 keeps four.
+    # The sums run in the same order, so the results are bit-identical,
+    # including ragged last mini-batches, probe updates from iteration 1 and
+    # iteration boundaries inside the fused pass
+    O, P, pos, I = tiny_scan(M, Nw, Nd, n_side, step, 2, seed=Nd + 1, jitter=1)
+    order = synth.random_orders(len(pos), 3, 4)
+    res = []
+    for v in (0, 4):
+        tune.set_variant(Nd, v)
+        Og, Pg = tc64(np.ones_like(O)), tc64(P * 0.9)
+        e = api.ptycho_iterate(Og, Pg, tf32(I), pos, 3, alg="rpie", alpha=0.3, beta=0.2, batch=B,
+                               update_probe=True, probe_start_iter=1, order=order)
+        res.append((Og.cpu(), Pg.cpu(), e.cpu()))
+    tune.set_variant(Nd, 0)
+    for a, b in zip(*res):
+        assert torch.equal(a, b)
