@@ -80,7 +80,7 @@ __device__ __forceinline__ void level0_eval(const float* cnt, int K, const FuseC
             gi[kk] = c.radiometric ? (I - c.dark) * c.scale[kk] : Ib;
         }
     }
-    const float inv = 1.f / fmaxf(wsum, 1e-30f);
+    const float inv = __builtin_amdgcn_rcpf(fmaxf(wsum, 1e-30f));  // ~1 ulp, far inside the 1e-6 weight bound
 #pragma unroll
     for (int kk = 0; kk < KM; ++kk) gw[kk] = gw[kk] * inv;
 }
@@ -187,6 +187,46 @@ k_fuse_level1_tiled(const uint16_t* __restrict__ raw, int K, int H, int W, size_
         }
     }
     __syncthreads();
+    // separable reduce: every footprint row filtered along x at the tile's
+    // output columns (the same taps and order as the untiled kernel: row sums
+    // first, then the column sum).  The row sums are formed in registers and,
+    // after a barrier, written over the level-0 tile, so the block's LDS stays
+    // that of the tile.
+    constexpr int NH = kL1RY * kL1TX, HPER = (NH + THREADS - 1) / THREADS;
+    float hi[HPER][KM], hw[HPER][KM];
+#pragma unroll
+    for (int u = 0; u < HPER; ++u) {
+        const int e = min((int)threadIdx.x + u * THREADS, NH - 1);
+        const int ry = e / kL1TX, tx = e - ry * kL1TX;
+        const int p = ry * kL1RX + 2 * tx;
+#pragma unroll
+        for (int kk = 0; kk < KM; ++kk) {
+            float ri = 0.f, rw = 0.f;
+            if (kk < K) {
+#pragma unroll
+                for (int bb = 0; bb < 5; ++bb) {
+                    ri += binom5(bb) * LI[kk * kL1R + p + bb];
+                    rw += binom5(bb) * LW[kk * kL1R + p + bb];
+                }
+            }
+            hi[u][kk] = ri;
+            hw[u][kk] = rw;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < HPER; ++u) {
+        const int e = (int)threadIdx.x + u * THREADS;
+        if (e < NH) {
+#pragma unroll
+            for (int kk = 0; kk < KM; ++kk)
+                if (kk < K) {
+                    LI[kk * NH + e] = hi[u][kk];
+                    LW[kk * NH + e] = hw[u][kk];
+                }
+        }
+    }
+    __syncthreads();
     const int ty = threadIdx.x / kL1TX, tx = threadIdx.x % kL1TX;
     const int oy = oy0 + ty, ox = ox0 + tx;
     if (oy >= h1 || ox >= w1) return;
@@ -195,24 +235,13 @@ k_fuse_level1_tiled(const uint16_t* __restrict__ raw, int K, int H, int W, size_
     for (int kk = 0; kk < KM; ++kk) si[kk] = sw[kk] = 0.f;
 #pragma unroll
     for (int a = 0; a < 5; ++a) {
-        float ri[KM], rw[KM];
+        const int e = (2 * ty + a) * kL1TX + tx;
 #pragma unroll
-        for (int kk = 0; kk < KM; ++kk) ri[kk] = rw[kk] = 0.f;
-#pragma unroll
-        for (int bb = 0; bb < 5; ++bb) {
-            const int p = (2 * ty + a) * kL1RX + 2 * tx + bb;
-#pragma unroll
-            for (int kk = 0; kk < KM; ++kk)
-                if (kk < K) {
-                    ri[kk] += binom5(bb) * LI[kk * kL1R + p];
-                    rw[kk] += binom5(bb) * LW[kk * kL1R + p];
-                }
-        }
-#pragma unroll
-        for (int kk = 0; kk < KM; ++kk) {
-            si[kk] += binom5(a) * ri[kk];
-            sw[kk] += binom5(a) * rw[kk];
-        }
+        for (int kk = 0; kk < KM; ++kk)
+            if (kk < K) {
+                si[kk] += binom5(a) * LI[kk * NH + e];
+                sw[kk] += binom5(a) * LW[kk * NH + e];
+            }
     }
     const size_t i = (size_t)jj * h1 * w1 + (size_t)oy * w1 + ox;
 #pragma unroll
@@ -410,6 +439,72 @@ k_fuse_band(const float* __restrict__ GI, const float* __restrict__ GW, size_t s
     F[i] = acc;
 }
 
+// Band level l < L as k_fuse_band, one thread per level-(l+1) pixel, i.e. per
+// 2 x 2 quad of level-l pixels (totalc = nj * (h/2) * (w/2)): the quad's
+// expand taps share the 3 x 3 neighbourhood of each exposure's level-(l+1)
+// image (separable expand as in k_fuse_final_quad); the quad's level-l
+// values are two 64-bit loads per array.  K == KM exposures, summed in order.
+struct BandQuant {
+    float step[kMaxK];  // quantisation step of each exposure at this level (0 = none)
+    float inv[kMaxK];   // 1 / step
+};
+
+template <int KM>
+__global__ void __launch_bounds__(256)
+k_fuse_band_quad(const float* __restrict__ GI, const float* __restrict__ GW, size_t stride,
+                 const float* __restrict__ GIc, size_t stride_c, int h, int w, size_t totalc, BandQuant q,
+                 float* __restrict__ F) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= totalc) return;
+    const int hc = h >> 1, wc = w >> 1;
+    const size_t jj = i / ((size_t)hc * wc);
+    const int r = (int)(i - jj * (size_t)hc * wc);
+    const int cy = r / wc, cx = r - cy * wc;
+    const int ry[3] = {cy > 0 ? cy - 1 : 1, cy, cy + 1 < hc ? cy + 1 : hc - 1};
+    const int rx[3] = {cx > 0 ? cx - 1 : 1, cx, cx + 1 < wc ? cx + 1 : wc - 1};
+    const size_t fo = jj * (size_t)h * w + (size_t)(2 * cy) * w + 2 * cx;
+    const size_t co = jj * (size_t)hc * wc;
+    float g[KM][9];
+    float2 vi[KM][2], vw[KM][2];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        const float* gc = GIc + (size_t)k * stride_c + co;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) g[k][3 * a + b] = gc[(size_t)ry[a] * wc + rx[b]];
+        const float* gi = GI + (size_t)k * stride + fo;
+        const float* gw = GW + (size_t)k * stride + fo;
+        vi[k][0] = *(const float2*)gi;
+        vi[k][1] = *(const float2*)(gi + w);
+        vw[k][0] = *(const float2*)gw;
+        vw[k][1] = *(const float2*)(gw + w);
+    }
+    float acc[4];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        float he[3], ho[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            he[a] = fmaf(0.125f, g[k][3 * a], fmaf(0.75f, g[k][3 * a + 1], 0.125f * g[k][3 * a + 2]));
+            ho[a] = fmaf(0.5f, g[k][3 * a + 1], 0.5f * g[k][3 * a + 2]);
+        }
+        const float up[4] = {fmaf(0.125f, he[0], fmaf(0.75f, he[1], 0.125f * he[2])),
+                             fmaf(0.125f, ho[0], fmaf(0.75f, ho[1], 0.125f * ho[2])),
+                             fmaf(0.5f, he[1], 0.5f * he[2]), fmaf(0.5f, ho[1], 0.5f * ho[2])};
+        const float fi[4] = {vi[k][0].x, vi[k][0].y, vi[k][1].x, vi[k][1].y};
+        const float fw[4] = {vw[k][0].x, vw[k][0].y, vw[k][1].x, vw[k][1].y};
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+            float v = fw[d] * (fi[d] - up[d]);
+            if (q.step[k] > 0.f) v = q.step[k] * rintf(v * q.inv[k]);
+            acc[d] = k == 0 ? v : acc[d] + v;
+        }
+    }
+    *(float2*)(F + fo) = make_float2(acc[0], acc[1]);
+    *(float2*)(F + fo + w) = make_float2(acc[2], acc[3]);
+}
+
 // Collapse step: R_l = U(R_{l+1}) + F_l, written to out (F_l in place, or the
 // fused output at level 0).
 __global__ void __launch_bounds__(256)
@@ -490,7 +585,125 @@ k_fuse_final(const uint16_t* __restrict__ raw, int K, int H, int W, size_t total
     out[i] = F + (BATCH ? expand_sum(e, rv) : expand_at(R1 + (size_t)jj * h1 * w1, h1, w1, y, x));
 }
 
+// Level 0 and the output as k_fuse_final (L >= 1), one thread per 2 x 2 quad of
+// level-0 pixels, i.e. per level-1 pixel (total1 = nj * (H/2) * (W/2)): the
+// expand taps of the quad's four pixels all lie in the 3 x 3 level-1
+// neighbourhood rows {c-1, c, c+1} x columns {c-1, c, c+1} of its level-1
+// pixel (reflected as in expand_taps), so every exposure's level-1 image and
+// R_1 are loaded once per quad, expanded separably (per row the even-column
+// value (1 6 1)/8 and the odd-column value (1 1)/2, then the same weights
+// down the rows), and the two raw counts of a quad row are one 32-bit load.
+// K == KM exposures; quantisation multiplies by the step's reciprocal.
+struct Level0Quant {
+    float step[kMaxK];  // level-0 quantisation step of each exposure (0 = none)
+    float inv[kMaxK];   // 1 / step
+};
+
+template <int KM>
+__global__ void __launch_bounds__(256)
+k_fuse_final_quad(const uint16_t* __restrict__ raw, int H, int W, size_t total1, FuseConsts c, Level0Quant q,
+                  const float* __restrict__ GI1, const float* __restrict__ R1, float* __restrict__ out,
+                  float* __restrict__ weights_out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // the chunk keeps totals below 2^31
+    if (i >= (int)total1) return;
+    const int h1 = H >> 1, w1 = W >> 1;
+    const int jj = i / (h1 * w1), r = i - jj * (h1 * w1);
+    const int cy = r / w1, cx = r - cy * w1;
+    const size_t npix = (size_t)H * W;
+    const size_t n1 = total1;  // level-1 pixels of the chunk (exposure stride of GI1)
+    // the quad's raw counts: two adjacent 16-bit counts per row and exposure
+    const uint16_t* base = raw + (size_t)jj * KM * npix + (size_t)(2 * cy) * W + 2 * cx;
+    uint32_t q0[KM], q1[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) {
+        q0[k] = *(const uint32_t*)(base + (size_t)k * npix);
+        q1[k] = *(const uint32_t*)(base + (size_t)k * npix + W);
+    }
+    // 3 x 3 level-1 neighbourhood (g[-1] = g[1], g[n] = g[n-1])
+    const int ry[3] = {cy > 0 ? cy - 1 : 1, cy, cy + 1 < h1 ? cy + 1 : h1 - 1};
+    const int rx[3] = {cx > 0 ? cx - 1 : 1, cx, cx + 1 < w1 ? cx + 1 : w1 - 1};
+    const size_t off1 = (size_t)jj * h1 * w1;
+    float g[KM + 1][9];
+#pragma unroll
+    for (int k = 0; k <= KM; ++k) {
+        const float* src = k < KM ? GI1 + (size_t)k * n1 + off1 : R1 + off1;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) g[k][3 * a + b] = src[(size_t)ry[a] * w1 + rx[b]];
+    }
+    // separable expand of each coarse image at the quad's four pixels: up[k][2 dy + dx]
+    float up[KM + 1][4];
+#pragma unroll
+    for (int k = 0; k <= KM; ++k) {
+        float he[3], ho[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            he[a] = fmaf(0.125f, g[k][3 * a], fmaf(0.75f, g[k][3 * a + 1], 0.125f * g[k][3 * a + 2]));
+            ho[a] = fmaf(0.5f, g[k][3 * a + 1], 0.5f * g[k][3 * a + 2]);
+        }
+        up[k][0] = fmaf(0.125f, he[0], fmaf(0.75f, he[1], 0.125f * he[2]));
+        up[k][1] = fmaf(0.125f, ho[0], fmaf(0.75f, ho[1], 0.125f * ho[2]));
+        up[k][2] = fmaf(0.5f, he[1], 0.5f * he[2]);
+        up[k][3] = fmaf(0.5f, ho[1], 0.5f * ho[2]);
+    }
+    float res[4];
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+        const int dy = d >> 1, dx = d & 1;
+        float cnt[KM];
+#pragma unroll
+        for (int k = 0; k < KM; ++k) cnt[k] = (float)(((dy ? q1[k] : q0[k]) >> (16 * dx)) & 0xffffu);
+        float gi[KM], gw[KM];
+        level0_eval<KM>(cnt, KM, c, gi, gw);
+        if (weights_out) {
+            const size_t pq = (size_t)(2 * cy + dy) * W + 2 * cx + dx;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) weights_out[((size_t)jj * KM + k) * npix + pq] = gw[k];
+        }
+        float F = 0.f;
+#pragma unroll
+        for (int k = 0; k < KM; ++k) {
+            float v = gw[k] * (gi[k] - up[k][d]);
+            if (q.step[k] > 0.f) v = q.step[k] * rintf(v * q.inv[k]);
+            F = k == 0 ? v : F + v;
+        }
+        res[d] = F + up[KM][d];
+    }
+    float* o = out + (size_t)jj * npix + (size_t)(2 * cy) * W + 2 * cx;
+    *(float2*)o = make_float2(res[0], res[1]);
+    *(float2*)(o + W) = make_float2(res[2], res[3]);
+}
+
 inline dim3 grid1d(size_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+// Launch helpers dispatching on the exposure count so that the per-exposure
+// loops of the level-0 kernels are exactly K long.
+template <int KM>
+int launch_level1(mnf_ctx* ctx, hipStream_t st, const uint16_t* rawc, int K, int H, int W, size_t n1, int nj,
+                  const FuseConsts& c, float* GI1, float* GW1) {
+    const size_t tiles = (size_t)((W / 2 + kL1TX - 1) / kL1TX) * ((H / 2 + kL1TY - 1) / kL1TY) * nj;
+    MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level1_tiled<KM>, dim3((unsigned)tiles), dim3(kL1TY * kL1TX), rawc, K, H,
+               W, n1, c, GI1, GW1);
+    return MNF_OK;
+}
+
+template <int KM>
+int launch_band_quad(mnf_ctx* ctx, hipStream_t st, const float* GI, const float* GW, size_t stride, const float* GIc,
+                     size_t stride_c, int h, int w, size_t totalc, const BandQuant& q, float* F) {
+    MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_band_quad<KM>, grid1d(totalc), dim3(256), GI, GW, stride, GIc, stride_c, h,
+               w, totalc, q, F);
+    return MNF_OK;
+}
+
+template <int KM>
+int launch_final_quad(mnf_ctx* ctx, hipStream_t st, const uint16_t* rawc, int H, int W, size_t n1,
+                      const FuseConsts& c, const Level0Quant& q, const float* GI1, const float* R1, float* outc,
+                      float* wout) {
+    MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_final_quad<KM>, grid1d(n1), dim3(256), rawc, H, W, n1, c, q, GI1, R1, outc,
+               wout);
+    return MNF_OK;
+}
 
 }  // namespace
 
@@ -597,10 +810,15 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
         const uint16_t* rawc = raw + (size_t)j0 * K * npix;
         const size_t n1 = (size_t)nj * n1pos;
         if (L >= 1) {
+            switch (K) {
+                case 1: MNF_TRY(launch_level1<1>(ctx, st, rawc, K, H, W, n1, nj, c, GI1, GW1)); break;
+                case 2: MNF_TRY(launch_level1<2>(ctx, st, rawc, K, H, W, n1, nj, c, GI1, GW1)); break;
+                case 3: MNF_TRY(launch_level1<3>(ctx, st, rawc, K, H, W, n1, nj, c, GI1, GW1)); break;
+                case 4: MNF_TRY(launch_level1<4>(ctx, st, rawc, K, H, W, n1, nj, c, GI1, GW1)); break;
+                case 5: MNF_TRY(launch_level1<5>(ctx, st, rawc, K, H, W, n1, nj, c, GI1, GW1)); break;
+                default: break;
+            }
             if (K <= 5) {
-                const size_t tiles = (size_t)((W / 2 + kL1TX - 1) / kL1TX) * ((H / 2 + kL1TY - 1) / kL1TY) * nj;
-                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level1_tiled<5>, dim3((unsigned)tiles), dim3(kL1TY * kL1TX),
-                           rawc, K, H, W, n1, c, GI1, GW1);
             } else if (small_k)
                 MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level1<8>, grid1d(n1), dim3(256), rawc, K, H, W, n1, c, GI1, GW1);
             else
@@ -622,6 +840,29 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
             for (int l = 1; l <= L; ++l) {
                 const int h = H >> l, w = W >> l;
                 const size_t nn = (size_t)nj * h * w;
+                // the quad form reads each level-l array with 64-bit loads: every
+                // exposure's array must start 8-byte aligned (even stride)
+                if (l < L && small_k && sstride(l) % 2 == 0) {
+                    BandQuant bq{};
+                    for (int k = 0; k < K; ++k) {
+                        bq.step[k] = step[(size_t)l * K + k];
+                        bq.inv[k] = bq.step[k] > 0.f ? (float)(1.0 / (double)bq.step[k]) : 0.f;
+                    }
+                    const size_t nc = nn / 4;
+                    const float *gi = lvlI(l), *gw = lvlW(l), *gc = lvlI(l + 1);
+                    const size_t ss = sstride(l);
+                    switch (K) {
+                        case 1: MNF_TRY(launch_band_quad<1>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
+                        case 2: MNF_TRY(launch_band_quad<2>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
+                        case 3: MNF_TRY(launch_band_quad<3>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
+                        case 4: MNF_TRY(launch_band_quad<4>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
+                        case 5: MNF_TRY(launch_band_quad<5>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
+                        case 6: MNF_TRY(launch_band_quad<6>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
+                        case 7: MNF_TRY(launch_band_quad<7>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
+                        default: MNF_TRY(launch_band_quad<8>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
+                    }
+                    continue;
+                }
                 BandSteps bs{};
                 for (int k = 0; k < K; ++k) bs.step[k] = l < L ? step[(size_t)l * K + k] : 0.f;
                 MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_band, grid1d(nn), dim3(256), lvlI(l), lvlW(l), sstride(l),
@@ -638,7 +879,26 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
         float* outc = fused + (size_t)j0 * npix;
         float* wout = weights_out ? weights_out + (size_t)j0 * K * npix : (float*)nullptr;
         const float* R1 = L >= 1 ? F : (const float*)nullptr;  // fused level 1 sits first in F
-        if (small_k)
+        // the quad kernel reads two counts per 32-bit load and writes two outputs
+        // per 64-bit store (W is even when L >= 1)
+        const bool quad = L >= 1 && small_k && (uintptr_t)raw % 4 == 0 && (uintptr_t)fused % 8 == 0;
+        if (quad) {
+            Level0Quant qq{};
+            for (int k = 0; k < K; ++k) {
+                qq.step[k] = q0.step[k];
+                qq.inv[k] = q0.step[k] > 0.f ? (float)(1.0 / (double)q0.step[k]) : 0.f;
+            }
+            switch (K) {
+                case 1: MNF_TRY(launch_final_quad<1>(ctx, st, rawc, H, W, n1, c, qq, GI1, R1, outc, wout)); break;
+                case 2: MNF_TRY(launch_final_quad<2>(ctx, st, rawc, H, W, n1, c, qq, GI1, R1, outc, wout)); break;
+                case 3: MNF_TRY(launch_final_quad<3>(ctx, st, rawc, H, W, n1, c, qq, GI1, R1, outc, wout)); break;
+                case 4: MNF_TRY(launch_final_quad<4>(ctx, st, rawc, H, W, n1, c, qq, GI1, R1, outc, wout)); break;
+                case 5: MNF_TRY(launch_final_quad<5>(ctx, st, rawc, H, W, n1, c, qq, GI1, R1, outc, wout)); break;
+                case 6: MNF_TRY(launch_final_quad<6>(ctx, st, rawc, H, W, n1, c, qq, GI1, R1, outc, wout)); break;
+                case 7: MNF_TRY(launch_final_quad<7>(ctx, st, rawc, H, W, n1, c, qq, GI1, R1, outc, wout)); break;
+                default: MNF_TRY(launch_final_quad<8>(ctx, st, rawc, H, W, n1, c, qq, GI1, R1, outc, wout)); break;
+            }
+        } else if (small_k)
             MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_final<8>, grid1d(n0), dim3(256), rawc, K, H, W, n0, c, q0,
                        (const float*)GI1, R1, L, outc, wout);
         else
