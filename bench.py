@@ -29,6 +29,10 @@ entry is the network's forward pass in TFLOP/s against the bf16 MFMA peak.
 positions with the same density, through the Fourier-translated-probe entry
 points (translation passes added to every mini-batch); traffic is null there
 (the stored counters describe the integer-position kernels).
+--workload small runs the small configuration: 192^2 object, 64^2 probe
+(r = 16), 10 x 10 raster of pitch 8 (100 positions), 3 exposures (1, 10, 100;
+12 bit, read noise 2), 4-level fusion, 50 ePIE iterations with mini-batches
+of one, probe refined from iteration 5 (one workgroup runs the whole call).
 --workload grad times the loss gradient (the adjoint) on the 2048^2 /
 512^2 / 1000-position gradient workload in position-gradients/s.
 --workload unet times the network's training step and inference alone.
@@ -159,7 +163,8 @@ def batch_update_all_cores(O, P, A, pos, idx, alpha, beta, update_probe, workers
     return O_new, P_new, err
 
 
-def cpu_baseline(w, O_true, P, clean, scale, seconds: float, sub: bool = False):
+def cpu_baseline(w, O_true, P, clean, scale, seconds: float, sub: bool = False, alg: str = "rpie",
+                 step: float = 0.1):
     """The float64 oracle on the host: rPIE mini-batches of the same workload
     (at real positions with the sub-pixel oracle when `sub`), repeated for
     about `seconds`; returns position updates per second."""
@@ -170,7 +175,7 @@ def cpu_baseline(w, O_true, P, clean, scale, seconds: float, sub: bool = False):
     A = ptycho.amplitudes(I)
     O = np.ones_like(O_true)
     Pk = P * math.sqrt(scale)
-    prm = ptycho.PtychoParams("rpie", 0.1, 0.1, w.batch, True)
+    prm = ptycho.PtychoParams(alg, step, step, w.batch, True)
     order = np.random.default_rng(0).permutation(w.J)
     n = 0
     t0 = time.perf_counter()
@@ -218,7 +223,7 @@ def profile_dominant(api, run_step, classes):
     torch.cuda.synchronize()
     ranks = api.profile_read()
     api.profile([])
-    dominant = max((k for k in ranks if k in ("rows_fwd", "cols_modulus", "rows_inv", "object_update")),
+    dominant = max((k for k in ranks if k in ("rows_fwd", "cols_modulus", "rows_inv", "object_update", "small_run")),
                    key=lambda k: ranks[k][1])
     return dominant, ranks
 
@@ -252,6 +257,7 @@ def roofline(dominant, nlaunch, kms, positions_per_launch, N, B, counters=True, 
 
 PASSES = ["rows_fwd", "cols_modulus", "rows_inv", "object_update", "fuse"]
 SUB_PASSES = PASSES + ["shift", "probe_update"]
+SMALL_PASSES = PASSES + ["small_run"]
 
 
 def tune_sizes(sizes, batch):
@@ -266,11 +272,14 @@ def run_lab(args, api, synth, dev):
     import torch
 
     sub = args.workload == "subpixel"
-    w = synth.lab_subpixel_workload() if sub else synth.lab_workload()
+    small = args.workload == "small"
+    w = synth.lab_subpixel_workload() if sub else (synth.small_workload() if small else synth.lab_workload())
+    # the small workload runs textbook ePIE (unit steps); the lab ones rPIE 0.1
+    alg, step_a = ("epie", 1.0) if small else ("rpie", 0.1)
     forward = api.ptycho_forward_subpixel if sub else api.ptycho_forward
     iterate = api.ptycho_iterate_subpixel if sub else api.ptycho_iterate
     n_iter = args.iters
-    tuned = tune_sizes([w.Nd], w.batch) if args.tune else None
+    tuned = tune_sizes([w.Nd], w.batch) if args.tune and not small else None
     if getattr(args, "three_launch", False):
         from paper_2608_01746_amd import tune
         tune.set_variant(w.Nd, tune.get_variant(w.Nd) | 4)
@@ -301,10 +310,10 @@ def run_lab(args, api, synth, dev):
         O.copy_(O0)
         Pw.copy_(P0)
         api.fuse_exposures(raw, w.t, w.levels, sat=float(w.sat), delta=delta, out=fused)
-        state["err"] = iterate(O, Pw, fused, w.pos, n_iter, alg="rpie", alpha=0.1, beta=0.1,
+        state["err"] = iterate(O, Pw, fused, w.pos, n_iter, alg=alg, alpha=step_a, beta=step_a,
                                batch=w.batch, update_probe=True, probe_start_iter=5, order=order, graph=graph)
 
-    dominant, ranks = profile_dominant(api, step, SUB_PASSES if sub else PASSES)
+    dominant, ranks = profile_dominant(api, step, SUB_PASSES if sub else (SMALL_PASSES if small else PASSES))
     graph = args.graph
     print("# per-class ms (warm-up step): " +
           ", ".join(f"{k} {v[1]:.2f} ({v[0]})" for k, v in ranks.items()), file=sys.stderr, flush=True)
@@ -326,8 +335,14 @@ def run_lab(args, api, synth, dev):
     nlaunch, kms = ranks[dominant] if graph else prof[dominant]
     dt = (t1 - t0) / args.steps
     value = w.J * n_iter / dt
-    per_launch = w.J / math.ceil(w.J / w.batch)
-    if sub:
+    # positions one launch of the dominant kernel processes (the whole run for
+    # the single-workgroup kernel of the small workload)
+    per_launch = w.J * n_iter * args.steps / nlaunch if dominant == "small_run" else w.J / math.ceil(w.J / w.batch)
+    if small:
+        metric = "scan-position updates/s at 64^2 FP32 (small ePIE, mini-batch 1, fusion included)"
+        wl = ("small-64: 192^2 object, 64^2 probe, 100 positions, 3 exposures, 4-level fusion, ePIE B=1, "
+              "%d iterations" % n_iter)
+    elif sub:
         metric = ("scan-position updates/s at 256^2 FP32 (lab-scale rPIE at real Fermat-spiral positions, "
                   "Fourier-translated probes, mini-batch 32, fusion included)")
         wl = ("lab-256-subpixel: 1024^2 object, 256^2 probe, 400 real Fermat-spiral positions, 5 exposures, "
@@ -351,7 +366,7 @@ def run_lab(args, api, synth, dev):
         "data": "synthetic (seeded object/probe, simulated Poisson+Gaussian exposures)",
         "config": {"workload": wl, "positions": w.J, "pattern": w.Nd, "batch": w.batch, "iterations": n_iter,
                    "exposures": len(w.t), "levels": w.levels},
-        "roofline": roofline(dominant, nlaunch, kms, per_launch, w.Nd, w.batch, counters=not sub,
+        "roofline": roofline(dominant, nlaunch, kms, per_launch, w.Nd, w.batch, counters=not (sub or small),
                              updates_per_step=w.J * n_iter, ms_per_step=dt * 1e3),
         "per_class_ms_one_step": {k: round(v[1], 3) for k, v in ranks.items()},
         "launch_variants": tuned,
@@ -359,13 +374,13 @@ def run_lab(args, api, synth, dev):
         "final_fourier_error": float(state["err"][-1].item()),
     }
     if not args.no_cpu:
-        v, n, sec = cpu_baseline(w, O_true, P, clean, scale, args.cpu_seconds, sub)
+        v, n, sec = cpu_baseline(w, O_true, P, clean, scale, args.cpu_seconds, sub, alg, step_a)
         model, _ = host_cpu()
         out["cpu_baseline"] = {"value": round(v, 3), "unit": "position-updates/s", "cores": 1,
                                "kind": "oracle", "host": model,
-                               "sample": f"{n} rPIE position updates (mini-batches of {w.batch}) of the "
+                               "sample": f"{n} {alg} position updates (mini-batches of {w.batch}) of the "
                                          f"same workload in float64 NumPy, {sec:.1f} s"}
-        if not sub:
+        if not (sub or small):
             v2, n2, sec2, cores = cpu_baseline_all_cores(w, O_true, P, clean, scale, args.cpu_seconds)
             out["cpu_baseline_all_cores"] = {
                 "value": round(v2, 3), "unit": "position-updates/s", "cores": cores,
@@ -959,7 +974,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--iters", type=int, default=None, help="iterations per step (200 lab, 20 multiscan)")
-    ap.add_argument("--workload", choices=["lab", "subpixel", "multiscan", "grad", "warmstart", "batch-sweep",
+    ap.add_argument("--workload", choices=["lab", "subpixel", "small", "multiscan", "grad", "warmstart", "batch-sweep",
                                            "fusion-compare", "unet", "broadband"], default="lab")
     ap.add_argument("--train-seconds", type=float, default=240.0, help="warm start: training time budget")
     ap.add_argument("--train-objects", type=int, default=500, help="warm start: training objects x 100 patterns")
@@ -982,7 +997,7 @@ def main() -> int:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         return 2
     if args.iters is None:
-        args.iters = 200 if args.workload in ("lab", "subpixel") else 20
+        args.iters = {"lab": 200, "subpixel": 200, "small": 50}.get(args.workload, 20)
 
     import torch
 
@@ -995,7 +1010,7 @@ def main() -> int:
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    run = {"lab": run_lab, "subpixel": run_lab, "multiscan": run_multiscan, "grad": run_grad, "warmstart": run_warmstart,
+    run = {"lab": run_lab, "subpixel": run_lab, "small": run_lab, "multiscan": run_multiscan, "grad": run_grad, "warmstart": run_warmstart,
            "batch-sweep": run_batch_sweep, "fusion-compare": run_fusion_compare, "unet": run_unet,
            "broadband": run_broadband}[args.workload]
     out = run(args, api, synth, dev)

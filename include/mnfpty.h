@@ -382,10 +382,12 @@ int detector_resample(mnf_ctx* ctx, const float* I, int J, int Nd, float scale, 
  * Bit 2 selects the pass structure of a single-scan, integer-position,
  * single-mode reconstruction whose object box is at most 1024 pixels wide:
  * three launches per mini-batch (the object update fused with the next
- * mini-batch's exit-wave rows) instead of four.  Eight variants per detector
- * size; they change only launch geometry and pass structure, never the
- * algorithm or the mini-batch, and give identical results up to the order of
- * float64 partial sums of the error.
+ * mini-batch's exit-wave rows) instead of four.  Such a reconstruction with
+ * mini-batches of one on a detector of at most 64^2 runs as a whole in one
+ * workgroup (pattern and probe in LDS, one launch per call) unless bit 3 is
+ * set.  Variants change only launch geometry and pass structure, never the
+ * algorithm or the mini-batch, and give identical objects and probes (the
+ * errors up to the order of float64 partial sums).
  *
  * mnf_autotune times the eight variants on a synthetic scan of `nslots`
  * positions (one mini-batch of that size per iteration, `reps` iterations)
@@ -396,7 +398,7 @@ int detector_resample(mnf_ctx* ctx, const float* I, int J, int Nd, float scale, 
  * It synchronises the stream.  mnf_set_variant / mnf_get_variant store or
  * read a variant (e.g. from a tuning cache kept by the caller). */
 int mnf_autotune(mnf_ctx* ctx, int Nd, int nslots, int reps, double* times_us, void* stream);
-int mnf_set_variant(mnf_ctx* ctx, int Nd, int variant);
+int mnf_set_variant(mnf_ctx* ctx, int Nd, int variant);   /* variant 0..15 */
 int mnf_get_variant(mnf_ctx* ctx, int Nd);
 
 /* ------------------------------------------------------------------------
@@ -407,7 +409,8 @@ int mnf_get_variant(mnf_ctx* ctx, int Nd);
  * 2 rows_inv (inverse row transforms + exit-wave difference), 3 probe_update
  * (the translated probe update of real positions), 4 object_update, 5 small
  * (copies, reductions), 6 fuse, 7 forward, 8 grad_cols, 9 grad_scatter,
- * 10 shift (Fourier translation of probes).  mask 0 disables timing.
+ * 10 shift (Fourier translation of probes), 11 small_run (a whole run of
+ * mini-batches of one in one workgroup).  mask 0 disables timing.
  * mnf_profile_read waits for the recorded events and returns the launch
  * count and summed duration (ms) of class cls since the last reset. */
 int mnf_profile(mnf_ctx* ctx, uint32_t class_mask);

@@ -26,6 +26,7 @@ enum MnfKernelClass {
     MNF_K_GRAD_COLS,      // gradient column pass
     MNF_K_GRAD_SCATTER,   // gradient object/probe scatter
     MNF_K_SHIFT,          // Fourier translation of probes (real positions)
+    MNF_K_SMALL_RUN,      // a whole mini-batch-of-one run in one workgroup
     MNF_K_NCLASS
 };
 

@@ -141,7 +141,7 @@ extern "C" {
 
 static const char* kClassNames[MNF_K_NCLASS] = {
     "rows_fwd", "cols_modulus", "rows_inv", "probe_update", "object_update",
-    "small", "fuse", "forward", "grad_cols", "grad_scatter", "shift"};
+    "small", "fuse", "forward", "grad_cols", "grad_scatter", "shift", "small_run"};
 
 int mnf_profile(mnf_ctx* ctx, uint32_t class_mask) {
     MNF_TRY(mnf::begin(ctx));

@@ -116,7 +116,7 @@ struct RegDFT {
                 if (e != 0) {
                     const float c = W.c[e];
                     const float s = INV ? W.s[e] : -W.s[e];
-                    v = make_float2(v.x * c - v.y * s, v.x * s + v.y * c);
+                    v = make_float2(fmaf(v.x, c, -(v.y * s)), fmaf(v.x, s, v.y * c));
                 }
                 y[n2 * F + k1] = v;
             }
@@ -155,8 +155,8 @@ struct RegDFT<3, INV> {
         const float h = 0.86602540378443864676f;
         float2 s = cadd(a[1], a[2]);
         float2 d = csub(a[1], a[2]);
-        float2 m = make_float2(a[0].x - 0.5f * s.x, a[0].y - 0.5f * s.y);
-        float2 r = make_float2(h * d.y, -h * d.x);  // -i h d
+        float2 m = make_float2(fmaf(-0.5f, s.x, a[0].x), fmaf(-0.5f, s.y, a[0].y));
+        float2 r = make_float2(__fmul_rn(h, d.y), -__fmul_rn(h, d.x));  // -i h d (products kept out of the sums)
         if (INV) r = make_float2(-r.x, -r.y);
         a[0] = cadd(a[0], s);
         a[1] = cadd(m, r);
@@ -186,11 +186,12 @@ struct RegDFT<8, INV> {
         RegDFT<4, INV>::run(e);
         RegDFT<4, INV>::run(o);
         // twiddles W_8^k, k = 0..3
-        float2 o1 = INV ? make_float2(r * (o[1].x - o[1].y), r * (o[1].x + o[1].y))
-                        : make_float2(r * (o[1].x + o[1].y), r * (o[1].y - o[1].x));
+        // the products are rounded on their own (never fused into the sums below)
+        float2 o1 = INV ? make_float2(__fmul_rn(r, o[1].x - o[1].y), __fmul_rn(r, o[1].x + o[1].y))
+                        : make_float2(__fmul_rn(r, o[1].x + o[1].y), __fmul_rn(r, o[1].y - o[1].x));
         float2 o2 = cmul_mi<INV>(o[2]);
-        float2 o3 = INV ? make_float2(-r * (o[3].x + o[3].y), r * (o[3].x - o[3].y))
-                        : make_float2(r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y));
+        float2 o3 = INV ? make_float2(-__fmul_rn(r, o[3].x + o[3].y), __fmul_rn(r, o[3].x - o[3].y))
+                        : make_float2(__fmul_rn(r, o[3].y - o[3].x), -__fmul_rn(r, o[3].x + o[3].y));
         a[0] = cadd(e[0], o[0]);
         a[4] = csub(e[0], o[0]);
         a[1] = cadd(e[1], o1);

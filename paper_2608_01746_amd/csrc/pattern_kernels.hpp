@@ -572,7 +572,7 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                     }
                     if constexpr (DEN) {
                         const float o2 = cabs2(o[idx]);
-                        c_den[line * N + n] = rpie ? (1.f - beta) * o2 + beta * mO : mO / beta;
+                        c_den[line * N + n] = rpie ? fmaf(1.f - beta, o2, beta * mO) : mO / beta;
                     }
                 }
             }
@@ -639,8 +639,8 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                 for (int q = 0; q < NM; ++q) {
                     if (q >= nmodes) break;
                     float2 p = s_prow[q * N + n];
-                    p.x += num[q][c].x * inv;
-                    p.y += num[q][c].y * inv;
+                    p.x = fmaf(num[q][c].x, inv, p.x);
+                    p.y = fmaf(num[q][c].y, inv, p.y);
                     sc.P[(size_t)q * Nw * Nw + (size_t)r * Nw + n] = p;
                 }
             }
@@ -652,8 +652,8 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             if constexpr (MODE == 4) DP[(size_t)r * Nw + n] = den[c];
             if (MODE == 1 && den[c] > 0.0) {
                 const float inv = (float)(1.0 / den[c]);  // the float64 denominator, inverted once
-                p.x += num[0][c].x * inv;
-                p.y += num[0][c].y * inv;
+                p.x = fmaf(num[0][c].x, inv, p.x);
+                p.y = fmaf(num[0][c].y, inv, p.y);
                 sc.P[(size_t)r * Nw + n] = p;
             }
         }

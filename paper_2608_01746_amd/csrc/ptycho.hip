@@ -15,6 +15,7 @@
 #include "common.hpp"
 #include "objrow_kernels.hpp"
 #include "pattern_kernels.hpp"
+#include "small_kernels.hpp"
 #include "shift_kernels.hpp"
 #include "update_kernels.hpp"
 
@@ -64,6 +65,9 @@ int row_lines(mnf_ctx* ctx, int N) { return (variant_of(ctx, N) & 1) ? row_lines
 // variant bit 2: three launches per mini-batch where the object update can be
 // fused with the next mini-batch's exit-wave rows (k_obj_rows)
 bool three_launch(mnf_ctx* ctx, int N) { return (variant_of(ctx, N) & 4) != 0; }
+// variant bit 3: no single-workgroup run for mini-batches of one (k_small_run)
+bool small_run_off(mnf_ctx* ctx, int N) { return (variant_of(ctx, N) & 8) != 0; }
+
 int col_groups(mnf_ctx* ctx, int N) {
     const int c0 = kColGroup < N ? kColGroup : N;
     return N / ((variant_of(ctx, N) & 2) ? c0 / 2 : c0);
@@ -517,6 +521,21 @@ int issue_obj_rows_any(mnf_ctx* ctx, const CallPlan& pl, int N, const Launch* Lu
 
 // ----------------------------------------------------------------- iterate
 
+template <int N>
+int launch_small_run(mnf_ctx* ctx, const CallPlan& pl, int J, int n_iter, const ptycho_params& p, int upd_from,
+                     const double* sumA2, double* err, hipStream_t st) {
+    if constexpr (N > kSmallMaxN) {
+        return set_error(ctx, MNF_EUNSUPPORTED, "no single-workgroup run at N = %d", N);
+    } else {
+        const float2* tw;
+        MNF_TRY(twiddles(ctx, N, &tw));
+        MNF_LAUNCH(ctx, MNF_K_SMALL_RUN, st, k_small_run<N>, dim3(1), dim3(kSmallThreads), (const ScanDev*)pl.d_scans,
+                   (const SlotDev*)pl.d_slots, J, n_iter, p.alg == 1 ? 1 : 0, p.alpha, p.beta, upd_from, sumA2, err, tw);
+        return MNF_OK;
+    }
+}
+
+
 int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const ptycho_params& p, hipStream_t st) {
     const int ns = (int)in.size();
     if (p.alg != 0 && p.alg != 1) return set_error(ctx, MNF_EINVAL, "alg must be 0 (ePIE) or 1 (rPIE)");
@@ -716,7 +735,19 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
         MNF_HIP(ctx, hipStreamBeginCapture(run, hipStreamCaptureModeThreadLocal));
     }
     int rc = MNF_OK;
-    size_t li = 0;
+    // A single scan at integer positions with one mode and mini-batches of one
+    // on patterns of at most 64^2 runs in one launch of one workgroup.
+    const bool small = ns == 1 && !sub && modes == 1 && p.batch == 1 && in[0].Nd <= kSmallMaxN &&
+                       !small_run_off(ctx, in[0].Nd);
+    if (small) {
+        const int upd_from = !p.update_probe ? n_iter : std::min(n_iter, std::max(0, p.probe_start_iter - p.it0));
+        switch (in[0].Nd) {
+            case 16: rc = launch_small_run<16>(ctx, pl, in[0].J, n_iter, p, upd_from, sA2[0], in[0].err_out ? err_dst(0) : nullptr, run); break;
+            case 32: rc = launch_small_run<32>(ctx, pl, in[0].J, n_iter, p, upd_from, sA2[0], in[0].err_out ? err_dst(0) : nullptr, run); break;
+            default: rc = launch_small_run<64>(ctx, pl, in[0].J, n_iter, p, upd_from, sA2[0], in[0].err_out ? err_dst(0) : nullptr, run); break;
+        }
+    }
+    size_t li = small ? pl.launches.size() : 0;
     const size_t nL = pl.launches.size();
     auto Sbuf = [&](size_t b) { return (float2*)S + (fused ? (b % 2) * sS : 0); };
     for (int i = 0; i < n_iter && rc == MNF_OK; ++i) {
@@ -735,7 +766,7 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
                 rc = issue_obj_rows_any(ctx, pl, L.N, &L, li + 1 < nL ? &pl.launches[li + 1] : nullptr, Sbuf(li),
                                         Sbuf(li + 1), (float*)mO, p, run);
         }
-        if (rc == MNF_OK && any_err) {
+        if (rc == MNF_OK && any_err && !small) {
             hipLaunchKernelGGL(k_sum_jobs, dim3(ns), dim3(256), 0, run, (const SumJob*)d_jobs + (size_t)i * ns, 1.0);
         }
     }
@@ -1063,7 +1094,7 @@ int mnf_autotune(mnf_ctx* ctx, int Nd, int nslots, int reps, double* times_us, v
 int mnf_set_variant(mnf_ctx* ctx, int Nd, int variant) {
     MNF_TRY(begin(ctx));
     if (!size_supported(Nd)) return set_error(ctx, MNF_EUNSUPPORTED, "detector size %d has no FFT plan", Nd);
-    if (variant < 0 || variant > 7) return set_error(ctx, MNF_EINVAL, "variant must be 0..7");
+    if (variant < 0 || variant > 15) return set_error(ctx, MNF_EINVAL, "variant must be 0..15");
     ctx->variant[Nd] = variant;
     return MNF_OK;
 }

@@ -132,8 +132,8 @@ k_probe_sum_update(const float2* __restrict__ G, const GroupDev* __restrict__ gr
     }
     if (!(den > 0.0)) return;
     const float inv = (float)(1.0 / den);  // the float64 denominator, inverted once
-    p.x += acc.x * inv;
-    p.y += acc.y * inv;
+    p.x = fmaf(acc.x, inv, p.x);
+    p.y = fmaf(acc.y, inv, p.y);
     P[q] = p;
 }
 

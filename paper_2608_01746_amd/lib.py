@@ -101,7 +101,7 @@ SIGNATURES = {
 }
 
 KERNEL_CLASSES = ["rows_fwd", "cols_modulus", "rows_inv", "probe_update", "object_update",
-                  "small", "fuse", "forward", "grad_cols", "grad_scatter", "shift"]
+                  "small", "fuse", "forward", "grad_cols", "grad_scatter", "shift", "small_run"]
 
 _lib = None
 

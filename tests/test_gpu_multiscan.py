@@ -177,3 +177,50 @@ def test_three_launch_path_equals_four_launch_path(api, Nd, Nw, M, B, n_side, st
     tune.set_variant(Nd, 0)
     for a, b in zip(*res):
         assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("alg,Nd,Nw,M,n_side,step,upd", [("epie", 64, 64, 192, 6, 20, True),
+                                                          ("rpie", 64, 48, 160, 5, 20, True),
+                                                          ("rpie", 32, 32, 96, 5, 12, False),
+                                                          ("epie", 16, 12, 48, 5, 6, True)])
+def test_single_workgroup_run_equals_multi_pass(api, alg, Nd, Nw, M, n_side, step, upd):
+    # mini-batches of one on patterns of at most 64^2 run as a whole in one
+    # workgroup; launch-shape bit 3 keeps the four passes per position.  The
+    # two agree to float32 rounding (bit for bit at 16^2; at 32^2 and 64^2 the
+    # transforms round a few values differently) and both match the float64
+    # oracle at the one-iteration bar.
+    O, P, pos, I = tiny_scan(M, Nw, Nd, n_side, step, 2, seed=Nd + Nw, jitter=1)
+    order = synth.random_orders(len(pos), 3, 8)
+    P0 = c64(soft_probe(P, 3) * np.exp(0.2j))
+    res = []
+    for v in (0, 8):
+        tune.set_variant(Nd, v)
+        Og, Pg = tc64(np.ones_like(O)), tc64(P0)
+        e = api.ptycho_iterate(Og, Pg, tf32(I), pos, 3, alg=alg, alpha=0.3, beta=0.3, batch=1,
+                               update_probe=upd, probe_start_iter=1, order=order)
+        res.append((Og.cpu(), Pg.cpu(), e.cpu()))
+    tune.set_variant(Nd, 0)
+    (Oa, Pa, ea), (Ob, Pb, eb) = res
+    if Nd == 16:
+        assert torch.equal(Oa, Ob) and torch.equal(Pa, Pb)
+    assert rel(Oa.numpy(), Ob.numpy()) < 1e-5 and rel(Pa.numpy(), Pb.numpy()) < 1e-5
+    torch.testing.assert_close(ea, eb, rtol=1e-6, atol=0)
+    Or, Pr, er = ptycho.iterate(c64(np.ones_like(O)), P0, I, pos, 3, ptycho.PtychoParams(alg, 0.3, 0.3, 1, upd, 1),
+                                order)
+    assert rel(Oa.numpy(), Or) < 1e-5 and rel(Pa.numpy(), Pr) < 1e-5
+    np.testing.assert_allclose(ea.numpy(), er, rtol=1e-5)
+
+
+def test_single_workgroup_run_reports_errors_and_graph(api):
+    # err_out and graph capture through the single-workgroup path
+    O, P, pos, I = tiny_scan(96, 32, 32, 5, 12, 2, seed=3)
+    order = synth.random_orders(len(pos), 4, 2)
+    out = []
+    for graph in (False, True, True):
+        Og, Pg = tc64(np.ones_like(O)), tc64(P * 0.9)
+        e = api.ptycho_iterate(Og, Pg, tf32(I), pos, 4, alg="epie", batch=1, update_probe=True, order=order,
+                               graph=graph)
+        out.append((Og.cpu(), Pg.cpu(), e.cpu()))
+    for o in out[1:]:
+        assert all(torch.equal(a, b) for a, b in zip(out[0], o))
+    assert torch.all(out[0][2][1:] < out[0][2][:-1])  # the error falls on noiseless data
