@@ -529,7 +529,7 @@ int launch_small_run(mnf_ctx* ctx, const CallPlan& pl, int J, int n_iter, const 
     } else {
         const float2* tw;
         MNF_TRY(twiddles(ctx, N, &tw));
-        MNF_LAUNCH(ctx, MNF_K_SMALL_RUN, st, k_small_run<N>, dim3(1), dim3(kSmallThreads), (const ScanDev*)pl.d_scans,
+        MNF_LAUNCH(ctx, MNF_K_SMALL_RUN, st, k_small_run<N>, dim3(1), dim3(SmallCfg<N>::THREADS), (const ScanDev*)pl.d_scans,
                    (const SlotDev*)pl.d_slots, J, n_iter, p.alg == 1 ? 1 : 0, p.alpha, p.beta, upd_from, sumA2, err, tw);
         return MNF_OK;
     }

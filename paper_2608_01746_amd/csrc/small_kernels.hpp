@@ -22,17 +22,20 @@
 
 namespace mnf {
 
-constexpr int kSmallThreads = 256;
 constexpr int kSmallMaxN = 64;
 
+// T threads per line and every line of a pass in one round: N * T threads
+// (512 at 64^2, two waves per SIMD), each holding E pattern elements.
 template <int N>
 struct SmallCfg {
     static constexpr int T = PlanInfo<N>::T, V = PlanInfo<N>::V;
-    static constexpr int LINES = kSmallThreads / T;             // lines transformed per round
-    static constexpr int ROUNDS = (N + LINES - 1) / LINES;
-    static constexpr int R = N > LINES ? N : LINES;             // rows and columns of the LDS tile
-    static constexpr int S = R + R / 16;                        // row stride (one pad element per 16)
-    static constexpr int E = (N * N + kSmallThreads - 1) / kSmallThreads;  // elements per thread
+    static constexpr int THREADS = N * T;
+    static constexpr int LINES = N;                              // lines transformed per round
+    static constexpr int ROUNDS = 1;
+    static constexpr int R = N;                                  // rows and columns of the LDS tile
+    static constexpr int S = R + R / 16;                         // row stride (one pad element per 16)
+    static constexpr int E = (N * N + THREADS - 1) / THREADS;    // elements per thread
+    static constexpr int W = (THREADS + 63) / 64;                // waves
 };
 
 // pattern element (y, x) of the padded LDS tile
@@ -53,7 +56,7 @@ struct SmallCol {
     __device__ __forceinline__ int operator()(int p) const { return small_at<N>(p, col); }
 };
 
-// One block of kSmallThreads threads.  scans[0] is the scan (O, P, amplitudes
+// One block of SmallCfg<N>::THREADS threads.  scans[0] is the scan (O, P, amplitudes
 // A in FFT order or, if A is NULL, the intensities I), slots[it * J + t] the
 // t-th position of local iteration it; the probe is updated from local
 // iteration upd_from on (n_iter: never).  err (n_iter doubles) receives the
@@ -61,24 +64,24 @@ struct SmallCol {
 // squared amplitudes); a non-finite error, or one above max(10 x the first,
 // 1e-6), is recorded in the scan's status word.
 template <int N>
-__global__ void __launch_bounds__(kSmallThreads)
+__global__ void __launch_bounds__(SmallCfg<N>::THREADS)
 k_small_run(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots, int J, int n_iter, int rpie,
             float alpha, float beta, int upd_from, const double* __restrict__ sumA2, double* __restrict__ err,
             const float2* __restrict__ tw_g) {
     using C = SmallCfg<N>;
-    constexpr int T = C::T, V = C::V, LINES = C::LINES, E = C::E;
+    constexpr int T = C::T, V = C::V, LINES = C::LINES, E = C::E, NT = C::THREADS, NW = C::W;
     static_assert(N <= kSmallMaxN, "pattern and probe must fit the LDS");
     __shared__ float2 X[C::R * C::S];
     __shared__ float2 Pl[N * N];
     __shared__ float2 tw[N];
-    __shared__ float red_f[2 * (kSmallThreads / 64)];
-    __shared__ double red_d[kSmallThreads / 64];
+    __shared__ float red_f[2 * NW];
+    __shared__ double red_d[NW];
     const ScanDev sc = scans[0];
     const int Nw = sc.Nw, Mx = sc.Mx;
     const int tid = threadIdx.x, w = tid >> 6;
     const int line = tid / T, t = tid % T;
-    for (int i = tid; i < N; i += kSmallThreads) tw[i] = tw_g[i];
-    for (int e = tid; e < N * N; e += kSmallThreads) {
+    for (int i = tid; i < N; i += NT) tw[i] = tw_g[i];
+    for (int e = tid; e < N * N; e += NT) {
         const int y = e / N, x = e % N;
         Pl[e] = y < Nw && x < Nw ? sc.P[(size_t)y * Nw + x] : make_float2(0.f, 0.f);
     }
@@ -109,13 +112,13 @@ k_small_run(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots
             float mO = 0.f, mP = 0.f;
 #pragma unroll
             for (int i = 0; i < E; ++i) {
-                const int e = min(tid + i * kSmallThreads, N * N - 1);
+                const int e = min(tid + i * NT, N * N - 1);
                 const int y = e / N, x = e % N;
                 o[i] = ldg(sc.O, (size_t)(sd.py + min(y, Nw - 1)) * Mx + sd.px + min(x, Nw - 1));
             }
 #pragma unroll
             for (int i = 0; i < E; ++i) {
-                const int e = tid + i * kSmallThreads;
+                const int e = tid + i * NT;
                 const int y = e / N, x = e % N;
                 const bool in = e < N * N && y < Nw && x < Nw;
                 const float2 p = in ? Pl[e] : make_float2(0.f, 0.f);
@@ -133,15 +136,15 @@ k_small_run(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots
             mP = wave_max(mP);
             if ((tid & 63) == 0) {
                 red_f[w] = mO;
-                red_f[kSmallThreads / 64 + w] = mP;
+                red_f[NW + w] = mP;
             }
             __syncthreads();
             mO = red_f[0];
-            mP = red_f[kSmallThreads / 64];
+            mP = red_f[NW];
 #pragma unroll
-            for (int q = 1; q < kSmallThreads / 64; ++q) {
+            for (int q = 1; q < NW; ++q) {
                 mO = fmaxf(mO, red_f[q]);
-                mP = fmaxf(mP, red_f[kSmallThreads / 64 + q]);
+                mP = fmaxf(mP, red_f[NW + q]);
             }
             // forward row transforms
 #pragma unroll
@@ -194,7 +197,7 @@ k_small_run(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots
             const double cstO = rpie ? (double)alpha * (double)mP : (double)mP / (double)alpha;
 #pragma unroll
             for (int i = 0; i < E; ++i) {
-                const int e = tid + i * kSmallThreads;
+                const int e = tid + i * NT;
                 const int y = e / N, x = e % N;
                 if (e >= N * N || y >= Nw || x >= Nw) continue;
                 const float2 p = Pl[e];
@@ -229,7 +232,7 @@ k_small_run(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots
         __syncthreads();
         if (tid == 0 && err) {  // sumA2 exists only when errors are requested
             double tot = red_d[0];
-            for (int q = 1; q < kSmallThreads / 64; ++q) tot += red_d[q];
+            for (int q = 1; q < NW; ++q) tot += red_d[q];
             const double e = *sumA2 > 0.0 ? tot / *sumA2 : 0.0;
             err[it] = e;
             if (!isfinite(e)) atomicOr(sc.status, kStatusNonFinite);
@@ -238,7 +241,7 @@ k_small_run(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots
         }
         __syncthreads();
     }
-    for (int e = tid; e < N * N; e += kSmallThreads) {
+    for (int e = tid; e < N * N; e += NT) {
         const int y = e / N, x = e % N;
         if (y < Nw && x < Nw && upd_from < n_iter) sc.P[(size_t)y * Nw + x] = Pl[e];
     }
