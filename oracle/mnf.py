@@ -30,7 +30,14 @@ design notes):
   * the collapse is recursive: R_{l-1} = U(R_l) + L_tilde_{l-1};
   * the quantisation step of exposure k at level l is
     delta_l * t_1 / t_k (delta_l in ADU of that exposure), a zero step
-    disables quantisation; rounding is half-to-even.
+    disables quantisation; rounding is half-to-even;
+  * optional contrast factor (Mertens-style; the paper's weight is Eq. 5
+    alone, which contrast_exp = 0 gives exactly): the raw weight of
+    exposure k is multiplied by (C_k + CONTRAST_EPS) ** contrast_exp, with
+    C_k = |4-neighbour Laplacian of I_bar_k| on the level-0 grid
+    (reflect-101 borders; along an axis of length one the neighbours are
+    the pixel itself) and CONTRAST_EPS = 1e-6, so that flat regions,
+    where every C_k is zero, keep the Eq. 5 weights.
 """
 from __future__ import annotations
 
@@ -43,6 +50,10 @@ from scipy.ndimage import correlate1d
 # Binomial smoothing kernel w_G (Eq. 6 reading).
 W_G = np.array([1.0, 4.0, 6.0, 4.0, 1.0]) / 16.0
 
+# Offset added to the contrast before the exponent (flat regions keep the
+# well-exposedness weights).
+CONTRAST_EPS = 1e-6
+
 
 @dataclasses.dataclass
 class FuseParams:
@@ -53,6 +64,7 @@ class FuseParams:
     dark: float = 0.0
     delta: Sequence[float] = ()       # per-level step in ADU, l = 0 finest; empty => no quantisation
     radiometric: bool = True
+    contrast_exp: float = 0.0         # 0: the paper's weight (Eq. 5 only)
 
     def delta_at(self, l: int) -> float:
         return float(self.delta[l]) if l < len(self.delta) else 0.0
@@ -70,9 +82,22 @@ def raw_weight(Ibar: np.ndarray, mu: float, sigma: float) -> np.ndarray:
     return np.exp(-((Ibar - mu) ** 2) / (2.0 * sigma * sigma))
 
 
-def normalised_weights(Ibars: np.ndarray, mu: float, sigma: float) -> np.ndarray:
-    """Eq. 5 followed by the normalisation sum_k W_k = 1 (per pixel)."""
+def contrast(Ibar: np.ndarray) -> np.ndarray:
+    """C = |I(y-1,x) + I(y+1,x) + I(y,x-1) + I(y,x+1) - 4 I(y,x)| of one
+    normalised image, neighbours past the edge reflected without repeating
+    the edge pixel (numpy's 'reflect', which repeats the pixel itself along
+    an axis of length one)."""
+    g = np.pad(np.asarray(Ibar, np.float64), 1, mode="reflect")
+    return np.abs(g[:-2, 1:-1] + g[2:, 1:-1] + g[1:-1, :-2] + g[1:-1, 2:] - 4.0 * g[1:-1, 1:-1])
+
+
+def normalised_weights(Ibars: np.ndarray, mu: float, sigma: float, contrast_exp: float = 0.0) -> np.ndarray:
+    """Eq. 5 (times the optional contrast factor) followed by the
+    normalisation sum_k W_k = 1 (per pixel); Ibars is [K][H][W]."""
     W = raw_weight(Ibars, mu, sigma)
+    if contrast_exp > 0.0:
+        C = np.stack([contrast(Ibars[k]) for k in range(Ibars.shape[0])])
+        W = W * (C + CONTRAST_EPS) ** contrast_exp
     s = W.sum(axis=0)
     return W / np.maximum(s, 1e-30)
 
@@ -158,7 +183,7 @@ def fuse_position(raw: np.ndarray, t: Sequence[float], p: FuseParams,
     """I_MNF for one scan position from its bracket raw[K][H][W] (Eqs. 5-10)."""
     K = raw.shape[0]
     Ibar, Itil = exposure_images(raw, t, p)
-    W = normalised_weights(Ibar, p.mu, p.sigma)
+    W = normalised_weights(Ibar, p.mu, p.sigma, p.contrast_exp)
     total = np.zeros(raw.shape[1:])
     parts = []
     for k in range(K):
@@ -183,4 +208,4 @@ def fuse(raw: np.ndarray, t: Sequence[float], p: FuseParams) -> np.ndarray:
 def weights(raw: np.ndarray, p: FuseParams) -> np.ndarray:
     """Normalised weights [J][K][H][W] of every bracket (Eq. 5 + normalisation)."""
     Ibar = normalised_intensity(raw, p.sat, p.dark)
-    return np.stack([normalised_weights(Ibar[j], p.mu, p.sigma) for j in range(raw.shape[0])])
+    return np.stack([normalised_weights(Ibar[j], p.mu, p.sigma, p.contrast_exp) for j in range(raw.shape[0])])

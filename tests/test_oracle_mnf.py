@@ -231,3 +231,79 @@ def test_literal_mode_step_ignores_exposure_times():
     for k in range(3):
         assert mnf.step_size(p, 0, t, k) == 4.0 / 4095.0
         assert mnf.step_size(p, 1, t, k) == 2.0 / 4095.0
+
+
+# --- optional contrast factor (the paper's weight is contrast_exp = 0) ------
+
+def test_contrast_of_a_single_bright_pixel():
+    # by hand: a lone value v gives 4v at the pixel and v at its four
+    # neighbours, zero elsewhere (interior pixel)
+    g = np.zeros((8, 9))
+    g[3, 4] = 0.5
+    C = mnf.contrast(g)
+    want = np.zeros((8, 9))
+    want[3, 4] = 2.0
+    for y, x in [(2, 4), (4, 4), (3, 3), (3, 5)]:
+        want[y, x] = 0.5
+    np.testing.assert_array_equal(C, want)
+
+
+def test_contrast_reflects_without_repeating_the_edge():
+    # reflect-101: a value one row in from the top edge is seen twice by the
+    # edge pixel above it (its neighbours at rows -1 and 1 are both row 1),
+    # so that edge pixel's contrast is 2v, not v (a repeated edge) or v + 0
+    g = np.zeros((6, 7))
+    g[1, 3] = 0.25
+    C = mnf.contrast(g)
+    assert C[0, 3] == 0.5
+    assert C[1, 3] == 1.0 and C[2, 3] == 0.25 and C[1, 2] == 0.25 and C[1, 4] == 0.25
+    assert C.sum() == 0.5 + 1.0 + 3 * 0.25
+
+
+def test_contrast_of_a_ramp_is_zero_inside_and_twice_the_slope_at_the_edges():
+    # I = a + b x: the second difference vanishes inside; at x = 0 the
+    # reflected neighbour is x = 1, giving |2 (a + b) - 2 a| = 2 b, and
+    # likewise at x = W - 1
+    a, b = 0.2, 0.05
+    g = np.tile(a + b * np.arange(10.0), (5, 1))
+    C = mnf.contrast(g)
+    np.testing.assert_allclose(C[:, 1:-1], 0.0, atol=1e-15)
+    np.testing.assert_allclose(C[:, 0], 2 * b, rtol=1e-12)
+    np.testing.assert_allclose(C[:, -1], 2 * b, rtol=1e-12)
+
+
+def test_contrast_exponent_zero_is_the_paper_weight():
+    rng = np.random.default_rng(7)
+    raw = rng.integers(0, 4096, size=(2, 3, 16, 16)).astype(np.float64)
+    W0 = mnf.weights(raw, mnf.FuseParams(sat=4095.0))
+    Wc = mnf.weights(raw, mnf.FuseParams(sat=4095.0, contrast_exp=0.0))
+    np.testing.assert_array_equal(W0, Wc)
+
+
+def test_contrast_weights_at_one_pixel_by_hand():
+    # K = 2 at the peak of exposure 1 (a lone pixel of I_bar = 0.6 on zero)
+    # while exposure 0 is flat at I_bar = 0.3: W_1 / W_0 =
+    # E(0.6) (4 * 0.6 + eps)^c / (E(0.3) eps^c), E(x) = exp(-(x - mu)^2 / (2 s^2))
+    mu, s, c, sat = 0.5, 0.2, 1.5, 1000.0
+    raw = np.zeros((1, 2, 5, 5))
+    raw[0, 0] = 300.0
+    raw[0, 1, 2, 2] = 600.0
+    W = mnf.weights(raw, mnf.FuseParams(mu=mu, sigma=s, sat=sat, contrast_exp=c))[0]
+    E = lambda x: math.exp(-(x - mu) ** 2 / (2 * s * s))
+    r = E(0.6) * (2.4 + 1e-6) ** c / (E(0.3) * 1e-6 ** c)
+    assert W[1, 2, 2] == pytest.approx(r / (1 + r), rel=1e-12)
+    assert W[0, 2, 2] == pytest.approx(1 / (1 + r), rel=1e-12)
+    # a neighbour of the peak: contrast 0.6 in exposure 1, still 0 in exposure 0
+    # (I_bar of exposure 1 is 0 there)
+    r1 = E(0.0) * (0.6 + 1e-6) ** c / (E(0.3) * 1e-6 ** c)
+    assert W[1, 1, 2] == pytest.approx(r1 / (1 + r1), rel=1e-12)
+
+
+def test_contrast_leaves_flat_brackets_at_the_paper_weight():
+    # every exposure flat: every C_k = 0, the common factor eps^c cancels in
+    # the normalisation, and the fused result is that of the paper's weight
+    raw = np.stack([np.full((16, 16), v) for v in (200.0, 900.0, 3000.0)])
+    t = [1.0, 4.0, 16.0]
+    p0 = mnf.FuseParams(levels=2, sat=4095.0)
+    pc = mnf.FuseParams(levels=2, sat=4095.0, contrast_exp=2.0)
+    np.testing.assert_allclose(mnf.fuse_position(raw, t, pc), mnf.fuse_position(raw, t, p0), rtol=1e-12)
