@@ -77,3 +77,43 @@ def loss_and_grad(O: np.ndarray, P: np.ndarray, I_centred: np.ndarray, pos: np.n
         gO[y:y + Nw, x:x + Nw] += np.conj(P) * gpsi
         gP += np.conj(O[y:y + Nw, x:x + Nw]) * gpsi
     return total, gO, gP
+
+
+def step_sizes(O: np.ndarray, P: np.ndarray, pos: np.ndarray) -> Tuple[float, float]:
+    """Fixed gradient-descent step sizes (a reading; the paper fixes none):
+    eta_O = 1 / (2 max_x sum_j |P(x - p_j)|^2) over the object grid and
+    eta_P = 1 / (2 max_u sum_j |O_j(u)|^2) over the probe window, i.e. the
+    inverse of the largest diagonal curvature of the amplitude loss in O
+    (resp. P) with the other held fixed."""
+    Nw = P.shape[0]
+    illum = np.zeros(O.shape)
+    cover = np.zeros(P.shape)
+    for p in pos:
+        y, x = int(p[0]), int(p[1])
+        illum[y:y + Nw, x:x + Nw] += np.abs(P) ** 2
+        cover += np.abs(O[y:y + Nw, x:x + Nw]) ** 2
+    return 1.0 / (2.0 * illum.max()), 1.0 / (2.0 * cover.max())
+
+
+def descend(O: np.ndarray, P: np.ndarray, I_centred: np.ndarray, pos: np.ndarray, kind: str = "poisson",
+            eps: float = 1e-6, n_steps: int = 1, eta_O: float = 0.0, eta_P: float = 0.0,
+            update_probe: bool = True):
+    """Full-batch gradient descent on the loss above: per step the loss and
+    both gradients at the current (O, P), then O -= eta_O gO and, with
+    update_probe, P -= eta_P gP.  Step sizes <= 0 take step_sizes() of the
+    starting O and P and stay fixed.  Returns (O, P, losses[n_steps]), the
+    loss of step s taken before its update."""
+    O = np.array(O, np.complex128)
+    P = np.array(P, np.complex128)
+    eO, eP = step_sizes(O, P, pos)
+    if eta_O > 0.0:
+        eO = eta_O
+    if eta_P > 0.0:
+        eP = eta_P
+    losses = np.zeros(n_steps)
+    for s in range(n_steps):
+        losses[s], gO, gP = loss_and_grad(O, P, I_centred, pos, kind, eps)
+        O = O - eO * gO
+        if update_probe:
+            P = P - eP * gP
+    return O, P, losses

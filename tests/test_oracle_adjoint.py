@@ -91,3 +91,54 @@ def test_gradient_with_padded_window_matches_differences():
         d = np.zeros_like(P); d[idx] = h
         fd = (f(O, P + d) - f(O, P - d)) / (2 * h) + 1j * (f(O, P + 1j * d) - f(O, P - 1j * d)) / (2 * h)
         assert abs(fd - gP[idx]) <= 1e-6 * max(1.0, abs(fd))
+
+
+# --- gradient descent (full batch, fixed steps) ------------------------------
+
+def test_one_descent_step_is_the_modulus_projection():
+    # unit probe covering the whole object at one position (Nw = Nd = M), the
+    # amplitude loss: gO = 2 (psi - F^-1(sqrt(I) Psi / |Psi|)), the automatic
+    # eta_O = 1 / (2 * 1) = 1/2, so one step lands exactly on the Fourier
+    # modulus projection of the object (the error-reduction update)
+    rng = np.random.default_rng(5)
+    N = 16
+    O0 = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))
+    I_fft = rng.uniform(0.5, 2.0, size=(N, N)) ** 2
+    I_centred = np.fft.fftshift(I_fft)[None]
+    P = np.ones((N, N), complex)
+    pos = np.zeros((1, 2), int)
+    O1, P1, losses = adjoint.descend(O0, P, I_centred, pos, "amplitude", 0.0, n_steps=1, update_probe=False)
+    Psi = np.fft.fft2(O0, norm="ortho")
+    want = np.fft.ifft2(np.sqrt(I_fft) * Psi / np.abs(Psi), norm="ortho")
+    np.testing.assert_allclose(O1, want, rtol=0, atol=1e-12)
+    np.testing.assert_array_equal(P1, P)
+    assert losses[0] == pytest.approx(float(np.sum((np.abs(Psi) - np.sqrt(I_fft)) ** 2)), rel=1e-12)
+
+
+def test_step_sizes_by_hand():
+    # |P|^2 = 4 everywhere, |O|^2 = 1/4 everywhere; three windows, two of them
+    # at the same corner: the illumination peaks at 2 * 4 = 8 (eta_O = 1/16) and
+    # every probe pixel sees 3 * 1/4 (eta_P = 2/3)
+    P = np.full((4, 4), 2.0 + 0j)
+    O = np.full((12, 12), 0.5j)
+    pos = np.array([[0, 0], [0, 0], [6, 5]])
+    eO, eP = adjoint.step_sizes(O, P, pos)
+    assert eO == pytest.approx(1 / 16, rel=1e-15)
+    assert eP == pytest.approx(2 / 3, rel=1e-15)
+    # disjoint windows: eta_O = 1/8
+    assert adjoint.step_sizes(O, P, np.array([[0, 0], [6, 5]]))[0] == pytest.approx(1 / 8, rel=1e-15)
+
+
+def test_descent_lowers_the_amplitude_loss():
+    # noiseless data from a true object, a perturbed start: every fixed step
+    # lowers the loss, object and probe updated together
+    rng = np.random.default_rng(8)
+    M, Nw = 40, 16
+    O_true = synth.make_object(M, 3)
+    P = synth.make_probe(Nw, Nw / 4, 1.0)
+    pos = np.array([[y, x] for y in range(0, M - Nw + 1, 6) for x in range(0, M - Nw + 1, 6)])
+    I = ptycho.forward_intensity(O_true, P, pos, Nw)
+    O0 = O_true * (1 + 0.1 * rng.standard_normal((M, M)))
+    _, _, losses = adjoint.descend(O0, P * 1.05, I, pos, "amplitude", 0.0, n_steps=6)
+    assert np.all(np.diff(losses) < 0), losses
+    assert losses[-1] < 0.5 * losses[0]
