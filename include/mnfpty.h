@@ -84,6 +84,13 @@ int mnf_supported_sizes(int32_t* sizes, int cap);
  *         with base sum_k G_L[W_k] G_L[I_tilde_k],
  *   Q_{l,k}(x) = step * rint(x / step), step = delta[l] * t[0] / t[k]
  *   (radiometric) or delta[l] / (sat - dark) (literal); step 0 = identity.
+ * With contrast_exp = e > 0 (not part of the paper's method, which weighs by
+ * Eq. 5 alone) each raw weight is first multiplied by (C_k + 1e-6)^e,
+ * C_k = |I_bar_k(y-1,x) + I_bar_k(y+1,x) + I_bar_k(y,x-1) + I_bar_k(y,x+1)
+ *        - 4 I_bar_k(y,x)| with reflect-101 neighbours (the pixel itself along
+ * an axis of length one); where every exposure is flat the Eq. 5 weights
+ * remain.  This path stores the level-0 weights in scratch (4 K H W bytes
+ * per position) and uses the per-pixel kernels.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t levels;        /* L band-pass levels (0..12); H and W must be divisible by 2^L, and H, W >= 2^(L+1) */
@@ -93,6 +100,7 @@ typedef struct {
     float   dark;          /* dark level in ADU */
     float   delta[16];     /* quantisation step per level in ADU, l = 0 finest; 0 disables */
     int32_t radiometric;   /* 1: fuse counts scaled to the shortest exposure; 0: fuse I_bar */
+    float   contrast_exp;  /* optional contrast factor, in [0, 4]; 0 (the paper's Eq. 5 weight) disables it */
 } mnf_fuse_params;
 
 /* raw        device uint16 [J][K][H][W]   exposure brackets

@@ -97,8 +97,11 @@ def supported_sizes():
 def fuse_exposures(raw: torch.Tensor, t: Sequence[float], levels: int, mu: float = 0.5,
                    sigma: float = 0.2, sat: float = 65535.0, dark: float = 0.0,
                    delta: Sequence[float] = (), radiometric: bool = True,
-                   return_weights: bool = False, out: Optional[torch.Tensor] = None):
-    """MNF fusion of raw[J][K][H][W] (uint16 counts) -> fused float32 [J][H][W]."""
+                   return_weights: bool = False, out: Optional[torch.Tensor] = None,
+                   contrast_exp: float = 0.0):
+    """MNF fusion of raw[J][K][H][W] (uint16 counts) -> fused float32 [J][H][W].
+    contrast_exp > 0 adds the optional Laplacian-contrast factor to the weights
+    (0, the default, is the paper's weight)."""
     _dev(raw, "raw", (torch.uint16, torch.int16), 4)
     J, K, H, W = raw.shape
     if len(t) != K:
@@ -115,6 +118,7 @@ def fuse_exposures(raw: torch.Tensor, t: Sequence[float], levels: int, mu: float
     for i, d in enumerate(delta):
         prm.delta[i] = float(d)
     prm.radiometric = 1 if radiometric else 0
+    prm.contrast_exp = float(contrast_exp)
     tt = (ctypes.c_float * K)(*[float(x) for x in t])
     ctx = _ctx(raw.device)
     rc = _L.load().fuse_exposures(ctx, _ptr(raw), tt, J, K, H, W, ctypes.byref(prm), _ptr(out), _ptr(wts),

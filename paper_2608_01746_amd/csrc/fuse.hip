@@ -39,6 +39,7 @@ constexpr int kMaxLevels = 12;
 
 struct FuseConsts {
     float inv_range;          // 1 / (sat - dark)
+    float range;              // sat - dark
     float dark;
     float mu, inv_2s2;        // weight centre and 1 / (2 sigma^2)
     float scale[kMaxK];       // I_tilde_k = (I_k - dark) * scale[k]  (radiometric) or I_bar_k
@@ -85,13 +86,67 @@ __device__ __forceinline__ void level0_eval(const float* cnt, int K, const FuseC
     for (int kk = 0; kk < KM; ++kk) gw[kk] = gw[kk] * inv;
 }
 
-// Level 1 of the image and weight pyramids of all K exposures, reduced from
-// the recomputed level 0: thread per level-1 pixel of the chunk (total =
-// nj * (H/2) * (W/2)); GI1 and GW1 are [K][total].
+// Offset added to the contrast before its exponent: where every exposure is
+// flat the common factor cancels in the normalisation and the Eq. 5 weights
+// remain.  With exponents up to kMaxContrastExp the factor stays a normal
+// float (1e-24 at the cap).
+constexpr float kContrastEps = 1e-6f;
+constexpr float kMaxContrastExp = 4.f;
+
+// Dark-subtracted count clamped to [0, sat - dark]: I_bar times (sat - dark).
+// For integer counts and dark level the Laplacian of these values is an
+// exact integer sum, so the contrast is rounded once, when normalised, and
+// not cancelled from rounded I_bar values.
+__device__ __forceinline__ float clamped_count(const uint16_t* px, const FuseConsts& c) {
+    return fminf(fmaxf((float)*px - c.dark, 0.f), c.range);
+}
+
+// Optional contrast weights (contrast exponent > 0; the paper's weight is
+// Eq. 5 alone): per level-0 pixel of the chunk (total = nj * H * W), the Eq. 5
+// weight of every exposure times (C_k + eps)^e, C_k = |4-neighbour Laplacian
+// of I_bar_k| (reflect-101 neighbours, clamped into an axis of length one),
+// normalised over the K frames into W0 [nj][K][H][W].
 template <int KM>
 __global__ void __launch_bounds__(256)
+k_fuse_contrast_weights(const uint16_t* __restrict__ raw, int K, int H, int W, size_t total, FuseConsts c,
+                        float cexp, float* __restrict__ W0) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;  // the chunk keeps totals below 2^31
+    if (i >= (int)total) return;
+    const size_t npix = (size_t)H * W;
+    const int jj = i / (H * W), pq = i - jj * (H * W);
+    const int y = pq / W, x = pq - y * W;
+    const int ym = min(reflect101(y - 1, H), H - 1), yp = max(reflect101(y + 1, H), 0);
+    const int xm = min(reflect101(x - 1, W), W - 1), xp = max(reflect101(x + 1, W), 0);
+    float w[KM];
+    float wsum = 0.f;
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk) {
+        w[kk] = 0.f;
+        if (kk < K) {
+            const uint16_t* im = raw + ((size_t)jj * K + kk) * npix;
+            const float v = clamped_count(im + pq, c);
+            const float lap = clamped_count(im + (size_t)ym * W + x, c) + clamped_count(im + (size_t)yp * W + x, c) +
+                              clamped_count(im + (size_t)y * W + xm, c) + clamped_count(im + (size_t)y * W + xp, c) -
+                              4.f * v;
+            const float d = v * c.inv_range - c.mu;
+            w[kk] = expf(-d * d * c.inv_2s2) * powf(fabsf(lap) * c.inv_range + kContrastEps, cexp);
+            wsum += w[kk];
+        }
+    }
+    const float inv = 1.f / fmaxf(wsum, 1e-30f);
+#pragma unroll
+    for (int kk = 0; kk < KM; ++kk)
+        if (kk < K) W0[((size_t)jj * K + kk) * npix + pq] = w[kk] * inv;
+}
+
+// Level 1 of the image and weight pyramids of all K exposures, reduced from
+// the recomputed level 0: thread per level-1 pixel of the chunk (total =
+// nj * (H/2) * (W/2)); GI1 and GW1 are [K][total].  With CW the level-0
+// weights are read from W0 (k_fuse_contrast_weights) instead.
+template <int KM, bool CW>
+__global__ void __launch_bounds__(256)
 k_fuse_level1(const uint16_t* __restrict__ raw, int K, int H, int W, size_t total, FuseConsts c,
-              float* __restrict__ GI1, float* __restrict__ GW1) {
+              const float* __restrict__ W0, float* __restrict__ GI1, float* __restrict__ GW1) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;  // the chunk keeps totals below 2^31
     if (i >= (int)total) return;
     const int h1 = H >> 1, w1 = W >> 1;
@@ -118,6 +173,12 @@ k_fuse_level1(const uint16_t* __restrict__ raw, int K, int H, int W, size_t tota
         for (int b = 0; b < 5; ++b) {
             float gi[KM], gw[KM];
             level0_eval<KM>(cnt[b], K, c, gi, gw);
+            if (CW) {
+                const float* w0 = W0 + (size_t)jj * K * npix + (size_t)yy * W + reflect101(2 * ox + b - 2, W);
+#pragma unroll
+                for (int kk = 0; kk < KM; ++kk)
+                    if (kk < K) gw[kk] = w0[(size_t)kk * npix];
+            }
 #pragma unroll
             for (int kk = 0; kk < KM; ++kk) {
                 ri[kk] += binom5(b) * gi[kk];
@@ -526,12 +587,13 @@ struct Level0Steps {
 // level-0 coefficient of every exposure, G_0[W_k] (G_0[I_k] - U(G_1[I_k])),
 // quantised with its own step and summed over k, plus U(R_1) (the fused
 // pyramid collapsed to level 1).  With L = 0 the output is the weighted sum
-// of the level-0 images.  Optionally writes the normalised weights.
-template <int KM>
+// of the level-0 images.  Optionally writes the normalised weights.  With CW
+// the level-0 weights are read from W0 (k_fuse_contrast_weights) instead.
+template <int KM, bool CW>
 __global__ void __launch_bounds__(256)
 k_fuse_final(const uint16_t* __restrict__ raw, int K, int H, int W, size_t total, FuseConsts c, Level0Steps q,
-             const float* __restrict__ GI1, const float* __restrict__ R1, int L, float* __restrict__ out,
-             float* __restrict__ weights_out) {
+             const float* __restrict__ W0, const float* __restrict__ GI1, const float* __restrict__ R1, int L,
+             float* __restrict__ out, float* __restrict__ weights_out) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;  // the chunk keeps totals below 2^31
     if (i >= (int)total) return;
     const size_t npix = (size_t)H * W;
@@ -555,6 +617,11 @@ k_fuse_final(const uint16_t* __restrict__ raw, int K, int H, int W, size_t total
     }
     float gi[KM], gw[KM];
     level0_eval<KM>(cnt, K, c, gi, gw);
+    if (CW) {
+#pragma unroll
+        for (int kk = 0; kk < KM; ++kk)
+            if (kk < K) gw[kk] = W0[((size_t)jj * K + kk) * npix + pq];
+    }
     if (weights_out) {
 #pragma unroll
         for (int kk = 0; kk < KM; ++kk)
@@ -752,10 +819,15 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
         if (!(t[k] > 0.f)) return set_error(ctx, MNF_EINVAL, "exposure time %d must be positive", k);
     for (int l = 0; l < 16; ++l)
         if (!(p->delta[l] >= 0.f)) return set_error(ctx, MNF_EINVAL, "delta[%d] must be >= 0", l);
+    if (!(p->contrast_exp >= 0.f && p->contrast_exp <= kMaxContrastExp))
+        return set_error(ctx, MNF_EINVAL, "contrast_exp %g outside [0, %g]", (double)p->contrast_exp,
+                         (double)kMaxContrastExp);
+    const bool cw = p->contrast_exp > 0.f;
 
     hipStream_t st = (hipStream_t)stream;
     FuseConsts c{};
     c.inv_range = (float)(1.0 / ((double)p->sat - (double)p->dark));
+    c.range = (float)((double)p->sat - (double)p->dark);
     c.dark = p->dark;
     c.mu = p->mu;
     c.inv_2s2 = (float)(1.0 / (2.0 * (double)p->sigma * (double)p->sigma));
@@ -781,7 +853,9 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
     for (int l = 1; l <= L; ++l) offF[l + 1] = offF[l] + (size_t)(H >> l) * (W >> l);
     for (int l = 2; l <= L; ++l) offS[l + 1] = offS[l] + (size_t)(H >> l) * (W >> l);
     const size_t n1pos = L >= 1 ? (size_t)(H >> 1) * (W >> 1) : 0;
-    const size_t per_pos = 2 * (size_t)K * n1pos + 2 * (size_t)K * offS[L + 1] + offF[L + 1];
+    // (plus the level-0 weights of all K exposures with the contrast factor)
+    const size_t per_pos =
+        2 * (size_t)K * n1pos + 2 * (size_t)K * offS[L + 1] + offF[L + 1] + (cw ? (size_t)K * H * W : 0);
     const size_t budget = (size_t)1 << 30;
     size_t chunk_cap = per_pos == 0 ? (size_t)J : budget / (per_pos * sizeof(float));
     chunk_cap = std::min(chunk_cap, (size_t)(INT32_MAX / 2) / npix_all);  // 32-bit pixel indices in a chunk
@@ -800,6 +874,12 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
         SW = (float*)a4;
         F = (float*)a5;
     }
+    float* W0 = nullptr;
+    if (cw) {
+        void* a;
+        MNF_TRY(scratch(ctx, "fuseW0", (size_t)chunk * K * H * W * sizeof(float), &a));
+        W0 = (float*)a;
+    }
     Level0Steps q0{};
     for (int k = 0; k < K; ++k) q0.step[k] = L >= 1 ? step[k] : 0.f;
     const size_t npix = (size_t)H * W;
@@ -809,7 +889,16 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
         const int nj = std::min(chunk, J - j0);
         const uint16_t* rawc = raw + (size_t)j0 * K * npix;
         const size_t n1 = (size_t)nj * n1pos;
-        if (L >= 1) {
+        if (cw) {
+            const size_t n0 = (size_t)nj * npix;
+            if (small_k)
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_contrast_weights<8>, grid1d(n0), dim3(256), rawc, K, H, W, n0,
+                           c, p->contrast_exp, W0);
+            else
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_contrast_weights<kMaxK>, grid1d(n0), dim3(256), rawc, K, H, W,
+                           n0, c, p->contrast_exp, W0);
+        }
+        if (L >= 1 && !cw && K <= 5) {
             switch (K) {
                 case 1: MNF_TRY(launch_level1<1>(ctx, st, rawc, K, H, W, n1, nj, c, GI1, GW1)); break;
                 case 2: MNF_TRY(launch_level1<2>(ctx, st, rawc, K, H, W, n1, nj, c, GI1, GW1)); break;
@@ -818,12 +907,23 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
                 case 5: MNF_TRY(launch_level1<5>(ctx, st, rawc, K, H, W, n1, nj, c, GI1, GW1)); break;
                 default: break;
             }
-            if (K <= 5) {
-            } else if (small_k)
-                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level1<8>, grid1d(n1), dim3(256), rawc, K, H, W, n1, c, GI1, GW1);
+        } else if (L >= 1) {
+            // the generic level-1 kernel: more than five exposures, or level-0
+            // weights from the contrast pass
+            if (small_k && cw)
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, (k_fuse_level1<8, true>), grid1d(n1), dim3(256), rawc, K, H, W, n1, c,
+                           (const float*)W0, GI1, GW1);
+            else if (small_k)
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, (k_fuse_level1<8, false>), grid1d(n1), dim3(256), rawc, K, H, W, n1, c,
+                           (const float*)nullptr, GI1, GW1);
+            else if (cw)
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, (k_fuse_level1<kMaxK, true>), grid1d(n1), dim3(256), rawc, K, H, W, n1,
+                           c, (const float*)W0, GI1, GW1);
             else
-                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_level1<kMaxK>, grid1d(n1), dim3(256), rawc, K, H, W, n1, c, GI1,
-                           GW1);
+                MNF_LAUNCH(ctx, MNF_K_FUSE, st, (k_fuse_level1<kMaxK, false>), grid1d(n1), dim3(256), rawc, K, H, W, n1,
+                           c, (const float*)nullptr, GI1, GW1);
+        }
+        if (L >= 1) {
             // level-l arrays (l >= 1) of exposure k and of the fused pyramid;
             // exposure k's arrays of level l sit at k * sstride(l) from exposure 0's
             const size_t sS = (size_t)nj * offS[L + 1];
@@ -881,7 +981,7 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
         const float* R1 = L >= 1 ? F : (const float*)nullptr;  // fused level 1 sits first in F
         // the quad kernel reads two counts per 32-bit load and writes two outputs
         // per 64-bit store (W is even when L >= 1)
-        const bool quad = L >= 1 && small_k && (uintptr_t)raw % 4 == 0 && (uintptr_t)fused % 8 == 0;
+        const bool quad = L >= 1 && small_k && !cw && (uintptr_t)raw % 4 == 0 && (uintptr_t)fused % 8 == 0;
         if (quad) {
             Level0Quant qq{};
             for (int k = 0; k < K; ++k) {
@@ -898,12 +998,18 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
                 case 7: MNF_TRY(launch_final_quad<7>(ctx, st, rawc, H, W, n1, c, qq, GI1, R1, outc, wout)); break;
                 default: MNF_TRY(launch_final_quad<8>(ctx, st, rawc, H, W, n1, c, qq, GI1, R1, outc, wout)); break;
             }
-        } else if (small_k)
-            MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_final<8>, grid1d(n0), dim3(256), rawc, K, H, W, n0, c, q0,
-                       (const float*)GI1, R1, L, outc, wout);
+        } else if (small_k && cw)
+            MNF_LAUNCH(ctx, MNF_K_FUSE, st, (k_fuse_final<8, true>), grid1d(n0), dim3(256), rawc, K, H, W, n0, c, q0,
+                       (const float*)W0, (const float*)GI1, R1, L, outc, wout);
+        else if (small_k)
+            MNF_LAUNCH(ctx, MNF_K_FUSE, st, (k_fuse_final<8, false>), grid1d(n0), dim3(256), rawc, K, H, W, n0, c, q0,
+                       (const float*)nullptr, (const float*)GI1, R1, L, outc, wout);
+        else if (cw)
+            MNF_LAUNCH(ctx, MNF_K_FUSE, st, (k_fuse_final<kMaxK, true>), grid1d(n0), dim3(256), rawc, K, H, W, n0, c,
+                       q0, (const float*)W0, (const float*)GI1, R1, L, outc, wout);
         else
-            MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_final<kMaxK>, grid1d(n0), dim3(256), rawc, K, H, W, n0, c, q0,
-                       (const float*)GI1, R1, L, outc, wout);
+            MNF_LAUNCH(ctx, MNF_K_FUSE, st, (k_fuse_final<kMaxK, false>), grid1d(n0), dim3(256), rawc, K, H, W, n0, c,
+                       q0, (const float*)nullptr, (const float*)GI1, R1, L, outc, wout);
     }
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;

@@ -23,7 +23,7 @@ ERROR_NAMES = {MNF_EINVAL: "MNF_EINVAL", MNF_EUNSUPPORTED: "MNF_EUNSUPPORTED",
 
 class FuseParamsC(ctypes.Structure):
     _fields_ = [("levels", c_int32), ("mu", c_float), ("sigma", c_float), ("sat", c_float),
-                ("dark", c_float), ("delta", c_float * 16), ("radiometric", c_int32)]
+                ("dark", c_float), ("delta", c_float * 16), ("radiometric", c_int32), ("contrast_exp", c_float)]
 
 
 class PtychoParamsC(ctypes.Structure):

@@ -115,6 +115,42 @@ def test_fusion_parameters_match_oracle(api, K, radiometric):
     assert rel(wts.cpu().numpy(), Wref) < 1e-6
 
 
+@pytest.mark.parametrize("H,W,K,L,J,cexp", [(40, 24, 3, 3, 2, 1.0),   # generic level-1 and final kernels
+                                            (32, 48, 7, 2, 2, 2.0),   # K > 5
+                                            (32, 32, 10, 2, 1, 0.5),  # K > 8: the 16-wide instantiation
+                                            (16, 1, 2, 0, 2, 4.0)])   # L = 0, an axis of length one
+def test_fusion_with_contrast_factor_matches_oracle(api, H, W, K, L, J, cexp):
+    # the optional contrast factor: sparse patterns with flat zero background
+    # (where the Eq. 5 weights must remain) and steep peaks
+    rng = np.random.default_rng(70 + K)
+    t = [2.5 ** k for k in range(K)]
+    base = rng.gamma(0.5, 300.0, size=(J, 1, H, W)) * (rng.random((J, 1, H, W)) < 0.4)
+    raw = np.clip(rng.poisson(base * np.array(t)[None, :, None, None]) + 3, 0, 4095).astype(np.uint16)
+    p = mnf.FuseParams(levels=L, sat=4095.0, dark=3.0, contrast_exp=cexp)
+    ref = mnf.fuse(raw, t, p)
+    Wref = mnf.weights(raw, p)
+    out, wts = api.fuse_exposures(torch.from_numpy(raw).to(DEV), t, L, sat=4095.0, dark=3.0, contrast_exp=cexp,
+                                  return_weights=True)
+    assert rel(out.cpu().numpy(), ref) < 1e-5
+    assert rel(wts.cpu().numpy(), Wref) < 1e-6
+    # the flat background keeps the paper's weights
+    W0 = mnf.weights(raw, mnf.FuseParams(levels=L, sat=4095.0, dark=3.0))
+    flat = np.all(raw == 3, axis=1, keepdims=True)
+    flat = flat & np.roll(flat, 1, 2) & np.roll(flat, -1, 2) & np.roll(flat, 1, 3) & np.roll(flat, -1, 3)
+    flat[:, :, [0, -1], :] = False
+    flat[:, :, :, [0, -1]] = False
+    m = np.broadcast_to(flat, W0.shape)
+    if m.any():
+        np.testing.assert_allclose(wts.cpu().numpy()[m], W0[m], rtol=1e-5)
+
+
+def test_fusion_rejects_contrast_exponents_outside_range(api):
+    raw = torch.zeros((1, 2, 16, 16), dtype=torch.uint16, device=DEV)
+    for e in (-0.5, 4.5, float("nan")):
+        with pytest.raises(api.MnfError):
+            api.fuse_exposures(raw, [1.0, 2.0], 2, contrast_exp=e)
+
+
 def test_fusion_literal_mode_with_quantisation_matches_oracle(api):
     # the literal reading (radiometric = 0) with quantisation steps in ADU,
     # i.e. delta / (sat - dark) on the normalised images
