@@ -98,11 +98,17 @@ def step_sizes(O: np.ndarray, P: np.ndarray, pos: np.ndarray) -> Tuple[float, fl
 def descend(O: np.ndarray, P: np.ndarray, I_centred: np.ndarray, pos: np.ndarray, kind: str = "poisson",
             eps: float = 1e-6, n_steps: int = 1, eta_O: float = 0.0, eta_P: float = 0.0,
             update_probe: bool = True):
-    """Full-batch gradient descent on the loss above: per step the loss and
-    both gradients at the current (O, P), then O -= eta_O gO and, with
-    update_probe, P -= eta_P gP.  Step sizes <= 0 take step_sizes() of the
-    starting O and P and stay fixed.  Returns (O, P, losses[n_steps]), the
-    loss of step s taken before its update."""
+    """Full-batch gradient descent on the loss above with backtracking (a
+    reading; the paper prescribes no descent schedule).  Pass s evaluates the
+    loss L_s and both gradients at the current (O, P):
+      * L_s <= the lowest loss so far (or s = 0): the pass is accepted, its
+        point and gradients become the best, and O -= eta_O gO (and, with
+        update_probe, P -= eta_P gP);
+      * otherwise both step sizes are halved and the next point is the best
+        point minus the halved steps along the best point's gradients.
+    Step sizes <= 0 start from step_sizes() of the starting O and P.
+    Returns (O, P, losses[n_steps], accepted[n_steps]); O and P are the last
+    point formed (its loss not evaluated)."""
     O = np.array(O, np.complex128)
     P = np.array(P, np.complex128)
     eO, eP = step_sizes(O, P, pos)
@@ -111,9 +117,16 @@ def descend(O: np.ndarray, P: np.ndarray, I_centred: np.ndarray, pos: np.ndarray
     if eta_P > 0.0:
         eP = eta_P
     losses = np.zeros(n_steps)
+    accepted = np.zeros(n_steps, bool)
+    best = None  # (loss, O, P, gO, gP)
     for s in range(n_steps):
         losses[s], gO, gP = loss_and_grad(O, P, I_centred, pos, kind, eps)
-        O = O - eO * gO
-        if update_probe:
-            P = P - eP * gP
-    return O, P, losses
+        if best is None or losses[s] <= best[0]:
+            accepted[s] = True
+            best = (losses[s], O, P, gO, gP)
+        else:
+            eO, eP = eO / 2.0, eP / 2.0
+        _, Ob, Pb, gOb, gPb = best
+        O = Ob - eO * gOb
+        P = Pb - eP * gPb if update_probe else Pb
+    return O, P, losses, accepted

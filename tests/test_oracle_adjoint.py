@@ -107,7 +107,7 @@ def test_one_descent_step_is_the_modulus_projection():
     I_centred = np.fft.fftshift(I_fft)[None]
     P = np.ones((N, N), complex)
     pos = np.zeros((1, 2), int)
-    O1, P1, losses = adjoint.descend(O0, P, I_centred, pos, "amplitude", 0.0, n_steps=1, update_probe=False)
+    O1, P1, losses, acc = adjoint.descend(O0, P, I_centred, pos, "amplitude", 0.0, n_steps=1, update_probe=False)
     Psi = np.fft.fft2(O0, norm="ortho")
     want = np.fft.ifft2(np.sqrt(I_fft) * Psi / np.abs(Psi), norm="ortho")
     np.testing.assert_allclose(O1, want, rtol=0, atol=1e-12)
@@ -139,6 +139,35 @@ def test_descent_lowers_the_amplitude_loss():
     pos = np.array([[y, x] for y in range(0, M - Nw + 1, 6) for x in range(0, M - Nw + 1, 6)])
     I = ptycho.forward_intensity(O_true, P, pos, Nw)
     O0 = O_true * (1 + 0.1 * rng.standard_normal((M, M)))
-    _, _, losses = adjoint.descend(O0, P * 1.05, I, pos, "amplitude", 0.0, n_steps=6)
-    assert np.all(np.diff(losses) < 0), losses
+    _, _, losses, acc = adjoint.descend(O0, P * 1.05, I, pos, "amplitude", 0.0, n_steps=6)
+    assert acc.all() and np.all(np.diff(losses) < 0), losses
     assert losses[-1] < 0.5 * losses[0]
+
+
+def test_descent_backtracks_by_hand():
+    # one pixel (Nw = Nd = 1, the transform is the identity), amplitude loss
+    # (|P O| - 1)^2 with gradients gO = conj(P) g, gP = conj(O) g,
+    # g = 2 (psi - psi / |psi|), psi = P O, from O = 3, P = 1 (g = 4).
+    O0 = np.array([[3.0 + 0j]])
+    P0 = np.array([[1.0 + 0j]])
+    I = np.array([[[1.0]]])
+    pos = np.zeros((1, 2), int)
+    # object only, eta_O = 2:
+    #   pass 0: L = 4, accepted;       O = 3 - 2 * 4 = -5
+    #   pass 1: L = 16 > 4, rejected;  eta_O = 1, O = 3 - 1 * 4 = -1
+    #   pass 2: L = 0, accepted;       the gradient is 0, O stays -1
+    O, P, losses, acc = adjoint.descend(O0, P0, I, pos, "amplitude", 0.0, n_steps=3, eta_O=2.0,
+                                        update_probe=False)
+    np.testing.assert_allclose(losses, [4.0, 16.0, 0.0], atol=1e-12)
+    assert acc.tolist() == [True, False, True]
+    np.testing.assert_allclose(O, [[-1.0]], atol=1e-12)
+    np.testing.assert_array_equal(P, P0)
+    # object and probe, eta_O = 2, eta_P = 1 (gP = 3 * 4 = 12):
+    #   pass 0: L = 4, accepted;   O = -5, P = 1 - 12 = -11
+    #   pass 1: psi = 55, L = 2916, rejected; O = 3 - 4 = -1, P = 1 - 6 = -5
+    #   pass 2: psi = 5, L = 16 > 4, rejected; O = 3 - 2 = 1, P = 1 - 3 = -2
+    O, P, losses, acc = adjoint.descend(O0, P0, I, pos, "amplitude", 0.0, n_steps=3, eta_O=2.0, eta_P=1.0)
+    np.testing.assert_allclose(losses, [4.0, 2916.0, 16.0], atol=1e-9)
+    assert acc.tolist() == [True, False, False]
+    np.testing.assert_allclose(O, [[1.0]], atol=1e-12)
+    np.testing.assert_allclose(P, [[-2.0]], atol=1e-12)
