@@ -79,6 +79,11 @@ def loss_and_grad(O: np.ndarray, P: np.ndarray, I_centred: np.ndarray, pos: np.n
     return total, gO, gP
 
 
+# Relative increase of the loss over the reference that still counts as no
+# increase (descend()).
+DESCENT_TOL = 1e-6
+
+
 def step_sizes(O: np.ndarray, P: np.ndarray, pos: np.ndarray) -> Tuple[float, float]:
     """Fixed gradient-descent step sizes (a reading; the paper fixes none):
     eta_O = 1 / (2 max_x sum_j |P(x - p_j)|^2) over the object grid and
@@ -101,11 +106,16 @@ def descend(O: np.ndarray, P: np.ndarray, I_centred: np.ndarray, pos: np.ndarray
     """Full-batch gradient descent on the loss above with backtracking (a
     reading; the paper prescribes no descent schedule).  Pass s evaluates the
     loss L_s and both gradients at the current (O, P):
-      * L_s <= the lowest loss so far (or s = 0): the pass is accepted, its
-        point and gradients become the best, and O -= eta_O gO (and, with
+      * s = 0, or L_s <= L_ref + DESCENT_TOL |L_ref| with L_ref the loss of
+        the last accepted pass: the pass is accepted, its point, gradients
+        and loss become the reference, and O -= eta_O gO (and, with
         update_probe, P -= eta_P gP);
-      * otherwise both step sizes are halved and the next point is the best
-        point minus the halved steps along the best point's gradients.
+      * otherwise both step sizes are halved and the next point is the
+        reference point minus the halved steps along its gradients.
+    DESCENT_TOL bounds the float32 evaluation error of a loss: the Poisson
+    loss carries a large data-only constant, so late improvements are small
+    relative to it, and without the tolerance rounding noise could reject a
+    good step.
     Step sizes <= 0 start from step_sizes() of the starting O and P.
     Returns (O, P, losses[n_steps], accepted[n_steps]); O and P are the last
     point formed (its loss not evaluated)."""
@@ -118,10 +128,10 @@ def descend(O: np.ndarray, P: np.ndarray, I_centred: np.ndarray, pos: np.ndarray
         eP = eta_P
     losses = np.zeros(n_steps)
     accepted = np.zeros(n_steps, bool)
-    best = None  # (loss, O, P, gO, gP)
+    best = None  # the reference: (loss, O, P, gO, gP)
     for s in range(n_steps):
         losses[s], gO, gP = loss_and_grad(O, P, I_centred, pos, kind, eps)
-        if best is None or losses[s] <= best[0]:
+        if best is None or losses[s] <= best[0] + DESCENT_TOL * abs(best[0]):
             accepted[s] = True
             best = (losses[s], O, P, gO, gP)
         else:

@@ -171,3 +171,21 @@ def test_descent_backtracks_by_hand():
     assert acc.tolist() == [True, False, False]
     np.testing.assert_allclose(O, [[1.0]], atol=1e-12)
     np.testing.assert_allclose(P, [[-2.0]], atol=1e-12)
+
+
+def test_descent_tolerates_increases_below_the_tolerance():
+    # the one-pixel problem from O = 3 (L = 4, g = 4): a step to
+    # O = -(3 + d) gives L = (2 + d)^2 = 4 (1 + d + d^2 / 4); it is accepted
+    # for d = 5e-7 (an increase of 5e-7 relative, inside DESCENT_TOL = 1e-6)
+    # and rejected for d = 4e-6
+    O0 = np.array([[3.0 + 0j]])
+    P0 = np.array([[1.0 + 0j]])
+    I = np.array([[[1.0]]])
+    pos = np.zeros((1, 2), int)
+    assert adjoint.DESCENT_TOL == 1e-6
+    for d, ok in [(5e-7, True), (4e-6, False)]:
+        eta = (6.0 + d) / 4.0
+        _, _, losses, acc = adjoint.descend(O0, P0, I, pos, "amplitude", 0.0, n_steps=2, eta_O=eta,
+                                            update_probe=False)
+        assert losses[1] == pytest.approx((2.0 + d) ** 2, rel=1e-12)
+        assert acc.tolist() == [True, ok]
