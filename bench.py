@@ -391,12 +391,17 @@ def run_lab(args, api, synth, dev):
 
 
 def run_grad(args, api, synth, dev):
-    """Loss gradient (the adjoint of Eqs. 2-3) on the gradient workload: 2048^2
-    object, 512^2 probe, 1000 Fermat-spiral positions, MNF-fused data from
-    exposures simulated on the GPU (5 exposures, 16 bit, read noise 3,
-    6 levels).  A step is the Poisson loss and the object and probe gradients
-    over every position (exit waves recomputed in batches of 32), at a
-    perturbed start so the gradient is not zero.  value = positions / s."""
+    """Gradient-descent reconstruction (the adjoint of Eqs. 2-3 under the
+    Poisson model) on the gradient workload: 2048^2 object, 512^2 probe,
+    1000 Fermat-spiral positions, MNF-fused data from exposures simulated on
+    the GPU (5 exposures, 16 bit, read noise 3, 6 levels).  A step is one
+    full-batch descent step: the Poisson loss and the object and probe
+    gradients over every position (exit waves recomputed in batches of 32),
+    then the backtracking step of ptycho_descend, from a flat object and the
+    known probe (both updated).  The warm-up computes the initial step sizes; the
+    timed call resumes with the step sizes the warm-up ended with.
+    value = positions / s; the loss of every step and the final object NRMSE
+    are reported."""
     import numpy as np
     import torch
 
@@ -413,33 +418,45 @@ def run_grad(args, api, synth, dev):
     fused = api.fuse_exposures(raw, w.t, w.levels, sat=float(w.sat), delta=synth.default_deltas(w.levels, w.sigma_read))
     del raw
     torch.cuda.synchronize()
-    O0 = torch.from_numpy((synth.make_object(w.M, 44) * 0.2 + O_true * 0.8).astype(np.complex64)).to(dev)
+    O_start = np.ones((w.M, w.M), np.complex64)  # flat start, as the iterative engines
+    O0 = torch.from_numpy(O_start).to(dev)
     Pk = torch.from_numpy((np.sqrt(s) * P).astype(np.complex64)).to(dev)
-    state = {}
+    Ot_scaled = torch.from_numpy(O_true.astype(np.complex64)).to(dev)
+    mask = torch.from_numpy(_illum_mask(P, w.pos, (w.M, w.M)).astype(np.uint8)).to(dev)
+    nrmse0 = api.nrmse(O0, Ot_scaled, mask).item()
 
-    def step():
-        state["out"] = api.ptycho_grad(O0, Pk, fused, w.pos, "poisson", eps=1e-6, batch=w.batch)
-
-    classes = ["rows_fwd", "grad_cols", "rows_inv", "grad_scatter"]
+    # step sizes from the start and a profiled first step, then the rest of
+    # the warm-up
+    classes = ["rows_fwd", "grad_cols", "rows_inv", "grad_scatter", "small"]
     api.profile(classes)
     api.profile_reset()
-    step()
+    loss_w, eta = api.ptycho_descend(O0, Pk, fused, w.pos, 1, "poisson", 1e-6, w.batch)
     torch.cuda.synchronize()
     ranks = api.profile_read()
     api.profile([])
-    dominant = max(classes, key=lambda k: ranks[k][1])
-    for _ in range(args.warmup - 1):
-        step()
+    eta_O, eta_P = (float(x) for x in eta.cpu().tolist())
+    eta_start = (eta_O, eta_P)
+    losses = [loss_w]
+    if args.warmup > 1:
+        loss_w, eta = api.ptycho_descend(O0, Pk, fused, w.pos, args.warmup - 1, "poisson", 1e-6, w.batch,
+                                         eta_O=eta_O, eta_P=eta_P)
+        losses.append(loss_w)
+        eta_O, eta_P = (float(x) for x in eta.cpu().tolist())
+    dominant = max(classes[:4], key=lambda k: ranks[k][1])
     api.profile([dominant])
     api.profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    loss_t, eta = api.ptycho_descend(O0, Pk, fused, w.pos, args.steps, "poisson", 1e-6, w.batch, eta_O=eta_O,
+                                     eta_P=eta_P)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = api.profile_read()
     api.profile([])
+    losses.append(loss_t)
+    loss_hist = torch.cat(losses).cpu().tolist()
+    nrmse1 = api.nrmse(O0, Ot_scaled, mask).item()
+    api.check_status(dev)
     nlaunch, kms = prof[dominant]
     dt = (t1 - t0) / args.steps
     N, B = w.Nd, w.batch
@@ -450,24 +467,35 @@ def run_grad(args, api, synth, dev):
     bytes_pos = 20.0 * N * N + 16.0 * N * N / B
     avg_us = kms / nlaunch * 1e3
     achieved = bytes_pos * per_launch / (avg_us * 1e-6) / 1e9
+    # the step itself: O and gO read, O written (object grid), the same for P
+    bytes_step = 24.0 * (w.M * w.M + N * N)
+    pipe = (bytes_pos * w.J + bytes_step) / dt / 1e9
     out = {
-        "metric": "position-gradients/s at 512^2 FP32 (Poisson loss and object/probe gradients, batches of 32)",
+        "metric": "position-gradients/s at 512^2 FP32 (gradient-descent reconstruction: Poisson loss, object and "
+                  "probe gradients and the step, batches of 32)",
         "value": round(w.J / dt, 1), "unit": "position-gradients/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32",
         "data": "synthetic (seeded object/probe, exposures simulated on the GPU, MNF-fused)",
         "config": {"workload": "grad-512: 2048^2 object, 512^2 probe, 1000 Fermat-spiral positions, 5 exposures, "
-                               "6-level fusion, Poisson loss, recompute batches of 32"},
+                               "6-level fusion, Poisson loss, recompute batches of 32, full-batch descent with "
+                               "backtracking"},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "avg_launch_us": round(avg_us, 2), "launches": nlaunch,
-                     "algorithmic_bytes_per_launch": round(bytes_pos * per_launch)},
+                     "algorithmic_bytes_per_launch": round(bytes_pos * per_launch),
+                     "pipeline_achieved": round(pipe, 1), "pipeline_frac": round(pipe / HBM_PEAK_GBS, 4)},
         "per_class_ms_one_step": {k: round(v[1], 3) for k, v in ranks.items()},
-        "loss": float(state["out"][0].item()),
+        "step_sizes": {"start": list(eta_start), "end": [float(x) for x in eta.cpu().tolist()]},
+        "loss_per_step": [float(f"{x:.6e}") for x in loss_hist],
+        "nrmse_start": round(nrmse0, 5), "nrmse_end": round(nrmse1, 5),
+        "note": "MNF-fused patterns of this detector model hold every reconstruction (rPIE included) near object "
+                "NRMSE 0.2 (radiometric deviation of the fusion); on the noise-free patterns the same descent "
+                "from the same start reaches 0.005 after 200 steps",
     }
     if not args.no_cpu:
         from oracle import adjoint
-        O_np, P_np = O0.cpu().numpy().astype(np.complex128), Pk.cpu().numpy().astype(np.complex128)
+        O_np, P_np = O_start.astype(np.complex128), (np.sqrt(s) * P).astype(np.complex128)
         I_np = fused.cpu().numpy().astype(np.float64)
         n, t_start = 0, time.perf_counter()
         while time.perf_counter() - t_start < args.cpu_seconds and n < w.J:
@@ -476,7 +504,8 @@ def run_grad(args, api, synth, dev):
         sec = time.perf_counter() - t_start
         out["cpu_baseline"] = {"value": round(n / sec, 3), "unit": "position-gradients/s", "cores": 1,
                                "kind": "oracle",
-                               "sample": f"{n} positions' Poisson loss and gradients in float64 NumPy, {sec:.1f} s"}
+                               "sample": f"{n} positions' Poisson loss and gradients in float64 NumPy, {sec:.1f} s "
+                                         "(the step itself, one pass over the arrays, not included)"}
     return out
 
 

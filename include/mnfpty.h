@@ -281,6 +281,33 @@ int ptycho_grad(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P
                 int kind, float eps, int batch, const double* upstream,
                 double* loss_out, mnf_c64* gO, mnf_c64* gP, void* stream);
 
+/* Gradient-descent reconstruction on the loss of ptycho_grad (same kind, eps,
+ * batch and data layout), O and P updated in place.  Pass s takes the loss
+ * L_s and both gradients at the current (O, P); then (backtracking, a
+ * reading: the paper prescribes no descent schedule)
+ *   s = 0, or L_s <= L_ref + 1e-6 |L_ref| (L_ref: the loss of the last
+ *          accepted pass; the 1e-6 bounds float32 evaluation error): accepted,
+ *          the point, its gradients and L_s become the reference,
+ *          O -= eta_O gO and P -= eta_P gP (the probe only with update_probe);
+ *   otherwise: both step sizes are halved and the next point is the
+ *          reference point minus the halved steps along its gradients.
+ * Initial step sizes: eta_O = 0 takes 1 / (2 max_x sum_j |P(x - p_j)|^2) over
+ * the object grid and eta_P = 0 takes 1 / (2 max_u sum_j |O(p_j + u)|^2) over
+ * the probe window, from the starting O and P (the inverse of the largest
+ * diagonal curvature of the amplitude loss); a positive value is used as given.
+ * On return O and P are the last point formed (its loss not evaluated).
+ * loss_out device double [n_steps]: L_s of each pass (may be NULL);
+ * eta_out  device double [2]: the step sizes at the end of the call, halvings
+ *          included, i.e. the values with which to resume (may be NULL).
+ * Scratch: 8 (My Mx + Nw^2) bytes for the gradients and twice that for the
+ * best point.  Returns MNF_EINVAL for a bad argument (as ptycho_grad;
+ * negative or non-finite step sizes, n_steps < 0); a non-finite loss is
+ * recorded for mnf_status. */
+int ptycho_descend(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw,
+                   const float* I, int Nd, const int32_t* pos, int J,
+                   int kind, float eps, int batch, int n_steps, double eta_O, double eta_P,
+                   int update_probe, double* loss_out, double* eta_out, void* stream);
+
 /* ------------------------------------------------------------------------
  * Warm-start network: a four-level U-Net mapping a log-scaled fused pattern
  * [n][H][H] to the amplitude and phase of the illuminated object patch

@@ -353,6 +353,30 @@ def ptycho_grad(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, kind: st
     return loss, gO, gP
 
 
+def ptycho_descend(O: torch.Tensor, P: torch.Tensor, I: torch.Tensor, pos, n_steps: int, kind: str = "poisson",
+                   eps: float = 1e-6, batch: int = 32, eta_O: float = 0.0, eta_P: float = 0.0,
+                   update_probe: bool = True):
+    """Gradient descent with backtracking on the ptycho_grad loss, O and P
+    updated in place.  Returns (losses float64 [n_steps] on the device, the
+    loss of each pass; eta float64 [2] on the device, the step sizes at the
+    end, halvings included).  Step sizes of 0 start from the curvature bound
+    of the starting O and P."""
+    _dev(O, "O", torch.complex64, 2)
+    _dev(P, "P", torch.complex64, 2)
+    _dev(I, "I", torch.float32, 3)
+    posa = _host_i32(pos, (2,), "pos")
+    J = posa.shape[0]
+    losses = torch.empty((max(int(n_steps), 0),), dtype=torch.float64, device=O.device)
+    eta = torch.empty((2,), dtype=torch.float64, device=O.device)
+    ctx = _ctx(O.device)
+    rc = _L.load().ptycho_descend(ctx, _ptr(O), O.shape[0], O.shape[1], _ptr(P), P.shape[0], _ptr(I), I.shape[1],
+                                  _i32p(posa), J, LOSSES[kind], eps, batch, int(n_steps), float(eta_O), float(eta_P),
+                                  1 if update_probe else 0, _ptr(losses) if n_steps > 0 else None, _ptr(eta),
+                                  _stream(O.device))
+    _check(rc, ctx)
+    return losses, eta
+
+
 def status(device="cuda:0") -> int:
     """Wait for the device's current stream and return the numerical status
     recorded since the last call (0, MNF_ENONFINITE or MNF_EDIVERGED); the

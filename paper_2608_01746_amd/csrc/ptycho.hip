@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "common.hpp"
+#include "descent_kernels.hpp"
 #include "objrow_kernels.hpp"
 #include "pattern_kernels.hpp"
 #include "small_kernels.hpp"
@@ -861,9 +862,23 @@ int forward_n(mnf_ctx* ctx, const CallPlan& pl, float* I_out, const SubBufs* sb,
 
 // ------------------------------------------------------------------ grad
 
+// Gradient descent on top of the gradient pass: after each pass over all
+// positions the pass is accepted or rejected on its loss (k_descent_decide)
+// and the object (and the probe with update_probe) moves to the next point
+// from the gradients in s.gO / s.gP or the saved best; the pass's loss is
+// copied to loss[step].
+struct DescentArgs {
+    int n_steps;
+    int update_probe;
+    double* eta;         // device [2]: eta_O, eta_P (halved on rejection)
+    double* loss;        // device [n_steps] or NULL
+    DescentState* state;
+    float2 *Ob, *gOb, *Pb, *gPb;  // the best point and its gradients
+};
+
 template <int N, int RV, int CV>
 int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, const double* upstream, double* loss_out,
-           hipStream_t st) {
+           hipStream_t st, const DescentArgs* dsc) {
     const float2* tw;
     MNF_TRY(twiddles(ctx, N, &tw));
     void *S, *lossp, *d_job;
@@ -876,13 +891,13 @@ int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
     MNF_TRY(upload(ctx, "plan_scans", sd.data(), sizeof(ScanDev), st, &d_scans));
     SumJob job{(const double*)lossp, (size_t)s.J * col_groups(ctx, N), nullptr, loss_out, nullptr, ctx->d_status};
     MNF_TRY(upload(ctx, "plan_lossjob", &job, sizeof job, st, &d_job));
-    if (s.gO)
-        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_zero_c64, dim3((unsigned)(((size_t)s.My * s.Mx + 255) / 256)), dim3(256),
-                   s.gO, (size_t)s.My * s.Mx);
-    if (s.gP)
-        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_zero_c64, dim3((s.Nw * s.Nw + 255) / 256), dim3(256), s.gP,
-                   (size_t)s.Nw * s.Nw);
     const ScanDev* scans = (const ScanDev*)d_scans;
+    const size_t nO = (size_t)s.My * s.Mx, nP = (size_t)s.Nw * s.Nw;
+    const int passes = dsc ? dsc->n_steps : 1;
+    for (int step = 0; step < passes; ++step) {
+    if (s.gO)
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_zero_c64, dim3((unsigned)((nO + 255) / 256)), dim3(256), s.gO, nO);
+    if (s.gP) MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_zero_c64, dim3((unsigned)((nP + 255) / 256)), dim3(256), s.gP, nP);
     for (const Launch& L : pl.launches) {
         const SlotDev* slots = (const SlotDev*)pl.d_slots + L.slot_off;
         const GroupDev* groups = (const GroupDev*)pl.d_groups + L.group_off;
@@ -906,19 +921,44 @@ int grad_v(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float ep
                        groups, L.ngroups, (const float2*)S, N);
     }
     MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sum_jobs, dim3(1), dim3(256), (const SumJob*)d_job, 1.0);  // loss, status
+    if (dsc) {
+        // every gradient of this pass was taken at the pass's starting O and P
+        double* ldst = dsc->loss ? dsc->loss + step : (double*)nullptr;
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_descent_decide, dim3(1), dim3(64), (const double*)loss_out, step,
+                   dsc->state, dsc->eta, ldst);
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_descent_update,
+                   dim3((unsigned)((nO + kDescentThreads - 1) / kDescentThreads)), dim3(kDescentThreads), s.O,
+                   (const float2*)s.gO, dsc->Ob, dsc->gOb, nO, (const double*)dsc->eta,
+                   (const DescentState*)dsc->state);
+        if (dsc->update_probe)
+            MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_descent_update,
+                       dim3((unsigned)((nP + kDescentThreads - 1) / kDescentThreads)), dim3(kDescentThreads), s.P,
+                       (const float2*)s.gP, dsc->Pb, dsc->gPb, nP, (const double*)(dsc->eta + 1),
+                       (const DescentState*)dsc->state);
+    }
+    }
     MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
 }
 
 template <int N>
 int grad_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, const double* upstream, double* loss_out,
-           hipStream_t st) {
+           hipStream_t st, const DescentArgs* dsc) {
     switch (variant_of(ctx, N) & 3) {
-        case 1: return grad_v<N, 1, 0>(ctx, pl, s, kind, eps, upstream, loss_out, st);
-        case 2: return grad_v<N, 0, 1>(ctx, pl, s, kind, eps, upstream, loss_out, st);
-        case 3: return grad_v<N, 1, 1>(ctx, pl, s, kind, eps, upstream, loss_out, st);
-        default: return grad_v<N, 0, 0>(ctx, pl, s, kind, eps, upstream, loss_out, st);
+        case 1: return grad_v<N, 1, 0>(ctx, pl, s, kind, eps, upstream, loss_out, st, dsc);
+        case 2: return grad_v<N, 0, 1>(ctx, pl, s, kind, eps, upstream, loss_out, st, dsc);
+        case 3: return grad_v<N, 1, 1>(ctx, pl, s, kind, eps, upstream, loss_out, st, dsc);
+        default: return grad_v<N, 0, 0>(ctx, pl, s, kind, eps, upstream, loss_out, st, dsc);
     }
+}
+
+// n_steps descent passes, then the step sizes as they stand to eta_out.
+template <int N>
+int descend_n(mnf_ctx* ctx, const CallPlan& pl, const ScanIn& s, int kind, float eps, double* lossd, hipStream_t st,
+              const DescentArgs& dsc, double* eta_out) {
+    MNF_TRY(grad_n<N>(ctx, pl, s, kind, eps, (const double*)nullptr, lossd, st, &dsc));
+    if (eta_out) MNF_HIP(ctx, hipMemcpyAsync(eta_out, dsc.eta, 2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    return MNF_OK;
 }
 
 // Real positions host float [J][2] -> nearest integer corners (halves round up)
@@ -1212,7 +1252,61 @@ int ptycho_grad(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P
     ScanIn s{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, pos, J, nullptr, nullptr, (float2*)gO, (float2*)gP};
     CallPlan pl;
     MNF_TRY(plan_identity(ctx, s, batch, pl, st));
-    MNF_DISPATCH(Nd, grad_n, ctx, pl, s, kind, eps, upstream, loss_out, st)
+    MNF_DISPATCH(Nd, grad_n, ctx, pl, s, kind, eps, upstream, loss_out, st, (const DescentArgs*)nullptr)
+}
+
+int ptycho_descend(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw, const float* I, int Nd,
+                   const int32_t* pos, int J, int kind, float eps, int batch, int n_steps, double eta_O, double eta_P,
+                   int update_probe, double* loss_out, double* eta_out, void* stream) {
+    MNF_TRY(begin(ctx));
+    if (kind != 0 && kind != 1) return set_error(ctx, MNF_EINVAL, "kind must be 0 (Poisson) or 1 (amplitude)");
+    if (batch < 1 || batch > kMaxBatch) return set_error(ctx, MNF_EINVAL, "batch %d outside [1, %d]", batch, kMaxBatch);
+    if (!(eps >= 0.f)) return set_error(ctx, MNF_EINVAL, "eps must be >= 0");
+    if (n_steps < 0) return set_error(ctx, MNF_EINVAL, "n_steps must be >= 0 (%d)", n_steps);
+    if (!(eta_O >= 0.0) || !(eta_P >= 0.0) || !std::isfinite(eta_O) || !std::isfinite(eta_P))
+        return set_error(ctx, MNF_EINVAL, "step sizes must be finite and >= 0 (0: automatic)");
+    hipStream_t st = (hipStream_t)stream;
+    void *gO, *gP, *lossd, *etad, *partO, *partP, *dpos, *Ob, *gOb, *Pb, *gPb, *stt;
+    const size_t bO = sizeof(float2) * (size_t)std::max(My, 1) * std::max(Mx, 1);
+    const size_t bP = sizeof(float2) * (size_t)std::max(Nw, 1) * std::max(Nw, 1);
+    MNF_TRY(mnf::scratch(ctx, "descent_gO", bO, &gO));
+    MNF_TRY(mnf::scratch(ctx, "descent_gP", bP, &gP));
+    ScanIn s{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, pos, J, nullptr, nullptr, (float2*)gO, (float2*)gP};
+    CallPlan pl;
+    MNF_TRY(plan_identity(ctx, s, batch, pl, st));  // checks the scan (sizes, windows inside O)
+    const ScanDev& b = pl.scans[0];
+    const size_t box = (size_t)b.bh * b.bw;
+    const unsigned nbO = (unsigned)((box + kDescentThreads - 1) / kDescentThreads);
+    const unsigned nbP = (unsigned)(((size_t)Nw * Nw + kDescentThreads - 1) / kDescentThreads);
+    MNF_TRY(mnf::scratch(ctx, "descent_loss", sizeof(double), &lossd));
+    MNF_TRY(mnf::scratch(ctx, "descent_eta", 2 * sizeof(double), &etad));
+    MNF_TRY(mnf::scratch(ctx, "descent_partO", sizeof(float) * nbO, &partO));
+    MNF_TRY(mnf::scratch(ctx, "descent_partP", sizeof(float) * nbP, &partP));
+    MNF_TRY(upload(ctx, "descent_pos", pos, 2 * sizeof(int32_t) * (size_t)J, st, &dpos));
+    // step sizes from the starting object and probe, fixed for the call (the
+    // maxima only where a step size is not given)
+    if (!(eta_O > 0.0))
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_illum_max, dim3(nbO), dim3(kDescentThreads), (const float2*)P, Nw,
+                   (const int32_t*)dpos, J, b.by0, b.bx0, b.bh, b.bw, (float*)partO);
+    if (!(eta_P > 0.0))
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_cover_max, dim3(nbP), dim3(kDescentThreads), (const float2*)O, Mx, Nw,
+                   (const int32_t*)dpos, J, (float*)partP);
+    MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_step_sizes, dim3(1), dim3(kDescentThreads), (const float*)partO,
+               eta_O > 0.0 ? 0 : (int)nbO, (const float*)partP, eta_P > 0.0 ? 0 : (int)nbP, eta_O, eta_P,
+               (double*)etad);
+    if (n_steps == 0) {
+        if (eta_out) MNF_HIP(ctx, hipMemcpyAsync(eta_out, etad, 2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+        MNF_CHECK_LAUNCH(ctx);
+        return MNF_OK;
+    }
+    MNF_TRY(mnf::scratch(ctx, "descent_Ob", bO, &Ob));
+    MNF_TRY(mnf::scratch(ctx, "descent_gOb", bO, &gOb));
+    MNF_TRY(mnf::scratch(ctx, "descent_Pb", bP, &Pb));
+    MNF_TRY(mnf::scratch(ctx, "descent_gPb", bP, &gPb));
+    MNF_TRY(mnf::scratch(ctx, "descent_state", sizeof(DescentState), &stt));
+    const DescentArgs dsc{n_steps, update_probe ? 1 : 0, (double*)etad, loss_out, (DescentState*)stt,
+                          (float2*)Ob, (float2*)gOb, (float2*)Pb, (float2*)gPb};
+    MNF_DISPATCH(Nd, descend_n, ctx, pl, s, kind, eps, (double*)lossd, st, dsc, eta_out)
 }
 
 }  // extern "C"

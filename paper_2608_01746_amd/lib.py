@@ -76,6 +76,9 @@ SIGNATURES = {
     "ptycho_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
                             POINTER(c_int32), c_int, c_int, c_float, c_int, c_void_p,
                             c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ptycho_descend": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
+                               POINTER(c_int32), c_int, c_int, c_float, c_int, c_int, ctypes.c_double,
+                               ctypes.c_double, c_int, c_void_p, c_void_p, c_void_p]),
     "detector_expose": (c_int, [c_void_p, c_void_p, c_int, c_int, c_int, POINTER(c_float), c_int, c_float,
                                 c_float, c_float, ctypes.c_ulonglong, c_void_p, c_void_p]),
     "ptycho_stitch": (c_int, [c_void_p, c_void_p, c_void_p, c_int, POINTER(c_int32), c_int, c_int, c_void_p,

@@ -101,3 +101,5 @@ def test_host_paths_reject_a_null_context(lib):
     assert L.mnf_status(None, None) == lib.MNF_EINVAL
     assert L.ptycho_grad(None, None, 1, 1, None, 1, None, 16, None, 1, 0, 1e-6, 1, None, None, None, None,
                          None) == lib.MNF_EINVAL
+    assert L.ptycho_descend(None, None, 1, 1, None, 1, None, 16, None, 1, 0, 1e-6, 1, 1, 0.0, 0.0, 1, None, None,
+                            None) == lib.MNF_EINVAL

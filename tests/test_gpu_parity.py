@@ -400,6 +400,140 @@ def test_gradient_matches_oracle(api, kind, Nd, Nw, M, B, J):
     assert rel(gP_g.cpu().numpy(), gP_r) < 1e-5
 
 
+# ---------------------------------------------------------------- descent
+
+def _decisions_are_clear(losses, accepted, guard=2e-7):
+    # every accept/reject decision of the oracle's run lies further than
+    # float32 rounding of the loss from the rejection threshold (else the two
+    # sides may branch apart)
+    ref = losses[0]
+    for L, acc in zip(losses[1:], accepted[1:]):
+        if abs((L - ref) / abs(ref) - adjoint.DESCENT_TOL) <= guard:
+            return False
+        if acc:
+            ref = L
+    return True
+
+
+@pytest.mark.parametrize("kind", ["poisson", "amplitude"])
+@pytest.mark.parametrize("Nd,Nw,M,B,J,upd,boost", [(16, 16, 40, 4, 9, True, 1.0), (32, 24, 64, 5, 11, True, 1.0),
+                                                   (64, 64, 128, 32, 6, False, 1.0),
+                                                   # steps 8x the curvature bound: rejected passes
+                                                   (32, 24, 64, 5, 11, True, 8.0)])
+def test_descent_matches_oracle(api, kind, Nd, Nw, M, B, J, upd, boost):
+    # several full-batch passes from a perturbed start on noiseless data,
+    # ragged recompute batches, padded and unpadded windows
+    rng = np.random.default_rng(3 * Nd + Nw)
+    O_true = synth.make_object(M, 12)
+    P = soft_probe(synth.make_probe(Nw, Nw / 3, 1.0), 4)
+    pos = rng.integers(0, M - Nw + 1, size=(J, 2)).astype(np.int32)
+    I = f32(ptycho.forward_intensity(O_true, P, pos, Nd))
+    O0 = c64(O_true * (1 + 0.1 * rng.standard_normal((M, M))))
+    P0 = c64(P * 1.05)
+    n = 5
+    eta0 = np.array(adjoint.step_sizes(O0, P0, pos)) * boost
+    eO, eP = (float(eta0[0]), float(eta0[1])) if boost != 1.0 else (0.0, 0.0)
+    O_r, P_r, loss_r, acc_r = adjoint.descend(O0, P0, I, pos, kind, 1e-6, n_steps=n, eta_O=eO, eta_P=eP,
+                                              update_probe=upd)
+    assert _decisions_are_clear(loss_r, acc_r)
+    if boost != 1.0:
+        assert not acc_r.all()
+    Og, Pg = tc64(O0), tc64(P0)
+    loss_g, eta_g = api.ptycho_descend(Og, Pg, tf32(I), pos, n, kind, 1e-6, B, eta_O=eO, eta_P=eP,
+                                       update_probe=upd)
+    np.testing.assert_allclose(eta_g.cpu().numpy(), eta0 / 2.0 ** np.sum(~acc_r), rtol=1e-6)
+    np.testing.assert_allclose(loss_g.cpu().numpy(), loss_r, rtol=1e-5, atol=1e-4)
+    assert rel(Og.cpu().numpy(), O_r) < 1e-5
+    assert rel(Pg.cpu().numpy(), P_r) < 1e-5
+    if not upd:
+        assert np.array_equal(Pg.cpu().numpy(), P0)
+    assert api.status() == 0
+
+
+@pytest.mark.parametrize("kind,bar", [("amplitude", 0.012), ("poisson", 0.003)])
+def test_descent_reconstructs_noiseless_data(api, kind, bar):
+    # from a flat object with the known probe: 100 passes reach the oracle's
+    # own run (object NRMSE against the truth 0.0096 amplitude, 0.0024
+    # Poisson, no rejection), and the two runs agree to the full-run bar
+    M, Nw = 160, 64
+    O_true = synth.make_object(M, 21)
+    P = c64(synth.make_probe(Nw, 16.0, 1.0))
+    pos = np.array([[y, x] for y in range(0, M - Nw + 1, 12) for x in range(0, M - Nw + 1, 12)], np.int32)
+    I = f32(ptycho.forward_intensity(O_true, P, pos, Nw))
+    mask = ptycho.illumination_mask(P, pos, O_true.shape)
+    O0 = np.ones((M, M), np.complex64)
+    O_r, _, loss_r, acc_r = adjoint.descend(O0, P, I, pos, kind, 1e-6, n_steps=100, update_probe=False)
+    assert acc_r.all() and _decisions_are_clear(loss_r, acc_r)
+    Og, Pg = tc64(O0), tc64(P)
+    loss_g, _ = api.ptycho_descend(Og, Pg, tf32(I), pos, 100, kind, 1e-6, 16, update_probe=False)
+    Og = Og.cpu().numpy()
+    assert ptycho.nrmse(O_r, O_true, mask) < bar
+    assert ptycho.nrmse(Og, O_true, mask) < bar
+    assert ptycho.nrmse(Og, O_r, mask) < 1e-3
+    np.testing.assert_allclose(loss_g.cpu().numpy(), loss_r, rtol=1e-5)
+
+
+def test_descent_explicit_steps_and_zero_steps(api):
+    rng = np.random.default_rng(5)
+    M, Nw = 48, 16
+    O0 = c64(synth.make_object(M, 2))
+    P0 = c64(synth.make_probe(Nw, Nw / 3, 1.0))
+    pos = rng.integers(0, M - Nw + 1, size=(5, 2)).astype(np.int32)
+    I = f32(ptycho.forward_intensity(synth.make_object(M, 3), P0, pos, Nw))
+    # no step: the object and probe stay, the automatic step sizes are reported
+    Og, Pg = tc64(O0), tc64(P0)
+    loss, eta = api.ptycho_descend(Og, Pg, tf32(I), pos, 0)
+    assert loss.numel() == 0
+    np.testing.assert_allclose(eta.cpu().numpy(), adjoint.step_sizes(O0, P0, pos), rtol=1e-6)
+    assert np.array_equal(Og.cpu().numpy(), O0) and np.array_equal(Pg.cpu().numpy(), P0)
+    # given step sizes are used as they are
+    O_r, P_r, loss_r, acc_r = adjoint.descend(O0, P0, I, pos, "amplitude", 0.0, 2, eta_O=0.01, eta_P=0.002)
+    assert acc_r.all()
+    loss, eta = api.ptycho_descend(Og, Pg, tf32(I), pos, 2, "amplitude", 0.0, 2, eta_O=0.01, eta_P=0.002)
+    assert eta.cpu().tolist() == [0.01, 0.002]
+    np.testing.assert_allclose(loss.cpu().numpy(), loss_r, rtol=1e-5)
+    assert rel(Og.cpu().numpy(), O_r) < 1e-5 and rel(Pg.cpu().numpy(), P_r) < 1e-5
+    for bad in (dict(eta_O=-1.0), dict(eta_P=float("inf")), dict(n_steps=-1)):
+        args = dict(n_steps=1)
+        args.update(bad)
+        n_steps = args.pop("n_steps")
+        with pytest.raises(api.MnfError):
+            api.ptycho_descend(Og, Pg, tf32(I), pos, n_steps, **args)
+
+
+def test_descent_full_size_sampled(api):
+    # the gradient workload's geometry (2048^2 object, 512^2 probe, 1000
+    # Fermat-spiral positions, recompute batches of 32): the step sizes
+    # against the oracle's, and one step's object on an 8 x 8 patch against
+    # the oracle's step restricted to the windows covering the patch
+    # (noiseless data from a true object and a perturbed start, as in the
+    # small cases: with data unrelated to the object the Poisson gradient's
+    # I / |Psi|^2 is dominated by the far tails, where |Psi|^2 carries no
+    # float32 digits)
+    w = synth.gradient_workload()
+    rng = np.random.default_rng(44)
+    M, N = w.M, w.Nd
+    O_true = synth.make_object(M, 44)
+    P0 = c64(w.probe())
+    pos = np.asarray(w.pos, np.int32)
+    I = f32(ptycho.forward_intensity(O_true, P0, pos, N))
+    O0 = c64(O_true * (1 + 0.1 * rng.standard_normal((M, M))))
+    Og, Pg = tc64(O0), tc64(P0)
+    loss0, _, gP = api.ptycho_grad(Og, Pg, tf32(I), pos, "poisson", 1e-6, w.batch)
+    loss, eta = api.ptycho_descend(Og, Pg, tf32(I), pos, 1, "poisson", 1e-6, w.batch)
+    eta_r = adjoint.step_sizes(O0, P0, pos)
+    np.testing.assert_allclose(eta.cpu().numpy(), eta_r, rtol=1e-5)
+    assert loss[0].item() == loss0.item()  # the same pass at the same start
+    # probe: one step along the library's own gradient at the start
+    assert rel(Pg.cpu().numpy(), P0 - eta_r[1] * gP.cpu().numpy()) < 1e-6
+    y0, x0 = M // 2 - 4, M // 2 - 4
+    cover = [j for j, (py, px) in enumerate(pos) if py <= y0 and y0 + 8 <= py + N and px <= x0 and x0 + 8 <= px + N]
+    assert len(cover) > 10
+    _, gO_r, _ = adjoint.loss_and_grad(O0, P0, I[cover], pos[cover], "poisson", 1e-6)
+    want = O0[y0:y0 + 8, x0:x0 + 8] - eta_r[0] * gO_r[y0:y0 + 8, x0:x0 + 8]
+    assert rel(Og.cpu().numpy()[y0:y0 + 8, x0:x0 + 8], want) < 1e-5
+
+
 # ------------------------------------------------------------- edge cases
 
 def test_rejects_bad_arguments(api):
