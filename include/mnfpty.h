@@ -48,7 +48,8 @@ int mnf_create(mnf_ctx** out, int hip_device);
 void mnf_destroy(mnf_ctx* ctx);
 
 /* Message of the last failing call on ctx ("" if none).  Valid until the next call on ctx.
- * With ctx == NULL: the message of the last failed mnf_create on the calling thread. */
+ * With ctx == NULL: the message of the last call on the calling thread made without a
+ * context (mnf_create, ptycho_plan_info with ctx NULL); "" after a success. */
 const char* mnf_last_error(const mnf_ctx* ctx);
 
 /* Numerical status of the work issued on ctx (a guard the paper does not
@@ -262,6 +263,24 @@ typedef struct {
 
 int ptycho_iterate_many(mnf_ctx* ctx, const ptycho_scan* scans, int n_scans, int n_iter,
                         const ptycho_params* params, void* stream);
+
+/* Validates a ptycho_iterate_many call (the same checks, in the same order,
+ * with the same return codes) and plans it on the host, with no device work:
+ * the device pointers in `scans` are never dereferenced, and a plan can be
+ * taken on a machine without a GPU.  ctx may be NULL (default launch shapes;
+ * a failure's message is then read with mnf_last_error(NULL)); a context
+ * contributes the launch shapes set on it.  `order` and `pos` are read.
+ * info int64 [n_info] receives, in this order (entries past the last
+ * defined one are set to 0; n_info may be 0):
+ *   0  launches per call (one launch of each pass over a list of slots)
+ *   1  slots per call (exit waves formed: n_iter x sum over scans of J x modes)
+ *   2  groups per call (one per scan and mini-batch round)
+ *   3  object-update blocks per call (16 x 64 tiles of each group's window box)
+ *   4  slots of the largest launch
+ *   5  bytes of pattern scratch (the largest launch's patterns, complex64)
+ *   6  size classes (distinct detector sizes) */
+int ptycho_plan_info(mnf_ctx* ctx, const ptycho_scan* scans, int n_scans, int n_iter,
+                     const ptycho_params* params, int64_t* info, int n_info);
 
 /* ------------------------------------------------------------------------
  * Loss on fused intensities and its gradient (the adjoint of Eqs. 2-3; the

@@ -320,6 +320,42 @@ def ptycho_iterate_many(scans, n_iter: int, alg: str = "rpie", alpha: float = 0.
     return errs if err else None
 
 
+PLAN_INFO_KEYS = ("launches", "slots", "groups", "object_tiles", "max_launch_slots", "pattern_scratch_bytes",
+                  "size_classes")
+
+
+def plan_info(scans, n_iter: int, alg: str = "rpie", alpha: float = 0.1, beta: float = 0.1, batch: int = 32,
+              update_probe: bool = False, probe_start_iter: int = 0, context_device=None) -> dict:
+    """Validate and plan a ptycho_iterate_many call on the host, with no device
+    work (no GPU needed).  `scans` is a list of dicts with the shapes
+    My, Mx, Nw, Nd, the host positions pos [J][2] and optionally order
+    [n_iter][J]; the library is handed placeholder device addresses, which
+    the planner never dereferences.  Raises MnfError as the call itself
+    would (same checks and codes).  context_device: take the launch shapes
+    set on that device's context instead of the defaults."""
+    if not scans:
+        raise ValueError("no scans")
+    arr = (_L.PtychoScanC * len(scans))()
+    keep = []
+    for k, sc in enumerate(scans):
+        posa = _host_i32(sc["pos"], (2,), "pos")
+        J = posa.shape[0]
+        orda = _host_i32(sc["order"], (J,), "order") if sc.get("order") is not None else None
+        if J == 0:
+            raise ValueError("a scan needs at least one position")
+        if orda is not None and orda.shape[0] != n_iter:
+            raise ValueError("order must have one row per iteration")
+        keep += [posa, orda]
+        arr[k] = _L.PtychoScanC(8, int(sc["My"]), int(sc["Mx"]), 8, int(sc["Nw"]), 8, int(sc["Nd"]), _i32p(posa),
+                                J, _i32p(orda), None)
+    prm = _L.PtychoParamsC(ALGS[alg], alpha, beta, batch, 1 if update_probe else 0, probe_start_iter, 0, 0)
+    ctx = _ctx(torch.device(context_device)) if context_device is not None else None
+    info = (ctypes.c_int64 * len(PLAN_INFO_KEYS))()
+    rc = _L.load().ptycho_plan_info(ctx, arr, len(scans), int(n_iter), ctypes.byref(prm), info, len(info))
+    _check(rc, ctx)
+    return dict(zip(PLAN_INFO_KEYS, list(info)))
+
+
 # ------------------------------------------------------------------ adjoint
 
 LOSSES = {"poisson": 0, "amplitude": 1}

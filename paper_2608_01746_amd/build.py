@@ -66,5 +66,70 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+# Host code with AddressSanitizer and UndefinedBehaviorSanitizer.  Device
+# code is not compiled (relocatable host-only objects, so no code object is
+# referenced): kernels cannot be launched from this build, which serves the
+# CPU tests of the host paths (argument validation, planning, tiling).  Load
+# it into a process with the ASan runtime preloaded (asan_runtime()).
+SANITIZE_FLAGS = [
+    "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+    "-Xarch_host", "-fno-sanitize-recover=all", "-Xarch_host", "-fno-omit-frame-pointer",
+]
+SAN_DIR = os.path.join(HERE, "_build_san")
+SAN_LIB = os.path.join(SAN_DIR, "libmnfpty_san.so")
+
+
+def asan_runtime() -> str:
+    """Path of the compiler's shared ASan runtime (to preload)."""
+    clang = "/opt/rocm/llvm/bin/clang"
+    r = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("the ASan runtime library was not found")
+    return path
+
+
+def _sources_stamp(flags) -> str:
+    import hashlib
+    h = hashlib.sha256(" ".join(flags).encode())
+    for f in sorted(os.listdir(CSRC)):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()
+
+
+def build_host_sanitized() -> str:
+    """Build (when the sources changed since the last build) the sanitized
+    host-only library and return its path."""
+    hipcc = _hipcc()
+    flags = ["-fgpu-rdc", "--offload-host-only", "-O1", "-g", "-std=c++17", "-fPIC", *SANITIZE_FLAGS,
+             "-Wno-unused-command-line-argument"]
+    stamp = _sources_stamp(flags)
+    stamp_file = os.path.join(SAN_DIR, "stamp")
+    if os.path.exists(SAN_LIB) and os.path.exists(stamp_file) and open(stamp_file).read() == stamp:
+        return SAN_LIB
+    os.makedirs(SAN_DIR, exist_ok=True)
+
+    def compile_one(src):
+        obj = os.path.join(SAN_DIR, os.path.basename(src) + ".o")
+        r = subprocess.run([hipcc, *flags, "-c", src, "-o", obj], capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"hipcc (sanitized host) failed for {src}:\n{r.stderr}")
+        return obj
+
+    srcs = sources()
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(len(srcs), 8))) as ex:
+        objs = list(ex.map(compile_one, srcs))
+    tmp = SAN_LIB + ".tmp"
+    r = subprocess.run([hipcc, "-fgpu-rdc", "--offload-host-only", "-shared", "-fPIC", *objs, "-o", tmp],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link (sanitized host) failed:\n{r.stderr}")
+    os.replace(tmp, SAN_LIB)
+    with open(stamp_file, "w") as fh:
+        fh.write(stamp)
+    return SAN_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

@@ -80,6 +80,8 @@ struct mnf_ctx {
 namespace mnf {
 
 int set_error(mnf_ctx* ctx, int code, const char* fmt, ...);
+// the message mnf_last_error(NULL) returns (calls made without a context)
+void set_host_error(const std::string& msg);
 
 #define MNF_HIP(ctx, call)                                                          \
     do {                                                                            \

@@ -7,6 +7,12 @@
 
 namespace mnf {
 
+// message of the last failed call made without a context on this thread
+// (mnf_create, ptycho_plan_info), read with mnf_last_error(NULL)
+static thread_local std::string g_host_error;
+
+void set_host_error(const std::string& msg) { g_host_error = msg; }
+
 int set_error(mnf_ctx* ctx, int code, const char* fmt, ...) {
     if (ctx) {
         char buf[1024];
@@ -172,11 +178,8 @@ const char* mnf_kernel_class_name(int cls) {
     return (cls >= 0 && cls < MNF_K_NCLASS) ? kClassNames[cls] : "";
 }
 
-// message of the last failed mnf_create on this thread (mnf_last_error(NULL))
-static thread_local std::string g_create_error;
-
 static int create_failed(int code, const std::string& msg) {
-    g_create_error = msg;
+    mnf::set_host_error(msg);
     return code;
 }
 
@@ -218,7 +221,7 @@ int mnf_create(mnf_ctx** out, int hip_device) {
         mnf_destroy(c);
         return create_failed(rc, msg);
     }
-    g_create_error.clear();
+    mnf::set_host_error(std::string());
     *out = c;
     return MNF_OK;
 }
@@ -254,6 +257,6 @@ void mnf_destroy(mnf_ctx* ctx) {
     delete ctx;
 }
 
-const char* mnf_last_error(const mnf_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_error.c_str(); }
+const char* mnf_last_error(const mnf_ctx* ctx) { return ctx ? ctx->err.c_str() : mnf::g_host_error.c_str(); }
 
 }  // extern "C"

@@ -537,23 +537,26 @@ int launch_small_run(mnf_ctx* ctx, const CallPlan& pl, int J, int n_iter, const 
 }
 
 
-int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const ptycho_params& p, hipStream_t st) {
+// Validation and the host plan of an iterate call: the scan table, the size
+// classes and, for n_iter > 0, every launch's slot and group lists.  No
+// device work (the scans' device pointers are only copied).
+int plan_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const ptycho_params& p, unsigned* status,
+                 CallPlan& pl, std::map<int, std::vector<int>>& classes) {
     const int ns = (int)in.size();
+    if (ns <= 0) return set_error(ctx, MNF_EINVAL, "no scans");
     if (p.alg != 0 && p.alg != 1) return set_error(ctx, MNF_EINVAL, "alg must be 0 (ePIE) or 1 (rPIE)");
     if (p.batch < 1 || p.batch > kMaxBatch)
         return set_error(ctx, MNF_EINVAL, "batch %d outside [1, %d]", p.batch, kMaxBatch);
     if (!(p.alpha > 0.f) || !(p.beta > 0.f) || p.alpha > 1.f || p.beta > 1.f)
         return set_error(ctx, MNF_EINVAL, "alpha and beta must lie in (0, 1]");
     if (n_iter < 0) return set_error(ctx, MNF_EINVAL, "n_iter must be >= 0");
-    CallPlan pl;
     pl.scans.resize(ns);
-    std::map<int, std::vector<int>> classes;  // detector size -> scans
     int max_batches = 0;
     for (int k = 0; k < ns; ++k) {
         Box b;
         MNF_TRY(check_scan(ctx, in[k], k, &b));
         MNF_TRY(check_order(ctx, in[k].order, n_iter, in[k].J, k));
-        fill_scan_dev(pl.scans[k], in[k], b, ctx->d_status);
+        fill_scan_dev(pl.scans[k], in[k], b, status);
         classes[in[k].Nd].push_back(k);
         max_batches = std::max(max_batches, (in[k].J + p.batch - 1) / p.batch);
     }
@@ -568,9 +571,24 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
         return set_error(ctx, MNF_EINVAL, "batch x modes = %d exceeds %d", p.batch * modes, kMaxBatch);
     if (sub && !size_supported(in[0].Nw))
         return set_error(ctx, MNF_EUNSUPPORTED, "real positions need a probe window with an FFT plan (Nw=%d)", in[0].Nw);
-    if (n_iter == 0) return MNF_OK;
     pl.sub = sub;
     pl.modes = modes;
+    for (int i = 0; i < n_iter; ++i) {
+        for (int b = 0; b < max_batches; ++b)
+            for (auto& kv : classes) plan_round(ctx, pl, in, kv.second, i, b, p.batch, kv.first);
+        pl.iter_end.push_back((int)pl.launches.size());
+    }
+    return MNF_OK;
+}
+
+int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const ptycho_params& p, hipStream_t st) {
+    const int ns = (int)in.size();
+    CallPlan pl;
+    std::map<int, std::vector<int>> classes;  // detector size -> scans
+    MNF_TRY(plan_iterate(ctx, in, n_iter, p, ctx->d_status, pl, classes));
+    if (n_iter == 0) return MNF_OK;
+    const bool sub = pl.sub;
+    const int modes = pl.modes;
 
     // per-scan scratch: P2 [Nw^2], maxP2_row [Nw], amplitudes [J][Nd][Nd] (FFT order;
     // a call without allocations takes the square roots in the column pass
@@ -602,11 +620,6 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
             sA2[k] = d;
             d += 1;
         }
-    }
-    for (int i = 0; i < n_iter; ++i) {
-        for (int b = 0; b < max_batches; ++b)
-            for (auto& kv : classes) plan_round(ctx, pl, in, kv.second, i, b, p.batch, kv.first);
-        pl.iter_end.push_back((int)pl.launches.size());
     }
     MNF_TRY(upload_plan(ctx, pl, st));
     // error reduction jobs, one per scan per iteration.  A graph writes the
@@ -1239,6 +1252,38 @@ int ptycho_iterate_many(mnf_ctx* ctx, const ptycho_scan* scans, int n_scans, int
                             s.err_out, nullptr, nullptr});
     }
     return run_iterate(ctx, in, n_iter, *params, (hipStream_t)stream);
+}
+
+int ptycho_plan_info(mnf_ctx* ctx, const ptycho_scan* scans, int n_scans, int n_iter, const ptycho_params* params,
+                     int64_t* info, int n_info) {
+    // without a context: a host-only one for messages and the default launch
+    // shapes (nothing in it touches a device)
+    mnf_ctx host;
+    mnf_ctx* c = ctx ? ctx : &host;
+    auto done = [&](int rc) {
+        if (!ctx) mnf::set_host_error(rc == MNF_OK ? std::string() : host.err);
+        return rc;
+    };
+    if (!params || !scans || (!info && n_info > 0)) return done(set_error(c, MNF_EINVAL, "null pointer argument"));
+    if (n_scans <= 0) return done(set_error(c, MNF_EINVAL, "n_scans must be positive"));
+    if (n_info < 0) return done(set_error(c, MNF_EINVAL, "n_info must be >= 0"));
+    std::vector<ScanIn> in;
+    for (int k = 0; k < n_scans; ++k) {
+        const ptycho_scan& s = scans[k];
+        in.push_back(ScanIn{(float2*)s.O, s.My, s.Mx, (float2*)s.P, s.Nw, s.I, s.Nd, s.pos, s.J, s.order,
+                            s.err_out, nullptr, nullptr});
+    }
+    CallPlan pl;
+    std::map<int, std::vector<int>> classes;
+    const int rc = plan_iterate(c, in, n_iter, *params, nullptr, pl, classes);
+    if (rc != MNF_OK) return done(rc);
+    long long tiles = 0;
+    for (const Launch& L : pl.launches) tiles += L.tiles;
+    const int64_t v[] = {(int64_t)pl.launches.size(), (int64_t)pl.slots.size(), (int64_t)pl.groups.size(), tiles,
+                         pl.max_slots, (int64_t)pl.max_S, (int64_t)classes.size()};
+    for (int i = 0; i < n_info && i < (int)(sizeof v / sizeof v[0]); ++i) info[i] = v[i];
+    for (int i = (int)(sizeof v / sizeof v[0]); i < n_info; ++i) info[i] = 0;
+    return done(MNF_OK);
 }
 
 int ptycho_grad(mnf_ctx* ctx, const mnf_c64* O, int My, int Mx, const mnf_c64* P, int Nw, const float* I, int Nd,

@@ -76,6 +76,7 @@ SIGNATURES = {
     "ptycho_grad": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
                             POINTER(c_int32), c_int, c_int, c_float, c_int, c_void_p,
                             c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ptycho_plan_info": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_void_p, c_int]),
     "ptycho_descend": (c_int, [c_void_p, c_void_p, c_int, c_int, c_void_p, c_int, c_void_p, c_int,
                                POINTER(c_int32), c_int, c_int, c_float, c_int, c_int, ctypes.c_double,
                                ctypes.c_double, c_int, c_void_p, c_void_p, c_void_p]),
