@@ -74,14 +74,18 @@ def algo_bytes_per_update(N: int, B: int) -> float:
 
 HBM_PEAK_GBS = 8000.0
 KERNEL_SOURCES = ["fft.hpp", "kernels_common.hpp", "pattern_kernels.hpp", "shift_kernels.hpp", "update_kernels.hpp",
-                  "tables.hpp", "ptycho.hip", "../build.py"]  # build.py: the compiler flags
+                  "objrow_kernels.hpp", "small_kernels.hpp", "descent_kernels.hpp", "tables.hpp", "ptycho.hip"]
 
 
 def kernel_source_hash() -> str:
+    """Hash of the reconstruction kernels' sources, their launch code and the
+    compiler flags."""
+    from paper_2608_01746_amd import build as _build
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2608_01746_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    h.update(" ".join(_build.HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 
 
