@@ -443,8 +443,10 @@ int detector_resample(mnf_ctx* ctx, const float* I, int J, int Nd, float scale, 
  * algorithm or the mini-batch, and give identical objects and probes (the
  * errors up to the order of float64 partial sums).
  *
- * mnf_autotune times the eight variants on a synthetic scan of `nslots`
- * positions (one mini-batch of that size per iteration, `reps` iterations)
+ * mnf_autotune times the eight variants on a synthetic mini-batch of
+ * `nslots` windows spread as in a scan larger than the batch taken in a
+ * shuffled order (drawn from a raster of step Nd/8 over an object of side
+ * about 4 Nd; one mini-batch per iteration, `reps` iterations)
  * in three interleaved rounds, keeps for size Nd on this context the variant
  * with the lowest median time if it beats variant 0 by at least 3 % (else 0)
  * and returns its index (0..7), or a negative error.  times_us (host

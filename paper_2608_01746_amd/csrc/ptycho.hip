@@ -1014,10 +1014,15 @@ int autotune_impl(mnf_ctx* ctx, int N, int nslots, int reps, double* times_us, h
     if (!size_supported(N)) return set_error(ctx, MNF_EUNSUPPORTED, "detector size %d has no FFT plan", N);
     if (nslots < 1 || nslots > kMaxBatch) return set_error(ctx, MNF_EINVAL, "nslots outside [1, %d]", kMaxBatch);
     if (reps < 1) return set_error(ctx, MNF_EINVAL, "reps must be positive");
-    int side = 1;
-    while (side * side < nslots) ++side;
-    const int step = N / 4 > 0 ? N / 4 : 1;
-    const int M = N + (side - 1) * step;
+    // One mini-batch as it occurs in a scan larger than the batch taken in a
+    // shuffled order: nslots windows drawn (index stride 7919, coprime with
+    // the 625 raster points, so all distinct) from a 25 x 25 raster of step
+    // N/8 over an object of side 4N, so the object box the update passes
+    // cover is as wide as a real mini-batch's (a compact grid would favour
+    // the pass structures whose cost grows with that box).
+    constexpr int kGrid = 25;
+    const int step = N / 8 > 0 ? N / 8 : 1;
+    const int M = N + (kGrid - 1) * step;
     void *O, *P, *I;
     MNF_TRY(mnf::scratch(ctx, "tune_O", (size_t)M * M * sizeof(float2), &O));
     MNF_TRY(mnf::scratch(ctx, "tune_P", (size_t)N * N * sizeof(float2), &P));
@@ -1030,8 +1035,9 @@ int autotune_impl(mnf_ctx* ctx, int N, int nslots, int reps, double* times_us, h
                        (float*)I, (size_t)nslots * N * N, 1.f);
     std::vector<int32_t> pos(2 * nslots);
     for (int k = 0; k < nslots; ++k) {
-        pos[2 * k] = (k / side) * step;
-        pos[2 * k + 1] = (k % side) * step;
+        const int idx = (int)(((long long)k * 7919 + 13) % (kGrid * kGrid));
+        pos[2 * k] = (idx / kGrid) * step;
+        pos[2 * k + 1] = (idx % kGrid) * step;
     }
     std::vector<ScanIn> in{ScanIn{(float2*)O, M, M, (float2*)P, N, (const float*)I, N, pos.data(), nslots, nullptr,
                                   nullptr, nullptr, nullptr}};
