@@ -7,11 +7,11 @@
 //   1. k_fuse_level1_tiled (K <= 5; k_fuse_level1 beyond): level 1 of every
 //      exposure's image and weight pyramid straight from the raw counts
 //      (reduce of the recomputed level 0);
-//   2. levels 2..L of every exposure by LDS-tiled reduce (one launch per level), and
-//      the modulated, quantised band-pass coefficients of levels 1..L-1
-//      plus the weighted base of level L summed over exposures, in exposure
-//      order, into one fused pyramid F_l (one launch per level);
-//   3. collapse of F down to level 1;
+//   2. levels 2..L of every exposure by LDS-tiled reduce (one launch per level);
+//   3. from the weighted base of level L down to level 1, one launch per
+//      level: the modulated, quantised band-pass coefficients of the level
+//      summed over exposures in exposure order, plus the expanded collapse
+//      of the level above (R_l = F_l + U(R_{l+1}), R_L = F_L);
 //   4. k_fuse_final: per level-0 pixel, the level-0 coefficients of all
 //      exposures (recomputed level 0 minus the expanded level 1), quantised
 //      per exposure, summed, plus the expanded level-1 collapse.
@@ -442,7 +442,10 @@ __device__ __forceinline__ float expand_at(const float* __restrict__ g, int hc, 
 // base l = L: F_L = sum_k G_L[W_k] G_L[I_k].  Every exposure in one thread,
 // summed in exposure order; exposure k's level-l arrays start at k * stride,
 // its level-(l+1) image at k * stride_c.  The loads of four exposures are
-// issued before their terms are formed.
+// issued before their terms are formed.  With Rc (the collapsed level l + 1,
+// [nj][h/2][w/2]) the output is the collapse step R_l = F_l + U(R_{l+1})
+// (Eq. 9), so the levels run from the base to level 1 with no separate
+// collapse launches.
 struct BandSteps {
     float step[kMaxK];  // quantisation step of each exposure at this level (0 = none)
 };
@@ -450,7 +453,7 @@ struct BandSteps {
 __global__ void __launch_bounds__(256)
 k_fuse_band(const float* __restrict__ GI, const float* __restrict__ GW, size_t stride,
             const float* __restrict__ GIc, size_t stride_c, int K, int h, int w, size_t total, BandSteps q,
-            int base, float* __restrict__ F) {
+            int base, const float* __restrict__ Rc, float* __restrict__ F) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= total) return;
     constexpr int G = 4;
@@ -496,6 +499,7 @@ k_fuse_band(const float* __restrict__ GI, const float* __restrict__ GW, size_t s
                     acc = k0 + u == 0 ? v : acc + v;
                 }
         }
+        if (Rc) acc = acc + expand_at(Rc + jj * (size_t)hc * wc, hc, wc, y, x);
     }
     F[i] = acc;
 }
@@ -505,6 +509,8 @@ k_fuse_band(const float* __restrict__ GI, const float* __restrict__ GW, size_t s
 // expand taps share the 3 x 3 neighbourhood of each exposure's level-(l+1)
 // image (separable expand as in k_fuse_final_quad); the quad's level-l
 // values are two 64-bit loads per array.  K == KM exposures, summed in order.
+// With Rc the collapsed level l + 1 is expanded the same way and added
+// (R_l = F_l + U(R_{l+1})).
 struct BandQuant {
     float step[kMaxK];  // quantisation step of each exposure at this level (0 = none)
     float inv[kMaxK];   // 1 / step
@@ -514,7 +520,7 @@ template <int KM>
 __global__ void __launch_bounds__(256)
 k_fuse_band_quad(const float* __restrict__ GI, const float* __restrict__ GW, size_t stride,
                  const float* __restrict__ GIc, size_t stride_c, int h, int w, size_t totalc, BandQuant q,
-                 float* __restrict__ F) {
+                 const float* __restrict__ Rc, float* __restrict__ F) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= totalc) return;
     const int hc = h >> 1, wc = w >> 1;
@@ -527,6 +533,14 @@ k_fuse_band_quad(const float* __restrict__ GI, const float* __restrict__ GW, siz
     const size_t co = jj * (size_t)hc * wc;
     float g[KM][9];
     float2 vi[KM][2], vw[KM][2];
+    float rc[9];
+    if (Rc) {
+        const float* rp = Rc + co;
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+            for (int b = 0; b < 3; ++b) rc[3 * a + b] = rp[(size_t)ry[a] * wc + rx[b]];
+    }
 #pragma unroll
     for (int k = 0; k < KM; ++k) {
         const float* gc = GIc + (size_t)k * stride_c + co;
@@ -562,21 +576,20 @@ k_fuse_band_quad(const float* __restrict__ GI, const float* __restrict__ GW, siz
             acc[d] = k == 0 ? v : acc[d] + v;
         }
     }
+    if (Rc) {
+        float he[3], ho[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            he[a] = fmaf(0.125f, rc[3 * a], fmaf(0.75f, rc[3 * a + 1], 0.125f * rc[3 * a + 2]));
+            ho[a] = fmaf(0.5f, rc[3 * a + 1], 0.5f * rc[3 * a + 2]);
+        }
+        acc[0] += fmaf(0.125f, he[0], fmaf(0.75f, he[1], 0.125f * he[2]));
+        acc[1] += fmaf(0.125f, ho[0], fmaf(0.75f, ho[1], 0.125f * ho[2]));
+        acc[2] += fmaf(0.5f, he[1], 0.5f * he[2]);
+        acc[3] += fmaf(0.5f, ho[1], 0.5f * ho[2]);
+    }
     *(float2*)(F + fo) = make_float2(acc[0], acc[1]);
     *(float2*)(F + fo + w) = make_float2(acc[2], acc[3]);
-}
-
-// Collapse step: R_l = U(R_{l+1}) + F_l, written to out (F_l in place, or the
-// fused output at level 0).
-__global__ void __launch_bounds__(256)
-k_fuse_collapse(const float* __restrict__ Rc, const float* F, int h, int w, size_t total, float* out) {
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const size_t jj = i / ((size_t)h * w);
-    const int r = (int)(i % ((size_t)h * w));
-    const int y = r / w, x = r % w;
-    const int hc = h >> 1, wc = w >> 1;
-    out[i] = F[i] + expand_at(Rc + jj * (size_t)hc * wc, hc, wc, y, x);
 }
 
 struct Level0Steps {
@@ -757,9 +770,9 @@ int launch_level1(mnf_ctx* ctx, hipStream_t st, const uint16_t* rawc, int K, int
 
 template <int KM>
 int launch_band_quad(mnf_ctx* ctx, hipStream_t st, const float* GI, const float* GW, size_t stride, const float* GIc,
-                     size_t stride_c, int h, int w, size_t totalc, const BandQuant& q, float* F) {
+                     size_t stride_c, int h, int w, size_t totalc, const BandQuant& q, const float* Rc, float* F) {
     MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_band_quad<KM>, grid1d(totalc), dim3(256), GI, GW, stride, GIc, stride_c, h,
-               w, totalc, q, F);
+               w, totalc, q, Rc, F);
     return MNF_OK;
 }
 
@@ -937,9 +950,12 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
                 MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_reduce, dim3((unsigned)tiles, K), dim3(kL1TY * kL1TX), lvlI(l),
                            lvlW(l), sstride(l), h, w, lvlI(l + 1), lvlW(l + 1), sS);
             }
-            for (int l = 1; l <= L; ++l) {
+            // bands from the base to level 1, each collapsing onto the level
+            // below it: lvlF(l) receives R_l = F_l + U(R_{l+1}) (R_L = F_L)
+            for (int l = L; l >= 1; --l) {
                 const int h = H >> l, w = W >> l;
                 const size_t nn = (size_t)nj * h * w;
+                const float* Rc = l < L ? (const float*)lvlF(l + 1) : (const float*)nullptr;
                 // the quad form reads each level-l array with 64-bit loads: every
                 // exposure's array must start 8-byte aligned (even stride)
                 if (l < L && small_k && sstride(l) % 2 == 0) {
@@ -952,26 +968,21 @@ extern "C" int fuse_exposures(mnf_ctx* ctx, const uint16_t* raw, const float* t,
                     const float *gi = lvlI(l), *gw = lvlW(l), *gc = lvlI(l + 1);
                     const size_t ss = sstride(l);
                     switch (K) {
-                        case 1: MNF_TRY(launch_band_quad<1>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
-                        case 2: MNF_TRY(launch_band_quad<2>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
-                        case 3: MNF_TRY(launch_band_quad<3>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
-                        case 4: MNF_TRY(launch_band_quad<4>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
-                        case 5: MNF_TRY(launch_band_quad<5>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
-                        case 6: MNF_TRY(launch_band_quad<6>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
-                        case 7: MNF_TRY(launch_band_quad<7>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
-                        default: MNF_TRY(launch_band_quad<8>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, lvlF(l))); break;
+                        case 1: MNF_TRY(launch_band_quad<1>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, Rc, lvlF(l))); break;
+                        case 2: MNF_TRY(launch_band_quad<2>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, Rc, lvlF(l))); break;
+                        case 3: MNF_TRY(launch_band_quad<3>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, Rc, lvlF(l))); break;
+                        case 4: MNF_TRY(launch_band_quad<4>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, Rc, lvlF(l))); break;
+                        case 5: MNF_TRY(launch_band_quad<5>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, Rc, lvlF(l))); break;
+                        case 6: MNF_TRY(launch_band_quad<6>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, Rc, lvlF(l))); break;
+                        case 7: MNF_TRY(launch_band_quad<7>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, Rc, lvlF(l))); break;
+                        default: MNF_TRY(launch_band_quad<8>(ctx, st, gi, gw, ss, gc, sS, h, w, nc, bq, Rc, lvlF(l))); break;
                     }
                     continue;
                 }
                 BandSteps bs{};
                 for (int k = 0; k < K; ++k) bs.step[k] = l < L ? step[(size_t)l * K + k] : 0.f;
                 MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_band, grid1d(nn), dim3(256), lvlI(l), lvlW(l), sstride(l),
-                           l < L ? lvlI(l + 1) : (const float*)nullptr, sS, K, h, w, nn, bs, l == L ? 1 : 0, lvlF(l));
-            }
-            for (int l = L - 1; l >= 1; --l) {
-                const int h = H >> l, w = W >> l;
-                const size_t nn = (size_t)nj * h * w;
-                MNF_LAUNCH(ctx, MNF_K_FUSE, st, k_fuse_collapse, grid1d(nn), dim3(256), lvlF(l + 1), lvlF(l), h, w, nn,
+                           l < L ? lvlI(l + 1) : (const float*)nullptr, sS, K, h, w, nn, bs, l == L ? 1 : 0, Rc,
                            lvlF(l));
             }
         }
