@@ -248,7 +248,9 @@ int ptycho_iterate_modes(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, i
  * ptycho_iterate, applied to every scan).  Scans are grouped by detector
  * size; each pass of each mini-batch round is one launch covering the
  * current mini-batch of every scan of that size (grid y spans all of their
- * positions), so small scans share the GPU with large ones.  With
+ * positions), so small scans share the GPU with large ones; the size classes
+ * are issued on streams of their own (forked from and joined to `stream`),
+ * so their passes overlap (one stream while kernel timing is enabled).  With
  * params->graph = 1 the whole call is captured in one hipGraph and replayed.
  * Each scan's fields have the meaning of the ptycho_iterate arguments of the
  * same name; `order` has n_iter rows of that scan's J entries or is NULL. */

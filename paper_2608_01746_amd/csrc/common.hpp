@@ -66,6 +66,10 @@ struct mnf_ctx {
     // of the launch sequence it holds (a call whose sequence hashes to the same
     // key replays it instead of capturing again)
     hipStream_t capture_stream = nullptr;
+    // one stream per detector-size class of a many-scan call (forked from and
+    // joined to the call's stream by events) and the fork / join events
+    std::vector<hipStream_t> class_streams;
+    std::vector<hipEvent_t> class_events;  // [0] fork, [1 + c] class c's join
     hipGraphExec_t graph_exec = nullptr;
     uint64_t graph_key = 0;
     // status bits set by kernels (non-finite values, divergence), read and

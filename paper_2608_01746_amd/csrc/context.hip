@@ -251,6 +251,8 @@ void mnf_destroy(mnf_ctx* ctx) {
     for (auto e : ctx->prof.pool) (void)hipEventDestroy(e);
     if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    for (auto s : ctx->class_streams) (void)hipStreamDestroy(s);
+    for (auto e : ctx->class_events) (void)hipEventDestroy(e);
     if (ctx->pinned) (void)hipHostFree(ctx->pinned);
     if (ctx->pinned_done) (void)hipEventDestroy(ctx->pinned_done);
     if (ctx->d_status) (void)hipFree(ctx->d_status);

@@ -537,6 +537,28 @@ int launch_small_run(mnf_ctx* ctx, const CallPlan& pl, int J, int n_iter, const 
 }
 
 
+bool any_err_of(const std::vector<ScanIn>& in) {
+    for (const ScanIn& s : in)
+        if (s.err_out) return true;
+    return false;
+}
+
+// At least n streams (default priority, not synchronising with the null
+// stream) and n + 1 events on the context, created on first use.
+int class_streams(mnf_ctx* ctx, int n) {
+    while ((int)ctx->class_streams.size() < n) {
+        hipStream_t s;
+        MNF_HIP(ctx, hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        ctx->class_streams.push_back(s);
+    }
+    while ((int)ctx->class_events.size() < n + 1) {
+        hipEvent_t e;
+        MNF_HIP(ctx, hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->class_events.push_back(e);
+    }
+    return MNF_OK;
+}
+
 // Validation and the host plan of an iterate call: the scan table, the size
 // classes and, for n_iter > 0, every launch's slot and group lists.  No
 // device work (the scans' device pointers are only copied).
@@ -655,11 +677,49 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     // update, transforms and stores, is slower than the two passes it joins).
     const bool fused = ns == 1 && !sub && modes == 1 && pl.scans[0].bw <= kObjRowMaxWidth &&
                        three_launch(ctx, in[0].Nd);
+    // Size classes share no data (a scan has one detector size), so with more
+    // than one class each class's launches and error sums go on a stream of
+    // its own, forked from and joined to the call's stream by events, and the
+    // classes' passes overlap on the GPU; each class then takes its own region
+    // of the pattern and maxima scratch.  (A call without allocations keeps
+    // one stream and shared regions, and so does a context timing its kernel
+    // classes, whose per-kernel times would otherwise include the overlap.)
+    const int ncls = (int)classes.size();
+    const bool multi = ncls > 1 && !fused && ctx->arena == nullptr && ctx->prof.mask == 0;
+    std::map<int, size_t> offS, offM;  // class -> byte offset into S, float offset into maxO2
+    size_t bytesS = pl.max_S * (fused ? 2 : 1);
+    size_t floatsM = std::max(pl.max_maxO2, fused ? (size_t)pl.max_slots * in[0].Nw : (size_t)0);
+    if (multi) {
+        std::map<int, size_t> needS, needM;
+        for (const Launch& L : pl.launches) {
+            const int gr = (L.maxNw + row_lines(ctx, L.N) - 1) / row_lines(ctx, L.N);
+            needS[L.N] = std::max(needS[L.N], (size_t)L.nslots * L.N * L.N * sizeof(float2));
+            needM[L.N] = std::max(needM[L.N], (size_t)L.nslots * gr);
+        }
+        bytesS = floatsM = 0;
+        for (auto& kv : classes) {
+            offS[kv.first] = bytesS;
+            offM[kv.first] = floatsM;
+            bytesS += (needS[kv.first] + 255) & ~(size_t)255;
+            floatsM += (needM[kv.first] + 63) & ~(size_t)63;
+        }
+    }
     const size_t sS = pl.max_S / sizeof(float2);  // complex values of one pattern buffer
-    MNF_TRY(mnf::scratch(ctx, "S", pl.max_S * (fused ? 2 : 1), &S));
-    MNF_TRY(mnf::scratch(ctx, "maxO2",
-                         std::max(pl.max_maxO2, fused ? (size_t)pl.max_slots * in[0].Nw : (size_t)0) * sizeof(float),
-                         &mO));
+    MNF_TRY(mnf::scratch(ctx, "S", bytesS, &S));
+    MNF_TRY(mnf::scratch(ctx, "maxO2", std::max<size_t>(floatsM, 1) * sizeof(float), &mO));
+    // the error sums of each class's scans, iteration-major within the class
+    std::vector<int> cls_job0, cls_nscan;
+    void* d_cjobs = nullptr;
+    if (multi && any_err_of(in)) {
+        std::vector<SumJob> cjobs;
+        for (auto& kv : classes) {
+            cls_job0.push_back((int)cjobs.size());
+            cls_nscan.push_back((int)kv.second.size());
+            for (int i = 0; i < n_iter; ++i)
+                for (int k : kv.second) cjobs.push_back(jobs[(size_t)i * ns + k]);
+        }
+        MNF_TRY(upload(ctx, "plan_cjobs", cjobs.data(), sizeof(SumJob) * cjobs.size(), st, &d_cjobs));
+    }
     SubBufs sbuf{nullptr, nullptr, nullptr};
     const SubBufs* sb = nullptr;
     if (sub) {
@@ -727,7 +787,7 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
         kh.add(p);
         kh.add(n_iter);
         const void* ptrs[] = {pl.d_scans, pl.d_slots, pl.d_groups, pl.d_fracs, d_jobs, S, mO,
-                              sbuf.Pd, sbuf.G, sbuf.DP};
+                              sbuf.Pd, sbuf.G, sbuf.DP, d_cjobs};
         kh.add(ptrs, sizeof ptrs);
         for (auto& kv : classes) {
             const float2* tw;
@@ -764,12 +824,29 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     size_t li = small ? pl.launches.size() : 0;
     const size_t nL = pl.launches.size();
     auto Sbuf = [&](size_t b) { return (float2*)S + (fused ? (b % 2) * sS : 0); };
+    // the class streams: fork after everything issued so far on the call's stream
+    std::map<int, int> cls_of;  // detector size -> class index
+    {
+        int c = 0;
+        for (auto& kv : classes) cls_of[kv.first] = c++;
+    }
+    if (multi && rc == MNF_OK) {
+        rc = class_streams(ctx, ncls);
+        if (rc == MNF_OK && hipEventRecord(ctx->class_events[0], run) != hipSuccess) rc = MNF_EHIP;
+        for (int c = 0; c < ncls && rc == MNF_OK; ++c)
+            if (hipStreamWaitEvent(ctx->class_streams[c], ctx->class_events[0], 0) != hipSuccess) rc = MNF_EHIP;
+        if (rc == MNF_EHIP) rc = set_error(ctx, MNF_EHIP, "forking the size-class streams failed");
+    }
+    auto stream_of = [&](int N) { return multi ? ctx->class_streams[cls_of[N]] : run; };
     for (int i = 0; i < n_iter && rc == MNF_OK; ++i) {
         const int it = p.it0 + i;
         const bool upd = p.update_probe && it >= p.probe_start_iter;
         for (; li < (size_t)pl.iter_end[i] && rc == MNF_OK; ++li) {
             if (!fused) {
-                rc = issue_iterate_any(ctx, pl, pl.launches[li], p, upd, (float2*)S, (float*)mO, sb, run);
+                const Launch& L = pl.launches[li];
+                float2* SL = multi ? (float2*)((char*)S + offS[L.N]) : (float2*)S;
+                float* ML = multi ? (float*)mO + offM[L.N] : (float*)mO;
+                rc = issue_iterate_any(ctx, pl, L, p, upd, SL, ML, sb, stream_of(L.N));
                 continue;
             }
             const Launch& L = pl.launches[li];
@@ -781,7 +858,22 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
                                         Sbuf(li + 1), (float*)mO, p, run);
         }
         if (rc == MNF_OK && any_err && !small) {
-            hipLaunchKernelGGL(k_sum_jobs, dim3(ns), dim3(256), 0, run, (const SumJob*)d_jobs + (size_t)i * ns, 1.0);
+            if (multi) {
+                for (int c = 0; c < ncls; ++c)
+                    hipLaunchKernelGGL(k_sum_jobs, dim3(cls_nscan[c]), dim3(256), 0, ctx->class_streams[c],
+                                       (const SumJob*)d_cjobs + cls_job0[c] + (size_t)i * cls_nscan[c], 1.0);
+            } else {
+                hipLaunchKernelGGL(k_sum_jobs, dim3(ns), dim3(256), 0, run, (const SumJob*)d_jobs + (size_t)i * ns,
+                                   1.0);
+            }
+        }
+    }
+    // join the class streams back into the call's stream
+    if (multi) {
+        for (int c = 0; c < ncls; ++c) {
+            hipError_t e = hipEventRecord(ctx->class_events[1 + c], ctx->class_streams[c]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(run, ctx->class_events[1 + c], 0);
+            if (e != hipSuccess && rc == MNF_OK) rc = set_error(ctx, MNF_EHIP, "joining the size-class streams failed");
         }
     }
     // non-finite objects and probes are reported by mnf_status
