@@ -386,8 +386,10 @@ int mnf_conv2d_grad(mnf_ctx* ctx, int mode, const uint16_t* x, int n, int H, int
  * clean device float [J][H][W]; t host float [K] (K <= 16); raw device uint16 [J][K][H][W].
  * Random numbers come from the counter-based Philox4x32-10 generator keyed by
  * `seed`, one counter per output element, so the result depends only on the
- * seed and the element index.  Poisson draws use inversion below a mean of
- * 12 and a rounded normal approximation above; normals use Box-Muller.
+ * seed and the element index.  Poisson draws are exact: inversion below a
+ * mean of 10, Hoermann's transformed rejection with squeeze (PTRS, 1993)
+ * above (means beyond 1e8 saturate and are not drawn); normals use
+ * Box-Muller.
  * Errors: MNF_EINVAL for null pointers, non-positive sizes, K > 16,
  * negative scale or sigma_read, or sat outside (0, 65535]. */
 int detector_expose(mnf_ctx* ctx, const float* clean, int J, int H, int W, const float* t, int K, float scale,

@@ -34,8 +34,44 @@ __device__ __forceinline__ uint4 philox4x32_10(uint4 c, uint2 k) {
 // uniform in (0, 1]
 __device__ __forceinline__ float u01(uint32_t v) { return ((float)(v >> 8) + 1.f) * (1.f / 16777216.f); }
 
+// uniform in (0, 1), double, from 32 bits
+__device__ __forceinline__ double u01d(uint32_t v) { return ((double)v + 0.5) * (1.0 / 4294967296.0); }
+
+// Exact Poisson variate of mean lam >= 10 by transformed rejection with
+// squeeze (W. Hoermann, "The transformed rejection method for generating
+// Poisson random variables", Insurance: Mathematics and Economics 12, 1993:
+// the method PTRS, its hat and squeeze constants).  Trial t takes the pair
+// of uniforms (U, V) = words (2 (t mod 2), 2 (t mod 2) + 1) of the counter
+// block t / 2 + 1 of element i (block 0 feeds the read noise); the expected
+// number of trials is about 1.1, and after 64 rejections in a row
+// (probability below 1e-60) the mean rounded is returned.
+__device__ int poisson_ptrs(double lam, size_t i, uint2 key) {
+    const double slam = sqrt(lam), loglam = log(lam);
+    const double b = 0.931 + 2.53 * slam;
+    const double a = -0.059 + 0.02483 * b;
+    const double inv_alpha = 1.1239 + 1.1328 / (b - 3.4);
+    const double v_r = 0.9277 - 3.6224 / (b - 2.0);
+    uint4 r = make_uint4(0u, 0u, 0u, 0u);
+    for (int trial = 0; trial < 64; ++trial) {
+        if ((trial & 1) == 0)
+            r = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), (uint32_t)(trial / 2 + 1), 0u), key);
+        const double U = u01d((trial & 1) ? r.z : r.x) - 0.5;
+        const double V = u01d((trial & 1) ? r.w : r.y);
+        const double us = 0.5 - fabs(U);
+        if (us <= 0.0) continue;
+        const double kd = floor((2.0 * a / us + b) * U + lam + 0.43);
+        if (us >= 0.07 && V <= v_r) return (int)kd;
+        if (kd < 0.0 || (us < 0.013 && V > us)) continue;
+        // accept when V lies under the transformed density
+        if (log(V) + log(inv_alpha) - log(a / (us * us) + b) <= -lam + kd * loglam - lgamma(kd + 1.0))
+            return (int)kd;
+    }
+    return (int)rint(lam);
+}
+
 // counts = clip(rint(Poisson(scale t_k clean) + N(0, sigma^2)), 0, sat).
-// Poisson by inversion below lambda = 12, by a rounded normal above.
+// Poisson by inversion below lambda = 10, by transformed rejection above
+// (exact in both ranges).
 __global__ void k_expose(const float* __restrict__ clean, int J, int K, size_t npix, const float* __restrict__ t,
                          float scale, float sat, float sigma, uint2 key, uint16_t* __restrict__ raw) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -47,12 +83,11 @@ __global__ void k_expose(const float* __restrict__ clean, int J, int K, size_t n
     const size_t j = jk / K;
     const float lam = fmaxf(clean[j * npix + q], 0.f) * scale * t[k];
     const uint4 r = philox4x32_10(make_uint4((uint32_t)i, (uint32_t)(i >> 32), 0u, 0u), key);
-    // r.x drives the Poisson inversion; r.z, r.w give two normals (Box-Muller).
+    // r.x drives the Poisson inversion; r.z, r.w give the read noise (Box-Muller).
     const float u1 = u01(r.x), u3 = u01(r.z), u4 = u01(r.w);
-    const float rad = sqrtf(-2.f * logf(u3));
-    const float z1 = rad * cospif(2.f * u4), z2 = rad * sinpif(2.f * u4);
+    const float z = sqrtf(-2.f * logf(u3)) * sinpif(2.f * u4);
     float c;
-    if (lam < 12.f) {
+    if (lam < 10.f) {
         float p = expf(-lam), F = p;
         int x = 0;
         while (u1 > F && x < 64) {
@@ -61,10 +96,12 @@ __global__ void k_expose(const float* __restrict__ clean, int J, int K, size_t n
             F += p;
         }
         c = (float)x;
+    } else if (lam < 1e8f) {
+        c = (float)poisson_ptrs((double)lam, i, key);
     } else {
-        c = rintf(lam + sqrtf(lam) * z1);
+        c = lam;  // far beyond any full scale: the count clips to sat whatever the draw
     }
-    c = rintf(c + sigma * z2);
+    c = rintf(c + sigma * z);
     raw[i] = (uint16_t)fminf(fmaxf(c, 0.f), sat);
 }
 

@@ -55,6 +55,25 @@ def test_small_mean_is_exact_poisson(api):
         assert abs(np.mean(x == kval) - p) < 5 * np.sqrt(p * (1 - p) / n), kval
 
 
+@pytest.mark.parametrize("lam", [10.5, 30.0, 400.0])
+def test_large_means_are_exact_poisson(api, lam):
+    # the transformed-rejection range: the skewness 1/sqrt(lam) (zero for a
+    # rounded normal) and the probabilities of the values around the mean
+    # (a chi-square over the central 4 standard deviations)
+    from scipy import stats
+    x = _expose(api, lam, [1.0], 65535, 0.0, seed=5, n=1 << 20)[0]
+    n = x.size
+    skew = np.mean((x - x.mean()) ** 3) / x.std() ** 3
+    assert abs(skew - 1.0 / np.sqrt(lam)) < 5 * np.sqrt(6.0 / n), (skew, 1.0 / np.sqrt(lam))
+    lo, hi = int(lam - 4 * np.sqrt(lam)), int(lam + 4 * np.sqrt(lam))
+    ks = np.arange(max(lo, 0), hi + 1)
+    obs = np.array([np.sum(x == k) for k in ks], np.float64)
+    exp = n * stats.poisson.pmf(ks, lam)
+    chi2 = np.sum((obs - exp) ** 2 / exp)
+    assert chi2 < stats.chi2.ppf(0.9999, len(ks) - 1), (chi2, len(ks))
+    assert np.all(x == np.rint(x)) and x.min() >= 0
+
+
 def test_exposure_clips_and_is_seeded(api):
     a = _expose(api, 3000.0, [1.0, 10.0], 4095, 2.0, seed=7, n=1 << 14)
     assert a.max() == 4095 and a[0].max() < 4095 and a.min() >= 0
