@@ -597,7 +597,26 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             for (int c = 0; c < COLS; ++c) {
                 const int n = threadIdx.x + c * THREADS;
                 if (n < Nw) {
-                    for (int l = 0; l < nl; ++l) {
+                    int l0 = 0;
+                    if constexpr (!MIX) {
+                        // eight lines' values loaded before their adds, which
+                        // keep the line order of the loop below
+                        for (; l0 + 8 <= nl; l0 += 8) {
+                            float2 cn[8];
+                            float cd[8];
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                if constexpr (ACC) cn[u] = c_num[(l0 + u) * N + n];
+                                if constexpr (DEN) cd[u] = c_den[(l0 + u) * N + n];
+                            }
+#pragma unroll
+                            for (int u = 0; u < 8; ++u) {
+                                if constexpr (ACC) num[0][c] = cadd(num[0][c], cn[u]);
+                                if constexpr (DEN) den[c] += (double)cd[u];
+                            }
+                        }
+                    }
+                    for (int l = l0; l < nl; ++l) {
                         if constexpr (MIX) {
                             const int mm = (k0 + l) % nmodes;
                             if constexpr (ACC) {
