@@ -169,6 +169,65 @@ __device__ __forceinline__ uint4 load_a8(const ConvArgs& a, int m, int k) {
     }
 }
 
+// The output pixel of GEMM row m decomposed once (valid: m < M; for UP the
+// input pixel r of the row), so that the K loop's gathers need no division.
+struct RowGeom {
+    int valid, img, y, x;
+};
+
+template <int MODE>
+__device__ __forceinline__ RowGeom row_geom(const ConvArgs& a, int m) {
+    RowGeom g{m < a.M ? 1 : 0, 0, 0, 0};
+    if (!g.valid) return g;
+    if constexpr (MODE == UP) {
+        g.x = m % a.per_pad;  // the input pixel
+        g.valid = g.x < a.n * a.Hin * a.Win;
+    } else {
+        g.x = m % a.Wout;
+        const int t1 = m / a.Wout;
+        g.y = t1 % a.Hout;
+        g.img = t1 / a.Hout;
+    }
+    return g;
+}
+
+// Eight consecutive GEMM columns of tap `tap`, channels ci .. ci+7 (Cin a
+// multiple of 8), of a row with decomposed geometry: load_a8<VEC> without the
+// per-load index arithmetic.
+template <int MODE, bool MASK>
+__device__ __forceinline__ uint4 load_a8_geom(const ConvArgs& a, const RowGeom& g, int tap, int ci, bool kin) {
+    uint4 r = make_uint4(0, 0, 0, 0);
+    if (!g.valid || !kin) return r;
+    size_t pix;
+    if constexpr (MODE == UP) {
+        pix = (size_t)g.x;
+    } else {
+        int yy = g.y, xx = g.x;
+        if constexpr (MODE == CONV3) {
+            yy += tap / 3 - 1;
+            xx += tap % 3 - 1;
+        } else if constexpr (MODE == DOWN) {
+            yy = 2 * g.y + (tap >> 1);
+            xx = 2 * g.x + (tap & 1);
+        }
+        if (yy < 0 || yy >= a.Hin || xx < 0 || xx >= a.Win) return r;
+        pix = ((size_t)g.img * a.Hin + yy) * a.Win + xx;
+    }
+    r = *(const uint4*)(a.in + pix * a.in_cs + a.in_co + ci);
+    if constexpr (MASK) {
+        const uint4 gm = *(const uint4*)(a.mask + pix * a.mask_cs + a.mask_co + ci);
+        uint32_t* rv = (uint32_t*)&r;
+        const uint32_t* gv = (const uint32_t*)&gm;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const uint32_t lo = (gv[q] & 0xffffu), hi = gv[q] >> 16;
+            const bool plo = lo != 0 && !(lo & 0x8000u), phi = hi != 0 && !(hi & 0x8000u);
+            rv[q] = (plo ? (rv[q] & 0xffffu) : 0u) | (phi ? (rv[q] & 0xffff0000u) : 0u);
+        }
+    }
+    return r;
+}
+
 template <int MODE, bool MASK, bool VEC, bool OUT_F32, int BK>
 __global__ void __launch_bounds__(kGemmThreads) k_conv_gemm(ConvArgs a) {
     using G = GemmTile<BK>;
@@ -182,9 +241,24 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_gemm(ConvArgs a) {
     // per-thread load slots: A rows tid/TPR + RSTEP q, B rows likewise, eight columns each
     const int ar = tid / G::TPR, ac = (tid % G::TPR) * 8;
     uint4 ra[G::ACH], rb[G::BCH];
-    auto fetch = [&](int k0) {
+    // the thread's A rows, decomposed once (VEC: every column of the thread's
+    // eight lies in one tap, the same for all its rows)
+    RowGeom geo[G::ACH];
+    if constexpr (VEC) {
 #pragma unroll
-        for (int q = 0; q < G::ACH; ++q) ra[q] = load_a8<MODE, MASK, VEC>(a, m0 + G::RSTEP * q + ar, k0 + ac);
+        for (int q = 0; q < G::ACH; ++q) geo[q] = row_geom<MODE>(a, m0 + G::RSTEP * q + ar);
+    }
+    const int Ktot = (MODE == CONV3 ? 9 : (MODE == DOWN ? 4 : 1)) * a.Cin;
+    auto fetch = [&](int k0) {
+        if constexpr (VEC) {
+            const int k = k0 + ac;
+            const int tap = k / a.Cin, ci = k - tap * a.Cin;
+#pragma unroll
+            for (int q = 0; q < G::ACH; ++q) ra[q] = load_a8_geom<MODE, MASK>(a, geo[q], tap, ci, k < Ktot);
+        } else {
+#pragma unroll
+            for (int q = 0; q < G::ACH; ++q) ra[q] = load_a8<MODE, MASK, VEC>(a, m0 + G::RSTEP * q + ar, k0 + ac);
+        }
 #pragma unroll
         for (int q = 0; q < G::BCH; ++q) {
             const int n = n0 + G::RSTEP * q + ar;
@@ -210,7 +284,16 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_gemm(ConvArgs a) {
             acc1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, b1, acc1, 0, 0, 0);
         }
     }
-    // epilogue
+    // epilogue: the output pixel of each of the thread's 16 rows, once for
+    // both column halves
+    size_t opv[16];
+    bool okv[16];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+        const int m = m0 + 32 * w + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+        okv[v] = m < a.M && (MODE != UP || m % a.per_pad < a.n * a.Hin * a.Win);
+        opv[v] = okv[v] ? out_pixel<MODE>(a, m) : 0;
+    }
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
         const int j = n0 + 32 * nb + (lane & 31);
@@ -218,12 +301,9 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_gemm(ConvArgs a) {
         const float bj = a.bias ? a.bias[j] : 0.f;
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int i = 32 * w + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
-            const int m = m0 + i;
-            if (m >= a.M) continue;
-            if (MODE == UP && m % a.per_pad >= a.n * a.Hin * a.Win) continue;
+            if (!okv[v]) continue;
             float y = (nb == 0 ? acc0[v] : acc1[v]) + bj;
-            const size_t op = out_pixel<MODE>(a, m);
+            const size_t op = opv[v];
             if (a.resid) y += bf2f(a.resid[op * a.res_cs + a.res_co + j]);
             if (a.relu) y = fmaxf(y, 0.f);
             if constexpr (OUT_F32)
