@@ -1414,7 +1414,9 @@ int ptycho_descend(mnf_ctx* ctx, mnf_c64* O, int My, int Mx, mnf_c64* P, int Nw,
     const size_t bP = sizeof(float2) * (size_t)std::max(Nw, 1) * std::max(Nw, 1);
     MNF_TRY(mnf::scratch(ctx, "descent_gO", bO, &gO));
     MNF_TRY(mnf::scratch(ctx, "descent_gP", bP, &gP));
-    ScanIn s{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, pos, J, nullptr, nullptr, (float2*)gO, (float2*)gP};
+    // a fixed probe needs no probe gradient
+    ScanIn s{(float2*)O, My, Mx, (float2*)P, Nw, I, Nd, pos, J, nullptr, nullptr, (float2*)gO,
+             update_probe ? (float2*)gP : nullptr};
     CallPlan pl;
     MNF_TRY(plan_identity(ctx, s, batch, pl, st));  // checks the scan (sizes, windows inside O)
     const ScanDev& b = pl.scans[0];
