@@ -93,7 +93,7 @@ def test_gradient_with_padded_window_matches_differences():
         assert abs(fd - gP[idx]) <= 1e-6 * max(1.0, abs(fd))
 
 
-# --- gradient descent (full batch, fixed steps) ------------------------------
+# --- gradient descent (full batch, backtracking) -----------------------------
 
 def test_one_descent_step_is_the_modulus_projection():
     # unit probe covering the whole object at one position (Nw = Nd = M), the
@@ -130,8 +130,8 @@ def test_step_sizes_by_hand():
 
 
 def test_descent_lowers_the_amplitude_loss():
-    # noiseless data from a true object, a perturbed start: every fixed step
-    # lowers the loss, object and probe updated together
+    # noiseless data from a true object, a perturbed start: every step is
+    # accepted and lowers the loss, object and probe updated together
     rng = np.random.default_rng(8)
     M, Nw = 40, 16
     O_true = synth.make_object(M, 3)
