@@ -293,14 +293,14 @@ __device__ __forceinline__ void stage_exchange(float2* x, int t, float2* lds, co
 #pragma unroll
         for (int q = 0; q < R; ++q) lds[addr(base + q * L)] = x[i * R + q];
     }
-    __syncthreads();
+    ADDR::sync();
 #pragma unroll
     for (int i = 0; i < V / R2; ++i) {
         const int b = t + i * T;
 #pragma unroll
         for (int m = 0; m < R2; ++m) x[i * R2 + m] = lds[addr(b + m * (N / R2))];
     }
-    __syncthreads();
+    ADDR::sync();
 }
 
 template <int N, bool INV, int s, class ADDR>
@@ -314,8 +314,9 @@ struct StageRunner {
     }
 };
 
-// Full 1D transform of one line.  Every thread of the block must call it
-// (it synchronises the block between stages).
+// Full 1D transform of one line.  Every thread that ADDR::sync() waits for
+// must call it: the whole block, or the whole wavefront for a wave-local
+// layout.
 template <int N, bool INV, class ADDR>
 __device__ __forceinline__ void fft_line(float2* x, int t, float2* lds, const ADDR& addr, const float2* tw) {
     StageRunner<N, INV, 0, ADDR>::run(x, t, lds, addr, tw);
@@ -329,6 +330,24 @@ struct RowLds {
     static constexpr int stride = N + N / 16;
     __device__ __forceinline__ explicit RowLds(int line) : base(line * stride) {}
     __device__ __forceinline__ int operator()(int p) const { return base + p + (p >> 4); }
+    static __device__ __forceinline__ void sync() { __syncthreads(); }
+};
+
+// The same layout when each line's threads lie in one wavefront (T divides
+// 64 and line = threadIdx.x / T): a line's region of LDS is touched by that
+// wavefront only, whose LDS operations take effect in issue order, so a
+// stage exchange needs no block barrier, only a point the compiler moves no
+// LDS access across.  The wavefronts of a block then run their transforms
+// independently, one overlapping its loads with another's arithmetic.
+template <int N>
+struct RowLdsWave : RowLds<N> {
+    static_assert(64 % PlanInfo<N>::T == 0, "a line must not span wavefronts");
+    __device__ __forceinline__ explicit RowLdsWave(int line) : RowLds<N>(line) {}
+    static __device__ __forceinline__ void sync() {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
 };
 
 // LDS addressing: C lines stored interleaved (position-major), line fastest.
@@ -337,6 +356,7 @@ struct ColLds {
     int line;
     __device__ __forceinline__ explicit ColLds(int l) : line(l) {}
     __device__ __forceinline__ int operator()(int p) const { return p * C + line; }
+    static __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
 }  // namespace mnf

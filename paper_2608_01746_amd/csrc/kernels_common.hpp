@@ -46,6 +46,22 @@ __device__ __forceinline__ float2 ldg(const float2* p, size_t i) {
     return make_float2(v.x, v.y);
 }
 
+// Stores of results that a later kernel reads.  The L2 of one XCD is not
+// coherent with the other seven, so the release at the end of a kernel
+// writes back every line its waves left dirty, after the last wave and while
+// the next kernel waits.  A device-scope store (a relaxed atomic store at
+// agent scope: the scope only, no ordering) is written through the L2 while
+// the kernel runs instead.  Each element must be written by one thread.
+template <class T>
+using gptr_w = __attribute__((address_space(1))) T*;
+__device__ __forceinline__ void st_dev(float2* p, size_t i, float2 v) {
+    const unsigned long long b = ((unsigned long long)__float_as_uint(v.y) << 32) | __float_as_uint(v.x);
+    __hip_atomic_store((gptr_w<unsigned long long>)(p + i), b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev(float* p, size_t i, float v) {
+    __hip_atomic_store((gptr_w<float>)(p + i), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The twiddle table staged through registers: load() with a prologue's
 // other loads, store() to LDS just before the barrier that precedes the first
 // transform, so the table's load needs no wait of its own (a load-to-LDS

@@ -64,10 +64,10 @@ k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
         twr.load(tw_g);
         twr.store(tw);
         __syncthreads();
-        if (dx != 0.f) shift_regs<N>(p, dx, t, lds, RowLds<N>(line), tw);
+        if (dx != 0.f) shift_regs<N>(p, dx, t, lds, RowLdsWave<N>(line), tw);
         if (live && dx != 0.f) {
 #pragma unroll
-            for (int idx = 0; idx < V; ++idx) Pw[in_pos<N, false>(t, idx)] = p[idx];
+            for (int idx = 0; idx < V; ++idx) st_dev(Pw, in_pos<N, false>(t, idx), p[idx]);
         }
 #pragma unroll
         for (int idx = 0; idx < V; ++idx) {
@@ -92,11 +92,11 @@ k_rows_fwd(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
             mO = fmaxf(mO, in ? cabs2(o[idx]) : 0.f);
         }
     }
-    fft_line<N, false>(x, t, lds, RowLds<N>(line), tw);
+    fft_line<N, false>(x, t, lds, RowLdsWave<N>(line), tw);
     if (live) {
         float2* row = S + ((size_t)s * N + y) * N;
 #pragma unroll
-        for (int idx = 0; idx < V; ++idx) row[out_pos<N, false>(t, idx)] = x[idx];
+        for (int idx = 0; idx < V; ++idx) st_dev(row, out_pos<N, false>(t, idx), x[idx]);
     }
     if (maxO2_part) {
         mO = block_max(mO, red, false);
@@ -214,7 +214,7 @@ k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int y = out_pos<N, true>(t, idx);
-        if (y < Nw) col[(size_t)y * N] = x[idx];  // the 1/N of the unitary inverse is applied by the row pass
+        if (y < Nw) st_dev(col, (size_t)y * N, x[idx]);  // the 1/N of the unitary inverse is applied by the row pass
     }
     acc = block_sum(acc, red, false);
     if (threadIdx.x == 0) sc.err_part[(size_t)sd.j * gridDim.x + blockIdx.x] = acc;
@@ -251,7 +251,7 @@ k_cols_intensity(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int ky = out_pos<N, false>(t, idx);
-        Ij[(size_t)((ky + N / 2) % N) * N + sx] = cabs2(x[idx]) * sc2;
+        st_dev(Ij, (size_t)((ky + N / 2) % N) * N + sx, cabs2(x[idx]) * sc2);
     }
 }
 
@@ -338,7 +338,7 @@ k_cols_modulus_modes(const ScanDev* __restrict__ scans, const SlotDev* __restric
 #pragma unroll
         for (int idx = 0; idx < V; ++idx) {
             const int y = out_pos<N, true>(t, idx);
-            if (y < Nw) col[(size_t)y * N] = x[idx];
+            if (y < Nw) st_dev(col, (size_t)y * N, x[idx]);
         }
         __syncthreads();
     }
@@ -385,7 +385,7 @@ k_cols_intensity_modes(const ScanDev* __restrict__ scans, const SlotDev* __restr
 #pragma unroll
     for (int idx = 0; idx < V; ++idx) {
         const int ky = out_pos<N, false>(t, idx);
-        Ij[(size_t)((ky + N / 2) % N) * N + sx] = tot[idx] * sc2;
+        st_dev(Ij, (size_t)((ky + N / 2) % N) * N + sx, tot[idx] * sc2);
     }
 }
 
@@ -444,12 +444,17 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
     constexpr bool ACC = MODE == 1 || MODE == 2 || MODE == 6;     // probe-row sums over the batch
     constexpr bool DEN = MODE == 1 || MODE == 4 || MODE == 6;
     constexpr int NM = MIX ? kMaxModes : 1;                       // probe rows held
-    // the transform's exchange buffer doubles as the per-line numerator buffer
-    // once a round's transforms are done (both hold ULINES x N complex values)
+    // The transform's exchange buffer doubles as the per-line numerator
+    // buffer once a line's transform is done: line l's numerators go to its
+    // own region (c_num[l * CSTR + n]), which only its own wavefront touches
+    // until the block barrier before the sums.  Line strides of N + N/16
+    // (numerators) and N + T (denominators) put a wavefront's lines on
+    // different LDS banks.
+    constexpr int CSTR = RowLds<N>::stride, DSTR = N + T;
     __shared__ float2 lds[ULINES * RowLds<N>::stride];
     __shared__ float2 tw[N];
     __shared__ float2 s_prow[NM * N];
-    __shared__ float c_den[DEN ? ULINES * N : 1];
+    __shared__ float c_den[DEN ? ULINES * DSTR : 1];
     __shared__ float s_max[DEN ? kMaxBatch : 1];
     __shared__ int s_py[kMaxBatch], s_px[kMaxBatch];
     __shared__ float red[THREADS / 64 + 1];
@@ -487,14 +492,17 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
         const int i = min((int)threadIdx.x + q * THREADS, nrow - 1);
         prv[q] = ldg(Prow, (size_t)(i / N) * Nw * Nw + min(i % N, Nw - 1));
     }
+    // the slot table is held in registers until the per-slot maxima below
+    // have been loaded too, so that both wait on one round trip
     constexpr int SK = (kMaxBatch + THREADS - 1) / THREADS;
+    int spy[SK], spx[SK];
 #pragma unroll
     for (int q = 0; q < SK; ++q) {
         const int k = (int)threadIdx.x + q * THREADS;
         if (k < nb) {
             const SlotDev sd = slots[gd.s0 + k];
-            s_py[k] = sd.py;
-            s_px[k] = sd.px;
+            spy[q] = sd.py;
+            spx[q] = sd.px;
         }
     }
     if constexpr (DEN) {
@@ -518,6 +526,14 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             }
             for (int o = G / 2; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
             if (k < nb && lane == 0) s_max[k] = m;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < SK; ++q) {
+        const int k = (int)threadIdx.x + q * THREADS;
+        if (k < nb) {
+            s_py[k] = spy[q];
+            s_px[k] = spx[q];
         }
     }
     twr.store(tw);
@@ -554,7 +570,7 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             o[idx] = live && n < Nw ? Orow[n] : make_float2(0.f, 0.f);
             if constexpr (SUB) pv[idx] = live && n < Nw ? Psrow[n] : make_float2(0.f, 0.f);
         }
-        fft_line<N, true>(x, t, lds, RowLds<N>(line), tw);
+        fft_line<N, true>(x, t, lds, RowLdsWave<N>(line), tw);
         if (live) {
             float mO = 0.f;
             if constexpr (DEN) mO = s_max[k];
@@ -564,15 +580,15 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                 if (n < Nw) {
                     const float2 p = SUB ? pv[idx] : s_prow[(MIX ? k % nmodes : 0) * N + n];
                     const float2 d = MODE == 2 ? cscale(x[idx], scl) : csub(cscale(x[idx], scl), cmul(p, o[idx]));
-                    row[n] = cconjmul(p, d);
-                    if constexpr (ACC) c_num[line * N + n] = cconjmul(o[idx], d);
+                    st_dev(row, n, cconjmul(p, d));
+                    if constexpr (ACC) c_num[line * CSTR + n] = cconjmul(o[idx], d);
                     if constexpr (MODE == 4) {
                         if (gfrac) x[idx] = cconjmul(o[idx], d);  // translated below, then stored
-                        else G[((size_t)(gd.s0 + k) * Nw + r) * Nw + n] = cconjmul(o[idx], d);
+                        else st_dev(G, ((size_t)(gd.s0 + k) * Nw + r) * Nw + n, cconjmul(o[idx], d));
                     }
                     if constexpr (DEN) {
                         const float o2 = cabs2(o[idx]);
-                        c_den[line * N + n] = rpie ? fmaf(1.f - beta, o2, beta * mO) : mO / beta;
+                        c_den[line * DSTR + n] = rpie ? fmaf(1.f - beta, o2, beta * mO) : mO / beta;
                     }
                 }
             }
@@ -582,11 +598,11 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
 #pragma unroll
                 for (int idx = 0; idx < V; ++idx)
                     if (!live) x[idx] = make_float2(0.f, 0.f);
-                shift_regs<N>(x, live ? -gfrac[gd.s0 + kk].y : 0.f, t, lds, RowLds<N>(line), tw);
+                shift_regs<N>(x, live ? -gfrac[gd.s0 + kk].y : 0.f, t, lds, RowLdsWave<N>(line), tw);
                 if (live) {
                     float2* grow = G + ((size_t)(gd.s0 + k) * Nw + r) * Nw;
 #pragma unroll
-                    for (int idx = 0; idx < V; ++idx) grow[out_pos<N, true>(t, idx)] = x[idx];
+                    for (int idx = 0; idx < V; ++idx) st_dev(grow, out_pos<N, true>(t, idx), x[idx]);
                 }
             }
         }
@@ -606,8 +622,8 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                             float cd[8];
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
-                                if constexpr (ACC) cn[u] = c_num[(l0 + u) * N + n];
-                                if constexpr (DEN) cd[u] = c_den[(l0 + u) * N + n];
+                                if constexpr (ACC) cn[u] = c_num[(l0 + u) * CSTR + n];
+                                if constexpr (DEN) cd[u] = c_den[(l0 + u) * DSTR + n];
                             }
 #pragma unroll
                             for (int u = 0; u < 8; ++u) {
@@ -622,13 +638,13 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                             if constexpr (ACC) {
 #pragma unroll
                                 for (int q = 0; q < NM; ++q)
-                                    if (q == mm) num[q][c] = cadd(num[q][c], c_num[l * N + n]);
+                                    if (q == mm) num[q][c] = cadd(num[q][c], c_num[l * CSTR + n]);
                             }
                             if constexpr (DEN)
-                                if (mm == 0) den[c] += (double)c_den[l * N + n];
+                                if (mm == 0) den[c] += (double)c_den[l * DSTR + n];
                         } else {
-                            if constexpr (ACC) num[0][c] = cadd(num[0][c], c_num[l * N + n]);
-                            if constexpr (DEN) den[c] += (double)c_den[l * N + n];
+                            if constexpr (ACC) num[0][c] = cadd(num[0][c], c_num[l * CSTR + n]);
+                            if constexpr (DEN) den[c] += (double)c_den[l * DSTR + n];
                         }
                     }
                 }
@@ -650,7 +666,7 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
             float q2 = 0.f;
             for (int q = 0; q < nmodes; ++q) q2 += cabs2(s_prow[q * N + n]);
             const float p2 = q2 / (float)nmodes;
-            sc.P2[(size_t)r * Nw + n] = p2;
+            st_dev(sc.P2, (size_t)r * Nw + n, p2);
             pmax = fmaxf(pmax, p2);
             if (MODE == 6 && den[c] > 0.0) {
                 const float inv = (float)(1.0 / den[c]);  // the float64 denominator, inverted once
@@ -660,20 +676,20 @@ k_rows_inv_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__
                     float2 p = s_prow[q * N + n];
                     p.x = fmaf(num[q][c].x, inv, p.x);
                     p.y = fmaf(num[q][c].y, inv, p.y);
-                    sc.P[(size_t)q * Nw * Nw + (size_t)r * Nw + n] = p;
+                    st_dev(sc.P, (size_t)q * Nw * Nw + (size_t)r * Nw + n, p);
                 }
             }
         } else {
             float2 p = s_prow[n];
             const float p2 = cabs2(p);
-            sc.P2[(size_t)r * Nw + n] = p2;
+            st_dev(sc.P2, (size_t)r * Nw + n, p2);
             pmax = fmaxf(pmax, p2);
             if constexpr (MODE == 4) DP[(size_t)r * Nw + n] = den[c];
             if (MODE == 1 && den[c] > 0.0) {
                 const float inv = (float)(1.0 / den[c]);  // the float64 denominator, inverted once
                 p.x = fmaf(num[0][c].x, inv, p.x);
                 p.y = fmaf(num[0][c].y, inv, p.y);
-                sc.P[(size_t)r * Nw + n] = p;
+                st_dev(sc.P, (size_t)r * Nw + n, p);
             }
         }
     }

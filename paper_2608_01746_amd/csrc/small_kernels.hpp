@@ -48,12 +48,14 @@ struct SmallRow {
     int row;
     __device__ __forceinline__ explicit SmallRow(int r) : row(r) {}
     __device__ __forceinline__ int operator()(int p) const { return small_at<N>(row, p); }
+    static __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 template <int N>
 struct SmallCol {
     int col;
     __device__ __forceinline__ explicit SmallCol(int c) : col(c) {}
     __device__ __forceinline__ int operator()(int p) const { return small_at<N>(p, col); }
+    static __device__ __forceinline__ void sync() { __syncthreads(); }
 };
 
 // One block of SmallCfg<N>::THREADS threads.  scans[0] is the scan (O, P, amplitudes
