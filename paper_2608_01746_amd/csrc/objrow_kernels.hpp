@@ -140,33 +140,45 @@ k_obj_rows(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots_
             den[q] = 0.0;
         }
         for (int k0 = 0; k0 < cu; k0 += kObjRowChunk) {
+            // slots past the window count (uniform) issue no loads; pixels
+            // outside a window add zero
+            const int nc = min(kObjRowChunk, cu - k0);
             float2 wv[kObjRowChunk][R];
             float p2[kObjRowChunk][R];
             bool in[kObjRowChunk][R];
 #pragma unroll
             for (int c = 0; c < kObjRowChunk; ++c) {
-                const int k = min(k0 + c, cu - 1);
-                const int ux = xx - u_px[k];
-                const bool inx = k0 + c < cu && ux >= 0 && ux < Nw && xi < bw;
-                const int uxc = min(max(ux, 0), Nw - 1);
-                const float2* Sk = S_u + (size_t)u_slot[k] * N * N + uxc;
+                if (c < nc) {
+                    const int k = k0 + c;
+                    const int ux = xx - u_px[k];
+                    const bool inx = ux >= 0 && ux < Nw && xi < bw;
+                    const int uxc = min(max(ux, 0), Nw - 1);
+                    const float2* Sk = S_u + (size_t)u_slot[k] * N * N + uxc;
 #pragma unroll
-                for (int q = 0; q < R; ++q) {
-                    const int uy = y0 + q - u_py[k];
-                    in[c][q] = inx && q < rows && uy >= 0 && uy < Nw;
-                    const int uyc = min(max(uy, 0), Nw - 1);
-                    wv[c][q] = Sk[(size_t)uyc * N];
-                    p2[c][q] = ldg(sc.P2, (size_t)uyc * Nw + uxc);
+                    for (int q = 0; q < R; ++q) {
+                        const int uy = y0 + q - u_py[k];
+                        in[c][q] = inx && q < rows && uy >= 0 && uy < Nw;
+                        const int uyc = min(max(uy, 0), Nw - 1);
+                        wv[c][q] = Sk[(size_t)uyc * N];
+                        p2[c][q] = ldg(sc.P2, (size_t)uyc * Nw + uxc);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        in[c][q] = false;
+                        wv[c][q] = make_float2(0.f, 0.f);
+                        p2[c][q] = 0.f;
+                    }
                 }
             }
 #pragma unroll
             for (int c = 0; c < kObjRowChunk; ++c)
 #pragma unroll
-                for (int q = 0; q < R; ++q)
-                    if (in[c][q]) {
-                        num[q] = cadd(num[q], wv[c][q]);
-                        den[q] += (double)(a * p2[c][q]) + cst;
-                    }
+                for (int q = 0; q < R; ++q) {
+                    const bool u = in[c][q];
+                    num[q] = cadd(num[q], u ? wv[c][q] : make_float2(0.f, 0.f));
+                    den[q] += u ? (double)(a * p2[c][q]) + cst : 0.0;
+                }
         }
 #pragma unroll
         for (int q = 0; q < R; ++q) {
@@ -176,7 +188,7 @@ k_obj_rows(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots_
                 const float inv = (float)(1.0 / den[q]);  // the float64 denominator, inverted once
                 v.x = fmaf(num[q].x, inv, v.x);
                 v.y = fmaf(num[q].y, inv, v.y);
-                sc.O[(size_t)(y0 + q) * Mx + xx] = v;
+                st_dev(sc.O, (size_t)(y0 + q) * Mx + xx, v);
             }
             orow[q][xi] = v;
         }
@@ -211,16 +223,16 @@ k_obj_rows(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots_
             x[idx] = in ? cmul(p[idx], o) : make_float2(0.f, 0.f);
             mO = fmaxf(mO, in ? cabs2(o) : 0.f);
         }
-        fft_line<N, false>(x, t, lds, RowLds<N>(line), tw);
+        fft_line<N, false>(x, t, lds, RowLdsWave<N>(line), tw);
         if (live) {
             float2* row = S_f + ((size_t)f_slot[e] * N + r) * N;
 #pragma unroll
-            for (int idx = 0; idx < V; ++idx) row[out_pos<N, false>(t, idx)] = x[idx];
+            for (int idx = 0; idx < V; ++idx) st_dev(row, out_pos<N, false>(t, idx), x[idx]);
         }
         // maximum over the line's T lanes (consecutive lanes of one wave)
 #pragma unroll
         for (int o = T / 2; o > 0; o >>= 1) mO = fmaxf(mO, __shfl_xor(mO, o, 64));
-        if (live && t == 0) maxO2_part[(size_t)f_slot[e] * Nw + r] = mO;
+        if (live && t == 0) st_dev(maxO2_part, (size_t)f_slot[e] * Nw + r, mO);
     }
 }
 

@@ -76,7 +76,9 @@ __device__ __forceinline__ int tile_window_list(const SlotDev* __restrict__ slot
 // inverse row pass) and, from the batch-start probe intensity P2 = |P|^2,
 //   rPIE: d_O = (1 - alpha) P2 + alpha max P2;  ePIE: d_O = max P2 / alpha.
 // Each thread owns one column and kObjRows rows of a 16 x 64 tile; the loads
-// of a chunk of windows are all issued before any is used.
+// of a chunk of windows are all issued before any is used.  Slots of a chunk
+// past the tile's window count (uniform over the block) issue no loads, and
+// pixels outside a window add zero rather than branch.
 __global__ void __launch_bounds__(kObjThreads)
 k_object_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots,
                 const GroupDev* __restrict__ groups, int ngroups, const float2* __restrict__ S, int N,
@@ -119,33 +121,43 @@ k_object_update(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ s
         den[q] = 0.0;
     }
     for (int k0 = 0; k0 < cnt; k0 += kObjChunk) {
+        const int nc = min(kObjChunk, cnt - k0);  // uniform over the block
         float2 w[kObjChunk][kObjRows];
         float p2[kObjChunk][kObjRows];
         bool in[kObjChunk][kObjRows];
 #pragma unroll
         for (int c = 0; c < kObjChunk; ++c) {
-            const int k = min(k0 + c, cnt - 1);
-            const int ux = xx - l_px[k];
-            const bool inx = k0 + c < cnt && ux >= 0 && ux < Nw;
-            const int uxc = min(max(ux, 0), Nw - 1);
-            const float2* Sk = S + (size_t)l_slot[k] * N * N + uxc;
+            if (c < nc) {
+                const int k = k0 + c;
+                const int ux = xx - l_px[k];
+                const bool inx = ux >= 0 && ux < Nw;
+                const int uxc = min(max(ux, 0), Nw - 1);
+                const float2* Sk = S + (size_t)l_slot[k] * N * N + uxc;
 #pragma unroll
-            for (int q = 0; q < kObjRows; ++q) {
-                const int uy = yb + q - l_py[k];
-                in[c][q] = inx && uy >= 0 && uy < Nw;
-                const int uyc = min(max(uy, 0), Nw - 1);
-                w[c][q] = Sk[(size_t)uyc * N];
-                p2[c][q] = ldg(P2, (size_t)uyc * Nw + uxc);
+                for (int q = 0; q < kObjRows; ++q) {
+                    const int uy = yb + q - l_py[k];
+                    in[c][q] = inx && uy >= 0 && uy < Nw;
+                    const int uyc = min(max(uy, 0), Nw - 1);
+                    w[c][q] = Sk[(size_t)uyc * N];
+                    p2[c][q] = ldg(P2, (size_t)uyc * Nw + uxc);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < kObjRows; ++q) {
+                    in[c][q] = false;
+                    w[c][q] = make_float2(0.f, 0.f);
+                    p2[c][q] = 0.f;
+                }
             }
         }
 #pragma unroll
         for (int c = 0; c < kObjChunk; ++c)
 #pragma unroll
-            for (int q = 0; q < kObjRows; ++q)
-                if (in[c][q]) {
-                    num[q] = cadd(num[q], w[c][q]);
-                    den[q] += (double)(a * p2[c][q]) + cst;
-                }
+            for (int q = 0; q < kObjRows; ++q) {
+                const bool u = in[c][q];
+                num[q] = cadd(num[q], u ? w[c][q] : make_float2(0.f, 0.f));
+                den[q] += u ? (double)(a * p2[c][q]) + cst : 0.0;
+            }
     }
     if (xx >= sc.bx0 + sc.bw) return;
     // the object values are read together (rows clamped into the box), then
@@ -191,29 +203,37 @@ k_grad_object(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slo
         any[q] = false;
     }
     for (int k0 = 0; k0 < cnt; k0 += kObjChunk) {
+        const int nc = min(kObjChunk, cnt - k0);  // uniform over the block
         float2 w[kObjChunk][kObjRows];
         bool in[kObjChunk][kObjRows];
 #pragma unroll
         for (int c = 0; c < kObjChunk; ++c) {
-            const int k = min(k0 + c, cnt - 1);
-            const int ux = xx - l_px[k];
-            const bool inx = k0 + c < cnt && ux >= 0 && ux < Nw;
-            const float2* Sk = S + (size_t)l_slot[k] * N * N + min(max(ux, 0), Nw - 1);
+            if (c < nc) {
+                const int k = k0 + c;
+                const int ux = xx - l_px[k];
+                const bool inx = ux >= 0 && ux < Nw;
+                const float2* Sk = S + (size_t)l_slot[k] * N * N + min(max(ux, 0), Nw - 1);
 #pragma unroll
-            for (int q = 0; q < kObjRows; ++q) {
-                const int uy = yb + q - l_py[k];
-                in[c][q] = inx && uy >= 0 && uy < Nw;
-                w[c][q] = Sk[(size_t)min(max(uy, 0), Nw - 1) * N];
+                for (int q = 0; q < kObjRows; ++q) {
+                    const int uy = yb + q - l_py[k];
+                    in[c][q] = inx && uy >= 0 && uy < Nw;
+                    w[c][q] = Sk[(size_t)min(max(uy, 0), Nw - 1) * N];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < kObjRows; ++q) {
+                    in[c][q] = false;
+                    w[c][q] = make_float2(0.f, 0.f);
+                }
             }
         }
 #pragma unroll
         for (int c = 0; c < kObjChunk; ++c)
 #pragma unroll
-            for (int q = 0; q < kObjRows; ++q)
-                if (in[c][q]) {
-                    acc[q] = cadd(acc[q], w[c][q]);
-                    any[q] = true;
-                }
+            for (int q = 0; q < kObjRows; ++q) {
+                acc[q] = cadd(acc[q], in[c][q] ? w[c][q] : make_float2(0.f, 0.f));
+                any[q] = any[q] || in[c][q];
+            }
     }
     if (xx >= sc.bx0 + sc.bw) return;
     float2 gv[kObjRows];
@@ -222,7 +242,7 @@ k_grad_object(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slo
 #pragma unroll
     for (int q = 0; q < kObjRows; ++q) {
         const int yy = yb + q;
-        if (yy < sc.by0 + sc.bh && any[q]) sc.gO[(size_t)yy * sc.Mx + xx] = cadd(gv[q], acc[q]);
+        if (yy < sc.by0 + sc.bh && any[q]) st_dev(sc.gO, (size_t)yy * sc.Mx + xx, cadd(gv[q], acc[q]));
     }
 }
 
