@@ -46,7 +46,10 @@ ePIE iterations reach on each).
 
 Roofline: achieved = (algorithmic bytes per position update, 20 N^2 + 16 N^2 / B)
 x (positions one launch of the dominant kernel processes) / (its mean launch
-duration, HIP events on the launch stream over the timed region).  traffic =
+duration, HIP events on the launch stream over the timed region, around
+every k-th launch of that kernel, k <= 16 leaving at least 64 timed launches:
+an event pair costs the queue a few microseconds, which timing every launch
+would add to the step).  traffic =
 counter-measured bytes per launch of that kernel from profiles/, or null when
 the kernel sources changed since the counters were taken.
 
@@ -217,6 +220,18 @@ def cpu_baseline_all_cores(w, O_true, P, clean, scale, seconds: float):
     return n / dt, n, dt, workers
 
 
+# In a timed region the dominant kernel's launch durations come from HIP
+# events recorded around every k-th launch of it (the first included): each
+# timed launch costs the queue a few microseconds of event work, which
+# bracketing every launch would add to the step time.  k is at most
+# TIMING_PERIOD and leaves at least 64 timed launches.
+TIMING_PERIOD = 16
+
+
+def timing_period(expected_launches):
+    return max(1, min(TIMING_PERIOD, int(expected_launches) // 64))
+
+
 def profile_dominant(api, run_step, classes):
     """Time one step with events around every launch of `classes`; return the
     dominant class and the per-class (launches, ms)."""
@@ -233,7 +248,7 @@ def profile_dominant(api, run_step, classes):
 
 
 def roofline(dominant, nlaunch, kms, positions_per_launch, N, B, counters=True, updates_per_step=None,
-             ms_per_step=None):
+             ms_per_step=None, timed_every=1):
     """`counters`: the stored counter readings describe this launch (the
     integer-position lab workload).  With the step's updates and duration the
     entry also carries pipeline_frac: the whole step's algorithmic bytes per
@@ -247,7 +262,7 @@ def roofline(dominant, nlaunch, kms, positions_per_launch, N, B, counters=True, 
     out = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
            "traffic": None if traffic is None else round(traffic),
-           "avg_launch_us": round(avg_us, 2), "launches": nlaunch,
+           "avg_launch_us": round(avg_us, 2), "launches": nlaunch, "timed_every": timed_every,
            "algorithmic_bytes_per_launch": round(bytes_launch)}
     if updates_per_step and ms_per_step:
         gbs = algo_bytes_per_update(N, B) * updates_per_step / (ms_per_step * 1e-3) / 1e9
@@ -323,8 +338,10 @@ def run_lab(args, api, synth, dev):
           ", ".join(f"{k} {v[1]:.2f} ({v[0]})" for k, v in ranks.items()), file=sys.stderr, flush=True)
     for _ in range(args.warmup - 1):
         step()
-    # timed region: events bracket only the dominant kernel's launches
-    api.profile([dominant])
+    # timed region: events bracket a sample of the dominant kernel's launches
+    # (all of them for the single-workgroup run: one launch per call)
+    every = 1 if dominant == "small_run" else timing_period(ranks[dominant][0] * args.steps)
+    api.profile([dominant], every=every)
     api.profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -371,7 +388,8 @@ def run_lab(args, api, synth, dev):
         "config": {"workload": wl, "positions": w.J, "pattern": w.Nd, "batch": w.batch, "iterations": n_iter,
                    "exposures": len(w.t), "levels": w.levels},
         "roofline": roofline(dominant, nlaunch, kms, per_launch, w.Nd, w.batch, counters=not (sub or small),
-                             updates_per_step=w.J * n_iter, ms_per_step=dt * 1e3),
+                             updates_per_step=w.J * n_iter, ms_per_step=dt * 1e3,
+                             timed_every=1 if graph else every),
         "per_class_ms_one_step": {k: round(v[1], 3) for k, v in ranks.items()},
         "launch_variants": tuned,
         "graph": graph,
@@ -447,7 +465,8 @@ def run_grad(args, api, synth, dev):
         losses.append(loss_w)
         eta_O, eta_P = (float(x) for x in eta.cpu().tolist())
     dominant = max(classes[:4], key=lambda k: ranks[k][1])
-    api.profile([dominant])
+    every = timing_period(ranks[dominant][0] * args.steps)
+    api.profile([dominant], every=every)
     api.profile_reset()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -486,7 +505,7 @@ def run_grad(args, api, synth, dev):
                                "backtracking"},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "avg_launch_us": round(avg_us, 2), "launches": nlaunch,
+                     "avg_launch_us": round(avg_us, 2), "launches": nlaunch, "timed_every": every,
                      "algorithmic_bytes_per_launch": round(bytes_pos * per_launch),
                      "pipeline_achieved": round(pipe, 1), "pipeline_frac": round(pipe / HBM_PEAK_GBS, 4)},
         "per_class_ms_one_step": {k: round(v[1], 3) for k, v in ranks.items()},

@@ -472,8 +472,16 @@ int mnf_get_variant(mnf_ctx* ctx, int Nd);
  * 10 shift (Fourier translation of probes), 11 small_run (a whole run of
  * mini-batches of one in one workgroup).  mask 0 disables timing.
  * mnf_profile_read waits for the recorded events and returns the launch
- * count and summed duration (ms) of class cls since the last reset. */
+ * count and summed duration (ms) of class cls since the last reset.
+ *
+ * mnf_profile_sampled times only every period-th launch of each class in
+ * the mask (the first, then every period-th after it, counted per class
+ * from the last reset); mnf_profile_read then counts and sums the timed
+ * launches only, so total_ms / launches stays the mean duration of a launch
+ * while the events' own cost (a few microseconds per timed launch) falls by
+ * the period.  period < 1: MNF_EINVAL.  mnf_profile resets the period to 1. */
 int mnf_profile(mnf_ctx* ctx, uint32_t class_mask);
+int mnf_profile_sampled(mnf_ctx* ctx, uint32_t class_mask, int period);
 int mnf_profile_read(mnf_ctx* ctx, int cls, long long* launches, double* total_ms);
 int mnf_profile_reset(mnf_ctx* ctx);
 const char* mnf_kernel_class_name(int cls);

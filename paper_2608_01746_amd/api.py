@@ -434,15 +434,20 @@ def check_status(device="cuda:0") -> None:
 
 # ------------------------------------------------------------ launch timing
 
-def profile(classes, device="cuda:0") -> None:
-    """Time every launch of the named kernel classes with HIP events
-    (empty / None disables)."""
+def profile(classes, device="cuda:0", every: int = 1) -> None:
+    """Time the launches of the named kernel classes with HIP events (empty /
+    None disables): every launch, or with `every` > 1 the first and then
+    every `every`-th launch of each class (profile_read then reports the
+    timed launches only)."""
     mask = 0
     for c in classes or ():
         mask |= 1 << _L.KERNEL_CLASSES.index(c)
     dev = torch.device(device)
     ctx = _ctx(dev)
-    _check(_L.load().mnf_profile(ctx, mask), ctx)
+    if every == 1:
+        _check(_L.load().mnf_profile(ctx, mask), ctx)
+    else:
+        _check(_L.load().mnf_profile_sampled(ctx, mask, int(every)), ctx)
 
 
 def profile_reset(device="cuda:0") -> None:

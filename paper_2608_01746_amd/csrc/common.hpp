@@ -32,6 +32,8 @@ enum MnfKernelClass {
 
 struct MnfProfile {
     uint32_t mask = 0;
+    int period = 1;                          // time every period-th launch of a class
+    long long seen[MNF_K_NCLASS] = {};       // launches of each class since the last reset
     std::vector<hipEvent_t> pool;
     struct Pending { int cls; hipEvent_t a, b; };
     std::vector<Pending> pending;
@@ -125,9 +127,16 @@ int noalloc_setup(mnf_ctx* ctx);
 int prof_pair(mnf_ctx* ctx, hipEvent_t* e0, hipEvent_t* e1);
 void prof_push(mnf_ctx* ctx, int cls, hipEvent_t e0, hipEvent_t e1);
 
+// Whether this launch of class `cls` is one to time (every period-th one,
+// the first included).
+inline bool prof_take(mnf_ctx* ctx, int cls) {
+    if (!(ctx->prof.mask & (1u << cls))) return false;
+    return ctx->prof.seen[cls]++ % ctx->prof.period == 0;
+}
+
 #define MNF_LAUNCH(ctx, cls, st, kernel, grid, block, ...)                                   \
     do {                                                                                     \
-        if ((ctx)->prof.mask & (1u << (cls))) {                                              \
+        if (::mnf::prof_take((ctx), (cls))) {                                                \
             hipEvent_t e0_ = nullptr, e1_ = nullptr;                                         \
             MNF_TRY(::mnf::prof_pair((ctx), &e0_, &e1_));                                    \
             hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0_, e1_, 0, __VA_ARGS__);     \

@@ -152,6 +152,15 @@ static const char* kClassNames[MNF_K_NCLASS] = {
 int mnf_profile(mnf_ctx* ctx, uint32_t class_mask) {
     MNF_TRY(mnf::begin(ctx));
     ctx->prof.mask = class_mask;
+    ctx->prof.period = 1;
+    return MNF_OK;
+}
+
+int mnf_profile_sampled(mnf_ctx* ctx, uint32_t class_mask, int period) {
+    MNF_TRY(mnf::begin(ctx));
+    if (period < 1) return mnf::set_error(ctx, MNF_EINVAL, "sampling period %d (must be >= 1)", period);
+    ctx->prof.mask = class_mask;
+    ctx->prof.period = period;
     return MNF_OK;
 }
 
@@ -170,6 +179,7 @@ int mnf_profile_reset(mnf_ctx* ctx) {
     for (int i = 0; i < MNF_K_NCLASS; ++i) {
         ctx->prof.launches[i] = 0;
         ctx->prof.ms[i] = 0.0;
+        ctx->prof.seen[i] = 0;
     }
     return MNF_OK;
 }

@@ -99,6 +99,7 @@ SIGNATURES = {
     "mnf_set_variant": (c_int, [c_void_p, c_int, c_int]),
     "mnf_get_variant": (c_int, [c_void_p, c_int]),
     "mnf_profile": (c_int, [c_void_p, ctypes.c_uint32]),
+    "mnf_profile_sampled": (c_int, [c_void_p, ctypes.c_uint32, c_int]),
     "mnf_profile_read": (c_int, [c_void_p, c_int, POINTER(ctypes.c_longlong), POINTER(c_double)]),
     "mnf_profile_reset": (c_int, [c_void_p]),
     "mnf_kernel_class_name": (ctypes.c_char_p, [c_int]),
