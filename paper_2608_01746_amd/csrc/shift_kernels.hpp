@@ -72,10 +72,10 @@ k_shift_rows(const float2* src, size_t src_stride, float2* dst, const float2* __
     const float d = sign * frac[s].y;  // uniform over the block
     twr.store(tw);
     __syncthreads();
-    if (d != 0.f) shift_regs<N>(x, d, t, lds, RowLds<N>(line), tw);
+    if (d != 0.f) shift_regs<N>(x, d, t, lds, RowLdsWave<N>(line), tw);
     float2* row = dst + ((size_t)s * N + y) * N;
 #pragma unroll
-    for (int idx = 0; idx < V; ++idx) row[out_pos<N, true>(t, idx)] = x[idx];
+    for (int idx = 0; idx < V; ++idx) st_dev(row, out_pos<N, true>(t, idx), x[idx]);
 }
 
 // grid (N / C, nslots).  dst[s] column kx = column kx of src[s] translated
@@ -102,7 +102,7 @@ k_shift_cols(const float2* src, size_t src_stride, float2* dst, const float2* __
     __syncthreads();
     if (d != 0.f) shift_regs<N>(x, d, t, lds, ColLds<C>(c), tw);
 #pragma unroll
-    for (int idx = 0; idx < V; ++idx) col[(size_t)out_pos<N, true>(t, idx) * N] = x[idx];
+    for (int idx = 0; idx < V; ++idx) st_dev(col, (size_t)out_pos<N, true>(t, idx) * N, x[idx]);
 }
 
 // grid (ceil(N^2 / 256), ngroups).  Probe update at real positions: G[s]
@@ -134,7 +134,7 @@ k_probe_sum_update(const float2* __restrict__ G, const GroupDev* __restrict__ gr
     const float inv = (float)(1.0 / den);  // the float64 denominator, inverted once
     p.x = fmaf(acc.x, inv, p.x);
     p.y = fmaf(acc.y, inv, p.y);
-    P[q] = p;
+    st_dev(P, q, p);
 }
 
 }  // namespace mnf
