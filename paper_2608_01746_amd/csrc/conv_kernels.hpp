@@ -1099,33 +1099,45 @@ __global__ void __launch_bounds__(256) k_wgrad_c1(WgradArgs a, int per) {
 //   kind 2: Bt[tap][co][ci]       = W[tap][ci][co]            (forward UP)
 //   kind 3: Bt[tap][ci][co]       = W[tap][ci][co]            (input gradient of DOWN, as UP)
 //   kind 4: Bt[ci][tap * Co + co] = W[tap][ci][co]            (input gradient of UP / CONV1, as DOWN / CONV1)
-// Rows are padded with zeros to Kpad.
-__global__ void k_prep_weights(const float* __restrict__ W, int taps, int Ci, int Co, int kind, int Kpad,
-                               uint16_t* __restrict__ Bt) {
-    const size_t total = (kind == 2 || kind == 3) ? (size_t)taps * (kind == 2 ? Co : Ci) * Kpad
-                                                  : (size_t)(kind == 0 ? Co : Ci) * Kpad;
-    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const int k = (int)(i % Kpad);
-    const size_t row = i / Kpad;
-    float v = 0.f;
-    if (kind == 0) {
-        const int co = (int)row;
-        if (k < taps * Ci) v = W[((size_t)(k / Ci) * Ci + k % Ci) * Co + co];
-    } else if (kind == 1 || kind == 4) {
-        const int ci = (int)row;
-        if (k < taps * Co) {
-            const int tap = kind == 1 ? taps - 1 - k / Co : k / Co;
-            v = W[((size_t)tap * Ci + ci) * Co + k % Co];
+// Rows are padded with zeros to Kpad.  Every array of a network is packed by
+// one launch (a job per array, passed by value): blockIdx.y is the job, the
+// blocks along x stride over its elements.
+struct PrepJob {
+    const float* W;
+    uint16_t* Bt;
+    unsigned long long total;  // elements of Bt
+    int taps, Ci, Co, kind, Kpad, pad_;
+};
+constexpr int kMaxPrepJobs = 48;
+struct PrepJobs {
+    PrepJob j[kMaxPrepJobs];
+};
+
+__global__ void __launch_bounds__(256) k_prep_weights(const PrepJobs jobs) {
+    const PrepJob J = jobs.j[blockIdx.y];
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < J.total; i += (size_t)gridDim.x * blockDim.x) {
+        const int k = (int)(i % J.Kpad);
+        const size_t row = i / J.Kpad;
+        const int taps = J.taps, Ci = J.Ci, Co = J.Co;
+        float v = 0.f;
+        if (J.kind == 0) {
+            const int co = (int)row;
+            if (k < taps * Ci) v = J.W[((size_t)(k / Ci) * Ci + k % Ci) * Co + co];
+        } else if (J.kind == 1 || J.kind == 4) {
+            const int ci = (int)row;
+            if (k < taps * Co) {
+                const int tap = J.kind == 1 ? taps - 1 - k / Co : k / Co;
+                v = J.W[((size_t)tap * Ci + ci) * Co + k % Co];
+            }
+        } else if (J.kind == 2) {
+            const int tap = (int)(row / Co), co = (int)(row % Co);
+            if (k < Ci) v = J.W[((size_t)tap * Ci + k) * Co + co];
+        } else {
+            const int tap = (int)(row / Ci), ci = (int)(row % Ci);
+            if (k < Co) v = J.W[((size_t)tap * Ci + ci) * Co + k];
         }
-    } else if (kind == 2) {
-        const int tap = (int)(row / Co), co = (int)(row % Co);
-        if (k < Ci) v = W[((size_t)tap * Ci + k) * Co + co];
-    } else {
-        const int tap = (int)(row / Ci), ci = (int)(row % Ci);
-        if (k < Co) v = W[((size_t)tap * Ci + ci) * Co + k];
+        J.Bt[i] = f2bf(v);
     }
-    Bt[i] = f2bf(v);
 }
 
 }  // namespace mnf

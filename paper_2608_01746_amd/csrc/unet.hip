@@ -10,6 +10,7 @@
 // order.  Activations and gradients are bf16, channels last; the
 // concatenation is a shared 2*c2-channel buffer written in place by its two
 // producers.
+#include <algorithm>
 #include <cmath>
 #include <string>
 #include <vector>
@@ -200,8 +201,9 @@ ConvArgs dgrad_args(int mode, View dY, View act, bool mask, int n, int Hout, int
     return a;
 }
 
-// bf16 weights for the forward and input-gradient GEMMs of a layer.
-int prep_layer_weights(mnf_ctx* ctx, const LayerDesc& L, const float* W, uint16_t* Bf, uint16_t* Bd, hipStream_t st) {
+// bf16 weights for the forward and input-gradient GEMMs of a layer: its
+// packing jobs are appended to `jobs` (Bd may be null).
+void layer_prep_jobs(const LayerDesc& L, const float* W, uint16_t* Bf, uint16_t* Bd, std::vector<PrepJob>& jobs) {
     const int taps = taps_of(L.mode);
     int kf, kd, Kf, Kd;
     size_t nf, nd;
@@ -227,9 +229,31 @@ int prep_layer_weights(mnf_ctx* ctx, const LayerDesc& L, const float* W, uint16_
             nf = (size_t)L.co * Kf; nd = (size_t)L.ci * Kd;
             break;
     }
-    hipLaunchKernelGGL(k_prep_weights, dim3(g1(nf)), dim3(256), 0, st, W, taps, L.ci, L.co, kf, Kf, Bf);
-    if (Bd) hipLaunchKernelGGL(k_prep_weights, dim3(g1(nd)), dim3(256), 0, st, W, taps, L.ci, L.co, kd, Kd, Bd);
+    jobs.push_back(PrepJob{W, Bf, (unsigned long long)nf, taps, L.ci, L.co, kf, Kf, 0});
+    if (Bd) jobs.push_back(PrepJob{W, Bd, (unsigned long long)nd, taps, L.ci, L.co, kd, Kd, 0});
+}
+
+// One launch packing every job (in groups of kMaxPrepJobs).
+int launch_prep(mnf_ctx* ctx, const std::vector<PrepJob>& jobs, hipStream_t st) {
+    for (size_t j0 = 0; j0 < jobs.size(); j0 += kMaxPrepJobs) {
+        const int n = (int)std::min<size_t>(kMaxPrepJobs, jobs.size() - j0);
+        PrepJobs pj{};
+        size_t most = 1;
+        for (int j = 0; j < n; ++j) {
+            pj.j[j] = jobs[j0 + j];
+            most = std::max<size_t>(most, jobs[j0 + j].total);
+        }
+        const unsigned gx = (unsigned)std::min<size_t>(256, (most + 255) / 256);
+        hipLaunchKernelGGL(k_prep_weights, dim3(gx, n), dim3(256), 0, st, pj);
+    }
+    MNF_CHECK_LAUNCH(ctx);
     return MNF_OK;
+}
+
+int prep_layer_weights(mnf_ctx* ctx, const LayerDesc& L, const float* W, uint16_t* Bf, uint16_t* Bd, hipStream_t st) {
+    std::vector<PrepJob> jobs;
+    layer_prep_jobs(L, W, Bf, Bd, jobs);
+    return launch_prep(ctx, jobs, st);
 }
 
 size_t bf_size(const LayerDesc& L) {
@@ -512,8 +536,9 @@ int net_forward(mnf_ctx* ctx, Net& net, const float* params, const float* I, flo
                 hipStream_t st) {
     const size_t nx = (size_t)net.n * net.H * net.H;
     hipLaunchKernelGGL(k_log_input, dim3(g1(nx)), dim3(256), 0, st, I, nx, log_scale, net.x.p);
-    for (size_t i = 0; i < net.L.size(); ++i)
-        MNF_TRY(prep_layer_weights(ctx, net.L[i], params + net.woff[i], net.Bf[i], net.Bd[i], st));
+    std::vector<PrepJob> jobs;
+    for (size_t i = 0; i < net.L.size(); ++i) layer_prep_jobs(net.L[i], params + net.woff[i], net.Bf[i], net.Bd[i], jobs);
+    MNF_TRY(launch_prep(ctx, jobs, st));
     View in = net.x;
     for (size_t i = 0; i < net.L.size(); ++i) {
         const LayerDesc& L = net.L[i];
