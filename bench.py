@@ -47,7 +47,7 @@ ePIE iterations reach on each).
 Roofline: achieved = (algorithmic bytes per position update, 20 N^2 + 16 N^2 / B)
 x (positions one launch of the dominant kernel processes) / (its mean launch
 duration, HIP events on the launch stream over the timed region, around
-every k-th launch of that kernel, k <= 16 leaving at least 64 timed launches:
+every k-th launch of that kernel, k <= 64 leaving at least 64 timed launches:
 an event pair costs the queue a few microseconds, which timing every launch
 would add to the step).  traffic =
 counter-measured bytes per launch of that kernel from profiles/, or null when
@@ -225,7 +225,7 @@ def cpu_baseline_all_cores(w, O_true, P, clean, scale, seconds: float):
 # timed launch costs the queue a few microseconds of event work, which
 # bracketing every launch would add to the step time.  k is at most
 # TIMING_PERIOD and leaves at least 64 timed launches.
-TIMING_PERIOD = 16
+TIMING_PERIOD = 64
 
 
 def timing_period(expected_launches):
