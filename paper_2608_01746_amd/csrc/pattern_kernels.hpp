@@ -125,17 +125,31 @@ __device__ __forceinline__ float2 col_pointwise(float2 v, float Iq, float eps, f
         accf += d * d;  // a thread's V terms in float32, then float64 across threads
         return nz ? cscale(v, a * r) : make_float2(a, 0.f);
     } else if constexpr (OP == ColOp::PoissonGrad) {
-        // l = |Psi|^2 - I ln(|Psi|^2 + eps); g = 2 (1 - I / (|Psi|^2 + eps)) Psi
+        // l = |Psi|^2 - I ln(|Psi|^2 + eps); g = 2 (1 - I / (|Psi|^2 + eps)) Psi.
+        // One hardware log2 (about 1 ulp) times ln 2 and one hardware
+        // reciprocal (about 1 ulp) replace the library logarithm and the
+        // correctly rounded quotient, which made this pass bound by their
+        // arithmetic at 512^2.  A subnormal q (only with eps below the
+        // smallest normal float) is scaled by 2^32 first, as the hardware
+        // instructions take normal inputs.
         const float I = fmaxf(Iq, 0.f);
-        acc += (double)(m2 - I * logf(m2 + eps));
-        return cscale(v, 2.f * (1.f - I / (m2 + eps)));
+        const float q = m2 + eps;
+        const bool sub = q < 1.17549435e-38f;
+        const float qs = sub ? q * 4294967296.f : q;
+        const float lg = (__builtin_amdgcn_logf(qs) - (sub ? 32.f : 0.f)) * 0.693147180559945309f;
+        const float rq = __builtin_amdgcn_rcpf(qs) * (sub ? 4294967296.f : 1.f);
+        acc += (double)(m2 - I * lg);
+        return cscale(v, 2.f * (1.f - I * rq));
     } else {
-        // l = (|Psi| - sqrt I)^2; g = 2 (Psi - sqrt(I) Psi / |Psi|)
+        // l = (|Psi| - sqrt I)^2; g = 2 (Psi - sqrt(I) Psi / |Psi|), with one
+        // hardware reciprocal square root r ~ 1/|Psi| giving |Psi| = |Psi|^2 r
+        // and sqrt(I) / |Psi| = sqrt(I) r
         const float a = sqrtf(fmaxf(Iq, 0.f));
-        const float mag = sqrtf(m2);
-        const float d = mag - a;
+        const bool nz = m2 > 1e-30f;
+        const float r = __builtin_amdgcn_rsqf(nz ? m2 : 1.f);
+        const float d = (nz ? m2 * r : 0.f) - a;
         accf += d * d;
-        const float f = m2 > 1e-30f ? 2.f * (1.f - a / mag) : 2.f;
+        const float f = nz ? 2.f * (1.f - a * r) : 2.f;
         return cscale(v, f);
     }
 }
