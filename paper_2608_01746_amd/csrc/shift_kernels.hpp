@@ -19,13 +19,14 @@
 
 namespace mnf {
 
-// exp(-2 pi i k' d / N), k' the signed frequency of FFT-order index k
+// exp(-2 pi i k' d / N), k' the signed frequency of FFT-order index k.  The
+// angle in turns, -k' d / N, lies in [-1/4, 1/4] (|k'| <= N/2, |d| <= 1/2);
+// the hardware sine and cosine take turns directly.
 template <int N>
 __device__ __forceinline__ float2 shift_ramp(int k, float d) {
     const int ks = k < N / 2 ? k : k - N;
-    float s, c;
-    sincospif(-2.f * (float)ks * d / (float)N, &s, &c);
-    return make_float2(c, s);
+    const float turns = -(float)ks * d * (1.f / (float)N);
+    return make_float2(__builtin_amdgcn_cosf(turns), __builtin_amdgcn_sinf(turns));
 }
 
 // A line held in registers at the positions in_pos<N, false> (the same as
