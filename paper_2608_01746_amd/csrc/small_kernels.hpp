@@ -43,12 +43,18 @@ template <int N>
 __device__ __forceinline__ int small_at(int y, int x) {
     return y * SmallCfg<N>::S + x + (x >> 4);
 }
+// A row of the tile as a transform's exchange space.  A row's T threads lie
+// in one wavefront (line = threadIdx / T, T divides 64) and its region of
+// the tile is touched by them alone between the block barriers around a row
+// pass, so the stage exchanges synchronise the wavefront only (as
+// RowLdsWave does).
 template <int N>
 struct SmallRow {
+    static_assert(64 % PlanInfo<N>::T == 0, "a row must not span wavefronts");
     int row;
     __device__ __forceinline__ explicit SmallRow(int r) : row(r) {}
     __device__ __forceinline__ int operator()(int p) const { return small_at<N>(row, p); }
-    static __device__ __forceinline__ void sync() { __syncthreads(); }
+    static __device__ __forceinline__ void sync() { RowLdsWave<N>::sync(); }
 };
 template <int N>
 struct SmallCol {
@@ -155,6 +161,7 @@ k_small_run(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots
                 float2 x[V];
 #pragma unroll
                 for (int idx = 0; idx < V; ++idx) x[idx] = X[small_at<N>(row, in_pos<N, false>(t, idx))];
+                SmallRow<N>::sync();  // the row is read before its first exchange overwrites it
                 fft_line<N, false>(x, t, X, SmallRow<N>(row), tw);
 #pragma unroll
                 for (int idx = 0; idx < V; ++idx) X[small_at<N>(row, out_pos<N, false>(t, idx))] = x[idx];
@@ -188,6 +195,7 @@ k_small_run(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots
                 float2 x[V];
 #pragma unroll
                 for (int idx = 0; idx < V; ++idx) x[idx] = X[small_at<N>(row, in_pos<N, true>(t, idx))];
+                SmallRow<N>::sync();  // the row is read before its first exchange overwrites it
                 fft_line<N, true>(x, t, X, SmallRow<N>(row), tw);
 #pragma unroll
                 for (int idx = 0; idx < V; ++idx) X[small_at<N>(row, out_pos<N, true>(t, idx))] = x[idx];
