@@ -46,6 +46,11 @@ __device__ __forceinline__ float2 ldg(const float2* p, size_t i) {
     return make_float2(v.x, v.y);
 }
 
+// Amplitude sqrt(max(I, 0)) of an intensity: the hardware square root
+// (about 1 ulp), the same in every kernel that forms amplitudes, so the
+// precomputed and the on-the-fly amplitudes agree bit for bit.
+__device__ __forceinline__ float amplitude_of(float I) { return __builtin_amdgcn_sqrtf(fmaxf(I, 0.f)); }
+
 // Stores of results that a later kernel reads.  The L2 of one XCD is not
 // coherent with the other seven, so the release at the end of a kernel
 // writes back every line its waves left dirty, after the last wave and while

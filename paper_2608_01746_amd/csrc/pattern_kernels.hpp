@@ -144,7 +144,7 @@ __device__ __forceinline__ float2 col_pointwise(float2 v, float Iq, float eps, f
         // l = (|Psi| - sqrt I)^2; g = 2 (Psi - sqrt(I) Psi / |Psi|), with one
         // hardware reciprocal square root r ~ 1/|Psi| giving |Psi| = |Psi|^2 r
         // and sqrt(I) / |Psi| = sqrt(I) r
-        const float a = sqrtf(fmaxf(Iq, 0.f));
+        const float a = amplitude_of(Iq);
         const bool nz = m2 > 1e-30f;
         const float r = __builtin_amdgcn_rsqf(nz ? m2 : 1.f);
         const float d = (nz ? m2 * r : 0.f) - a;
@@ -214,7 +214,7 @@ k_cols_pointwise(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ 
         if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(sc.status, kStatusNonFinite);
         if constexpr (OP == ColOp::Modulus) {
 #pragma unroll
-            for (int idx = 0; idx < V; ++idx) Iq[idx] = sqrtf(fmaxf(Iq[idx], 0.f));
+            for (int idx = 0; idx < V; ++idx) Iq[idx] = amplitude_of(Iq[idx]);
         }
     }
 
@@ -305,7 +305,7 @@ k_cols_modulus_modes(const ScanDev* __restrict__ scans, const SlotDev* __restric
 #pragma unroll
         for (int idx = 0; idx < V; ++idx) {
             const int ky = out_pos<N, false>(t, idx);
-            a[idx] = sqrtf(fmaxf(ldg(Ij, (size_t)((ky + N / 2) % N) * N + sx), 0.f));
+            a[idx] = amplitude_of(ldg(Ij, (size_t)((ky + N / 2) % N) * N + sx));
         }
     }
 #pragma unroll

@@ -737,9 +737,9 @@ int run_iterate(mnf_ctx* ctx, const std::vector<ScanIn>& in, int n_iter, const p
     }
     // the amplitudes every iteration projects onto, once per call
     for (int k = 0; k < ns && amp; ++k)
-        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_amplitude_prep,
-                   dim3((unsigned)((in[k].Nd * in[k].Nd + 255) / 256), (unsigned)in[k].J), dim3(256), in[k].I,
-                   in[k].Nd, (float*)pl.scans[k].A, ctx->d_status);
+        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_amplitude_prep, dim3((unsigned)in[k].Nd, (unsigned)in[k].J),
+                   dim3((unsigned)std::min(in[k].Nd, 256)), in[k].I, in[k].Nd, (float*)pl.scans[k].A,
+                   ctx->d_status);
     bool any_err = false;
     for (int k = 0; k < ns; ++k) any_err |= in[k].err_out != nullptr;
     if (any_err) {

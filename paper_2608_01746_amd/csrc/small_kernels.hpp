@@ -138,7 +138,7 @@ k_small_run(const ScanDev* __restrict__ scans, const SlotDev* __restrict__ slots
 #pragma unroll
                 for (int rd = 0; rd < C::ROUNDS; ++rd)
 #pragma unroll
-                    for (int idx = 0; idx < V; ++idx) aq[rd][idx] = sqrtf(fmaxf(aq[rd][idx], 0.f));
+                    for (int idx = 0; idx < V; ++idx) aq[rd][idx] = amplitude_of(aq[rd][idx]);
             }
             mO = wave_max(mO);
             mP = wave_max(mP);

@@ -315,18 +315,22 @@ k_check_finite(const float2* __restrict__ a, size_t n, unsigned* __restrict__ st
 // Amplitudes of the fused intensities in FFT order (the detector-centred
 // patterns shifted by N/2 along both axes):
 //   A[j][ky][kx] = sqrt(max(I[j][(ky + N/2) mod N][(kx + N/2) mod N], 0)).
-// grid (ceil(N*N / 256), J).
+// grid (N, J), min(N, 256) threads: block (ky, j) owns row ky of pattern j,
+// so the source row is one value per block and no thread divides by N.
 // A non-finite intensity sets kStatusNonFinite (its amplitude becomes 0).
 __global__ void __launch_bounds__(256)
 k_amplitude_prep(const float* __restrict__ I, int N, float* __restrict__ A, unsigned* __restrict__ status) {
-    const int q = blockIdx.x * 256 + threadIdx.x;
+    const int ky = blockIdx.x;
+    const int sy = ky + N / 2 < N ? ky + N / 2 : ky - N / 2;
+    const size_t base = (size_t)blockIdx.y * N * N;
+    const float* src = I + base + (size_t)sy * N;
+    float* dst = A + base + (size_t)ky * N;
     bool bad = false;
-    if (q < N * N) {
-        const int ky = q / N, kx = q % N;
-        const size_t base = (size_t)blockIdx.y * N * N;
-        const float v = I[base + (size_t)((ky + N / 2) % N) * N + (kx + N / 2) % N];
-        bad = !isfinite(v);
-        A[base + q] = sqrtf(fmaxf(v, 0.f));
+    for (int kx = threadIdx.x; kx < N; kx += blockDim.x) {
+        const int sx = kx + N / 2 < N ? kx + N / 2 : kx - N / 2;
+        const float v = src[sx];
+        bad |= !isfinite(v);
+        dst[kx] = amplitude_of(v);
     }
     if (__ballot(bad) != 0ull && (threadIdx.x & 63) == 0) atomicOr(status, kStatusNonFinite);
 }
