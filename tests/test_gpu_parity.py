@@ -400,6 +400,23 @@ def test_gradient_matches_oracle(api, kind, Nd, Nw, M, B, J):
     assert rel(gP_g.cpu().numpy(), gP_r) < 1e-5
 
 
+@pytest.mark.parametrize("eps", [0.0, 1e-3])
+def test_poisson_gradient_other_eps(api, eps):
+    """The Poisson loss and gradient with eps = 0 (the log and the quotient of
+    |Psi|^2 alone) and a larger eps, against the oracle's at the same eps."""
+    Nd, Nw, M, B, J = 64, 48, 120, 4, 9
+    rng = np.random.default_rng(77)
+    O = c64(synth.make_object(M, 8) * (1 + 0.05 * rng.standard_normal((M, M))))
+    P = c64(soft_probe(synth.make_probe(Nw, Nw / 3, 1.0), 4))
+    pos = rng.integers(0, M - Nw + 1, size=(J, 2)).astype(np.int32)
+    I = f32(ptycho.forward_intensity(synth.make_object(M, 9), P, pos, Nd) * rng.uniform(0.8, 1.2))
+    loss_r, gO_r, gP_r = adjoint.loss_and_grad(O, P, I, pos, "poisson", eps, upstream=1.0)
+    loss_g, gO_g, gP_g = api.ptycho_grad(tc64(O), tc64(P), tf32(I), pos, "poisson", eps, B)
+    assert np.isfinite(loss_r) and abs(loss_g.item() - loss_r) <= 1e-5 * abs(loss_r) + 1e-3
+    assert rel(gO_g.cpu().numpy(), gO_r) < 1e-5
+    assert rel(gP_g.cpu().numpy(), gP_r) < 1e-5
+
+
 # ---------------------------------------------------------------- descent
 
 def _decisions_are_clear(losses, accepted, guard=2e-7):
