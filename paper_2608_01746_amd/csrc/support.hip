@@ -156,27 +156,97 @@ k_sync_gram(const float* __restrict__ patches, const float2* __restrict__ P, con
 
 // Leading eigenvector of C by power iteration from the all-ones vector (C is
 // positive semidefinite), projected to unit modulus, common phase chosen so
-// that sum_j c_j is real and positive.  One block of 1024 threads, J <= 1024.
+// that sum_j c_j is real and positive.  One block of 64 ceil(J / 64) threads,
+// J <= 1024: with J <= 64 the iterations run in one wavefront.  C is staged in
+// LDS once when it fits (J^2 <= kSyncLds); each iteration then reads only LDS.
+constexpr int kSyncLds = 8192;  // float2 entries of C staged in LDS (J <= 90)
+
 __global__ void __launch_bounds__(1024) k_sync_power(const float2* __restrict__ C, int J, int iters,
                                                      float2* __restrict__ c) {
     __shared__ float2 v[1024];
+    __shared__ float2 Cs[kSyncLds];
     __shared__ float red[16];
     const int t = threadIdx.x;
+    const bool staged = J * J <= kSyncLds;  // uniform over the block
+    if (staged)
+        for (int i = t; i < J * J; i += blockDim.x) Cs[i] = C[i];
     if (t < J) v[t] = make_float2(1.f, 0.f);
     __syncthreads();
     for (int it = 0; it < iters; ++it) {
         float2 acc = make_float2(0.f, 0.f);
         if (t < J) {
-            const float2* row = C + (size_t)t * J;
-            for (int k = 0; k < J; ++k) {
-                const float2 q = cmul(row[k], v[k]);
-                acc.x += q.x;
-                acc.y += q.y;
+            // row t of C times v, in k order (indexing the LDS arrays directly
+            // keeps their reads LDS reads)
+            if (staged) {
+                const int r0 = t * J;
+                for (int k = 0; k < J; ++k) {
+                    const float2 q = cmul(Cs[r0 + k], v[k]);
+                    acc.x += q.x;
+                    acc.y += q.y;
+                }
+            } else {
+                const float2* row = C + (size_t)t * J;
+                for (int k = 0; k < J; ++k) {
+                    const float2 q = cmul(row[k], v[k]);
+                    acc.x += q.x;
+                    acc.y += q.y;
+                }
             }
         }
         const float m = block_max(sqrtf(cabs2(acc)), red);
         __syncthreads();
         if (t < J) v[t] = m > 0.f ? make_float2(acc.x / m, acc.y / m) : make_float2(1.f, 0.f);
+        __syncthreads();
+    }
+    float2 u = make_float2(1.f, 0.f);
+    if (t < J) {
+        const float r = sqrtf(cabs2(v[t]));
+        if (r > 0.f) u = make_float2(v[t].x / r, v[t].y / r);
+    }
+    const float sr = block_sum_f(t < J ? u.x : 0.f, red);
+    const float si = block_sum_f(t < J ? u.y : 0.f, red);
+    const float sm = sqrtf(sr * sr + si * si);
+    if (t < J) c[t] = sm > 0.f ? cmul(u, make_float2(sr / sm, -si / sm)) : u;
+}
+
+// The same power iteration for J <= 64 with 16 lanes per row of C: lane l of
+// row j forms the partial sum over k = l, l + 16, ... of C_jk v_k, the 16
+// partials are combined by butterfly (a fixed order), and the maximum of the
+// row norms is taken across the 4 rows of a wavefront and then across
+// wavefronts.  C (J^2 <= 4096) is staged in LDS once.  One block of
+// 64 ceil(J / 4) threads.
+__global__ void __launch_bounds__(1024) k_sync_power16(const float2* __restrict__ C, int J, int iters,
+                                                       float2* __restrict__ c) {
+    __shared__ float2 Cs[64 * 64];
+    __shared__ float2 v[64];
+    __shared__ float red[16];
+    const int t = threadIdx.x, row = t >> 4, l = t & 15, w = t >> 6, nw = (int)(blockDim.x >> 6);
+    for (int i = t; i < J * J; i += blockDim.x) Cs[i] = C[i];
+    if (t < J) v[t] = make_float2(1.f, 0.f);
+    __syncthreads();
+    for (int it = 0; it < iters; ++it) {
+        float2 acc = make_float2(0.f, 0.f);
+        if (row < J) {
+            for (int k = l; k < J; k += 16) {
+                const float2 q = cmul(Cs[row * J + k], v[k]);
+                acc.x += q.x;
+                acc.y += q.y;
+            }
+        }
+#pragma unroll
+        for (int o = 8; o > 0; o >>= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+        }
+        // every lane of a row holds its sum: the wave's maximum over its 4 rows
+        float m = row < J ? sqrtf(cabs2(acc)) : 0.f;
+        m = fmaxf(m, __shfl_xor(m, 16, 64));
+        m = fmaxf(m, __shfl_xor(m, 32, 64));
+        if ((t & 63) == 0) red[w] = m;
+        __syncthreads();
+        m = red[0];
+        for (int q = 1; q < nw; ++q) m = fmaxf(m, red[q]);
+        if (row < J && l == 0) v[row] = m > 0.f ? make_float2(acc.x / m, acc.y / m) : make_float2(1.f, 0.f);
         __syncthreads();
     }
     float2 u = make_float2(1.f, 0.f);
@@ -333,8 +403,12 @@ int ptycho_stitch(mnf_ctx* ctx, const float* patches, const mnf_c64* P, int Nw, 
         MNF_TRY(scratch(ctx, "sync_phasors", sizeof(float2) * (size_t)J, &cv));
         MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sync_gram, dim3(J, J), dim3(256), patches, (const float2*)P,
                    (const int2*)dpos, J, Nw, (float2*)C);
-        MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sync_power, dim3(1), dim3(1024), (const float2*)C, J, kSyncIters,
-                   (float2*)cv);
+        if (J <= 64)
+            MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sync_power16, dim3(1), dim3((unsigned)(64 * ((J + 3) / 4))),
+                       (const float2*)C, J, kSyncIters, (float2*)cv);
+        else
+            MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_sync_power, dim3(1), dim3((unsigned)(64 * ((J + 63) / 64))),
+                       (const float2*)C, J, kSyncIters, (float2*)cv);
         phasors = (float2*)cv;
     }
     MNF_LAUNCH(ctx, MNF_K_SMALL, st, k_stitch, dim3((Mx + 15) / 16, (My + 15) / 16), dim3(256), patches,
