@@ -354,8 +354,10 @@ __global__ void __launch_bounds__(256) k_conv3_c1(ConvArgs a) {
 }
 
 // 3x3 convolution (forward, or input gradient with flipped taps) as a direct
-// tiled kernel: a block computes TH x TW = 128 output pixels of one image x
-// 32 NB output channels (NB = 1 for layers with at most 32).  Per chunk of 32
+// tiled kernel: a block of WV waves computes TH x TW = 32 WV output pixels of
+// one image x 32 NB output channels (NB = 1 for layers with at most 32); the
+// weights staged per chunk serve all of the block's pixels, so a larger
+// block loads them fewer times per pixel.  Per chunk of 32
 // input channels it stages the input patch ((TH + 2) x (TW + 2) pixels, zero
 // padded, ReLU-masked for MASK) and the 9 x 32 NB x 32 weights in LDS once,
 // then every wave runs its 32 pixels x 32 NB channels through 9 taps x 2 K16
@@ -366,15 +368,16 @@ __global__ void __launch_bounds__(256) k_conv3_c1(ConvArgs a) {
 constexpr int kTileCh = 32;               // input channels per chunk
 constexpr int kTileLds = kTileCh + 8;     // padded LDS row (bf16) per pixel / weight row
 
-template <bool MASK, bool OUT_F32, int TW, int NB = 2>
-__global__ void __launch_bounds__(kGemmThreads) k_conv3_tiled(ConvArgs a) {
-    constexpr int TH = kGemmBM / TW;
+template <bool MASK, bool OUT_F32, int TW, int NB = 2, int WV = 4>
+__global__ void __launch_bounds__(64 * WV) k_conv3_tiled(ConvArgs a) {
+    constexpr int THREADS = 64 * WV, BM = 32 * WV;  // WV waves, 32 output pixels each
+    constexpr int TH = BM / TW;
     constexpr int BN = 32 * NB;  // output channels of the block
     constexpr int PW = TW + 2, PH = TH + 2, NPIX = PW * PH;
     constexpr int A_LOADS = NPIX * (kTileCh / 8);        // 16-byte pieces of the patch
     constexpr int B_LOADS = 9 * BN * (kTileCh / 8);      // 16-byte pieces of the weights
-    constexpr int A_PER = (A_LOADS + kGemmThreads - 1) / kGemmThreads;
-    constexpr int B_PER = (B_LOADS + kGemmThreads - 1) / kGemmThreads;
+    constexpr int A_PER = (A_LOADS + THREADS - 1) / THREADS;
+    constexpr int B_PER = (B_LOADS + THREADS - 1) / THREADS;
     __shared__ __attribute__((aligned(16))) uint16_t sA[NPIX * kTileLds];
     __shared__ __attribute__((aligned(16))) uint16_t sB[9 * BN * kTileLds];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -388,7 +391,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv3_tiled(ConvArgs a) {
     auto fetch = [&](int c0) {
 #pragma unroll
         for (int q = 0; q < A_PER; ++q) {
-            const int e = tid + q * kGemmThreads;
+            const int e = tid + q * THREADS;
             uint4 v = make_uint4(0, 0, 0, 0);
             if (e < A_LOADS) {
                 const int pix = e / (kTileCh / 8), piece = e % (kTileCh / 8);
@@ -413,7 +416,7 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv3_tiled(ConvArgs a) {
         }
 #pragma unroll
         for (int q = 0; q < B_PER; ++q) {
-            const int e = tid + q * kGemmThreads;
+            const int e = tid + q * THREADS;
             const int row = e / (kTileCh / 8), piece = e % (kTileCh / 8);  // row = tap * BN + co
             const int t = row / BN, n = n0 + row % BN;
             rb[q] = e < B_LOADS && n < a.Nout
@@ -428,12 +431,12 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv3_tiled(ConvArgs a) {
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < A_PER; ++q) {
-            const int e = tid + q * kGemmThreads;
+            const int e = tid + q * THREADS;
             if (e < A_LOADS) *(uint4*)(sA + (e / (kTileCh / 8)) * kTileLds + 8 * (e % (kTileCh / 8))) = ra[q];
         }
 #pragma unroll
         for (int q = 0; q < B_PER; ++q) {
-            const int e = tid + q * kGemmThreads;
+            const int e = tid + q * THREADS;
             if (e < B_LOADS) *(uint4*)(sB + (e / (kTileCh / 8)) * kTileLds + 8 * (e % (kTileCh / 8))) = rb[q];
         }
         __syncthreads();

@@ -84,30 +84,41 @@ int launch_conv(mnf_ctx* ctx, int mode, bool mask, bool out_f32, const ConvArgs&
         return MNF_OK;
     }
     if (mode == CONV3 && vec && a.Cin % kTileCh == 0 && a.Hin == a.Hout && a.Win == a.Wout) {
-        // direct tiled 3x3: tiles of 2 x 64 pixels, or 4 x 32 for narrow images
+        // direct tiled 3x3: 8-wave blocks of 4 x 64 pixels, or 8 x 32 for
+        // narrow images (4-wave blocks of half the height where the height
+        // does not divide)
         const int TW = a.Wout % 64 == 0 ? 64 : (a.Wout % 32 == 0 && a.Hout % 4 == 0 ? 32 : 0);
-        if (TW == 64 && a.Hout % 2 == 0 && a.Nout <= 32) {  // one 32-channel output tile
-            const dim3 gt((unsigned)(a.n * (a.Hout / 2) * (a.Wout / 64)), 1);
-            if (mask) hipLaunchKernelGGL((k_conv3_tiled<true, false, 64, 1>), gt, dim3(kGemmThreads), 0, st, a);
-            else if (out_f32)
-                hipLaunchKernelGGL((k_conv3_tiled<false, true, 64, 1>), gt, dim3(kGemmThreads), 0, st, a);
-            else hipLaunchKernelGGL((k_conv3_tiled<false, false, 64, 1>), gt, dim3(kGemmThreads), 0, st, a);
+        const bool big = TW > 0 && a.Hout % (256 / TW) == 0;
+        const int TH = (big ? 256 : 128) / (TW > 0 ? TW : 1);
+        const dim3 bt(big ? 512 : kGemmThreads);
+#define MNF_TILED(TWv, NBv)                                                                               \
+    do {                                                                                                  \
+        if (big) {                                                                                        \
+            if (mask) hipLaunchKernelGGL((k_conv3_tiled<true, false, TWv, NBv, 8>), gt, bt, 0, st, a);    \
+            else if (out_f32) hipLaunchKernelGGL((k_conv3_tiled<false, true, TWv, NBv, 8>), gt, bt, 0, st, a); \
+            else hipLaunchKernelGGL((k_conv3_tiled<false, false, TWv, NBv, 8>), gt, bt, 0, st, a);       \
+        } else {                                                                                          \
+            if (mask) hipLaunchKernelGGL((k_conv3_tiled<true, false, TWv, NBv, 4>), gt, bt, 0, st, a);    \
+            else if (out_f32) hipLaunchKernelGGL((k_conv3_tiled<false, true, TWv, NBv, 4>), gt, bt, 0, st, a); \
+            else hipLaunchKernelGGL((k_conv3_tiled<false, false, TWv, NBv, 4>), gt, bt, 0, st, a);       \
+        }                                                                                                 \
+    } while (0)
+        if (TW == 64 && a.Hout % TH == 0 && a.Nout <= 32) {  // one 32-channel output tile
+            const dim3 gt((unsigned)(a.n * (a.Hout / TH) * (a.Wout / 64)), 1);
+            MNF_TILED(64, 1);
             return MNF_OK;
         }
-        if (TW == 64 && a.Hout % 2 == 0) {
-            const dim3 gt((unsigned)(a.n * (a.Hout / 2) * (a.Wout / 64)), g1((size_t)a.Nout, kGemmBN));
-            if (mask) hipLaunchKernelGGL((k_conv3_tiled<true, false, 64>), gt, dim3(kGemmThreads), 0, st, a);
-            else if (out_f32) hipLaunchKernelGGL((k_conv3_tiled<false, true, 64>), gt, dim3(kGemmThreads), 0, st, a);
-            else hipLaunchKernelGGL((k_conv3_tiled<false, false, 64>), gt, dim3(kGemmThreads), 0, st, a);
+        if (TW == 64 && a.Hout % TH == 0) {
+            const dim3 gt((unsigned)(a.n * (a.Hout / TH) * (a.Wout / 64)), g1((size_t)a.Nout, kGemmBN));
+            MNF_TILED(64, 2);
             return MNF_OK;
         }
-        if (TW == 32) {
-            const dim3 gt((unsigned)(a.n * (a.Hout / 4) * (a.Wout / 32)), g1((size_t)a.Nout, kGemmBN));
-            if (mask) hipLaunchKernelGGL((k_conv3_tiled<true, false, 32>), gt, dim3(kGemmThreads), 0, st, a);
-            else if (out_f32) hipLaunchKernelGGL((k_conv3_tiled<false, true, 32>), gt, dim3(kGemmThreads), 0, st, a);
-            else hipLaunchKernelGGL((k_conv3_tiled<false, false, 32>), gt, dim3(kGemmThreads), 0, st, a);
+        if (TW == 32 && a.Hout % TH == 0) {
+            const dim3 gt((unsigned)(a.n * (a.Hout / TH) * (a.Wout / 32)), g1((size_t)a.Nout, kGemmBN));
+            MNF_TILED(32, 2);
             return MNF_OK;
         }
+#undef MNF_TILED
     }
     const dim3 grid(g1((size_t)a.M, kGemmBM), g1((size_t)a.Nout, kGemmBN));
 #define MNF_CONV_BK(MD, MK, VC, OF)                                                                    \
