@@ -34,11 +34,13 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 enum ConvMode { CONV3 = 0, DOWN = 1, UP = 2, CONV1 = 3 };
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// float -> bf16, round to nearest even; infinities kept, NaNs kept quiet.
+// Both results are formed and one selected, so a wave takes no branch.
 __device__ __forceinline__ uint16_t f2bf(float f) {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffff) ? 0x40 : 0));  // inf / nan
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-    return (uint16_t)(u >> 16);
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t rne = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    const uint32_t special = (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);  // inf / nan
+    return (uint16_t)((u & 0x7f800000u) == 0x7f800000u ? special : rne);
 }
 
 struct ConvArgs {
@@ -459,23 +461,38 @@ __global__ void __launch_bounds__(64 * WV) k_conv3_tiled(ConvArgs a) {
             }
         }
     }
-    // epilogue: accumulator row i is pixel 32 w + i of the tile
+    // epilogue: accumulator row i is pixel 32 w + i of the tile.  The wave's
+    // 32 pixels lie in one tile row (32 divides TW), so value v of a lane is
+    // pixel op0 + 8 (v / 4) + v % 4 of the image: one base address per lane,
+    // compile-time pixel offsets scaled by the uniform channel strides.
+    const size_t op0 = ((size_t)img * a.Hout + y0 + (32 * w) / TW) * a.Wout + x0 + (32 * w) % TW + 4 * (lane >> 5);
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb) {
         const int j = n0 + 32 * nb + (lane & 31);
         if (j >= a.Nout) continue;
         const float bj = a.bias ? a.bias[j] : 0.f;
+        float yv[16];
+#pragma unroll
+        for (int v = 0; v < 16; ++v) yv[v] = (nb == 0 ? acc0[v] : acc1[v]) + bj;
+        if (a.resid) {
+            const uint16_t* rp = a.resid + op0 * a.res_cs + a.res_co + j;
+            uint16_t rv[16];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) rv[v] = rp[(size_t)(8 * (v / 4) + v % 4) * a.res_cs];
+#pragma unroll
+            for (int v = 0; v < 16; ++v) yv[v] += bf2f(rv[v]);
+        }
+        if (a.relu) {
+#pragma unroll
+            for (int v = 0; v < 16; ++v) yv[v] = fmaxf(yv[v], 0.f);
+        }
 #pragma unroll
         for (int v = 0; v < 16; ++v) {
-            const int i = 32 * w + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
-            const size_t op = ((size_t)img * a.Hout + y0 + i / TW) * a.Wout + x0 + i % TW;
-            float yv = (nb == 0 ? acc0[v] : acc1[v]) + bj;
-            if (a.resid) yv += bf2f(a.resid[op * a.res_cs + a.res_co + j]);
-            if (a.relu) yv = fmaxf(yv, 0.f);
+            const size_t off = (size_t)(8 * (v / 4) + v % 4) * a.out_cs;
             if constexpr (OUT_F32)
-                ((float*)a.out)[op * a.out_cs + a.out_co + j] = yv;
+                ((float*)a.out)[(op0 * a.out_cs + a.out_co + j) + off] = yv[v];
             else
-                ((uint16_t*)a.out)[op * a.out_cs + a.out_co + j] = f2bf(yv);
+                ((uint16_t*)a.out)[(op0 * a.out_cs + a.out_co + j) + off] = f2bf(yv[v]);
         }
     }
 }
