@@ -290,11 +290,40 @@ __global__ void __launch_bounds__(kGemmThreads) k_conv_gemm(ConvArgs a) {
     // both column halves
     size_t opv[16];
     bool okv[16];
+    if (MODE == UP && a.Win >= 4) {
+        // The block's rows lie in one parity group (per_pad is a multiple of
+        // the row tile), so the group is uniform; a lane's rows come in four
+        // runs of four consecutive input pixels: one division-based
+        // decomposition per run, then at most one row carry per step (Win > 3).
+        const int q = m0 / a.per_pad, npx = a.n * a.Hin * a.Win;
+        const int rl = m0 - q * a.per_pad + 32 * w + 4 * (lane >> 5);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
-        const int m = m0 + 32 * w + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
-        okv[v] = m < a.M && (MODE != UP || m % a.per_pad < a.n * a.Hin * a.Win);
-        opv[v] = okv[v] ? out_pixel<MODE>(a, m) : 0;
+        for (int g = 0; g < 4; ++g) {
+            const int r = rl + 8 * g;
+            const int x = r % a.Win, t1 = r / a.Win;
+            const int y = t1 % a.Hin, img = t1 / a.Hin;
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const int v = 4 * g + d;
+                int xd = x + d, yd = y, id = img;
+                if (xd >= a.Win) {
+                    xd -= a.Win;
+                    if (++yd == a.Hin) {
+                        yd = 0;
+                        ++id;
+                    }
+                }
+                okv[v] = m0 + 32 * w + 4 * (lane >> 5) + 8 * g + d < a.M && r + d < npx;
+                opv[v] = okv[v] ? ((size_t)id * a.Hout + 2 * yd + q / 2) * a.Wout + 2 * xd + q % 2 : 0;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int m = m0 + 32 * w + 8 * (v / 4) + 4 * (lane >> 5) + (v % 4);
+            okv[v] = m < a.M && (MODE != UP || m % a.per_pad < a.n * a.Hin * a.Win);
+            opv[v] = okv[v] ? out_pixel<MODE>(a, m) : 0;
+        }
     }
 #pragma unroll
     for (int nb = 0; nb < 2; ++nb) {
