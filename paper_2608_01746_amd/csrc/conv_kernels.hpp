@@ -34,14 +34,11 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 enum ConvMode { CONV3 = 0, DOWN = 1, UP = 2, CONV1 = 3 };
 
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-// float -> bf16, round to nearest even; infinities kept, NaNs kept quiet.
-// Both results are formed and one selected, so a wave takes no branch.
-__device__ __forceinline__ uint16_t f2bf(float f) {
-    const uint32_t u = __float_as_uint(f);
-    const uint32_t rne = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
-    const uint32_t special = (u >> 16) | ((u & 0xffffu) ? 0x40u : 0u);  // inf / nan
-    return (uint16_t)((u & 0x7f800000u) == 0x7f800000u ? special : rne);
-}
+// float -> bf16, round to nearest even (subnormals included), infinities
+// kept, NaNs quiet: the hardware conversion (v_cvt_pk_bf16_f32), which for
+// every non-NaN input gives the bits of the integer rounding
+// (u + 0x7fff + ((u >> 16) & 1)) >> 16 of the float's bits u.
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 struct ConvArgs {
     const uint16_t* in;     // [n][Hin][Win][in_cs] bf16, channels [in_co, in_co + Cin)
