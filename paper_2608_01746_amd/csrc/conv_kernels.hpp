@@ -1051,19 +1051,24 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, size_
     dW[i] = s;
 }
 
-// The same sum for many partials and few outputs: one wave per output, lane l
-// adding partials l, l + 64, ..., then a butterfly across the wave (a fixed
-// order); grid ceil(count / 4), block 256.
+// The same sum for many partials: a block owns 64 consecutive outputs; wave w
+// adds partials w, w + 4, w + 8, ... of its lane's output in that order (each
+// load instruction reads 64 consecutive values of one partial array), and the
+// four wave sums are added as (w0 + w1) + (w2 + w3): a fixed order.
+// grid ceil(count / 64), block 256.
 __global__ void __launch_bounds__(256) k_wgrad_reduce_wide(const float* __restrict__ part, int splits, size_t count,
                                                            float* __restrict__ dW) {
-    const size_t i = (size_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const size_t i = (size_t)blockIdx.x * 64 + lane;
     float s = 0.f;
-    if (i < count)
-        for (int k = lane; k < splits; k += 64) s += part[(size_t)k * count + i];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-    if (i < count && lane == 0) dW[i] = s;
+    if (i < count) {
+#pragma unroll 8
+        for (int k = w; k < splits; k += 4) s += part[(size_t)k * count + i];
+    }
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && i < count) dW[i] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 // Weight and bias gradient of a 3x3 convolution with one input channel (the

@@ -285,10 +285,10 @@ size_t bd_size(const LayerDesc& L) {
 }
 
 // Fixed-order sum of `splits` float32 partial arrays of `count` values: one
-// thread per value for few partials, one wave per value for many.
+// thread per value for few partials, four (one per wave) for many.
 void reduce_partials(const float* part, int splits, size_t count, float* out, hipStream_t st) {
     if (splits >= 64)
-        hipLaunchKernelGGL(k_wgrad_reduce_wide, dim3(g1(count, 4)), dim3(256), 0, st, part, splits, count, out);
+        hipLaunchKernelGGL(k_wgrad_reduce_wide, dim3(g1(count, 64)), dim3(256), 0, st, part, splits, count, out);
     else
         hipLaunchKernelGGL(k_wgrad_reduce, dim3(g1(count)), dim3(256), 0, st, part, splits, count, out);
 }
