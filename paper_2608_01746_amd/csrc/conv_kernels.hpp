@@ -1051,6 +1051,64 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int splits, size_
     dW[i] = s;
 }
 
+// Weight and bias gradient of a 1x1 convolution to CO output channels (the
+// head), unmasked: dW[ci][co] = sum_p x[p][ci] g[p][co], db[co] = sum_p g[p][co].
+// Thread t owns input channels 8 (t % G) .. + 7 (G = Cin / 8) and every
+// (256 / G)-th pixel of the block's range [z per, (z + 1) per), 16-byte input
+// loads; its 8 CO sums (and, for t % G == 0, the CO bias sums) are added
+// across the pixel lanes in lane order through LDS.  part [blocks][Cin][CO],
+// bpart [blocks][CO].  Needs Cin a multiple of 8 with Cin / 8 dividing 256, and
+// 16-byte aligned input channel groups.
+template <int CO>
+__global__ void __launch_bounds__(256) k_wgrad_head(WgradArgs a, int per) {
+    __shared__ float red[256 * 8 * CO];
+    __shared__ float bred[256 * CO];
+    const int G = a.Cin / 8, lanes = 256 / G;
+    const int g = threadIdx.x % G, pl = threadIdx.x / G;
+    const int p_begin = blockIdx.x * per, p_end = min(a.P, p_begin + per);
+    float acc[8][CO], bs[CO];
+#pragma unroll
+    for (int c = 0; c < CO; ++c) {
+        bs[c] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k][c] = 0.f;
+    }
+#pragma unroll 4
+    for (int p = p_begin + pl; p < p_end; p += lanes) {
+        const uint4 xv = *(const uint4*)(a.in + (size_t)p * a.in_cs + a.in_co + 8 * g);
+        const uint16_t* xs = (const uint16_t*)&xv;
+        float gv[CO];
+#pragma unroll
+        for (int c = 0; c < CO; ++c) gv[c] = bf2f(a.dout[(size_t)p * a.dout_cs + c]);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const float xk = bf2f(xs[k]);
+#pragma unroll
+            for (int c = 0; c < CO; ++c) acc[k][c] = fmaf(xk, gv[c], acc[k][c]);
+        }
+#pragma unroll
+        for (int c = 0; c < CO; ++c) bs[c] += gv[c];
+    }
+    // lane pl's sums at red[pl][(8 g + k) CO + c]
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+#pragma unroll
+        for (int c = 0; c < CO; ++c) red[pl * (8 * G * CO) + (8 * g + k) * CO + c] = acc[k][c];
+#pragma unroll
+    for (int c = 0; c < CO; ++c) bred[threadIdx.x * CO + c] = bs[c];
+    __syncthreads();
+    for (int o = threadIdx.x; o < a.Cin * CO; o += 256) {
+        float r = 0.f;
+        for (int l = 0; l < lanes; ++l) r += red[l * (8 * G * CO) + o];
+        a.part[(size_t)blockIdx.x * a.Cin * CO + o] = r;
+    }
+    if (threadIdx.x < CO) {
+        float r = 0.f;
+        for (int l = 0; l < lanes; ++l) r += bred[(l * G) * CO + threadIdx.x];  // the g == 0 thread of each lane
+        a.bpart[(size_t)blockIdx.x * CO + threadIdx.x] = r;
+    }
+}
+
 // The same sum for many partials: a block owns 64 consecutive outputs; wave w
 // adds partials w, w + 4, w + 8, ... of its lane's output in that order (each
 // load instruction reads 64 consecutive values of one partial array), and the

@@ -387,6 +387,22 @@ int layer_wgrad(mnf_ctx* ctx, const LayerDesc& L, View x, int n, int Hin, View d
         reduce_partials((const float*)bpart, splits, (size_t)L.co, db, st);
         return MNF_OK;
     }
+    // the 1x1 head to two channels: a streaming reduction over the pixels
+    if (L.mode == CONV1 && L.co == 2 && !mask && L.ci % 8 == 0 && 256 % (L.ci / 8) == 0 && x.cs % 8 == 0 &&
+        x.co % 8 == 0) {
+        const int nb = (int)std::min<long long>(1024, ((long long)a.P + 255) / 256);
+        const int per = (a.P + nb - 1) / nb;
+        void* part;
+        void* bpart;
+        MNF_TRY(scratch(ctx, "unet_wpart", (size_t)nb * count * sizeof(float), &part));
+        MNF_TRY(scratch(ctx, "unet_bpart", (size_t)nb * L.co * sizeof(float), &bpart));
+        a.part = (float*)part;
+        a.bpart = (float*)bpart;
+        hipLaunchKernelGGL(k_wgrad_head<2>, dim3(nb), dim3(256), 0, st, a, per);
+        reduce_partials((const float*)part, nb, count, dW, st);
+        reduce_partials((const float*)bpart, nb, (size_t)L.co, db, st);
+        return MNF_OK;
+    }
     const int tiles = g1((size_t)L.co, 64) * g1((size_t)L.ci, 64) * taps;
     a.splits = std::max(1, std::min(target_blocks / std::max(1, tiles), (a.P + 4095) / 4096));
     const int btaps = L.mode == UP ? 4 : 1;
